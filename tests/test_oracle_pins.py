@@ -1,0 +1,443 @@
+"""Pins for the CPU oracle: it is checked against what the paper and the
+mathematics fix, never against itself.
+
+* rounding helpers vs numpy/torch conversions and the paper's Table 1;
+* exact summation and residuals vs rational arithmetic;
+* Algorithm 1 closed forms: diagonal and permutation matrices, full pattern;
+* fixed-pattern columns vs the least-squares definition (numpy lstsq and
+  exact rational normal equations);
+* candidate scores vs brute-force univariate minimisation, selection rule,
+  monotonicity and the Frobenius/infinity-norm bounds of Section 3.1;
+* GMRES vs the exact Krylov least-squares minimiser, the exact-preconditioner
+  case of Table 5, and the limiting accuracy of Theorems 1-2.
+"""
+import math
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _csr(dense):
+    S = sp.csr_matrix(dense)
+    S.sort_indices()
+    S.eliminate_zeros()
+    return W.CSR(S.shape[0], S.indptr.astype(np.int32), S.indices.astype(np.int32),
+                 S.data.astype(np.float64))
+
+
+def _dense(A):
+    return A.to_scipy().toarray()
+
+
+def _random_dd(n, rng, density=0.3, dom=1.5):
+    """random nonsymmetric, nonzero diagonal, row diagonally dominant"""
+    M = rng.standard_normal((n, n)) * (rng.random((n, n)) < density)
+    np.fill_diagonal(M, 0.0)
+    np.fill_diagonal(M, dom * np.abs(M).sum(1) + 1.0)
+    M *= np.where(rng.random(n) < 0.5, -1.0, 1.0)[:, None]   # random row signs
+    return M
+
+
+# ---------------------------------------------------------------------------
+# precision helpers
+# ---------------------------------------------------------------------------
+
+def _special_f32(rng, count):
+    vals = list(rng.standard_normal(count // 2) * 10.0 ** rng.integers(-9, 6, count // 2))
+    vals += list(np.ldexp(rng.integers(-2**23, 2**23, count // 2).astype(np.float64), -30))
+    vals += [0.0, -0.0, 65504.0, 65519.99, 65520.0, -65520.0, 6.1e-5, 5.96e-8, 2.98e-8, 1e-9,
+             3.0e38, 1.2e-38, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11]
+    return np.array(vals, dtype=np.float32).astype(np.float64)
+
+
+def test_round_fp16_matches_numpy_conversion():
+    xs = _special_f32(np.random.default_rng(1), 20000)
+    ours = np.array([O.round_to(x, "fp16") for x in xs])
+    ref = xs.astype(np.float32).astype(np.float16).astype(np.float64)
+    assert np.array_equal(ours, ref, equal_nan=True)
+
+
+def test_round_bf16_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    xs = _special_f32(np.random.default_rng(2), 20000)
+    xs = xs[np.abs(xs) < 3.0e38]
+    ours = np.array([O.round_to(x, "bf16") for x in xs])
+    ref = torch.tensor(xs, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_unit_roundoff_matches_table1():
+    """Max relative rounding error over normal values equals the printed u."""
+    table = {}
+    for line in open(f"{GOLDEN}/table1_unit_roundoff.txt"):
+        if line.strip() and not line.startswith("#"):
+            name, _bits, e = line.split()
+            table[name] = 2.0 ** int(e)
+    rng = np.random.default_rng(3)
+    xs = np.exp(rng.uniform(-5, 5, 50000))
+    for name, uf in (("half", "fp16"), ("single", "fp32")):
+        rel = max(abs(O.round_to(x, uf) - x) / abs(x) for x in xs)
+        u = table[name]
+        assert rel <= u * (1 + 1e-12)
+        assert rel > 0.9 * u, (name, rel, u)
+
+
+# ---------------------------------------------------------------------------
+# exact summation and residual
+# ---------------------------------------------------------------------------
+
+def test_exact_sum_vs_fsum_and_fractions():
+    rng = random.Random(4)
+    for _ in range(300):
+        k = rng.randint(1, 40)
+        xs = [rng.choice([1, -1]) * rng.random() * 2.0 ** rng.randint(-60, 60) for _ in range(k)]
+        xs += [-x for x in xs[: rng.randint(0, k)]]        # cancellation
+        xs.append(rng.random() * 2.0 ** -80)
+        rng.shuffle(xs)
+        exact = float(sum(Fraction(x) for x in xs))         # Fraction -> float rounds correctly
+        assert O.exact_sum(xs) == exact == math.fsum(xs)
+
+
+def test_residual_is_exactly_rounded():
+    rng = np.random.default_rng(5)
+    for n in (7, 23):
+        A = _csr(_random_dd(n, rng))
+        x = rng.standard_normal(n)
+        b = rng.standard_normal(n)
+        r = O.residual(A, b, x)
+        D = _dense(A)
+        for i in range(n):
+            exact = Fraction(b[i]) - sum(Fraction(D[i, j]) * Fraction(x[j]) for j in range(n) if D[i, j] != 0)
+            assert r[i] == float(exact)
+
+
+@pytest.mark.parametrize("make", [lambda: W.convdiff_small(32), lambda: W.convdiff_adaptive(24),
+                                  lambda: W.aniso_fixed(8), lambda: W.random_system(300)])
+def test_exact_rhs_has_zero_residual(make):
+    w = make()
+    assert np.all(O.residual(w.A, w.b, w.x_true) == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1: closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("uf", ["fp64", "fp32", "fp16", "bf16"])
+def test_diagonal_matrix_gives_exact_inverse(uf):
+    """B = A^T D is diagonal with B_kk = d_k a_kk, within one FP64 rounding of
+    sign(a_kk); rounded to a u_f coarser than FP64 it is +-1 exactly, so m-bar =
+    +-1, the residual is 0 and P = diag(d_k sign(a_kk)) = diag(fl(1/a_kk)).
+    Extra pattern entries get exactly zero coefficients."""
+    rng = np.random.default_rng(6)
+    n = 40
+    diag = rng.uniform(0.1, 50.0, n) * np.where(rng.random(n) < 0.5, -1, 1)
+    A = _csr(np.diag(diag))
+    for pattern in (None, W.pattern_of(_csr(np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)))):
+        R = O.spai(A, pattern, eps=0.1, alpha=5, beta=8, maxfill=8, uf=uf)
+        assert np.all(R.steps == 0) and np.all(R.flags == 0)
+        pp, pc, pv = R.P_csr(n)
+        Pd = sp.csr_matrix((pv * R.d[pc], pc, pp), shape=(n, n)).toarray()
+        assert np.count_nonzero(Pd - np.diag(np.diag(Pd))) == 0
+        if uf == "fp64":
+            assert np.all(R.res <= 2.0 ** -52)
+            assert np.all(np.abs(np.diag(Pd) * diag - 1.0) <= 4 * 2.0 ** -53)
+        else:
+            assert np.all(R.res == 0.0)
+            assert np.array_equal(np.diag(Pd), 1.0 / diag)
+
+
+@pytest.mark.parametrize("uf", ["fp64", "fp32", "fp16"])
+def test_permutation_matrix_closed_form_trace(uf):
+    """Identity start on a permutation matrix: fixed points stop at step 0 with
+    m-bar = 1; every other column finds its single candidate j* = pi^{-1}(k) with
+    rho = 0 = rho-bar, stops after one augmentation with J_k = (k, j*), m-bar =
+    (0, 1), residual 0, and P A = I exactly.  This pins the residual on the full
+    column (k outside the shadow contributes 1) and the full-column score."""
+    rng = np.random.default_rng(7)
+    n = 60
+    perm = np.arange(n)
+    perm[5:] = 5 + rng.permutation(n - 5)       # 0..4 (and maybe more) are fixed points
+    Pm = np.zeros((n, n))
+    Pm[np.arange(n), perm] = 1.0                # A(k, pi(k)) = 1
+    A = _csr(Pm)
+    R = O.spai(A, None, eps=0.2, alpha=-(-n // 8), beta=8, maxfill=10, uf=uf)
+    inv = np.argsort(perm)                       # pi^{-1}
+    for k in range(n):
+        if perm[k] == k:
+            assert R.steps[k] == 0 and R.length[k] == 1 and R.m[k, 0] == 1.0
+        else:
+            assert R.steps[k] == 1 and R.length[k] == 2
+            assert list(R.J[k, :2]) == [k, inv[k]]
+            assert R.m[k, 0] == 0.0 and R.m[k, 1] == 1.0
+        assert R.res[k] == 0.0
+    pp, pc, pv = R.P_csr(n)
+    PA = sp.csr_matrix((pv * R.d[pc], pc, pp), shape=(n, n)) @ A.to_scipy()
+    assert np.array_equal(PA.toarray(), np.eye(n))
+
+
+@pytest.mark.parametrize("uf,tol", [("fp64", 1e-12), ("fp32", 2e-4)])
+def test_full_pattern_reproduces_dense_inverse(uf, tol):
+    """With J = all indices each column solves B m_k = e_k exactly (Section 3.1
+    notes the full-pattern limit), so P = M^T D = A^{-1}."""
+    rng = np.random.default_rng(8)
+    n = 30
+    Ad = _random_dd(n, rng, density=0.4)
+    A = _csr(Ad)
+    full = W.Pattern(n, np.arange(0, n * n + 1, n, dtype=np.int32), np.tile(np.arange(n, dtype=np.int32), n))
+    R = O.spai(A, full, eps=1e-30, alpha=0, beta=8, maxfill=n, uf=uf)
+    pp, pc, pv = R.P_csr(n)
+    P = sp.csr_matrix((pv * R.d[pc], pc, pp), shape=(n, n)).toarray()
+    Ainv = np.linalg.inv(Ad)
+    err = np.abs(P - Ainv).max() / np.abs(Ainv).max()
+    kappa = np.linalg.cond(Ad, 1)
+    assert err <= tol * max(1.0, kappa / 10.0), (err, kappa)
+
+
+# ---------------------------------------------------------------------------
+# fixed-pattern columns vs the least-squares definition
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make", [lambda: W.convdiff_small(16), lambda: W.aniso_fixed(6)])
+def test_fixed_pattern_fp64_matches_lstsq(make):
+    w = make()
+    A = w.A
+    R = O.spai(A, w.pattern, eps=w.spai.eps, alpha=0, beta=8, maxfill=w.spai.maxfill, uf="fp64")
+    worst = 0.0
+    for k in range(A.n):
+        L = R.length[k]
+        J = R.J[k, :L]
+        assert sorted(J) == sorted(w.pattern.idx[w.pattern.ptr[k]:w.pattern.ptr[k + 1]])
+        mbar, res = O.ls_column(A, R.d, k, J)
+        worst = max(worst, np.abs(R.m[k, :L] - mbar).max() / np.abs(mbar).max())
+        assert abs(R.res[k] - res) <= 1e-12 * max(res, 1e-300) + 1e-15
+    assert worst < 1e-12
+
+
+def test_fixed_pattern_fp64_matches_exact_normal_equations():
+    """Exact rational solution of (A-bar^T A-bar) m = A-bar^T e-bar on tiny inputs."""
+    rng = np.random.default_rng(9)
+    n = 9
+    Ad = _random_dd(n, rng, density=0.35)
+    A = _csr(Ad)
+    pat = _csr((rng.random((n, n)) < 0.3) | np.eye(n, dtype=bool))
+    pattern = W.Pattern(n, pat.rowptr, pat.col)
+    R = O.spai(A, pattern, eps=1e-30, alpha=0, beta=8, maxfill=n, uf="fp64")
+    d = O.scaling(A)
+    for k in range(n):
+        L = R.length[k]
+        J = [int(j) for j in R.J[k, :L]]
+        I = sorted({i for j in J for i in range(n) if Ad[j, i] != 0})
+        Ab = [[Fraction(d[j] * Ad[j, i]) for j in J] for i in I]   # B(i, j) = d_j a_ji (FP64 product)
+        e = [Fraction(int(i == k)) for i in I]
+        p = len(J)
+        G = [[sum(Ab[r][a] * Ab[r][b] for r in range(len(I))) for b in range(p)] for a in range(p)]
+        h = [sum(Ab[r][a] * e[r] for r in range(len(I))) for a in range(p)]
+        # Gauss-Jordan in exact arithmetic
+        M = [row[:] + [h[a]] for a, row in enumerate(G)]
+        for c in range(p):
+            piv = next(r for r in range(c, p) if M[r][c] != 0)
+            M[c], M[piv] = M[piv], M[c]
+            M[c] = [v / M[c][c] for v in M[c]]
+            for r in range(p):
+                if r != c and M[r][c] != 0:
+                    M[r] = [a - M[r][c] * b for a, b in zip(M[r], M[c])]
+        exact = np.array([float(M[a][p]) for a in range(p)])
+        kap = np.linalg.cond(np.array([[float(v) for v in row] for row in Ab]))
+        assert np.abs(R.m[k, :L] - exact).max() <= 10 * kap * 2.0 ** -53 * np.abs(exact).max() * 10
+
+
+# ---------------------------------------------------------------------------
+# candidate scores, selection and invariants of the adaptive loop
+# ---------------------------------------------------------------------------
+
+def test_rho_is_the_univariate_minimum():
+    """rho_j^2 = min_mu ||r - mu B e_j||^2 with r = e_k - B m_k on all n rows,
+    and adding j alone to J leaves a residual no larger than rho_j."""
+    w = W.convdiff_adaptive(12)
+    A = w.A
+    Bd = (_dense(A).T * O.scaling(A)[None, :])     # B = A^T D
+    n = A.n
+    rng = np.random.default_rng(10)
+    for k in rng.choice(n, 25, replace=False):
+        J = [int(k)]
+        for _ in range(3):
+            pr = O.spai_probe(A, int(k), J, "fp64")
+            mfull = np.zeros(n)
+            mfull[J] = pr.mbar
+            r = np.eye(n)[:, k] - Bd @ mfull
+            assert abs(np.linalg.norm(r) - pr.res) <= 1e-12
+            for j, rho in zip(pr.cand, pr.rho):
+                bj = Bd[:, j]
+                mu = (r @ bj) / (bj @ bj)
+                brute = np.linalg.norm(r - mu * bj)
+                assert abs(brute - rho) <= 1e-10 * max(1.0, brute)
+                pj = O.spai_probe(A, int(k), J + [int(j)], "fp64")
+                assert pj.res <= rho + 1e-12
+            assert abs(pr.rbar - pr.rho.mean()) <= 1e-12
+            # every column index that meets the shadow's rows (or row k) is a candidate
+            L = set(pr.I.tolist()) | {int(k)}
+            cands = sorted({int(j) for j in range(n) if j not in J and any(Bd[l, j] != 0 for l in L)})
+            assert list(pr.cand) == cands
+            J = J + [int(pr.cand[np.argmin(pr.rho)])]
+
+
+@pytest.mark.parametrize("uf", ["fp64", "fp32"])
+def test_selection_rule_and_invariants(uf):
+    """Replaying each column from its insertion-ordered J: every step adds the
+    min(beta, |acceptable|, maxfill - |J|) acceptable candidates with the
+    smallest (rho, j); residuals never increase (exact LS property, up to
+    rounding); the stop happens at res <= eps, the fill cap or alpha."""
+    w = W.convdiff_adaptive(16, u_f=uf)
+    A, s = w.A, w.spai
+    R = O.spai(A, None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    u = 2.0 ** -53 if uf == "fp64" else 2.0 ** -24
+    for k in range(0, A.n, 7):
+        L = R.length[k]
+        Jk = [int(j) for j in R.J[k, :L]]
+        assert Jk[0] == k and len(set(Jk)) == L and L <= s.maxfill
+        pos = 1
+        hist = R.hist[k][~np.isnan(R.hist[k])]
+        assert len(hist) == R.steps[k] + 1
+        assert np.all(np.diff(hist) <= 1e3 * u)
+        for step in range(R.steps[k]):
+            pr = O.spai_probe(A, k, Jk[:pos], uf)
+            assert pr.res == hist[step] and pr.res > s.eps
+            acc = sorted([(rho, j) for j, rho in zip(pr.cand, pr.rho) if rho <= pr.rbar])
+            nsel = min(s.beta, len(acc), s.maxfill - pos)
+            assert Jk[pos:pos + nsel] == [j for _, j in acc[:nsel]]
+            pos += nsel
+        assert pos == L
+        if R.res[k] > s.eps:
+            assert R.flags[k] & O.FLAG_EPS and (L >= s.maxfill or R.steps[k] >= s.alpha)
+
+
+def test_frobenius_decoupling_and_bounds():
+    """||I - B M||_F^2 = sum_k ||e_k - B m_k||^2 (eq. fronormmin), <= n eps^2 when
+    every column meets eps, and ||I - P A||_inf <= 2 n eps (eq. AM1)."""
+    w = W.convdiff_adaptive(20, u_f="fp64")
+    A, s = w.A, w.spai
+    R = O.spai(A, None, s.eps, s.alpha, s.beta, s.maxfill, "fp64")
+    n = A.n
+    assert np.all(R.res <= s.eps)
+    pp, pc, pv = R.P_csr(n)
+    M_T = sp.csr_matrix((pv, pc, pp), shape=(n, n))             # row k = m_k^T
+    B = A.to_scipy().T @ sp.diags(R.d)
+    E = (sp.identity(n) - B @ M_T.T).toarray()
+    fro2 = (E ** 2).sum()
+    assert abs(fro2 - (R.res ** 2).sum()) <= 1e-10 * fro2
+    assert math.sqrt(fro2) <= math.sqrt(n) * s.eps
+    PA = (M_T @ sp.diags(R.d) @ A.to_scipy()).toarray()
+    assert np.abs(np.eye(n) - PA).sum(1).max() <= 2 * n * s.eps
+
+
+def test_larger_eps_gives_sparser_preconditioner_and_more_iterations():
+    """Section 4: a larger eps gives a sparser P and more GMRES iterations."""
+    w = W.convdiff_adaptive(32)
+    A, s, ir = w.A, w.spai, w.ir
+    nnz, tot = [], []
+    for eps in (0.5, 0.3, 0.2):
+        R = O.spai(A, None, eps, s.alpha, s.beta, 40, "fp32")
+        pp, pc, pv = R.P_csr(A.n)
+        res = O.gmres_ir(A, pp, pc, pv, R.d, "fp32", w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+        nnz.append(pp[-1])
+        tot.append(res.total)
+        assert O.ferr(res.x, w.x_true) <= 1e-12
+    assert nnz[0] < nnz[1] < nnz[2]
+    assert tot[0] > tot[1] > tot[2]
+
+
+def test_fp32_and_fp64_spai_give_similar_preconditioners():
+    """Section 3.1 / Table 5: no benefit from u_f finer than the eps-dictated level."""
+    w = W.convdiff_adaptive(32)
+    A, s, ir = w.A, w.spai, w.ir
+    out = {}
+    for uf in ("fp32", "fp64"):
+        R = O.spai(A, None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+        pp, pc, pv = R.P_csr(A.n)
+        res = O.gmres_ir(A, pp, pc, pv, R.d, uf, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+        out[uf] = (pp[-1], res.total)
+    assert abs(out["fp32"][0] - out["fp64"][0]) <= 0.02 * out["fp64"][0]
+    assert abs(out["fp32"][1] - out["fp64"][1]) <= 0.1 * out["fp64"][1]
+
+
+# ---------------------------------------------------------------------------
+# GMRES-IR
+# ---------------------------------------------------------------------------
+
+def test_gmres_step_is_the_krylov_least_squares_minimiser():
+    """After k iterations (tau = 0) MGS-GMRES returns d = argmin over K_k(PA, z)
+    of ||z - PA d||_2 with z = P r0; checked against an SVD-based solve."""
+    rng = np.random.default_rng(11)
+    n = 8
+    Ad = _random_dd(n, rng, density=0.6, dom=0.4)
+    A = _csr(Ad)
+    b = rng.standard_normal(n)
+    for use_identity in (True, False):
+        if use_identity:                                  # P = I: plain GMRES
+            pp, pc, pv, d = np.arange(n + 1), np.arange(n), np.ones(n), np.ones(n)
+        else:
+            R = O.spai(A, None, 0.6, 0, 8, 8, "fp64")      # a diagonal P
+            pp, pc, pv = R.P_csr(n)
+            d = R.d
+        P = sp.csr_matrix((pv * d[pc], pc, pp), shape=(n, n)).toarray()
+        for k in range(1, 6):
+            res = O.gmres_ir(A, pp, pc, pv, d, "fp64", b, 0.0, 1, k, 0.0)
+            assert res.its == [k]
+            x0 = P @ b
+            r0 = b - Ad @ x0
+            z = P @ r0
+            PA = P @ Ad
+            K = np.column_stack([np.linalg.matrix_power(PA, i) @ z for i in range(k)])
+            Q, _ = np.linalg.qr(K)
+            y, *_ = np.linalg.lstsq(PA @ Q, z, rcond=None)
+            dexp = Q @ y
+            assert np.abs((res.x - x0) - dexp).max() <= 1e-9 * np.abs(dexp).max()
+
+
+def test_exact_preconditioner_takes_one_iteration_per_step():
+    """Table 5 prints 1(1) for the exact (full LU, u_f = u) preconditioner."""
+    its_golden = int(open(f"{GOLDEN}/exact_preconditioner_its.txt").read().split("its_per_step")[1])
+    w = W.convdiff_small(10)
+    Ad = _dense(w.A)
+    Ainv = np.linalg.inv(Ad)
+    S = sp.csr_matrix(Ainv)
+    S.sort_indices()
+    res = O.gmres_ir(w.A, S.indptr, S.indices, S.data, np.ones(w.n), "fp64", w.b, 1e-8, 10, 50, W.TOL_IR)
+    assert all(k == its_golden for k in res.its)
+    assert len(res.its) <= 3
+    assert O.ferr(res.x, w.x_true) <= 1e-15
+
+
+def test_limiting_accuracy_convdiff_small():
+    """Theorems 1-2: with u_r <= u^2 the forward error reaches ~u and the
+    backward error ~q u (C1: FP32 SPAI on pattern(A), FP64 GMRES)."""
+    w = W.convdiff_small(32)
+    s, ir = w.spai, w.ir
+    R = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = R.P_csr(w.n)
+    res = O.gmres_ir(w.A, pp, pc, pv, R.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+    assert res.status & ~O.IR_STAGNATED == 0
+    assert O.ferr(res.x, w.x_true) <= 1e-12
+    assert O.nbe(w.A, w.b, res.x) <= 5 * 2.0 ** -53
+    assert len(res.its) >= 2
+
+
+def test_x0_in_fp32_is_sequential_fp32():
+    """x0 = P b in u_f: for a diagonal P the single product is the binary32
+    product of the binary32-rounded operands."""
+    rng = np.random.default_rng(12)
+    n = 50
+    pv = rng.standard_normal(n).astype(np.float32).astype(np.float64)
+    d = rng.uniform(0.5, 2.0, n)
+    b = rng.standard_normal(n)
+    x0 = O.x0(np.arange(n + 1), np.arange(n), pv, d, b, "fp32")
+    expect = (pv.astype(np.float32) * (d * b).astype(np.float32)).astype(np.float64)
+    assert np.array_equal(x0, expect)

@@ -1,0 +1,228 @@
+/*
+ * libspai — SPAI-GMRES-IR on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  The method is the one of Carson & Khan, "Mixed
+ * precision iterative refinement with sparse approximate inverse
+ * preconditioning": a Frobenius-norm sparse approximate inverse built column by
+ * column (Algorithm 1, Section 2.2) and used as the left preconditioner of
+ * GMRES-based iterative refinement in five precisions (Algorithm 3,
+ * Section 3.2).
+ *
+ * Conventions for every entry point
+ *   - Matrices are CSR with int32 indices, columns sorted ascending within a
+ *     row, no duplicate entries, FP64 values; every row must hold a nonzero
+ *     value (the column scaling of Section 4 divides by the row's largest
+ *     magnitude).  A stored zero is allowed and treated as a structural entry.
+ *   - Pointers named "device" point to device memory of the handle's device and
+ *     stay owned by the caller; they must stay valid and unmodified until the
+ *     call returns.  Host structs are read during the call only.
+ *   - Every call enqueues its work on the handle's stream and returns after that
+ *     work has completed (the calls need small device-to-host copies for sizes,
+ *     statistics and stopping decisions).  Calls on one handle must not overlap.
+ *   - Return value: 0 on success; a negative SPAI_E_* code on a hard error (no
+ *     output is produced, spai_last_error() describes it); a positive bit mask
+ *     of SPAI_W_* warnings when the result was produced but is flagged.
+ */
+#ifndef SPAI_H
+#define SPAI_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Floating-point formats (Table 1 of the paper lists half, single, double, quad). */
+typedef enum {
+    SPAI_FP64 = 0,
+    SPAI_FP32 = 1,
+    SPAI_FP16 = 2, /* storage format; arithmetic in FP32 */
+    SPAI_BF16 = 3, /* storage format; arithmetic in FP32 */
+    SPAI_DD = 4    /* double-double (residual precision u_r only) */
+} spai_prec;
+
+enum {
+    SPAI_OK = 0,
+    SPAI_E_ARG = -1,      /* bad shape, pointer, parameter or CSR structure */
+    SPAI_E_OOM = -2,      /* device allocation failed */
+    SPAI_E_HIP = -3,      /* a HIP runtime call failed (message has the error) */
+    SPAI_E_INTERNAL = -4, /* a device-side consistency check failed */
+    SPAI_W_EPS = 1,       /* some columns end with ||e_k - B m_k|| > eps (alpha or fill cap hit) */
+    SPAI_W_RANKDEF = 2,   /* a reduced problem was rank deficient (zero Householder norm) */
+    SPAI_W_NONFINITE = 4, /* a column produced a non-finite value in u_f */
+    SPAI_W_MAXIT = 8,     /* some GMRES solve hit maxit */
+    SPAI_W_NOCONV = 16    /* refinement stopped at imax or on stagnation */
+};
+
+typedef struct spai_handle spai_handle;
+typedef struct spai_precond spai_precond;
+
+/* Sparse matrix in CSR, device arrays (rowptr: n+1, col and val: nnz). */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t* rowptr;
+    const int32_t* col;
+    const double* val;
+} spai_csr;
+
+/* Prescribed initial sparsity pattern J (Algorithm 1 input): column k of M has
+ * row indices idx[ptr[k] .. ptr[k+1]) (device arrays; any order, no duplicates).
+ * Since P = M^T D, these are the column indices of row k of P.  Passing NULL
+ * instead of a pattern means the identity pattern (Section 4). */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t* ptr;
+    const int32_t* idx;
+} spai_pattern;
+
+/* Parameters of Algorithm 1 (its Require line: J, alpha, beta, eps) plus the fill
+ * cap of Section 2.2 and the precision u_f of Section 3.1. */
+typedef struct {
+    double eps;      /* column residual tolerance: stop once ||e_k - B m_k||_2 <= eps */
+    int32_t alpha;   /* maximum augmentation steps per column (0 = fixed pattern) */
+    int32_t beta;    /* maximum indices added per augmentation step */
+    int32_t maxfill; /* cap on |J_k| (never truncates the initial pattern) */
+    spai_prec u_f;   /* FP64, FP32, FP16 or BF16 */
+} spai_build_params;
+
+typedef struct {
+    int64_t nnz;            /* stored entries of P (pattern entries, exact zeros included) */
+    int32_t max_len;        /* largest |J_k| */
+    int32_t max_steps;      /* largest number of augmentation steps of a column */
+    int32_t max_shadow;     /* largest |I_k| at a final solve */
+    int32_t cols_over_eps;  /* columns ending above eps */
+    int32_t cols_rankdef;   /* columns with a rank-deficient reduced problem */
+    int32_t cols_nonfinite; /* columns with a non-finite value */
+    int32_t cols_deferred;  /* columns recomputed by the large-problem kernel */
+    double max_res;         /* largest final column residual */
+} spai_build_stats;
+
+/* Read-only view of a preconditioner P = M^T D (device pointers owned by P).
+ * Row k of P holds m_k: columns col[rowptr[k] .. rowptr[k+1]) ascending with
+ * values val (format val_prec); P w = M^T (D w) with d the FP64 scaling.
+ * j_ins / m_ins expose the build's per-column result before sorting: column k's
+ * indices J_k in insertion order (stride entries, -1 padded) with their values
+ * as FP64; steps / res / flags are the per-column statistics (NULL for an
+ * imported P). */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t* rowptr;
+    const int32_t* col;
+    const void* val;
+    spai_prec val_prec;
+    const double* d;
+    int32_t stride;
+    const int32_t* j_ins;
+    const double* m_ins;
+    const int32_t* len;
+    const int32_t* steps;
+    const double* res;
+    const int32_t* flags;
+} spai_precond_view;
+
+/* Parameters of Algorithm 3 (its Require line: i_max, tau) plus the GMRES cap and
+ * the refinement stopping rule.  u_g = u_p = u = FP64 (Section 4). */
+typedef struct {
+    spai_prec u_r;  /* residual precision: SPAI_DD (double-double) or SPAI_FP64 */
+    double tau;     /* GMRES stops when |g_{j+1}| <= tau ||P r_i||_2 */
+    int32_t imax;   /* maximum refinement steps (<= 32) */
+    int32_t maxit;  /* maximum GMRES iterations per step */
+    double tol_ir;  /* refinement stops when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf */
+} spai_ir_params;
+
+typedef struct {
+    int32_t steps;      /* refinement steps taken */
+    int32_t its[32];    /* GMRES iterations of each step */
+    int32_t total_its;
+    int32_t status;     /* SPAI_W_MAXIT | SPAI_W_NOCONV bits */
+    double gest[32];    /* |g_{k+1}| / ||P r_i|| at the end of each step */
+    double dnorm[32];   /* ||d_i||_inf of each step */
+} spai_ir_stats;
+
+/* Handle: binds the current HIP device, a stream (default: the null stream) and a
+ * grow-only device workspace.  Destroy frees the workspace. */
+int spai_create(spai_handle** h);
+int spai_destroy(spai_handle* h);
+int spai_set_stream(spai_handle* h, hipStream_t stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char* spai_last_error(void);
+
+/*
+ * Build the left preconditioner P = M^T D (Algorithm 3, first line, with the
+ * scaling of Section 4): D = diag(1 / max_j |a_ij|), Algorithm 1 runs on
+ * B = A^T D from the initial pattern J (NULL = identity), and every column solves
+ * min ||e_k - B(I_k, J_k) m|| by Householder QR in u_f, growing J_k by at most
+ * beta candidates with the smallest scores rho_jk <= mean per step until the
+ * residual is <= eps, alpha steps were taken or |J_k| reached maxfill.
+ * On success *P receives a new preconditioner owned by the caller (free with
+ * spai_precond_destroy) and *st (optional) the statistics.
+ * Errors: SPAI_E_ARG for n <= 0, NULL arrays, eps <= 0, beta < 0, alpha < 0,
+ * maxfill < 1, maxfill > 63, an unknown u_f, a pattern with a column longer than
+ * 63 or a malformed A/pattern (checked on the device); SPAI_E_OOM; SPAI_E_HIP.
+ */
+int spai_build(spai_handle* h, const spai_csr* A, const spai_pattern* J,
+               const spai_build_params* p, spai_precond** P, spai_build_stats* st);
+
+/* Wrap an existing preconditioner given as CSR(M^T) (device, columns ascending,
+ * FP64 values that must be exactly representable in val_prec) plus the scaling d
+ * (device, n): the data are copied, P is owned by the caller. */
+int spai_precond_import(spai_handle* h, int32_t n, int64_t nnz, const int32_t* rowptr,
+                        const int32_t* col, const double* val, spai_prec val_prec,
+                        const double* d, spai_precond** P);
+int spai_precond_view_get(const spai_precond* P, spai_precond_view* view);
+int spai_precond_destroy(spai_precond* P);
+
+/*
+ * SPAI-GMRES-IR (Algorithm 3): x0 = P b in u_f (the format of P's values; FP32
+ * arithmetic for FP16/BF16), then per refinement step r_i = b - A x_i in u_r
+ * (stored FP64), left-preconditioned MGS-GMRES on P A d = P r_i in FP64 with zero
+ * initial guess, stopped when the Givens estimate |g_{j+1}| <= tau ||P r_i||_2,
+ * and x_{i+1} = x_i + d_i in FP64.  Refinement stops when ||d_i||_inf <= tol_ir
+ * ||x_{i+1}||_inf, after imax steps, from the third step on when ||d_i||_inf >
+ * ||d_{i-1}||_inf / 2, or before a step whose P r_i is exactly zero.
+ * b and x are device arrays of n FP64 values (x is output only).
+ * Errors: SPAI_E_ARG (sizes differ, imax outside 1..32, maxit < 1, tau < 0);
+ * warnings SPAI_W_MAXIT, SPAI_W_NOCONV.
+ */
+int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
+                  double* x, const spai_ir_params* p, spai_ir_stats* st);
+
+/* Kernel timing for measurement: when enabled for a kernel class, every
+ * `sample_every`-th launch of that class is bracketed by a pair of HIP events
+ * recorded on the handle's stream.  spai_timing_read synchronises the stream,
+ * returns the number of timed launches and their summed duration in ms, and
+ * clears the counters.  sample_every <= 0 disables timing of the class. */
+enum {
+    SPAI_KT_COLUMNS = 0,  /* column kernel of Algorithm 1 (all configurations) */
+    SPAI_KT_SPMV_A = 1,   /* w = A v */
+    SPAI_KT_APPLY_P = 2,  /* y = P w */
+    SPAI_KT_MGS = 3,      /* one modified Gram-Schmidt pass */
+    SPAI_KT_RESIDUAL = 4, /* r = b - A x in u_r */
+    SPAI_KT_UPDATE = 5,   /* x += V y */
+    SPAI_KT_COUNT = 6
+};
+int spai_timing_enable(spai_handle* h, int kernel_class, int sample_every);
+int spai_timing_read(spai_handle* h, int kernel_class, int64_t* launches_timed, double* total_ms);
+
+/* Building blocks of Algorithm 3, exposed for testing (device arrays, length n). */
+/* r = b - A x evaluated in u_r (SPAI_DD or SPAI_FP64), rounded to FP64. */
+int spai_residual(spai_handle* h, const spai_csr* A, const double* b, const double* x, double* r,
+                  spai_prec u_r);
+/* y = P w = M^T (D w) in FP64. */
+int spai_precond_apply(spai_handle* h, const spai_precond* P, const double* w, double* y);
+/* x0 = P b in u_f (the format of P's values), stored in FP64. */
+int spai_precond_apply_uf(spai_handle* h, const spai_precond* P, const double* b, double* x0);
+/* y = A x in FP64. */
+int spai_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPAI_H */

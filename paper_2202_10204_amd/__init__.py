@@ -1,0 +1,341 @@
+"""Python binding of libspai (SPAI-GMRES-IR on MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libspai.so``; PyTorch provides device memory and the stream.  The names
+follow the C ABI in ``include/spai.h``.
+
+The library must have been built (``python -m paper_2202_10204_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+import torch  # imported before libspai so both share torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspai.so")
+
+FP64, FP32, FP16, BF16, DD = 0, 1, 2, 3, 4
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, "dd": DD}
+
+OK, E_ARG, E_OOM, E_HIP, E_INTERNAL = 0, -1, -2, -3, -4
+W_EPS, W_RANKDEF, W_NONFINITE, W_MAXIT, W_NOCONV = 1, 2, 4, 8, 16
+
+# kernel classes for sampled launch timing
+KERNELS = {"columns": 0, "spmv_a": 1, "apply_p": 2, "mgs": 3, "residual": 4, "update": 5}
+
+_c_i32, _c_i64, _c_f64, _p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", _c_i32), ("nnz", _c_i32), ("rowptr", _p), ("col", _p), ("val", _p)]
+
+
+class _Pattern(ctypes.Structure):
+    _fields_ = [("n", _c_i32), ("nnz", _c_i32), ("ptr", _p), ("idx", _p)]
+
+
+class _BuildParams(ctypes.Structure):
+    _fields_ = [("eps", _c_f64), ("alpha", _c_i32), ("beta", _c_i32), ("maxfill", _c_i32),
+                ("u_f", ctypes.c_int)]
+
+
+class _BuildStats(ctypes.Structure):
+    _fields_ = [("nnz", _c_i64), ("max_len", _c_i32), ("max_steps", _c_i32), ("max_shadow", _c_i32),
+                ("cols_over_eps", _c_i32), ("cols_rankdef", _c_i32), ("cols_nonfinite", _c_i32),
+                ("cols_deferred", _c_i32), ("max_res", _c_f64)]
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("n", _c_i32), ("nnz", _c_i64), ("rowptr", _p), ("col", _p), ("val", _p),
+                ("val_prec", ctypes.c_int), ("d", _p), ("stride", _c_i32), ("j_ins", _p),
+                ("m_ins", _p), ("len", _p), ("steps", _p), ("res", _p), ("flags", _p)]
+
+
+class _IrParams(ctypes.Structure):
+    _fields_ = [("u_r", ctypes.c_int), ("tau", _c_f64), ("imax", _c_i32), ("maxit", _c_i32),
+                ("tol_ir", _c_f64)]
+
+
+class _IrStats(ctypes.Structure):
+    _fields_ = [("steps", _c_i32), ("its", _c_i32 * 32), ("total_its", _c_i32), ("status", _c_i32),
+                ("gest", _c_f64 * 32), ("dnorm", _c_f64 * 32)]
+
+
+class SpaiError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libspai.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SpaiError(f"{LIB_PATH} is missing: build the HIP library first "
+                            "(python -m paper_2202_10204_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.spai_last_error.restype = ctypes.c_char_p
+        L.spai_last_error.argtypes = []
+        L.spai_create.argtypes = [P(_p)]
+        L.spai_destroy.argtypes = [_p]
+        L.spai_set_stream.argtypes = [_p, _p]
+        L.spai_build.argtypes = [_p, P(_Csr), P(_Pattern), P(_BuildParams), P(_p), P(_BuildStats)]
+        L.spai_precond_import.argtypes = [_p, _c_i32, _c_i64, _p, _p, _p, ctypes.c_int, _p, P(_p)]
+        L.spai_precond_view_get.argtypes = [_p, P(_View)]
+        L.spai_precond_destroy.argtypes = [_p]
+        L.spai_gmres_ir.argtypes = [_p, P(_Csr), _p, _p, _p, P(_IrParams), P(_IrStats)]
+        L.spai_residual.argtypes = [_p, P(_Csr), _p, _p, _p, ctypes.c_int]
+        L.spai_precond_apply.argtypes = [_p, _p, _p, _p]
+        L.spai_precond_apply_uf.argtypes = [_p, _p, _p, _p]
+        L.spai_spmv.argtypes = [_p, P(_Csr), _p, _p]
+        L.spai_timing_enable.argtypes = [_p, ctypes.c_int, ctypes.c_int]
+        L.spai_timing_read.argtypes = [_p, ctypes.c_int, P(_c_i64), P(_c_f64)]
+        for name in ("spai_timing_enable", "spai_timing_read", "spai_create", "spai_destroy", "spai_set_stream", "spai_build", "spai_precond_import",
+                     "spai_precond_view_get", "spai_precond_destroy", "spai_gmres_ir", "spai_residual",
+                     "spai_precond_apply", "spai_precond_apply_uf", "spai_spmv"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().spai_last_error().decode()
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise SpaiError(f"{what} failed ({rc}): {last_error()}")
+    return rc
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# device-resident inputs
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DeviceCSR:
+    """CSR matrix on the device (int32 indices, FP64 values)."""
+
+    n: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @classmethod
+    def from_host(cls, A, device="cuda") -> "DeviceCSR":
+        return cls(int(A.n), torch.as_tensor(np.asarray(A.rowptr, np.int32), device=device),
+                   torch.as_tensor(np.asarray(A.col, np.int32), device=device),
+                   torch.as_tensor(np.asarray(A.val, np.float64), device=device))
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def c(self) -> _Csr:
+        return _Csr(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
+
+
+@dataclasses.dataclass
+class DevicePattern:
+    n: int
+    ptr: torch.Tensor
+    idx: torch.Tensor
+
+    @classmethod
+    def from_host(cls, pat, device="cuda") -> "DevicePattern":
+        return cls(int(pat.n), torch.as_tensor(np.asarray(pat.ptr, np.int32), device=device),
+                   torch.as_tensor(np.asarray(pat.idx, np.int32), device=device))
+
+    def c(self) -> _Pattern:
+        return _Pattern(self.n, int(self.idx.numel()), self.ptr.data_ptr(), self.idx.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# preconditioner object
+# ---------------------------------------------------------------------------
+
+_VAL_DTYPE = {FP64: torch.float64, FP32: torch.float32, FP16: torch.float16, BF16: torch.bfloat16}
+
+
+def _copy_from_device_ptr(ptr: int, numel: int, dtype: torch.dtype, device) -> torch.Tensor:
+    """Copy `numel` elements at a device address owned by the library into a new tensor."""
+    out = torch.empty(numel, dtype=dtype, device=device)
+    if numel:
+        nbytes = numel * out.element_size()
+        _hip_memcpy_d2d(out.data_ptr(), ptr, nbytes)
+    return out
+
+
+_hip = None
+
+
+def _hip_memcpy_d2d(dst: int, src: int, nbytes: int):
+    """Device-to-device copy through the HIP runtime torch has loaded."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so.7", mode=ctypes.RTLD_GLOBAL)
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [_p, _p, ctypes.c_size_t, ctypes.c_int]
+    torch.cuda.current_stream().synchronize()
+    rc = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3)  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise SpaiError(f"hipMemcpy failed ({rc})")
+
+
+class Precond:
+    """P = M^T D owned by the library (freed with the object)."""
+
+    def __init__(self, handle: "Handle", raw: int, stats: Optional[dict] = None):
+        self._h = handle
+        self._raw = ctypes.c_void_p(raw)
+        self.stats = stats or {}
+
+    @property
+    def raw(self):
+        return self._raw
+
+    def view(self) -> _View:
+        v = _View()
+        _check(lib().spai_precond_view_get(self._raw, ctypes.byref(v)), "spai_precond_view_get")
+        return v
+
+    def csr(self, device="cuda"):
+        """Copies of (rowptr, col, val as stored, d)."""
+        v = self.view()
+        n, nnz = v.n, v.nnz
+        rowptr = _copy_from_device_ptr(v.rowptr, n + 1, torch.int32, device)
+        col = _copy_from_device_ptr(v.col, nnz, torch.int32, device)
+        val = _copy_from_device_ptr(v.val, nnz, _VAL_DTYPE[v.val_prec], device)
+        d = _copy_from_device_ptr(v.d, n, torch.float64, device)
+        return rowptr, col, val, d
+
+    def columns(self, device="cuda") -> dict:
+        """Per-column build results: J_k in insertion order, m-bar, len, steps, res, flags."""
+        v = self.view()
+        if not v.j_ins:
+            raise SpaiError("preconditioner was imported: no per-column build data")
+        n, s = v.n, v.stride
+        return {
+            "stride": s,
+            "J": _copy_from_device_ptr(v.j_ins, n * s, torch.int32, device).view(n, s),
+            "m": _copy_from_device_ptr(v.m_ins, n * s, torch.float64, device).view(n, s),
+            "len": _copy_from_device_ptr(v.len, n, torch.int32, device),
+            "steps": _copy_from_device_ptr(v.steps, n, torch.int32, device),
+            "res": _copy_from_device_ptr(v.res, n, torch.float64, device),
+            "flags": _copy_from_device_ptr(v.flags, n, torch.int32, device),
+        }
+
+    def __del__(self):
+        try:
+            if self._raw and self._raw.value:
+                lib().spai_precond_destroy(self._raw)
+                self._raw = ctypes.c_void_p(0)
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# handle
+# ---------------------------------------------------------------------------
+
+class Handle:
+    """Library handle bound to the current device and torch's current stream."""
+
+    def __init__(self, stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise SpaiError("no GPU available: libspai runs on the device only")
+        L = lib()
+        raw = ctypes.c_void_p()
+        _check(L.spai_create(ctypes.byref(raw)), "spai_create")
+        self._raw = raw
+        self.set_stream(stream or torch.cuda.current_stream())
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        _check(lib().spai_set_stream(self._raw, ctypes.c_void_p(stream.cuda_stream)), "spai_set_stream")
+
+    def close(self):
+        if getattr(self, "_raw", None) is not None and self._raw.value:
+            lib().spai_destroy(self._raw)
+            self._raw = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- Algorithm 1 ---------------------------------------------------------
+    def spai_build(self, A: DeviceCSR, pattern: Optional[DevicePattern], eps: float, alpha: int, beta: int,
+                   maxfill: int, u_f: str = "fp32"):
+        """Returns (Precond, warnings, stats dict)."""
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f])
+        st = _BuildStats()
+        out = ctypes.c_void_p()
+        csr = A.c()
+        pat = pattern.c() if pattern is not None else None
+        rc = _check(lib().spai_build(self._raw, ctypes.byref(csr), ctypes.byref(pat) if pat else None,
+                                     ctypes.byref(prm), ctypes.byref(out), ctypes.byref(st)), "spai_build")
+        stats = {f: getattr(st, f) for f, _ in _BuildStats._fields_}
+        return Precond(self, out.value, stats), rc, stats
+
+    def precond_import(self, n: int, rowptr: torch.Tensor, col: torch.Tensor, val_f64: torch.Tensor,
+                       val_prec: str, d: torch.Tensor) -> Precond:
+        out = ctypes.c_void_p()
+        _check(lib().spai_precond_import(self._raw, int(n), int(col.numel()), _ptr(rowptr), _ptr(col),
+                                         _ptr(val_f64), PREC[val_prec], _ptr(d), ctypes.byref(out)),
+               "spai_precond_import")
+        return Precond(self, out.value)
+
+    # -- Algorithm 3 ---------------------------------------------------------
+    def gmres_ir(self, A: DeviceCSR, P: Precond, b: torch.Tensor, x: torch.Tensor, tau: float, imax: int,
+                 maxit: int, tol_ir: float, u_r: str = "dd"):
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir))
+        st = _IrStats()
+        csr = A.c()
+        rc = _check(lib().spai_gmres_ir(self._raw, ctypes.byref(csr), P.raw, _ptr(b), _ptr(x),
+                                        ctypes.byref(prm), ctypes.byref(st)), "spai_gmres_ir")
+        s = st.steps
+        return {"steps": s, "its": list(st.its[:s]), "total_its": st.total_its, "status": rc,
+                "gest": list(st.gest[:s]), "dnorm": list(st.dnorm[:s])}
+
+    # -- measurement ---------------------------------------------------------
+    def timing_enable(self, kernel: str, sample_every: int = 1):
+        _check(lib().spai_timing_enable(self._raw, KERNELS[kernel], int(sample_every)), "spai_timing_enable")
+
+    def timing_read(self, kernel: str):
+        """(launches timed, summed duration in ms) since enabling or the last read."""
+        n = _c_i64()
+        ms = _c_f64()
+        _check(lib().spai_timing_read(self._raw, KERNELS[kernel], ctypes.byref(n), ctypes.byref(ms)),
+               "spai_timing_read")
+        return int(n.value), float(ms.value)
+
+    # -- building blocks -----------------------------------------------------
+    def residual(self, A: DeviceCSR, b, x, r, u_r: str = "dd"):
+        csr = A.c()
+        _check(lib().spai_residual(self._raw, ctypes.byref(csr), _ptr(b), _ptr(x), _ptr(r), PREC[u_r]),
+               "spai_residual")
+
+    def precond_apply(self, P: Precond, w, y):
+        _check(lib().spai_precond_apply(self._raw, P.raw, _ptr(w), _ptr(y)), "spai_precond_apply")
+
+    def precond_apply_uf(self, P: Precond, b, x0):
+        _check(lib().spai_precond_apply_uf(self._raw, P.raw, _ptr(b), _ptr(x0)), "spai_precond_apply_uf")
+
+    def spmv(self, A: DeviceCSR, x, y):
+        csr = A.c()
+        _check(lib().spai_spmv(self._raw, ctypes.byref(csr), _ptr(x), _ptr(y)), "spai_spmv")

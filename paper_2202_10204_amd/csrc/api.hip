@@ -1,0 +1,132 @@
+// Handle, error reporting and workspace management of libspai.
+#include <cstdlib>
+#include <string>
+
+#include "common.hpp"
+
+namespace spai {
+
+static thread_local std::string g_last_error = "no error";
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int buffer_reserve(Buffer& b, size_t bytes) {
+    if (bytes <= b.bytes && b.ptr) return SPAI_OK;
+    buffer_free(b);
+    size_t want = bytes + bytes / 8 + 256;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("device allocation of ") + std::to_string(want) + " bytes failed: " +
+                  hipGetErrorString(e));
+        return SPAI_E_OOM;
+    }
+    b.ptr = p;
+    b.bytes = want;
+    return SPAI_OK;
+}
+
+void buffer_free(Buffer& b) {
+    if (b.ptr) (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+}  // namespace spai
+
+static int pinned_reserve(spai::Buffer& b, size_t bytes) {
+    if (bytes <= b.bytes && b.ptr) return SPAI_OK;
+    if (b.ptr) (void)hipHostFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        spai::set_error(std::string("pinned host allocation failed: ") + hipGetErrorString(e));
+        return SPAI_E_OOM;
+    }
+    b.ptr = p;
+    b.bytes = bytes;
+    return SPAI_OK;
+}
+
+extern "C" const char* spai_last_error(void) { return spai::g_last_error.c_str(); }
+
+extern "C" int spai_create(spai_handle** h) {
+    if (!h) {
+        spai::set_error("invalid argument: NULL handle pointer");
+        return SPAI_E_ARG;
+    }
+    *h = nullptr;
+    int dev = 0;
+    SPAI_HIP(hipGetDevice(&dev));
+    spai_handle* H = new spai_handle();
+    H->device = dev;
+    H->stream = nullptr;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) H->num_cu = prop.multiProcessorCount;
+    int rc = pinned_reserve(H->host_pinned, 4096);
+    if (rc) {
+        delete H;
+        return rc;
+    }
+    *h = H;
+    return SPAI_OK;
+}
+
+extern "C" int spai_destroy(spai_handle* h) {
+    if (!h) return SPAI_OK;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto& t : h->timers)
+        for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    for (auto& b : h->ws) spai::buffer_free(b);
+    spai::buffer_free(h->red);
+    if (h->host_pinned.ptr) (void)hipHostFree(h->host_pinned.ptr);
+    delete h;
+    return SPAI_OK;
+}
+
+extern "C" int spai_set_stream(spai_handle* h, hipStream_t stream) {
+    if (!h) {
+        spai::set_error("invalid argument: NULL handle");
+        return SPAI_E_ARG;
+    }
+    h->stream = stream;
+    return SPAI_OK;
+}
+
+extern "C" int spai_timing_enable(spai_handle* h, int kc, int every) {
+    if (!h || kc < 0 || kc >= SPAI_KT_COUNT) {
+        spai::set_error("invalid argument: handle or kernel class");
+        return SPAI_E_ARG;
+    }
+    auto& t = h->timers[kc];
+    t.every = every > 0 ? every : 0;
+    t.seen = 0;
+    t.used = 0;
+    return SPAI_OK;
+}
+
+extern "C" int spai_timing_read(spai_handle* h, int kc, int64_t* launches, double* total_ms) {
+    if (!h || kc < 0 || kc >= SPAI_KT_COUNT || !launches || !total_ms) {
+        spai::set_error("invalid argument: handle, kernel class or outputs");
+        return SPAI_E_ARG;
+    }
+    auto& t = h->timers[kc];
+    SPAI_HIP(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    for (size_t q = 0; q < t.used; ++q) {
+        float ms = 0.0f;
+        SPAI_HIP(hipEventElapsedTime(&ms, t.ev[2 * q], t.ev[2 * q + 1]));
+        tot += ms;
+    }
+    *launches = (int64_t)t.used;
+    *total_ms = tot;
+    t.used = 0;
+    t.seen = 0;
+    return SPAI_OK;
+}

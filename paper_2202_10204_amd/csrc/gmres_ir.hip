@@ -1,0 +1,839 @@
+// SPAI-GMRES-IR on gfx950 (Algorithm 3, Section 3.2): x0 = P b in u_f, then per
+// refinement step the residual in double-double (u_r), left-preconditioned
+// MGS-GMRES in FP64 (u_g = u_p = u, Section 4) and the FP64 update.
+//
+// Kernels are HBM-bound streaming passes over CSR(A), CSR(P) and the Krylov
+// basis V (column-major, n x (maxit+1) FP64).  Every reduction is deterministic:
+// each thread sums a fixed set of elements, blocks reduce in a fixed tree, and
+// the last block to finish (ticket counter) reduces the per-block partials in
+// block order, so repeated runs give bit-identical results.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+
+namespace spai {
+
+constexpr int RB = 256;        // threads per reduction block
+constexpr int RBLOCKS = 1024;  // upper bound on reduction blocks
+
+// ---------------------------------------------------------------------------
+// double-double helpers (error-free transformations)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void fast_two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    e = b - (s - a);
+}
+
+// (xh, xl) + (yh, yl), accurate double-word addition (Joldes, Muller, Popescu 2017)
+__device__ __forceinline__ void dd_add(double xh, double xl, double yh, double yl, double& zh, double& zl) {
+    double sh, sl, th, tl;
+    two_sum(xh, yh, sh, sl);
+    two_sum(xl, yl, th, tl);
+    sl = sl + th;
+    fast_two_sum(sh, sl, sh, sl);
+    sl = sl + tl;
+    fast_two_sum(sh, sl, zh, zl);
+}
+
+// ---------------------------------------------------------------------------
+// solver state shared by the kernels of one refinement step
+// ---------------------------------------------------------------------------
+
+struct SolveState {
+    double beta0;   // ||P r_i||_2
+    double gabs;    // |g_{j+1}| after the last Givens update
+    int done;       // 0 running, 1 converged, 2 maxit reached, 3 device error
+    int its;        // GMRES iterations of the step once done
+    int err;        // 1: a grid-wide sum timed out
+    int pad;
+};
+
+// ---------------------------------------------------------------------------
+// sparse products (a set `done` flag turns them into no-ops so that steps
+// enqueued past convergence cost only their launch)
+// ---------------------------------------------------------------------------
+
+__global__ void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const double* __restrict__ av, const double* __restrict__ x, double* __restrict__ y,
+                       const SolveState* __restrict__ st) {
+    if (st && st->done) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) s = __builtin_fma(av[q], x[ci[q]], s);
+    y[i] = s;
+}
+
+// y = M^T (D w): row k of P holds m_k (values in VP), FP64 arithmetic
+template <int VP>
+__global__ void k_apply_P(int n, const int* __restrict__ pp, const int* __restrict__ pc,
+                          const typename ValType<VP>::T* __restrict__ pv, const double* __restrict__ d,
+                          const double* __restrict__ w, double* __restrict__ y, const SolveState* __restrict__ st) {
+    if (st && st->done) return;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double s = 0.0;
+    for (int q = pp[k]; q < pp[k + 1]; ++q) {
+        int j = pc[q];
+        s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
+    }
+    y[k] = s;
+}
+
+// x0 = P b in u_f: z_j = u_f(d_j b_j), products and sums in F, ascending column
+template <int VP>
+__global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ pc,
+                     const typename ValType<VP>::T* __restrict__ pv, const double* __restrict__ d,
+                     const double* __restrict__ b, double* __restrict__ x0) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    if constexpr (VP == SPAI_FP64) {
+        double s = 0.0;
+        for (int q = pp[k]; q < pp[k + 1]; ++q) {
+            int j = pc[q];
+            s = __builtin_fma(pv[q], d[j] * b[j], s);
+        }
+        x0[k] = s;
+    } else {
+        float s = 0.0f;
+        for (int q = pp[k]; q < pp[k + 1]; ++q) {
+            int j = pc[q];
+            float z = store<VP, float>((float)(d[j] * b[j]));
+            s = __builtin_fmaf(to_f32(pv[q]), z, s);
+        }
+        x0[k] = (double)s;
+    }
+}
+
+// r = b - A x: products split exactly with an FMA and accumulated in
+// double-double, rounded once to FP64 at the end (u_r = DD); or plain FP64
+template <bool DD>
+__global__ void k_residual(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ av, const double* __restrict__ b,
+                           const double* __restrict__ x, double* __restrict__ r) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if constexpr (DD) {
+        double sh = b[i], sl = 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            double a = av[q], xv = x[ci[q]];
+            double ph = a * xv;
+            double pl = __builtin_fma(a, xv, -ph);
+            dd_add(sh, sl, -ph, -pl, sh, sl);
+        }
+        r[i] = sh + sl;
+    } else {
+        double s = b[i];
+        for (int q = rp[i]; q < rp[i + 1]; ++q) s = __builtin_fma(-av[q], x[ci[q]], s);
+        r[i] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the Arnoldi step: one cooperative launch per step
+//
+// Modified Gram-Schmidt is a chain of j+2 dependent global sums per Arnoldi
+// step (h_lj = <y, v_l> with y already reduced by v_0 .. v_{l-1}, then ||y||),
+// so its cost is the latency of a grid-wide sum.  The launch keeps y in
+// registers (EPT elements per thread), streams each basis vector once and
+// prefetches the next one while the sum is in flight.  A grid-wide sum: every
+// block publishes its partial into its own write-once slot of the link (an
+// agent-scope atomic store of the 64-bit value; slots start as a signalling-NaN
+// sentinel no arithmetic produces), wave 0 of every block polls all slots with
+// agent-scope atomic loads and adds them in slot order, so every block obtains
+// the bit-identical sum.  Slots alternate between two buffers from one launch
+// to the next; each launch re-arms the other buffer.  Polls are bounded: a
+// timeout aborts every block and is reported through SolveState::err.
+// Block 0 then applies the Givens rotations to column j of H (in LDS), updates
+// g and sets `done` when |g_{j+1}| <= tau beta0, on an exact breakdown or at
+// maxit.
+// ---------------------------------------------------------------------------
+
+constexpr int AT = 512;   // threads per block of the Arnoldi kernel
+constexpr unsigned long long SENTINEL = 0x7ff4dead5eed0001ull;
+constexpr long long SPIN_LIMIT = 1ll << 20;   // about a second of polling
+
+struct ArnoldiArgs {
+    int n, j, ld, maxit, maxlinks, nb, parity;
+    const double* y;     // P A v_j
+    double* V;           // basis, column-major n x (maxit + 1)
+    double* H;           // ld x maxit
+    double* cs;
+    double* sn;
+    double* g;
+    double tau;
+    unsigned long long* slots;   // [2][maxlinks][nb]
+    SolveState* st;
+};
+
+__device__ __forceinline__ double grid_sum(double part, unsigned long long* slot_row, int nb, double* wsum,
+                                           double* bcast, int* abort_flag) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) wsum[wave] = part;
+    __syncthreads();
+    if (wave == 0) {
+        if (t == 0) {
+            double s = 0.0;
+            for (int w = 0; w < AT / 64; ++w) s += wsum[w];
+            __hip_atomic_store(&slot_row[blockIdx.x], (unsigned long long)__double_as_longlong(s),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        double acc = 0.0;
+        bool timeout = false;
+        for (int q = lane; q < nb; q += 64) {
+            unsigned long long v;
+            long long spins = 0;
+            while ((v = __hip_atomic_load(&slot_row[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == SENTINEL) {
+                if (++spins > SPIN_LIMIT) {
+                    timeout = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            acc += __longlong_as_double((long long)v);
+        }
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        uint64_t bad = ballot(timeout);
+        if (lane == 0) {
+            *bcast = acc;
+            if (bad) *abort_flag = 1;
+        }
+    }
+    __syncthreads();
+    return *bcast;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
+    extern __shared__ double dyn[];          // block 0: hcol (maxit+2), cs, sn (maxit each)
+    __shared__ double wsum[AT / 64];
+    __shared__ double bcast;
+    __shared__ int abort_flag;
+    if (a.st->done) return;                  // uniform: written by an earlier launch
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int gstride = a.nb * AT;
+    const int base = b * AT + t;
+    const int n = a.n, j = a.j;
+    unsigned long long* cur = a.slots + (size_t)a.parity * a.maxlinks * a.nb;
+    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * a.maxlinks * a.nb;
+    // re-arm the other buffer for the next launch (links 0 .. j+3)
+    const int lim = min(j + 4, a.maxlinks);
+    for (int l = t; l < lim; l += AT) nxt[(size_t)l * a.nb + b] = SENTINEL;
+    double* hcol = dyn;
+    double* csL = dyn + (a.maxit + 2);
+    double* snL = csL + a.maxit;
+    if (t == 0) abort_flag = 0;
+    if (b == 0)
+        for (int l = t; l < j; l += AT) {
+            csL[l] = a.cs[l];
+            snL[l] = a.sn[l];
+        }
+    double y[EPT], v[EPT], vn[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int i = base + e * gstride;
+        y[e] = i < n ? a.y[i] : 0.0;
+        v[e] = i < n ? a.V[i] : 0.0;
+        vn[e] = 0.0;
+    }
+    __syncthreads();
+    // h_lj = <y, v_l>; y -= h_lj v_l  (l = 0 .. j)
+    for (int l = 0; l <= j; ++l) {
+        if (l < j) {
+            const double* vnext = a.V + (size_t)(l + 1) * n;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                int i = base + e * gstride;
+                vn[e] = i < n ? vnext[i] : 0.0;
+            }
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], v[e], part);
+        double h = grid_sum(part, cur + (size_t)l * a.nb, a.nb, wsum, &bcast, &abort_flag);
+        if (abort_flag) break;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            y[e] = __builtin_fma(-h, v[e], y[e]);
+            v[e] = vn[e];
+        }
+        if (b == 0 && t == 0) hcol[l] = h;
+    }
+    // h_{j+1,j} = ||y||; v_{j+1} = y / h_{j+1,j}
+    double hn = 0.0;
+    if (!abort_flag) {
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], y[e], part);
+        hn = __builtin_sqrt(grid_sum(part, cur + (size_t)(j + 1) * a.nb, a.nb, wsum, &bcast, &abort_flag));
+    }
+    if (abort_flag) {
+        if (t == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    double* vout = a.V + (size_t)(j + 1) * n;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int i = base + e * gstride;
+        if (i < n) vout[i] = y[e] / hn;
+    }
+    if (b == 0 && t == 0) {
+        double* hh = hcol;
+        hh[j + 1] = hn;
+        for (int l = 0; l < j; ++l) {           // previous rotations
+            double x0 = hh[l], x1 = hh[l + 1];
+            hh[l] = csL[l] * x0 + snL[l] * x1;
+            hh[l + 1] = -snL[l] * x0 + csL[l] * x1;
+        }
+        double delta = hypot(hh[j], hh[j + 1]);
+        double c = hh[j] / delta, s = hh[j + 1] / delta;
+        hh[j] = delta;
+        hh[j + 1] = 0.0;
+        double gj = a.g[j];
+        a.g[j + 1] = -s * gj;
+        a.g[j] = c * gj;
+        a.cs[j] = c;
+        a.sn[j] = s;
+        double* Hc = a.H + (size_t)j * a.ld;
+        for (int l = 0; l <= j + 1; ++l) Hc[l] = hh[l];
+        double ga = fabs(-s * gj);
+        a.st->gabs = ga;
+        if (ga <= a.tau * a.st->beta0 || hn == 0.0) {
+            a.st->its = j + 1;
+            a.st->done = 1;
+        } else if (j + 1 == a.maxit) {
+            a.st->its = j + 1;
+            a.st->done = 2;
+        }
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t len, unsigned long long v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// reductions (standalone norms and the per-projection fallback path)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[RB / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < RB / 64; ++q) t += sh[q];
+    __syncthreads();
+    return t;   // valid in thread 0
+}
+
+// Last-block finalisation: every block writes its partial; the block that takes
+// the last ticket sums the partials in block order and writes the result.
+__device__ __forceinline__ bool last_block(unsigned* ticket) {
+    __shared__ bool is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned t = atomicAdd(ticket, 1u);
+        is_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    return is_last;
+}
+
+__device__ __forceinline__ double sum_partials(const double* partials, int nb) {
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += RB) acc += partials[q];
+    return block_sum(acc);
+}
+
+enum { MGS_DOT = 0, MGS_NORM = 1 };
+
+// One projection of the fallback path: if vprev is given, y -= (*hprev) vprev;
+// then out = <y, vcur> (MGS_DOT) or ||y||_2 (MGS_NORM).
+__global__ __launch_bounds__(RB) void k_mgs(int n, double* __restrict__ y, const double* __restrict__ vprev,
+                                            const double* __restrict__ hprev, const double* __restrict__ vcur,
+                                            double* __restrict__ out, double* __restrict__ partials,
+                                            unsigned* __restrict__ ticket, int mode, const SolveState* st) {
+    if (st && st->done) return;
+    const double coef = vprev ? *hprev : 0.0;
+    double acc = 0.0;
+    const int stride = gridDim.x * RB;
+    for (int i = blockIdx.x * RB + threadIdx.x; i < n; i += stride) {
+        double yi = y[i];
+        if (vprev) {
+            yi = __builtin_fma(-coef, vprev[i], yi);
+            y[i] = yi;
+        }
+        double vi = (mode == MGS_NORM) ? yi : vcur[i];
+        acc = __builtin_fma(yi, vi, acc);
+    }
+    double bs = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+    if (last_block(ticket)) {
+        double tot = sum_partials(partials, gridDim.x);
+        if (threadIdx.x == 0) {
+            *out = (mode == MGS_NORM) ? __builtin_sqrt(tot) : tot;
+            *ticket = 0u;
+        }
+    }
+}
+
+// v = y / (*h)
+__global__ void k_scale(int n, const double* __restrict__ y, const double* __restrict__ h, double* __restrict__ v,
+                        const SolveState* st) {
+    if (st && st->done) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = y[i] / *h;
+}
+
+// Fallback Givens update (one thread): rotations, new rotation, g, stop test.
+__global__ void k_givens(int j, int maxit, double* __restrict__ H, int ld, double* __restrict__ cs,
+                         double* __restrict__ sn, double* __restrict__ g, double tau, SolveState* st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || st->done) return;
+    double* h = H + (size_t)j * ld;
+    double hn = h[j + 1];
+    for (int l = 0; l < j; ++l) {
+        double a = h[l], c = h[l + 1];
+        h[l] = cs[l] * a + sn[l] * c;
+        h[l + 1] = -sn[l] * a + cs[l] * c;
+    }
+    double delta = hypot(h[j], h[j + 1]);
+    cs[j] = h[j] / delta;
+    sn[j] = h[j + 1] / delta;
+    h[j] = delta;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    st->gabs = fabs(g[j + 1]);
+    if (fabs(g[j + 1]) <= tau * st->beta0 || hn == 0.0) {
+        st->its = j + 1;
+        st->done = 1;
+    } else if (j + 1 == maxit) {
+        st->its = j + 1;
+        st->done = 2;
+    }
+}
+
+// y = H(0:k, 0:k)^{-1} g(0:k) by column-oriented back substitution (one block)
+__global__ __launch_bounds__(RB) void k_backsolve(int k, const double* __restrict__ H, int ld,
+                                                  const double* __restrict__ g, double* __restrict__ work,
+                                                  double* __restrict__ yk) {
+    for (int i = threadIdx.x; i < k; i += RB) work[i] = g[i];
+    __syncthreads();
+    for (int c = k - 1; c >= 0; --c) {
+        double yc = work[c] / H[(size_t)c * ld + c];
+        __syncthreads();
+        if (threadIdx.x == 0) yk[c] = yc;
+        for (int i = threadIdx.x; i < c; i += RB) work[i] = __builtin_fma(-H[(size_t)c * ld + i], yc, work[i]);
+        __syncthreads();
+    }
+}
+
+// x += V_k y; records ||d||_inf and ||x||_inf (non-negative doubles compare as integers)
+__global__ void k_update(int n, int k, const double* __restrict__ V, const double* __restrict__ yk,
+                         double* __restrict__ x, unsigned long long* __restrict__ maxbits) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double dm = 0.0, xm = 0.0;
+    if (i < n) {
+        double di = 0.0;
+        for (int c = 0; c < k; ++c) di = di + V[(size_t)c * n + i] * yk[c];
+        double xi = x[i] + di;
+        x[i] = xi;
+        dm = fabs(di);
+        xm = fabs(xi);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        dm = fmax(dm, __shfl_xor(dm, o, 64));
+        xm = fmax(xm, __shfl_xor(xm, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&maxbits[0], (unsigned long long)__double_as_longlong(dm));
+        atomicMax(&maxbits[1], (unsigned long long)__double_as_longlong(xm));
+    }
+}
+
+// g = beta0 e_1; fresh solver state
+__global__ void k_init_state(double* g, int len, const double* beta0, SolveState* st) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) g[i] = (i == 0) ? *beta0 : 0.0;
+    if (i == 0) {
+        st->beta0 = *beta0;
+        st->done = 0;
+        st->its = 0;
+        st->err = 0;
+        st->gabs = *beta0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+static inline int blocks_for(int n, int t) { return (n + t - 1) / t; }
+
+static int reduce_blocks(int n) {
+    int b = (n + RB * 4 - 1) / (RB * 4);
+    return std::max(1, std::min(b, RBLOCKS));
+}
+
+static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
+                          const SolveState* st = nullptr) {
+    int n = P->n, g = blocks_for(n, 256);
+    long tk = timer_begin(h, SPAI_KT_APPLY_P);
+    switch (P->val_prec) {
+    case SPAI_FP64: hipLaunchKernelGGL(k_apply_P<SPAI_FP64>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const double*)P->val, P->d, w, y, st); break;
+    case SPAI_FP32: hipLaunchKernelGGL(k_apply_P<SPAI_FP32>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const float*)P->val, P->d, w, y, st); break;
+    case SPAI_FP16: hipLaunchKernelGGL(k_apply_P<SPAI_FP16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __half*)P->val, P->d, w, y, st); break;
+    default: hipLaunchKernelGGL(k_apply_P<SPAI_BF16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __hip_bfloat16*)P->val, P->d, w, y, st); break;
+    }
+    timer_end(h, SPAI_KT_APPLY_P, tk);
+    SPAI_HIP(hipGetLastError());
+    return SPAI_OK;
+}
+
+static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
+                       const SolveState* st = nullptr) {
+    int n = A->n;
+    long tk = timer_begin(h, SPAI_KT_SPMV_A);
+    hipLaunchKernelGGL(k_spmv, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st);
+    timer_end(h, SPAI_KT_SPMV_A, tk);
+    SPAI_HIP(hipGetLastError());
+    return SPAI_OK;
+}
+
+static int launch_x0(const spai_precond* P, const double* b, double* x0, hipStream_t s) {
+    int n = P->n, g = blocks_for(n, 256);
+    switch (P->val_prec) {
+    case SPAI_FP64: hipLaunchKernelGGL(k_x0<SPAI_FP64>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const double*)P->val, P->d, b, x0); break;
+    case SPAI_FP32: hipLaunchKernelGGL(k_x0<SPAI_FP32>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const float*)P->val, P->d, b, x0); break;
+    case SPAI_FP16: hipLaunchKernelGGL(k_x0<SPAI_FP16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __half*)P->val, P->d, b, x0); break;
+    default: hipLaunchKernelGGL(k_x0<SPAI_BF16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __hip_bfloat16*)P->val, P->d, b, x0); break;
+    }
+    SPAI_HIP(hipGetLastError());
+    return SPAI_OK;
+}
+
+static int launch_residual(spai_handle* h, const spai_csr* A, const double* b, const double* x, double* r,
+                           spai_prec ur, hipStream_t s) {
+    int n = A->n, g = blocks_for(n, 256);
+    long tk = timer_begin(h, SPAI_KT_RESIDUAL);
+    if (ur == SPAI_DD)
+        hipLaunchKernelGGL(k_residual<true>, dim3(g), dim3(256), 0, s, n, A->rowptr, A->col, A->val, b, x, r);
+    else
+        hipLaunchKernelGGL(k_residual<false>, dim3(g), dim3(256), 0, s, n, A->rowptr, A->col, A->val, b, x, r);
+    timer_end(h, SPAI_KT_RESIDUAL, tk);
+    SPAI_HIP(hipGetLastError());
+    return SPAI_OK;
+}
+
+static int check_csr(const spai_csr* A) {
+    SPAI_ARG(A && A->n > 0 && A->nnz >= 0 && A->rowptr && A->col && A->val, "bad matrix");
+    return SPAI_OK;
+}
+
+// Launch configuration of the Arnoldi kernel: nb blocks of AT threads, EPT
+// elements per thread (a power of two); 0 when the cooperative kernel cannot
+// hold the problem (the per-projection path is used instead).
+struct ArnoldiCfg {
+    int nb = 0;
+    int ept = 0;
+    size_t shmem = 0;
+};
+
+template <int EPT>
+static int max_coresident(size_t shmem, int num_cu) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_arnoldi<EPT>, AT, shmem) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * num_cu;
+}
+
+static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit) {
+    ArnoldiCfg c;
+    if (const char* e = getenv("SPAI_ARNOLDI_PATH"))
+        if (std::string(e) == "projection") return c;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device) != hipSuccess || !coop) {
+        (void)hipGetLastError();
+        return c;
+    }
+    c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
+    if (c.shmem > 48 * 1024) return ArnoldiCfg{};
+    int nb = std::min(h->num_cu, std::max(1, blocks_for(n, AT)));
+    int ept = 1;
+    while ((long long)nb * AT * ept < n) ept <<= 1;
+    if (ept > 16) return ArnoldiCfg{};
+    int cap = 0;
+    switch (ept) {
+    case 1: cap = max_coresident<1>(c.shmem, h->num_cu); break;
+    case 2: cap = max_coresident<2>(c.shmem, h->num_cu); break;
+    case 4: cap = max_coresident<4>(c.shmem, h->num_cu); break;
+    case 8: cap = max_coresident<8>(c.shmem, h->num_cu); break;
+    default: cap = max_coresident<16>(c.shmem, h->num_cu); break;
+    }
+    if (cap < nb) return ArnoldiCfg{};
+    c.nb = nb;
+    c.ept = ept;
+    return c;
+}
+
+static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, hipStream_t s) {
+    void* args[] = {&a};
+    const void* fn = nullptr;
+    switch (c.ept) {
+    case 1: fn = (const void*)k_arnoldi<1>; break;
+    case 2: fn = (const void*)k_arnoldi<2>; break;
+    case 4: fn = (const void*)k_arnoldi<4>; break;
+    case 8: fn = (const void*)k_arnoldi<8>; break;
+    default: fn = (const void*)k_arnoldi<16>; break;
+    }
+    long tk = timer_begin(h, SPAI_KT_MGS);
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);
+    timer_end(h, SPAI_KT_MGS, tk);
+    SPAI_HIP(e);
+    return SPAI_OK;
+}
+
+int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b, double* x,
+                  const spai_ir_params* prm, spai_ir_stats* st) {
+    SPAI_ARG(h && P && b && x && prm, "NULL argument");
+    int rc = check_csr(A);
+    if (rc) return rc;
+    const int n = A->n;
+    SPAI_ARG(P->n == n, "preconditioner size differs from the matrix");
+    SPAI_ARG(prm->imax >= 1 && prm->imax <= 32, "imax must lie in 1..32");
+    SPAI_ARG(prm->maxit >= 1, "maxit must be positive");
+    SPAI_ARG(prm->tau >= 0.0, "tau must be non-negative");
+    SPAI_ARG(prm->u_r == SPAI_DD || prm->u_r == SPAI_FP64, "u_r must be DD or FP64");
+    SPAI_HIP(hipSetDevice(h->device));
+    hipStream_t s = h->stream;
+    const int maxit = std::min(prm->maxit, n);
+    const int ld = maxit + 1;
+    const ArnoldiCfg cfg = arnoldi_config(h, n, maxit);
+    const int maxlinks = maxit + 2;
+
+    // workspace
+    rc = buffer_reserve(h->ws[WS_SOLVE_V], sizeof(double) * (size_t)n * (size_t)(maxit + 1));
+    if (rc) return rc;
+    rc = buffer_reserve(h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
+    if (rc) return rc;
+    size_t slot_count = cfg.nb ? (size_t)2 * maxlinks * cfg.nb : 0;
+    size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count);
+    rc = buffer_reserve(h->ws[WS_SOLVE_H], hbytes);
+    if (rc) return rc;
+    double* V = (double*)h->ws[WS_SOLVE_V].ptr;
+    double* r = (double*)h->ws[WS_SOLVE_VEC].ptr;
+    double* w = r + n;
+    double* y = w + n;
+    double* H = (double*)h->ws[WS_SOLVE_H].ptr;
+    double* cs = H + (size_t)ld * maxit;
+    double* sn = cs + ld;
+    double* g = sn + ld;
+    double* yk = g + ld;
+    double* partials = yk + ld;
+    double* scal = partials + RBLOCKS;          // [0] beta0, [1] h_{j+1,j} (projection path)
+    SolveState* sst = (SolveState*)(scal + 8);
+    unsigned long long* maxbits = (unsigned long long*)(scal + 16);
+    unsigned* ticket = (unsigned*)(scal + 24);
+    unsigned long long* slots = (unsigned long long*)(scal + 64);
+    char* hp = (char*)h->host_pinned.ptr;
+
+    const int tb = 256, gb = blocks_for(n, tb);
+    const int nbr = reduce_blocks(n);
+    SPAI_HIP(hipMemsetAsync(ticket, 0, 16, s));
+    const int chunk = 8;   // Arnoldi steps enqueued between checks of the stop flag
+
+    int status = 0;
+    spai_ir_stats loc{};
+    if ((rc = launch_x0(P, b, x, s))) return rc;   // x0 = P b in u_f
+    double dprev = INFINITY;
+    for (int step = 0; step < prm->imax; ++step) {
+        if ((rc = launch_residual(h, A, b, x, r, prm->u_r, s))) return rc;
+        if ((rc = launch_apply_P(h, P, r, V, s))) return rc;              // z = P r into V(:,0)
+        hipLaunchKernelGGL(k_mgs, dim3(nbr), dim3(RB), 0, s, n, V, (const double*)nullptr,
+                           (const double*)nullptr, (const double*)V, scal, partials, ticket, (int)MGS_NORM,
+                           (const SolveState*)nullptr);
+        SPAI_HIP(hipGetLastError());
+        SPAI_HIP(hipMemcpyAsync(hp, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        SPAI_HIP(hipStreamSynchronize(s));
+        double beta0;
+        std::memcpy(&beta0, hp, sizeof(double));
+        if (beta0 == 0.0) break;   // P r_i = 0: x_i solves the system
+        loc.steps = step + 1;
+        hipLaunchKernelGGL(k_scale, dim3(gb), dim3(tb), 0, s, n, (const double*)V, (const double*)scal, V,
+                           (const SolveState*)nullptr);
+        hipLaunchKernelGGL(k_init_state, dim3(blocks_for(ld, 256)), dim3(256), 0, s, g, ld, (const double*)scal, sst);
+        if (cfg.nb) {
+            size_t len = slot_count;
+            hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, slots, len, SENTINEL);
+        }
+        SPAI_HIP(hipGetLastError());
+        SolveState ss{};
+        int sweep = 0;
+        for (int j0 = 0; j0 < maxit; j0 += chunk) {
+            int j1 = std::min(j0 + chunk, maxit);
+            for (int j = j0; j < j1; ++j) {
+                double* vj = V + (size_t)j * n;
+                double* hcol = H + (size_t)j * ld;
+                if ((rc = launch_spmv(h, A, vj, w, s, sst))) return rc;
+                if ((rc = launch_apply_P(h, P, w, y, s, sst))) return rc;
+                if (cfg.nb) {
+                    ArnoldiArgs aa{};
+                    aa.n = n; aa.j = j; aa.ld = ld; aa.maxit = maxit; aa.maxlinks = maxlinks; aa.nb = cfg.nb;
+                    aa.parity = sweep & 1;
+                    aa.y = y; aa.V = V; aa.H = H; aa.cs = cs; aa.sn = sn; aa.g = g; aa.tau = prm->tau;
+                    aa.slots = slots; aa.st = sst;
+                    if ((rc = launch_arnoldi(h, cfg, aa, s))) return rc;
+                    ++sweep;
+                } else {
+                    // one launch per projection: h_lj = <y, v_l>, y -= h_lj v_l, l = 0..j
+                    for (int l = 0; l <= j; ++l) {
+                        const double* vprev = l > 0 ? V + (size_t)(l - 1) * n : nullptr;
+                        const double* hprev = l > 0 ? hcol + (l - 1) : nullptr;
+                        long tm = timer_begin(h, SPAI_KT_MGS);
+                        hipLaunchKernelGGL(k_mgs, dim3(nbr), dim3(RB), 0, s, n, y, vprev, hprev,
+                                           (const double*)(V + (size_t)l * n), hcol + l, partials, ticket,
+                                           (int)MGS_DOT, (const SolveState*)sst);
+                        timer_end(h, SPAI_KT_MGS, tm);
+                    }
+                    hipLaunchKernelGGL(k_mgs, dim3(nbr), dim3(RB), 0, s, n, y, (const double*)vj,
+                                       (const double*)(hcol + j), (const double*)y, hcol + j + 1, partials, ticket,
+                                       (int)MGS_NORM, (const SolveState*)sst);
+                    hipLaunchKernelGGL(k_scale, dim3(gb), dim3(tb), 0, s, n, (const double*)y,
+                                       (const double*)(hcol + j + 1), V + (size_t)(j + 1) * n, (const SolveState*)sst);
+                    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, j, maxit, H, ld, cs, sn, g, prm->tau, sst);
+                    SPAI_HIP(hipGetLastError());
+                }
+            }
+            SPAI_HIP(hipMemcpyAsync(hp, sst, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+            SPAI_HIP(hipStreamSynchronize(s));
+            std::memcpy(&ss, hp, sizeof(ss));
+            if (ss.done) break;
+        }
+        if (ss.done == 3 || ss.err) {
+            set_error("a grid-wide sum of the Arnoldi kernel timed out");
+            return SPAI_E_INTERNAL;
+        }
+        if (ss.done == 0) {
+            set_error("GMRES ended without a stop decision");
+            return SPAI_E_INTERNAL;
+        }
+        const int kk = ss.its;
+        if (ss.done == 2) status |= SPAI_W_MAXIT;
+        loc.its[step] = kk;
+        loc.total_its += kk;
+        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(RB), 0, s, kk, (const double*)H, ld, (const double*)g, w, yk);
+        SPAI_HIP(hipMemsetAsync(maxbits, 0, 16, s));
+        long tu = timer_begin(h, SPAI_KT_UPDATE);
+        hipLaunchKernelGGL(k_update, dim3(gb), dim3(tb), 0, s, n, kk, (const double*)V, (const double*)yk, x, maxbits);
+        timer_end(h, SPAI_KT_UPDATE, tu);
+        SPAI_HIP(hipGetLastError());
+        SPAI_HIP(hipMemcpyAsync(hp, maxbits, 16, hipMemcpyDeviceToHost, s));
+        SPAI_HIP(hipStreamSynchronize(s));
+        double dn, xn;
+        std::memcpy(&dn, hp, 8);
+        std::memcpy(&xn, hp + 8, 8);
+        loc.gest[step] = ss.gabs / beta0;
+        loc.dnorm[step] = dn;
+        if (dn <= prm->tol_ir * xn) break;
+        if (step >= 2 && dn > 0.5 * dprev) {
+            status |= SPAI_W_NOCONV;
+            break;
+        }
+        dprev = dn;
+        if (step == prm->imax - 1) status |= SPAI_W_NOCONV;
+    }
+    loc.status = status;
+    if (st) *st = loc;
+    return status;
+}
+
+}  // namespace spai
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
+                             double* x, const spai_ir_params* p, spai_ir_stats* st) {
+    return spai::gmres_ir_impl(h, A, P, b, x, p, st);
+}
+
+extern "C" int spai_residual(spai_handle* h, const spai_csr* A, const double* b, const double* x, double* r,
+                             spai_prec u_r) {
+    if (!h || !b || !x || !r) {
+        spai::set_error("invalid argument: NULL argument");
+        return SPAI_E_ARG;
+    }
+    int rc = spai::check_csr(A);
+    if (rc) return rc;
+    if (u_r != SPAI_DD && u_r != SPAI_FP64) {
+        spai::set_error("invalid argument: u_r must be DD or FP64");
+        return SPAI_E_ARG;
+    }
+    SPAI_HIP(hipSetDevice(h->device));
+    rc = spai::launch_residual(h, A, b, x, r, u_r, h->stream);
+    if (rc) return rc;
+    SPAI_HIP(hipStreamSynchronize(h->stream));
+    return SPAI_OK;
+}
+
+extern "C" int spai_precond_apply(spai_handle* h, const spai_precond* P, const double* w, double* y) {
+    if (!h || !P || !w || !y) {
+        spai::set_error("invalid argument: NULL argument");
+        return SPAI_E_ARG;
+    }
+    SPAI_HIP(hipSetDevice(h->device));
+    int rc = spai::launch_apply_P(h, P, w, y, h->stream);
+    if (rc) return rc;
+    SPAI_HIP(hipStreamSynchronize(h->stream));
+    return SPAI_OK;
+}
+
+extern "C" int spai_precond_apply_uf(spai_handle* h, const spai_precond* P, const double* b, double* x0) {
+    if (!h || !P || !b || !x0) {
+        spai::set_error("invalid argument: NULL argument");
+        return SPAI_E_ARG;
+    }
+    SPAI_HIP(hipSetDevice(h->device));
+    int rc = spai::launch_x0(P, b, x0, h->stream);
+    if (rc) return rc;
+    SPAI_HIP(hipStreamSynchronize(h->stream));
+    return SPAI_OK;
+}
+
+extern "C" int spai_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y) {
+    if (!h || !x || !y) {
+        spai::set_error("invalid argument: NULL argument");
+        return SPAI_E_ARG;
+    }
+    int rc = spai::check_csr(A);
+    if (rc) return rc;
+    SPAI_HIP(hipSetDevice(h->device));
+    int n = A->n;
+    hipLaunchKernelGGL(spai::k_spmv, dim3((n + 255) / 256), dim3(256), 0, h->stream, n, A->rowptr, A->col,
+                       A->val, x, y, (const spai::SolveState*)nullptr);
+    SPAI_HIP(hipGetLastError());
+    SPAI_HIP(hipStreamSynchronize(h->stream));
+    return SPAI_OK;
+}

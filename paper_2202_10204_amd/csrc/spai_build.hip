@@ -1,0 +1,1086 @@
+// SPAI construction on gfx950: Algorithm 1 (Section 2.2) on B = A^T D with the
+// one-sided column scaling of Section 4, producing the left preconditioner
+// P = M^T D of Algorithm 3.
+//
+// Work decomposition.  The Frobenius norm decouples into n independent column
+// problems (eq. fronormmin).  A group of G lanes of one wavefront owns one
+// column k; a 64-wide wavefront holds floor(64/G) groups and a workgroup is one
+// wavefront, so groups never need a workgroup barrier.  The reduced matrix
+// A-bar = B(I_k, J_k) and e-bar live in LDS (column-major, odd leading
+// dimension): lane c of the group owns column c of A-bar and lane p owns e-bar,
+// so the Householder updates of the trailing columns run in parallel while
+// every inner sum runs sequentially over the rows in ascending order.  That is
+// the rounding model of the build, stated with the arithmetic helpers in
+// common.hpp: one precision F, sequential sums in a fixed index order, fused
+// multiply-adds for sums of products, and rounding to u_f at the storage points.
+// Index work (shadows, candidate sets) uses per-group bitonic sorts in LDS.
+//
+// Problems that exceed a kernel's LDS capacity (rows of the shadow, gathered
+// entries, raw candidates) are deferred to a second launch of a larger
+// configuration over the deferred list.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spai {
+
+// ---------------------------------------------------------------------------
+// preprocessing kernels
+// ---------------------------------------------------------------------------
+
+struct PrepOut {
+    int err;        // bit 0: bad rowptr, 1: column out of range / unsorted, 2: non-finite value,
+                    // 3: all-zero row, 4: bad pattern
+    int max_row;    // max nnz per row of A
+    int max_col;    // max nnz per column of A
+    int max_pat;    // longest initial pattern column
+};
+
+__global__ void k_validate_scale(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                                 const double* __restrict__ av, double* __restrict__ d,
+                                 int* __restrict__ colcount, PrepOut* out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int s = rp[j], e = rp[j + 1];
+    int err = 0;
+    if (j == 0 && s != 0) err |= 1;
+    if (j == n - 1 && e != nnz) err |= 1;
+    if (e < s || s < 0 || e > nnz) {
+        atomicOr(&out->err, err | 1);
+        d[j] = 1.0;
+        return;
+    }
+    double mx = 0.0;
+    int prev = -1;
+    for (int q = s; q < e; ++q) {
+        int c = ci[q];
+        double v = av[q];
+        if (c < 0 || c >= n || c <= prev) err |= 2;
+        prev = c;
+        if (!isfinite(v)) err |= 4;
+        double a = fabs(v);
+        if (a > mx) mx = a;
+        if (c >= 0 && c < n) atomicAdd(&colcount[c], 1);
+    }
+    if (!(mx > 0.0)) err |= 8;
+    // Section 4: scale so that the largest entry of every column of A^T D is 1
+    d[j] = mx > 0.0 ? 1.0 / mx : 1.0;
+    if (err) atomicOr(&out->err, err);
+    atomicMax(&out->max_row, e - s);
+}
+
+// ||B(:,j)||^2 = sum over row j of A (CSR order) of (u_f(d_j a_jl))^2, in F
+template <int UF>
+__global__ void k_colnorm(int n, const int* __restrict__ rp, const double* __restrict__ av,
+                          const double* __restrict__ d, typename UfTraits<UF>::F* __restrict__ bn) {
+    using F = typename UfTraits<UF>::F;
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double dj = d[j];
+    F s = F(0);
+    for (int q = rp[j]; q < rp[j + 1]; ++q) {
+        F b = scaled_entry<UF>(dj, av[q]);
+        s = ffma(b, b, s);
+    }
+    bn[j] = s;
+}
+
+__global__ void k_max_count(int n, const int* __restrict__ cnt, PrepOut* out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) atomicMax(&out->max_col, cnt[j]);
+}
+
+__global__ void k_fill_csc(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           int* __restrict__ cursor, int* __restrict__ ri) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int q = rp[j]; q < rp[j + 1]; ++q) {
+        int pos = atomicAdd(&cursor[ci[q]], 1);
+        ri[pos] = j;   // order inside a column is irrelevant: only the set N_l is used
+    }
+}
+
+__global__ void k_validate_pattern(int n, int pnnz, const int* __restrict__ pp, const int* __restrict__ pi,
+                                   PrepOut* out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int s = pp[k], e = pp[k + 1];
+    if (s < 0 || e < s || e > pnnz || (k == 0 && s != 0) || (k == n - 1 && e != pnnz)) {
+        atomicOr(&out->err, 16);
+        return;
+    }
+    int err = (e == s) ? 16 : 0;   // every column needs at least one index
+    for (int q = s; q < e; ++q) {
+        int j = pi[q];
+        if (j < 0 || j >= n) err = 16;
+        for (int q2 = s; q2 < q; ++q2)
+            if (pi[q2] == j) err = 16;
+    }
+    if (err) atomicOr(&out->err, err);
+    atomicMax(&out->max_pat, e - s);
+}
+
+// exclusive scan of n ints into out[0..n], out[n] = total (three passes)
+constexpr int SCAN_BLOCK = 1024;
+
+__global__ void k_scan_block(int n, const int* __restrict__ in, int* __restrict__ out,
+                             int* __restrict__ block_sums) {
+    __shared__ int sh[SCAN_BLOCK];
+    int i = blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+        int t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) out[i] = sh[threadIdx.x] - v;
+    if (threadIdx.x == SCAN_BLOCK - 1) block_sums[blockIdx.x] = sh[threadIdx.x];
+}
+
+__global__ void k_scan_sums(int nb, int* __restrict__ block_sums, int* __restrict__ total) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int run = 0;
+    for (int b = 0; b < nb; ++b) {
+        int v = block_sums[b];
+        block_sums[b] = run;
+        run += v;
+    }
+    *total = run;
+}
+
+__global__ void k_scan_add(int n, int* __restrict__ out, const int* __restrict__ block_sums,
+                           const int* __restrict__ total) {
+    int i = blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    if (i < n) out[i] += block_sums[blockIdx.x];
+    if (i == 0) out[n] = *total;
+}
+
+// ---------------------------------------------------------------------------
+// the column kernel
+// ---------------------------------------------------------------------------
+
+struct ColArgs {
+    int n;
+    const int* rp;
+    const int* ci;
+    const double* av;
+    const int* cp;      // CSC(A) structure: column l -> rows j with a_jl != 0
+    const int* ri;
+    const double* d;
+    const void* bnrm2;  // F per column of B
+    const int* pat_ptr;  // initial pattern (NULL: identity)
+    const int* pat_idx;
+    double eps;
+    int alpha, beta, maxfill;
+    const int* cols;    // problems to solve (NULL: 0..ncols-1)
+    int ncols;
+    int stride;
+    int* len;
+    int* jout;
+    double* mout;
+    int* steps;
+    double* res;
+    int* flags;
+    int* nI;
+    int* defer_list;
+    int* defer_count;
+};
+
+template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_>
+struct Cfg {
+    static constexpr int UF = UF_;
+    using F = typename UfTraits<UF_>::F;
+    static constexpr int G = G_;           // lanes per problem
+    static constexpr int MAXP = G_ - 1;    // columns of A-bar; lane MAXP can hold e-bar
+    static constexpr int MAXM = MAXM_;     // rows of A-bar
+    static constexpr int LD = MAXM_ + 1;   // odd leading dimension
+    static constexpr int EMAX = EMAX_;     // gathered entries of B(:, J) (power of two)
+    static constexpr int CMAX = CMAX_;     // raw candidate entries (power of two)
+    static constexpr int PPW = 64 / G_;    // problems per wavefront
+};
+
+template <class C>
+struct alignas(16) Smem {
+    using F = typename C::F;
+    uint64_t gkey[C::EMAX];  // (row i << 32) | slot, sorted by row then slot
+    union {
+        F A[(C::MAXP + 1) * C::LD];   // QR phase: columns of A-bar, then e-bar
+        struct {
+            int key[C::CMAX];         // raw candidates, sorted
+            int cj[C::CMAX];          // unique candidates (ascending j)
+            F rho[C::CMAX];
+        } c;
+    } u;
+    F gval[C::EMAX];         // u_f(d_j a_ji) by slot
+    uint8_t gcol[C::EMAX];   // position of j in J by slot
+    uint8_t gpos[C::EMAX];   // row position in I of sorted entry e
+    int I[C::MAXM];          // shadow, ascending
+    int seg[C::MAXM + 1];    // first sorted entry of each row of A-bar
+    F s[C::MAXM];            // residual s-bar
+    int J[C::MAXP + 1];
+    F mb[C::MAXP + 1];
+    F Rd[C::MAXP + 1];
+    F rf[C::G];              // group scratch
+    int ri[C::G];
+    int rj[C::G];
+    F fs[4];
+    int is[4];
+};
+
+__device__ __forceinline__ int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+template <int G, typename K>
+__device__ void group_sort(K* keys, int N, int lane) {
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < (N >> 1); t += G) {
+                int i = 2 * t - (t & (stride - 1));
+                int l = i + stride;
+                bool asc = (i & size) == 0;
+                K a = keys[i], b = keys[l];
+                if ((a > b) == asc) {
+                    keys[i] = b;
+                    keys[l] = a;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+__device__ __forceinline__ int bsearch_sorted(const int* v, int len, int key) {
+    int lo = 0, hi = len - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int x = v[mid];
+        if (x == key) return mid;
+        if (x < key) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+template <class C>
+__global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
+    using F = typename C::F;
+    constexpr int G = C::G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wl = threadIdx.x;
+    const int g = wl / G;
+    const int lane = wl - g * G;
+    if (g >= C::PPW) return;
+    const int prob = blockIdx.x * C::PPW + g;
+    if (prob >= a.ncols) return;
+    Smem<C>& S = reinterpret_cast<Smem<C>*>(smem_raw)[g];
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
+    const uint64_t below = (wl == 0) ? 0ull : ((~0ull) >> (64 - wl));
+    const F* bnrm2 = reinterpret_cast<const F*>(a.bnrm2);
+
+    const int k = a.cols ? a.cols[prob] : prob;
+    int p;
+    bool defer = false;
+    // initial pattern, ascending (Algorithm 1 input J; identity when absent)
+    if (a.pat_ptr) {
+        int s0 = a.pat_ptr[k];
+        p = a.pat_ptr[k + 1] - s0;
+        if (p > C::MAXP || p < 1) {
+            defer = (p > C::MAXP);
+            p = 0;
+        } else {
+            int my = lane < p ? a.pat_idx[s0 + lane] : INT_MAX;
+            int rank = 0;
+            for (int t = 0; t < p; ++t) {
+                int o = a.pat_idx[s0 + t];
+                rank += (o < my);
+            }
+            if (lane < p) S.J[rank] = my;
+        }
+    } else {
+        p = 1;
+        if (lane == 0) S.J[0] = k;
+    }
+    wave_sync();
+    const int cap = a.maxfill > p ? a.maxfill : p;
+    int flags = 0, step = 0, m = 0, kpos = -1;
+    F res = F(0);
+    if (p == 0 && !defer) flags |= CF_EPS;
+
+    for (step = 0; p > 0 && !defer; ++step) {
+        // ---- shadow I_k and A-bar = B(I_k, J_k), e-bar = e_k(I_k) ----
+        int myj = 0, mys = 0, myn = 0;
+        if (lane < p) {
+            myj = S.J[lane];
+            mys = a.rp[myj];
+            myn = a.rp[myj + 1] - mys;
+        }
+        S.ri[lane] = myn;
+        wave_sync();
+        int off = 0, E = 0;
+        for (int t = 0; t < G; ++t) {
+            int v = S.ri[t];
+            off += (t < lane) ? v : 0;
+            E += v;
+        }
+        wave_sync();
+        if (E > C::EMAX) { defer = true; break; }
+        if (lane < p) {
+            double dj = a.d[myj];
+            for (int q = 0; q < myn; ++q) {
+                int slot = off + q;
+                int i = a.ci[mys + q];
+                S.gkey[slot] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)slot;
+                S.gval[slot] = scaled_entry<C::UF>(dj, a.av[mys + q]);
+                S.gcol[slot] = (uint8_t)lane;
+            }
+        }
+        const int E2 = next_pow2(E > 0 ? E : 1);
+        for (int e = E + lane; e < E2; e += G) S.gkey[e] = ~0ull;
+        wave_sync();
+        group_sort<G>(S.gkey, E2, lane);
+        // count distinct rows
+        m = 0;
+        for (int base = 0; base < E; base += G) {
+            int e = base + lane;
+            bool head = false;
+            if (e < E) {
+                uint32_t i = (uint32_t)(S.gkey[e] >> 32);
+                head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
+            }
+            m += __popcll(ballot(head) & gmask);
+        }
+        if (m > C::MAXM) { defer = true; break; }
+        // positions, shadow list, row segments
+        {
+            int run = 0;
+            for (int base = 0; base < E; base += G) {
+                int e = base + lane;
+                bool head = false;
+                uint32_t i = 0;
+                if (e < E) {
+                    i = (uint32_t)(S.gkey[e] >> 32);
+                    head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
+                }
+                uint64_t bal = ballot(head) & gmask;
+                int before = __popcll(bal & below);
+                if (e < E) {
+                    int pos = run + before - (head ? 0 : 1);
+                    S.gpos[e] = (uint8_t)pos;
+                    if (head) {
+                        S.I[pos] = (int)i;
+                        S.seg[pos] = e;
+                    }
+                }
+                run += __popcll(bal);
+            }
+            if (lane == 0) {
+                S.seg[m] = E;
+                S.is[0] = -1;
+            }
+        }
+        // zero the p+1 columns (lane c zeroes column c)
+        if (lane <= p) {
+            F* col = &S.u.A[lane * C::LD];
+            for (int i = 0; i < m; ++i) col[i] = F(0);
+        }
+        wave_sync();
+        for (int e = lane; e < E; e += G) {
+            int slot = (int)(uint32_t)(S.gkey[e] & 0xffffffffu);
+            int pos = S.gpos[e];
+            S.u.A[S.gcol[slot] * C::LD + pos] = S.gval[slot];
+            if (S.I[pos] == k && S.seg[pos] == e) S.is[0] = pos;
+        }
+        wave_sync();
+        kpos = S.is[0];
+        if (lane == 0 && kpos >= 0) S.u.A[p * C::LD + kpos] = F(1);
+        wave_sync();
+
+        // ---- Householder QR of A-bar, applied to e-bar as well ----
+        // For x = A(t:m, t): sigma = ||x||, alpha = -sgn(x_t) sigma (sgn(0) = +1),
+        // v = x - alpha e_1 with v^T v = 2 sigma (sigma + |x_t|), so the reflector
+        // maps a column a to a - (v^T a / tau) v with tau = sigma (sigma + |x_t|).
+        bool rankdef = false;
+        const int qsteps = p < m ? p : m;
+        for (int t = 0; t < qsteps; ++t) {
+            if (lane == t) {
+                F* x = &S.u.A[t * C::LD];
+                F sig2 = F(0);
+                for (int i = t; i < m; ++i) sig2 = ffma(x[i], x[i], sig2);
+                F sigma = fsqrt(sig2);
+                if (sigma == F(0)) {
+                    S.Rd[t] = F(0);
+                    S.is[1] = 1;
+                } else {
+                    F xt = x[t];
+                    F alpha = (xt >= F(0)) ? -sigma : sigma;
+                    x[t] = store<C::UF>(xt - alpha);
+                    S.fs[0] = sigma * (sigma + fabs(xt));
+                    S.Rd[t] = store<C::UF>(alpha);
+                    S.is[1] = 0;
+                }
+            }
+            wave_sync();
+            if (S.is[1]) {
+                rankdef = true;
+                continue;
+            }
+            const F tau = S.fs[0];
+            if (lane > t && lane <= p) {
+                const F* v = &S.u.A[t * C::LD];
+                F* col = &S.u.A[lane * C::LD];
+                F dot = F(0);
+                for (int i = t; i < m; ++i) dot = ffma(v[i], col[i], dot);
+                F f = dot / tau;
+                for (int i = t; i < m; ++i) col[i] = store<C::UF>(ffma(-f, v[i], col[i]));
+            }
+            wave_sync();
+        }
+        if (p > m) rankdef = true;
+        // back substitution, c = p-1 down to 0, inner sum over c' ascending
+        if (lane == 0) {
+            int rd = 0;
+            for (int c = p - 1; c >= 0; --c) {
+                if (c >= m || S.Rd[c] == F(0)) {
+                    S.mb[c] = F(0);
+                    rd = 1;
+                    continue;
+                }
+                F s = S.u.A[p * C::LD + c];
+                for (int c2 = c + 1; c2 < p; ++c2) s = ffma(-S.u.A[c2 * C::LD + c], S.mb[c2], s);
+                S.mb[c] = store<C::UF>(s / S.Rd[c]);
+            }
+            S.is[2] = rd;
+        }
+        wave_sync();
+        if (S.is[2]) rankdef = true;
+        if (rankdef) flags |= CF_RANKDEF;
+
+        // ---- residual s-bar = A-bar m-bar - e-bar over the stored entries ----
+        for (int pos = lane; pos < m; pos += G) {
+            F acc = F(0);
+            for (int e = S.seg[pos]; e < S.seg[pos + 1]; ++e) {
+                int slot = (int)(uint32_t)(S.gkey[e] & 0xffffffffu);
+                acc = ffma(S.gval[slot], S.mb[S.gcol[slot]], acc);
+            }
+            S.s[pos] = acc - ((pos == kpos) ? F(1) : F(0));
+        }
+        wave_sync();
+        if (lane == 0) {
+            F r2 = F(0);
+            for (int pos = 0; pos < m; ++pos) r2 = ffma(S.s[pos], S.s[pos], r2);
+            // row k of the full residual is -1 when k lies outside the shadow
+            if (kpos < 0) r2 = r2 + F(1);
+            S.fs[1] = r2;
+        }
+        wave_sync();
+        const F res2 = S.fs[1];
+        res = fsqrt(res2);
+        if (!isfinite(res)) { flags |= CF_NONFINITE; break; }
+        if ((double)res <= a.eps) break;                        // stopping test
+        if (step >= a.alpha || p >= cap) { flags |= CF_EPS; break; }
+
+        // ---- candidates: L = I u {k}, J~ = (union of N_l) \ J ----
+        int cnt = 0;
+        for (int pos = lane; pos < m; pos += G) {
+            int l = S.I[pos];
+            cnt += a.cp[l + 1] - a.cp[l];
+        }
+        if (lane == 0 && kpos < 0) cnt += a.cp[k + 1] - a.cp[k];
+        S.ri[lane] = cnt;
+        wave_sync();
+        int coff = 0, Ec = 0;
+        for (int t = 0; t < G; ++t) {
+            int v = S.ri[t];
+            coff += (t < lane) ? v : 0;
+            Ec += v;
+        }
+        wave_sync();
+        if (Ec > C::CMAX) { defer = true; break; }
+        for (int pos = lane; pos < m; pos += G) {
+            int l = S.I[pos];
+            for (int q = a.cp[l]; q < a.cp[l + 1]; ++q) S.u.c.key[coff++] = a.ri[q];
+        }
+        if (lane == 0 && kpos < 0)
+            for (int q = a.cp[k]; q < a.cp[k + 1]; ++q) S.u.c.key[coff++] = a.ri[q];
+        const int Ec2 = next_pow2(Ec > 0 ? Ec : 1);
+        for (int e = Ec + lane; e < Ec2; e += G) S.u.c.key[e] = INT_MAX;
+        wave_sync();
+        group_sort<G>(S.u.c.key, Ec2, lane);
+        int nc = 0;
+        for (int base = 0; base < Ec; base += G) {
+            int e = base + lane;
+            bool head = false;
+            int j = 0;
+            if (e < Ec) {
+                j = S.u.c.key[e];
+                head = (e == 0 || S.u.c.key[e - 1] != j);
+                if (head)
+                    for (int c = 0; c < p; ++c)
+                        if (S.J[c] == j) head = false;
+            }
+            uint64_t bal = ballot(head) & gmask;
+            if (head) S.u.c.cj[nc + __popcll(bal & below)] = j;
+            nc += __popcll(bal);
+        }
+        wave_sync();
+        if (nc == 0) { flags |= CF_EPS; break; }
+        // scores rho_j = sqrt(max(res^2 - (r^T B e_j)^2 / ||B e_j||^2, 0)); the sum
+        // runs over the rows of B(:, j) (= columns of row j of A) ascending, r being
+        // the residual on L (s-bar on I, -1 at k when k is outside I)
+        for (int c = lane; c < nc; c += G) {
+            int j = S.u.c.cj[c];
+            double dj = a.d[j];
+            F tj = F(0);
+            for (int q = a.rp[j]; q < a.rp[j + 1]; ++q) {
+                int i = a.ci[q];
+                F r;
+                int pos = bsearch_sorted(S.I, m, i);
+                if (pos >= 0) r = S.s[pos];
+                else if (i == k) r = F(-1);
+                else continue;
+                tj = ffma(r, scaled_entry<C::UF>(dj, a.av[q]), tj);
+            }
+            F r2 = res2 - (tj * tj) / bnrm2[j];
+            if (r2 <= F(0)) r2 = F(0);
+            S.u.c.rho[c] = fsqrt(r2);
+        }
+        wave_sync();
+        if (lane == 0) {
+            F rs = F(0);
+            for (int c = 0; c < nc; ++c) rs = rs + S.u.c.rho[c];   // ascending j
+            S.fs[2] = rs / (F)nc;
+        }
+        wave_sync();
+        const F rbar = S.fs[2];
+        // acceptable: rho_j <= rho-bar; add the min(beta, #acceptable, cap - |J|)
+        // best, ordered by (rho, j)
+        int na = 0;
+        for (int base = 0; base < nc; base += G) {
+            int c = base + lane;
+            bool ok = (c < nc) && (S.u.c.rho[c] <= rbar);
+            na += __popcll(ballot(ok) & gmask);
+        }
+        int nsel = a.beta;
+        if (na < nsel) nsel = na;
+        if (cap - p < nsel) nsel = cap - p;
+        if (nsel <= 0) { flags |= CF_EPS; break; }
+        for (int sel = 0; sel < nsel; ++sel) {
+            F br = F(0);
+            int bj = INT_MAX, bc = -1;
+            for (int c = lane; c < nc; c += G) {
+                int j = S.u.c.cj[c];
+                F r = S.u.c.rho[c];
+                if (j >= 0 && r <= rbar && (bc < 0 || r < br || (r == br && j < bj))) {
+                    br = r;
+                    bj = j;
+                    bc = c;
+                }
+            }
+            S.rf[lane] = br;
+            S.rj[lane] = bj;
+            S.ri[lane] = bc;
+            wave_sync();
+            if (lane == 0) {
+                F r0 = F(0);
+                int j0 = INT_MAX, c0 = -1;
+                for (int t = 0; t < G; ++t) {
+                    int ct = S.ri[t];
+                    if (ct < 0) continue;
+                    F rt = S.rf[t];
+                    int jt = S.rj[t];
+                    if (c0 < 0 || rt < r0 || (rt == r0 && jt < j0)) {
+                        r0 = rt;
+                        j0 = jt;
+                        c0 = ct;
+                    }
+                }
+                S.J[p + sel] = j0;
+                S.u.c.cj[c0] = -1;   // taken
+            }
+            wave_sync();
+        }
+        p += nsel;
+    }
+
+    if (defer) {
+        if (lane == 0) {
+            a.flags[k] = CF_DEFERRED;
+            int slot = atomicAdd(a.defer_count, 1);
+            a.defer_list[slot] = k;
+        }
+        return;
+    }
+    // outputs: J_k in insertion order with m-bar of the last solve
+    const size_t o = (size_t)k * (size_t)a.stride;
+    for (int c = lane; c < a.stride; c += G) {
+        a.jout[o + c] = c < p ? S.J[c] : -1;
+        a.mout[o + c] = c < p ? (double)S.mb[c] : 0.0;
+    }
+    if (lane == 0) {
+        a.len[k] = p;
+        a.steps[k] = step;
+        a.res[k] = (double)res;
+        a.flags[k] = flags;
+        a.nI[k] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compaction: row k of P = m_k^T with columns ascending
+// ---------------------------------------------------------------------------
+
+template <int VP>
+__global__ void k_compact(int n, int stride, const int* __restrict__ len, const int* __restrict__ jin,
+                          const double* __restrict__ min_, const int* __restrict__ rowptr,
+                          int* __restrict__ col, typename ValType<VP>::T* __restrict__ val) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)n * stride) return;
+    int k = (int)(t / stride);
+    int c = (int)(t - (long long)k * stride);
+    int L = len[k];
+    if (c >= L) return;
+    const int* J = jin + (size_t)k * stride;
+    int j = J[c];
+    int rank = 0;
+    for (int c2 = 0; c2 < L; ++c2) rank += (J[c2] < j);
+    int pos = rowptr[k] + rank;
+    col[pos] = j;
+    double v = min_[(size_t)k * stride + c];
+    using T = typename ValType<VP>::T;
+    if constexpr (VP == SPAI_FP64) val[pos] = v;
+    else if constexpr (VP == SPAI_FP32) val[pos] = (float)v;
+    else if constexpr (VP == SPAI_FP16) val[pos] = __float2half_rn((float)v);
+    else val[pos] = T((float)v);
+}
+
+struct BuildStatsDev {
+    int over_eps, rankdef, nonfinite, max_len, max_steps, max_shadow;
+    unsigned long long max_res_bits;
+};
+
+__global__ void k_build_stats(int n, const int* __restrict__ len, const int* __restrict__ steps,
+                              const double* __restrict__ res, const int* __restrict__ flags,
+                              const int* __restrict__ nI, BuildStatsDev* st) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int f = flags[k];
+    if (f & CF_EPS) atomicAdd(&st->over_eps, 1);
+    if (f & CF_RANKDEF) atomicAdd(&st->rankdef, 1);
+    if (f & CF_NONFINITE) atomicAdd(&st->nonfinite, 1);
+    atomicMax(&st->max_len, len[k]);
+    atomicMax(&st->max_steps, steps[k]);
+    atomicMax(&st->max_shadow, nI[k]);
+    double r = res[k];
+    if (r >= 0.0) atomicMax(&st->max_res_bits, (unsigned long long)__double_as_longlong(r));
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <class C>
+static int launch_columns(spai_handle* h, const ColArgs& a, hipStream_t s) {
+    if (a.ncols <= 0) return SPAI_OK;
+    size_t sh = sizeof(Smem<C>) * C::PPW;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] {
+        attr_err = hipFuncSetAttribute((const void*)k_spai_columns<C>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    });
+    SPAI_HIP(attr_err);
+    int grid = (a.ncols + C::PPW - 1) / C::PPW;
+    long tk = timer_begin(h, SPAI_KT_COLUMNS);
+    hipLaunchKernelGGL(k_spai_columns<C>, dim3(grid), dim3(64), sh, s, a);
+    timer_end(h, SPAI_KT_COLUMNS, tk);
+    SPAI_HIP(hipGetLastError());
+    return SPAI_OK;
+}
+
+// configurations: lanes per problem G (|J| <= G-1), shadow rows, gathered entries,
+// raw candidates; the last one is the large-problem kernel for deferred columns
+template <int UF> using CfgS = Cfg<UF, 8, 32, 64, 256>;
+template <int UF> using CfgM = Cfg<UF, 16, 64, 128, 512>;
+template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 512>;
+template <int UF> using CfgL = Cfg<UF, 32, 64, 256, 512>;
+template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 2048>;
+
+template <int UF>
+static int run_columns(spai_handle* h, int pmax, ColArgs a, hipStream_t s, int* defer_list2, int* defer_count_dev,
+                       int* defer_count_host, int* cols_deferred) {
+    int rc;
+    int* dc = a.defer_count;
+    if (pmax <= CfgS<UF>::MAXP) rc = launch_columns<CfgS<UF>>(h, a, s);
+    else if (pmax <= CfgM<UF>::MAXP) rc = launch_columns<CfgM<UF>>(h, a, s);
+    else if (pmax <= CfgM21<UF>::MAXP) rc = launch_columns<CfgM21<UF>>(h, a, s);
+    else if (pmax <= CfgL<UF>::MAXP) rc = launch_columns<CfgL<UF>>(h, a, s);
+    else {
+        // everything goes straight to the large kernel
+        rc = launch_columns<CfgX<UF>>(h, a, s);
+        if (rc) return rc;
+        SPAI_HIP(hipMemcpyAsync(defer_count_host, dc, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPAI_HIP(hipStreamSynchronize(s));
+        *cols_deferred = 0;
+        if (*defer_count_host > 0) {
+            set_error("a column problem exceeds the largest kernel configuration");
+            return SPAI_E_ARG;
+        }
+        return SPAI_OK;
+    }
+    if (rc) return rc;
+    SPAI_HIP(hipMemcpyAsync(defer_count_host, dc, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPAI_HIP(hipStreamSynchronize(s));
+    int nd = *defer_count_host;
+    *cols_deferred = nd;
+    if (nd > 0) {
+        ColArgs b = a;
+        b.cols = a.defer_list;
+        b.ncols = nd;
+        b.defer_list = defer_list2;
+        b.defer_count = defer_count_dev;
+        SPAI_HIP(hipMemsetAsync(defer_count_dev, 0, sizeof(int), s));
+        rc = launch_columns<CfgX<UF>>(h, b, s);
+        if (rc) return rc;
+        SPAI_HIP(hipMemcpyAsync(defer_count_host, defer_count_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPAI_HIP(hipStreamSynchronize(s));
+        if (*defer_count_host > 0) {
+            set_error("a column problem exceeds the largest kernel configuration");
+            return SPAI_E_ARG;
+        }
+    }
+    return SPAI_OK;
+}
+
+static int scan_ints(int n, const int* in, int* out, int* tmp_blocks, int* total, hipStream_t s) {
+    int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(SCAN_BLOCK), 0, s, n, in, out, tmp_blocks);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1), 0, s, nb, tmp_blocks, total);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, n, out, tmp_blocks, total);
+    SPAI_HIP(hipGetLastError());
+    return SPAI_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static void precond_free(spai_precond* P) {
+    if (!P) return;
+    void* ptrs[] = {P->rowptr, P->col, P->val, P->d, P->j_ins, P->m_ins, P->len, P->steps, P->res, P->flags};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete P;
+}
+
+template <typename T>
+static int dev_alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(std::string("device allocation failed: ") + hipGetErrorString(e));
+        return SPAI_E_OOM;
+    }
+    return SPAI_OK;
+}
+
+static size_t val_size(spai_prec v) {
+    switch (v) {
+    case SPAI_FP64: return 8;
+    case SPAI_FP32: return 4;
+    default: return 2;
+    }
+}
+
+int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+               spai_precond** P_out, spai_build_stats* st) {
+    SPAI_ARG(h && A && p && P_out, "NULL handle, matrix, parameters or output");
+    *P_out = nullptr;
+    const int n = A->n;
+    SPAI_ARG(n > 0, "n must be positive");
+    SPAI_ARG(A->nnz >= n && A->rowptr && A->col && A->val, "matrix arrays missing or nnz < n");
+    SPAI_ARG(p->eps > 0.0, "eps must be positive");
+    SPAI_ARG(p->alpha >= 0 && p->beta >= 0, "alpha and beta must be non-negative");
+    SPAI_ARG(p->maxfill >= 1 && p->maxfill <= 63, "maxfill must lie in 1..63");
+    SPAI_ARG(p->u_f == SPAI_FP64 || p->u_f == SPAI_FP32 || p->u_f == SPAI_FP16 || p->u_f == SPAI_BF16,
+             "u_f must be FP64, FP32, FP16 or BF16");
+    if (J) {
+        SPAI_ARG(J->n == n && J->ptr && J->idx && J->nnz >= n, "pattern does not match the matrix");
+    }
+    hipStream_t s = h->stream;
+    SPAI_HIP(hipSetDevice(h->device));
+    const int nnz = A->nnz;
+    const size_t fsz = (p->u_f == SPAI_FP64) ? 8 : 4;
+
+    // workspace: d, bnrm2, col counts, cursor, CSC rows, scan blocks, defer lists, stats
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1;
+    size_t o_bn = take(fsz * n), o_cnt = take(4 * (size_t)n + 4), o_cp = take(4 * ((size_t)n + 1)),
+           o_cur = take(4 * (size_t)n), o_ri = take(4 * (size_t)nnz), o_blk = take(4 * (size_t)nb),
+           o_tot = take(16), o_dl = take(4 * (size_t)n), o_dl2 = take(4 * (size_t)n),
+           o_dc = take(16), o_prep = take(sizeof(PrepOut)), o_bst = take(sizeof(BuildStatsDev)),
+           o_nI = take(4 * (size_t)n);
+    int rc = buffer_reserve(h->ws[WS_BUILD0], off);
+    if (rc) return rc;
+    char* base = (char*)h->ws[WS_BUILD0].ptr;
+    void* bn = base + o_bn;
+    int* cnt = (int*)(base + o_cnt);
+    int* cp = (int*)(base + o_cp);
+    int* cur = (int*)(base + o_cur);
+    int* ri = (int*)(base + o_ri);
+    int* blk = (int*)(base + o_blk);
+    int* tot = (int*)(base + o_tot);
+    int* dl = (int*)(base + o_dl);
+    int* dl2 = (int*)(base + o_dl2);
+    int* dc = (int*)(base + o_dc);
+    PrepOut* prep = (PrepOut*)(base + o_prep);
+    BuildStatsDev* bst = (BuildStatsDev*)(base + o_bst);
+    int* nI = (int*)(base + o_nI);
+    char* hp = (char*)h->host_pinned.ptr;
+
+    spai_precond* P = new spai_precond();
+    P->n = n;
+    P->val_prec = p->u_f;
+    auto fail = [&](int code) { precond_free(P); return code; };
+
+    SPAI_HIP(hipMemsetAsync(cnt, 0, 4 * (size_t)n + 4, s));
+    SPAI_HIP(hipMemsetAsync(prep, 0, sizeof(PrepOut), s));
+    SPAI_HIP(hipMemsetAsync(dc, 0, 16, s));
+    SPAI_HIP(hipMemsetAsync(bst, 0, sizeof(BuildStatsDev), s));
+    if ((rc = dev_alloc(&P->d, n))) return fail(rc);
+    const int tb = 256, gb = (n + tb - 1) / tb;
+    hipLaunchKernelGGL(k_validate_scale, dim3(gb), dim3(tb), 0, s, n, nnz, A->rowptr, A->col, A->val,
+                       P->d, cnt, prep);
+    hipLaunchKernelGGL(k_max_count, dim3(gb), dim3(tb), 0, s, n, cnt, prep);
+    if (J)
+        hipLaunchKernelGGL(k_validate_pattern, dim3(gb), dim3(tb), 0, s, n, J->nnz, J->ptr, J->idx, prep);
+    SPAI_HIP(hipGetLastError());
+    SPAI_HIP(hipMemcpyAsync(hp, prep, sizeof(PrepOut), hipMemcpyDeviceToHost, s));
+    SPAI_HIP(hipStreamSynchronize(s));
+    PrepOut ph;
+    std::memcpy(&ph, hp, sizeof(PrepOut));
+    if (ph.err) {
+        std::string why;
+        if (ph.err & 1) why += " rowptr not monotone/consistent with nnz;";
+        if (ph.err & 2) why += " column index out of range or columns not strictly ascending;";
+        if (ph.err & 4) why += " non-finite value;";
+        if (ph.err & 8) why += " a row holds no nonzero value;";
+        if (ph.err & 16) why += " pattern malformed (range, duplicates or pointers);";
+        set_error("invalid argument:" + why);
+        return fail(SPAI_E_ARG);
+    }
+    const int pinit = J ? ph.max_pat : 1;
+    if (pinit > 63) {
+        set_error("invalid argument: an initial pattern column holds more than 63 indices");
+        return fail(SPAI_E_ARG);
+    }
+    const int pmax = std::max(p->maxfill, pinit);
+    const int stride = pmax;
+    P->stride = stride;
+
+    // CSC structure of A (rows of B) and ||B(:, j)||^2
+    if ((rc = scan_ints(n, cnt, cp, blk, tot, s))) return fail(rc);
+    SPAI_HIP(hipMemcpyAsync(cur, cp, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_fill_csc, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->col, cur, ri);
+    switch (p->u_f) {
+    case SPAI_FP64: hipLaunchKernelGGL(k_colnorm<SPAI_FP64>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (double*)bn); break;
+    case SPAI_FP32: hipLaunchKernelGGL(k_colnorm<SPAI_FP32>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (float*)bn); break;
+    case SPAI_FP16: hipLaunchKernelGGL(k_colnorm<SPAI_FP16>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (float*)bn); break;
+    default: hipLaunchKernelGGL(k_colnorm<SPAI_BF16>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (float*)bn); break;
+    }
+    SPAI_HIP(hipGetLastError());
+
+    // per-column outputs
+    if ((rc = dev_alloc(&P->j_ins, (size_t)n * stride))) return fail(rc);
+    if ((rc = dev_alloc(&P->m_ins, (size_t)n * stride))) return fail(rc);
+    if ((rc = dev_alloc(&P->len, n))) return fail(rc);
+    if ((rc = dev_alloc(&P->steps, n))) return fail(rc);
+    if ((rc = dev_alloc(&P->res, n))) return fail(rc);
+    if ((rc = dev_alloc(&P->flags, n))) return fail(rc);
+
+    ColArgs a{};
+    a.n = n; a.rp = A->rowptr; a.ci = A->col; a.av = A->val; a.cp = cp; a.ri = ri; a.d = P->d;
+    a.bnrm2 = bn;
+    a.pat_ptr = J ? J->ptr : nullptr;
+    a.pat_idx = J ? J->idx : nullptr;
+    a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.maxfill = p->maxfill;
+    a.cols = nullptr; a.ncols = n; a.stride = stride;
+    a.len = P->len; a.jout = P->j_ins; a.mout = P->m_ins; a.steps = P->steps; a.res = P->res;
+    a.flags = P->flags; a.nI = nI; a.defer_list = dl; a.defer_count = dc;
+    int cols_deferred = 0;
+    int* hcount = (int*)(hp + 256);
+    switch (p->u_f) {
+    case SPAI_FP64: rc = run_columns<SPAI_FP64>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    case SPAI_FP32: rc = run_columns<SPAI_FP32>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    case SPAI_FP16: rc = run_columns<SPAI_FP16>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    default: rc = run_columns<SPAI_BF16>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    }
+    if (rc) return fail(rc);
+
+    // compaction into CSR(P)
+    if ((rc = dev_alloc(&P->rowptr, (size_t)n + 1))) return fail(rc);
+    if ((rc = scan_ints(n, P->len, P->rowptr, blk, tot, s))) return fail(rc);
+    hipLaunchKernelGGL(k_build_stats, dim3(gb), dim3(tb), 0, s, n, P->len, P->steps, P->res, P->flags, nI, bst);
+    SPAI_HIP(hipMemcpyAsync(hp, tot, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPAI_HIP(hipMemcpyAsync(hp + 64, bst, sizeof(BuildStatsDev), hipMemcpyDeviceToHost, s));
+    SPAI_HIP(hipStreamSynchronize(s));
+    int total = *(int*)hp;
+    BuildStatsDev bs;
+    std::memcpy(&bs, hp + 64, sizeof(bs));
+    P->nnz = total;
+    if ((rc = dev_alloc(&P->col, (size_t)total))) return fail(rc);
+    {
+        void* v = nullptr;
+        hipError_t e = hipMalloc(&v, val_size(p->u_f) * (size_t)std::max(total, 1));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("device allocation failed for P values");
+            return fail(SPAI_E_OOM);
+        }
+        P->val = v;
+    }
+    long long work = (long long)n * stride;
+    int cg = (int)((work + 255) / 256);
+    switch (p->u_f) {
+    case SPAI_FP64: hipLaunchKernelGGL(k_compact<SPAI_FP64>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (double*)P->val); break;
+    case SPAI_FP32: hipLaunchKernelGGL(k_compact<SPAI_FP32>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (float*)P->val); break;
+    case SPAI_FP16: hipLaunchKernelGGL(k_compact<SPAI_FP16>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (__half*)P->val); break;
+    default: hipLaunchKernelGGL(k_compact<SPAI_BF16>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (__hip_bfloat16*)P->val); break;
+    }
+    SPAI_HIP(hipGetLastError());
+    SPAI_HIP(hipStreamSynchronize(s));
+
+    int warn = 0;
+    if (bs.over_eps) warn |= SPAI_W_EPS;
+    if (bs.rankdef) warn |= SPAI_W_RANKDEF;
+    if (bs.nonfinite) warn |= SPAI_W_NONFINITE;
+    if (st) {
+        st->nnz = total;
+        st->max_len = bs.max_len;
+        st->max_steps = bs.max_steps;
+        st->max_shadow = bs.max_shadow;
+        st->cols_over_eps = bs.over_eps;
+        st->cols_rankdef = bs.rankdef;
+        st->cols_nonfinite = bs.nonfinite;
+        st->cols_deferred = cols_deferred;
+        double mr;
+        std::memcpy(&mr, &bs.max_res_bits, sizeof(double));
+        st->max_res = mr;
+    }
+    *P_out = P;
+    return warn;
+}
+
+int precond_import_impl(spai_handle* h, int32_t n, int64_t nnz, const int32_t* rowptr,
+                        const int32_t* col, const double* val, spai_prec vp, const double* d,
+                        spai_precond** P_out);
+
+}  // namespace spai
+
+// ---------------------------------------------------------------------------
+// C ABI: build and preconditioner objects
+// ---------------------------------------------------------------------------
+
+template <int VP>
+__global__ void k_convert_vals(long long nnz, const double* __restrict__ in, typename spai::ValType<VP>::T* out) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    double v = in[t];
+    if constexpr (VP == SPAI_FP64) out[t] = v;
+    else if constexpr (VP == SPAI_FP32) out[t] = (float)v;
+    else if constexpr (VP == SPAI_FP16) out[t] = __float2half_rn((float)v);
+    else out[t] = typename spai::ValType<VP>::T((float)v);
+}
+
+int spai::precond_import_impl(spai_handle* h, int32_t n, int64_t nnz, const int32_t* rowptr,
+                              const int32_t* col, const double* val, spai_prec vp, const double* d,
+                              spai_precond** P_out) {
+    SPAI_ARG(h && P_out && rowptr && col && val && d, "NULL argument");
+    SPAI_ARG(n > 0 && nnz >= 0 && nnz < (1ll << 31), "bad sizes");
+    SPAI_ARG(vp == SPAI_FP64 || vp == SPAI_FP32 || vp == SPAI_FP16 || vp == SPAI_BF16, "bad value format");
+    *P_out = nullptr;
+    SPAI_HIP(hipSetDevice(h->device));
+    hipStream_t s = h->stream;
+    spai_precond* P = new spai_precond();
+    P->n = n;
+    P->nnz = nnz;
+    P->val_prec = vp;
+    auto fail = [&](int code) { precond_free(P); return code; };
+    int rc;
+    if ((rc = dev_alloc(&P->rowptr, (size_t)n + 1))) return fail(rc);
+    if ((rc = dev_alloc(&P->col, (size_t)nnz))) return fail(rc);
+    if ((rc = dev_alloc(&P->d, (size_t)n))) return fail(rc);
+    {
+        void* v = nullptr;
+        if (hipMalloc(&v, val_size(vp) * (size_t)std::max<int64_t>(nnz, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("device allocation failed for P values");
+            return fail(SPAI_E_OOM);
+        }
+        P->val = v;
+    }
+    SPAI_HIP(hipMemcpyAsync(P->rowptr, rowptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+    SPAI_HIP(hipMemcpyAsync(P->col, col, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    SPAI_HIP(hipMemcpyAsync(P->d, d, 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
+    int g = (int)((nnz + 255) / 256);
+    if (g < 1) g = 1;
+    switch (vp) {
+    case SPAI_FP64: hipLaunchKernelGGL(k_convert_vals<SPAI_FP64>, dim3(g), dim3(256), 0, s, (long long)nnz, val, (double*)P->val); break;
+    case SPAI_FP32: hipLaunchKernelGGL(k_convert_vals<SPAI_FP32>, dim3(g), dim3(256), 0, s, (long long)nnz, val, (float*)P->val); break;
+    case SPAI_FP16: hipLaunchKernelGGL(k_convert_vals<SPAI_FP16>, dim3(g), dim3(256), 0, s, (long long)nnz, val, (__half*)P->val); break;
+    default: hipLaunchKernelGGL(k_convert_vals<SPAI_BF16>, dim3(g), dim3(256), 0, s, (long long)nnz, val, (__hip_bfloat16*)P->val); break;
+    }
+    SPAI_HIP(hipGetLastError());
+    SPAI_HIP(hipStreamSynchronize(s));
+    *P_out = P;
+    return SPAI_OK;
+}
+
+extern "C" int spai_build(spai_handle* h, const spai_csr* A, const spai_pattern* J,
+                          const spai_build_params* p, spai_precond** P, spai_build_stats* st) {
+    return spai::build_impl(h, A, J, p, P, st);
+}
+
+extern "C" int spai_precond_import(spai_handle* h, int32_t n, int64_t nnz, const int32_t* rowptr,
+                                   const int32_t* col, const double* val, spai_prec val_prec,
+                                   const double* d, spai_precond** P) {
+    return spai::precond_import_impl(h, n, nnz, rowptr, col, val, val_prec, d, P);
+}
+
+extern "C" int spai_precond_view_get(const spai_precond* P, spai_precond_view* v) {
+    if (!P || !v) {
+        spai::set_error("invalid argument: NULL preconditioner or view");
+        return SPAI_E_ARG;
+    }
+    v->n = P->n;
+    v->nnz = P->nnz;
+    v->rowptr = P->rowptr;
+    v->col = P->col;
+    v->val = P->val;
+    v->val_prec = P->val_prec;
+    v->d = P->d;
+    v->stride = P->stride;
+    v->j_ins = P->j_ins;
+    v->m_ins = P->m_ins;
+    v->len = P->len;
+    v->steps = P->steps;
+    v->res = P->res;
+    v->flags = P->flags;
+    return SPAI_OK;
+}
+
+extern "C" int spai_precond_destroy(spai_precond* P) {
+    spai::precond_free(P);
+    return SPAI_OK;
+}

@@ -1,0 +1,84 @@
+"""The C-ABI library loads, exports every symbol include/spai.h declares, and
+rejects bad host-side arguments before touching the device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spai.h")
+LIB = os.path.join(ROOT, "paper_2202_10204_amd", "libspai.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(spai_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2202_10204_amd import build
+
+        build.build()
+    import paper_2202_10204_amd as S   # loads through the binding (torch first)
+
+    return S.lib()
+
+
+def test_header_declares_the_paper_calls():
+    names = _declared()
+    for required in ("spai_build", "spai_gmres_ir", "spai_create", "spai_destroy", "spai_last_error",
+                     "spai_precond_destroy", "spai_precond_view_get"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_null_arguments_are_rejected_without_a_device(lib):
+    import paper_2202_10204_amd as S
+
+    L = lib
+    assert L.spai_build(None, None, None, None, None, None) == S.E_ARG
+    assert "invalid argument" in S.last_error()
+    assert L.spai_gmres_ir(None, None, None, None, None, None, None) == S.E_ARG
+    assert L.spai_set_stream(None, None) == S.E_ARG
+    assert L.spai_precond_view_get(None, None) == S.E_ARG
+    assert L.spai_destroy(None) == S.OK
+    assert L.spai_precond_destroy(None) == S.OK
+
+
+def test_bad_parameters_are_rejected_before_any_device_work(lib):
+    """spai_build validates the host-side parameters first: a fake handle that
+    would fault if dereferenced by device code is never used."""
+    import paper_2202_10204_amd as S
+
+    L = lib
+    fake_handle = ctypes.c_void_p(1)
+    A = S._Csr(0, 0, None, None, None)
+    prm = S._BuildParams(0.3, 1, 8, 20, S.FP32)
+    out = ctypes.c_void_p()
+    assert L.spai_build(fake_handle, ctypes.byref(A), None, ctypes.byref(prm), ctypes.byref(out), None) == S.E_ARG
+    assert "n must be positive" in S.last_error()
+    A = S._Csr(4, 4, 8, 8, 8)
+    for bad in (S._BuildParams(0.0, 1, 8, 20, S.FP32), S._BuildParams(0.3, -1, 8, 20, S.FP32),
+                S._BuildParams(0.3, 1, 8, 0, S.FP32), S._BuildParams(0.3, 1, 8, 64, S.FP32),
+                S._BuildParams(0.3, 1, 8, 20, 7)):
+        assert L.spai_build(fake_handle, ctypes.byref(A), None, ctypes.byref(bad), ctypes.byref(out), None) == S.E_ARG
+    assert out.value is None
+
+
+def test_binding_refuses_to_run_without_a_gpu():
+    import torch
+
+    import paper_2202_10204_amd as S
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(S.SpaiError):
+        S.Handle()

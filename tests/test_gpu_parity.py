@@ -1,0 +1,380 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+The build follows the same rounding model as the oracle (one precision F,
+sequential sums in a fixed index order with fused multiply-adds, rounding to
+u_f at the storage points), so for every u_f the sparsity patterns, the
+insertion order, the step counts and the values of every column are compared
+for exact equality.  The solve is compared by its GMRES iteration tuple
+(exact), its forward error against the exactly known solution (<= 1e-12) and
+its distance to the oracle's solution.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2202_10204_amd as S
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return S
+
+
+@pytest.fixture(scope="module")
+def h(S):
+    return S.Handle()
+
+
+def _dev(a, dtype=None):
+    return torch.as_tensor(np.asarray(a) if dtype is None else np.asarray(a, dtype), device="cuda")
+
+
+def _build(S, h, w, uf=None, eps=None):
+    s = w.spai
+    A = S.DeviceCSR.from_host(w.A)
+    pat = S.DevicePattern.from_host(w.pattern) if w.pattern is not None else None
+    P, warn, stats = h.spai_build(A, pat, s.eps if eps is None else eps, s.alpha, s.beta, s.maxfill,
+                                  uf or s.u_f)
+    return A, P, warn, stats
+
+
+def _abar(A, d, k, J):
+    """B(I, J) in FP64 for the shadow I of J (B = A^T D)."""
+    I = sorted({int(i) for j in J for i in A.col[A.rowptr[j]:A.rowptr[j + 1]]})
+    pos = {i: t for t, i in enumerate(I)}
+    Ab = np.zeros((len(I), len(J)))
+    for c, j in enumerate(J):
+        for t in range(A.rowptr[j], A.rowptr[j + 1]):
+            Ab[pos[int(A.col[t])], c] = d[j] * A.val[t]
+    return Ab
+
+
+def _compare_columns(P, ref, what):
+    cols = P.columns()
+    L = cols["len"].cpu().numpy()
+    J = cols["J"].cpu().numpy()
+    M = cols["m"].cpu().numpy()
+    steps = cols["steps"].cpu().numpy()
+    res = cols["res"].cpu().numpy()
+    bad = []
+    for t, k in enumerate(ref.cols):
+        Lk = ref.length[t]
+        if (L[k] != Lk or steps[k] != ref.steps[t] or not np.array_equal(J[k, :Lk], ref.J[t, :Lk])
+                or not np.array_equal(M[k, :Lk], ref.m[t, :Lk]) or res[k] != ref.res[t]):
+            bad.append(int(k))
+    assert not bad, f"{what}: {len(bad)} of {len(ref.cols)} columns differ, first {bad[:8]}"
+    return cols
+
+
+# ---------------------------------------------------------------------------
+# building blocks of Algorithm 3
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("make", [W.convdiff_small, lambda: W.convdiff_adaptive(40), lambda: W.aniso_fixed(9),
+                                  lambda: W.random_system(777, 2)])
+def test_residual_double_double(S, h, make):
+    """r = b - A x in double-double vs the exactly rounded residual: within one
+    ulp of r plus u^2 (|b| + |A||x|)."""
+    w = make()
+    rng = np.random.default_rng(1)
+    A = S.DeviceCSR.from_host(w.A)
+    for x in (w.x_true, w.x_true + 1e-9 * rng.standard_normal(w.n), rng.standard_normal(w.n)):
+        r = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+        h.residual(A, _dev(w.b), _dev(x), r, "dd")
+        ref = O.residual(w.A, w.b, x)
+        absAx = abs(w.A.to_scipy()) @ np.abs(x) + np.abs(w.b)
+        err = np.abs(r.cpu().numpy() - ref)
+        assert np.all(err <= np.spacing(np.abs(ref)) + 4 * 2.0 ** -106 * absAx)
+        if x is w.x_true:
+            assert np.all(r.cpu().numpy() == 0.0)
+
+
+def test_spmv(S, h):
+    w = W.convdiff_adaptive(33)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(w.n)
+    y = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    h.spmv(S.DeviceCSR.from_host(w.A), _dev(x), y)
+    ref = w.A.to_scipy() @ x
+    assert np.allclose(y.cpu().numpy(), ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1: bit-exact against the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("uf", ["fp32", "fp64"])
+def test_fixed_pattern_convdiff_small(S, h, uf):
+    w = W.convdiff_small(32)
+    A, P, warn, stats = _build(S, h, w, uf=uf)
+    s = w.spai
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    cols = _compare_columns(P, ref, f"convdiff 32x32 pattern(A) {uf}")
+    assert stats["nnz"] == w.A.nnz == 4992
+    # values against the least-squares definition (FP64): the 1e-5 bar for FP32
+    rng = np.random.default_rng(3)
+    for k in rng.choice(w.n, 64, replace=False):
+        Lk = ref.length[k]
+        mbar, _ = O.ls_column(w.A, ref.d, int(k), ref.J[k, :Lk])
+        got = cols["m"][int(k), :Lk].cpu().numpy()
+        assert np.abs(got - mbar).max() <= (1e-5 if uf == "fp32" else 1e-13) * np.abs(mbar).max()
+
+
+@pytest.mark.parametrize("uf", ["fp16", "bf16", "fp32"])
+def test_fixed_pattern_aniso_low_precision(S, h, uf):
+    """pattern(A^2) (25 entries per interior column) with FP16/BF16 storage and
+    FP32 arithmetic: identical to the oracle's storage-rounding model, and within
+    2e-2 of the FP64 least-squares values (the FP16/BF16 bar)."""
+    w = W.aniso_fixed(10, u_f=uf)
+    A, P, warn, stats = _build(S, h, w, uf=uf)
+    s = w.spai
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    cols = _compare_columns(P, ref, f"aniso 10^3 pattern(A^2) {uf}")
+    tol = {"fp16": 2e-2, "bf16": 2e-2, "fp32": 1e-5}[uf]
+    u = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "fp32": 2.0 ** -24}[uf]
+    rng = np.random.default_rng(4)
+    for k in rng.choice(w.n, 64, replace=False):
+        Lk = ref.length[k]
+        J = ref.J[k, :Lk]
+        mbar, res = O.ls_column(w.A, ref.d, int(k), J)
+        Ab = _abar(w.A, ref.d, int(k), J)
+        kap = np.linalg.cond(Ab)
+        # least-squares perturbation bound (Higham, Thm 20.1) for relative data errors u
+        bound = kap * u + kap ** 2 * u * res / (np.linalg.norm(Ab, 2) * np.linalg.norm(mbar))
+        got = cols["m"][int(k), :Lk].cpu().numpy()
+        err = np.linalg.norm(got - mbar) / np.linalg.norm(mbar)
+        assert err <= max(tol, 4 * bound), (k, err, kap)
+    assert stats["max_len"] == 25
+
+
+@pytest.mark.parametrize("N,uf", [(40, "fp32"), (64, "fp32"), (48, "fp64")])
+def test_adaptive_convdiff(S, h, N, uf):
+    """Identity start, eps = 0.3, beta = 8, at most 20 entries per column: the
+    chosen indices (in insertion order), the step counts and the values agree
+    exactly with the oracle for every column."""
+    w = W.convdiff_adaptive(N, u_f=uf)
+    A, P, warn, stats = _build(S, h, w)
+    s = w.spai
+    ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    _compare_columns(P, ref, f"convdiff {N}x{N} adaptive {uf}")
+    assert stats["cols_over_eps"] == int(((ref.flags & O.FLAG_EPS) != 0).sum())
+    assert stats["max_steps"] == ref.steps.max()
+
+
+def test_adaptive_random_banded_and_deferred_columns(S, h):
+    """Random banded rows (up to 12 entries) grow shadows beyond the fast
+    kernel's capacity for some columns: those are deferred to the large kernel
+    and must still agree exactly."""
+    w = W.random_system(3000, 5)
+    A, P, warn, stats = _build(S, h, w)
+    s = w.spai
+    ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    _compare_columns(P, ref, "random banded n=3000 adaptive fp32")
+
+
+def test_closed_forms_on_device(S, h):
+    """Diagonal matrix -> P = diag(fl(1/a_kk)); permutation -> P A = I."""
+    rng = np.random.default_rng(5)
+    n = 300
+    diag = rng.uniform(0.1, 50.0, n) * np.where(rng.random(n) < 0.5, -1, 1)
+    Ad = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), diag)
+    P, warn, st = h.spai_build(S.DeviceCSR.from_host(Ad), None, 0.1, 5, 8, 8, "fp32")
+    rowptr, col, val, d = (t.cpu().numpy() for t in P.csr())
+    assert np.array_equal(col, np.arange(n)) and np.array_equal(val.astype(np.float64) * d, 1.0 / diag)
+    perm = np.arange(n)
+    perm[7:] = 7 + rng.permutation(n - 7)
+    Ap = W.CSR(n, np.arange(n + 1, dtype=np.int32), perm.astype(np.int32), np.ones(n))
+    P, warn, st = h.spai_build(S.DeviceCSR.from_host(Ap), None, 0.2, 40, 8, 10, "fp32")
+    rowptr, col, val, d = (t.cpu().numpy() for t in P.csr())
+    import scipy.sparse as sp
+
+    PM = sp.csr_matrix((val.astype(np.float64) * d[col], col, rowptr), shape=(n, n))
+    assert np.array_equal((PM @ Ap.to_scipy()).toarray(), np.eye(n))
+    assert st["max_steps"] == 1
+
+
+def test_build_is_deterministic(S, h):
+    w = W.convdiff_adaptive(40)
+    _, P1, _, _ = _build(S, h, w)
+    _, P2, _, _ = _build(S, h, w)
+    for a, b in zip(P1.csr(), P2.csr()):
+        assert torch.equal(a, b)
+
+
+def test_malformed_matrix_is_rejected(S, h):
+    w = W.convdiff_small(8)
+    col = w.A.col.copy()
+    col[3], col[4] = col[4], col[3]          # unsorted row
+    bad = W.CSR(w.n, w.A.rowptr, col, w.A.val)
+    with pytest.raises(S.SpaiError, match="ascending"):
+        h.spai_build(S.DeviceCSR.from_host(bad), None, 0.3, 2, 8, 20, "fp32")
+    val = w.A.val.copy()
+    val[w.A.rowptr[5]:w.A.rowptr[6]] = 0.0   # all-zero row
+    with pytest.raises(S.SpaiError, match="no nonzero"):
+        h.spai_build(S.DeviceCSR.from_host(W.CSR(w.n, w.A.rowptr, w.A.col, val)), None, 0.3, 2, 8, 20, "fp32")
+
+
+# ---------------------------------------------------------------------------
+# preconditioner application
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("uf", ["fp32", "fp16", "fp64"])
+def test_x0_and_apply(S, h, uf):
+    w = W.aniso_fixed(8, u_f=uf) if uf == "fp16" else W.convdiff_adaptive(36, u_f=uf)
+    A, P, warn, stats = _build(S, h, w, uf=uf)
+    s = w.spai
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    pp, pc, pv = ref.P_csr(w.n)
+    x0 = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    h.precond_apply_uf(P, _dev(w.b), x0)
+    assert np.array_equal(x0.cpu().numpy(), O.x0(pp, pc, pv, ref.d, w.b, uf))
+    rng = np.random.default_rng(6)
+    wv = rng.standard_normal(w.n)
+    y = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    h.precond_apply(P, _dev(wv), y)
+    yr = O.apply_P(pp, pc, pv, ref.d, wv)
+    assert np.allclose(y.cpu().numpy(), yr, rtol=1e-13, atol=1e-13 * np.abs(yr).max())
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3
+# ---------------------------------------------------------------------------
+
+def _solve(S, h, w, A, P, u_r="dd"):
+    ir = w.ir
+    b = _dev(w.b)
+    x = torch.zeros_like(b)
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r)
+    return x.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("make", [W.convdiff_small, lambda: W.convdiff_adaptive(48), lambda: W.aniso_fixed(10, "fp32")])
+def test_gmres_ir_matches_oracle(S, h, make):
+    """Same P (built on the GPU, bit-identical to the oracle's): identical GMRES
+    iteration tuple, forward error <= 1e-12, x close to the oracle's x."""
+    w = make()
+    A, P, warn, stats = _build(S, h, w)
+    s, ir = w.spai, w.ir
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+    x, st = _solve(S, h, w, A, P)
+    assert st["its"] == oref.its
+    assert O.ferr(x, w.x_true) <= 1e-12
+    assert O.ferr(oref.x, w.x_true) <= 1e-12
+    assert np.abs(x - oref.x).max() <= 1e-12 * np.abs(w.x_true).max()
+    assert O.nbe(w.A, w.b, x) <= 1e-15
+
+
+def test_gmres_ir_with_imported_oracle_preconditioner(S, h):
+    """P produced by the oracle and imported (CSR of M^T + D): same tuple."""
+    w = W.convdiff_adaptive(40)
+    s, ir = w.spai, w.ir
+    ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    P = h.precond_import(w.n, _dev(pp, np.int32), _dev(pc, np.int32), _dev(pv, np.float64), "fp32", _dev(ref.d))
+    A = S.DeviceCSR.from_host(w.A)
+    x, st = _solve(S, h, w, A, P)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+    assert st["its"] == oref.its
+    assert O.ferr(x, w.x_true) <= 1e-12
+
+
+def test_fp64_residual_plateaus_and_dd_does_not(S, h):
+    """u_r = FP64 stalls near u cond(A, x) while u_r = DD reaches ~u (Theorem 1)."""
+    w = W.aniso_fixed(12, "fp32")
+    A, P, warn, stats = _build(S, h, w)
+    xd, std = _solve(S, h, w, A, P, "dd")
+    xf, stf = _solve(S, h, w, A, P, "fp64")
+    assert O.ferr(xd, w.x_true) <= 1e-13
+    assert O.ferr(xd, w.x_true) <= O.ferr(xf, w.x_true)
+
+
+def test_solve_is_deterministic(S, h):
+    w = W.convdiff_adaptive(40)
+    A, P, _, _ = _build(S, h, w)
+    x1, s1 = _solve(S, h, w, A, P)
+    x2, s2 = _solve(S, h, w, A, P)
+    assert np.array_equal(x1, x2) and s1["its"] == s2["its"]
+
+
+# ---------------------------------------------------------------------------
+# the benchmark workload at full size (512 x 512, n = 262144)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def full(S, h):
+    w = W.convdiff_adaptive(512)
+    A, P, warn, stats = _build(S, h, w)
+    return w, A, P, stats
+
+
+def _golden512():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "convdiff512_oracle.json")
+    return json.load(open(path))
+
+
+def test_full_size_build_matches_oracle_digests(S, h, full):
+    """All 262,144 columns: the digests of the insertion-ordered indices, the
+    values and the step counts equal those of the oracle's full build (stored
+    by tests/golden/make_convdiff512_golden.py, which calls only the oracle)."""
+    import hashlib
+
+    w, A, P, stats = full
+    g = _golden512()
+    cols = P.columns()
+    assert cols["stride"] == g["stride"]
+    dig = lambda t: hashlib.sha256(np.ascontiguousarray(t.cpu().numpy()).tobytes()).hexdigest()
+    assert dig(cols["J"]) == g["sha256_J_insertion_order"]
+    assert dig(cols["steps"]) == g["sha256_steps"]
+    assert dig(cols["m"]) == g["sha256_m_insertion_order"]
+    assert stats["nnz"] == g["nnz_P"] and stats["max_steps"] == g["max_steps"]
+
+
+def test_full_size_sampled_columns(S, h, full):
+    """2048 sampled columns (and the first/last 64) recomputed one by one by the
+    oracle agree exactly with the GPU build."""
+    w, A, P, stats = full
+    s = w.spai
+    rng = np.random.default_rng(7)
+    sample = np.unique(np.concatenate([rng.choice(w.n, 2048, replace=False), np.arange(64),
+                                       np.arange(w.n - 64, w.n)])).astype(np.int32)
+    ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f, cols=sample, nthreads=8)
+    _compare_columns(P, ref, "convdiff 512x512 adaptive fp32 (sample)")
+    assert stats["cols_over_eps"] == 0
+
+
+def test_full_size_solve_matches_oracle_tuple(S, h, full):
+    """Same GMRES iteration tuple as the oracle's full solve, forward error
+    <= 1e-12 against the exact solution."""
+    w, A, P, stats = full
+    x, st = _solve(S, h, w, A, P)
+    g = _golden512()
+    assert st["its"] == g["its"]
+    assert O.ferr(x, w.x_true) <= 1e-12
+    assert O.nbe(w.A, w.b, x) <= 1e-15
+
+
+def test_projection_fallback_path_agrees(S, h, monkeypatch):
+    """The one-launch-per-projection path (used when a cooperative launch cannot
+    hold the problem) gives the same iteration tuple and solution accuracy."""
+    w = W.convdiff_adaptive(48)
+    A, P, _, _ = _build(S, h, w)
+    x1, s1 = _solve(S, h, w, A, P)
+    monkeypatch.setenv("SPAI_ARNOLDI_PATH", "projection")
+    x2, s2 = _solve(S, h, w, A, P)
+    assert s1["its"] == s2["its"]
+    assert O.ferr(x2, w.x_true) <= 1e-12
+    assert np.abs(x1 - x2).max() <= 1e-13 * np.abs(w.x_true).max()

@@ -349,7 +349,7 @@ class Workload:
         return self.A.n
 
 
-TOL_IR = 2.0 ** -50
+TOL_IR = 2.0 ** -45   # refinement stops once ||d||_inf <= 2^-45 ||x||_inf (about 256 u)
 
 
 def _convdiff_pbits(N: int, peclet: float, sbits: int) -> int:

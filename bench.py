@@ -54,6 +54,27 @@ def arnoldi_bytes_per_solve(its, n):
     return total, launches
 
 
+def profiled_traffic(kernel_file, sources):
+    """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    or None when the summary is missing or the kernel sources changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    hsh = hashlib.sha256()
+    for src in sources:
+        hsh.update(open(os.path.join(ROOT, src), "rb").read())
+    if kv.get("source_sha256") != hsh.hexdigest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=()):
     """Build + solve `steps` times after `warmup` untimed steps; per-step times in ms."""
     import torch
@@ -136,6 +157,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, default=512, help="grid side (512 is the benchmark workload)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="one untimed build + solve of the mixed form and a 256 MiB device copy "
+                         "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE); for profiler runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each system is solved on one "
@@ -156,6 +180,18 @@ def main():
     A = S.DeviceCSR.from_host(w.A)
     b = torch.as_tensor(w.b, device="cuda")
     x = torch.zeros_like(b)
+
+    if args.profile_run:
+        s, ir = w.spai, w.ir
+        P, _, bst = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, "fp32")
+        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd")
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": w.name, "its": st["its"], "nnz_P": bst["nnz"], "copy_bytes": 256 << 20}),
+              flush=True)
+        return
 
     kernels = [("columns", 1), ("mgs", 1), ("spmv_a", 3), ("apply_p", 3), ("residual", 1), ("update", 1)]
     rec, wall, timings = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels)
@@ -209,8 +245,10 @@ def main():
         cnt, ms = timings["mgs"]
         secs = ms * 1e-3 / args.steps
         achieved = tot_bytes / secs / 1e9
+        traffic = profiled_traffic("k_arnoldi_convdiff512_traffic.txt",
+                                   ["paper_2202_10204_amd/csrc/gmres_ir.hip", "paper_2202_10204_amd/csrc/common.hpp"])
         roof = {"bound": "hbm", "kernel": "k_arnoldi", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                 "bytes_per_launch": tot_bytes / real, "avg_launch_us": ms * 1e3 / cnt,
                 "launches_per_step": cnt / args.steps, "real_launches_per_step": real}
     elif per_class[dom]["avg_ms"]:

@@ -159,7 +159,9 @@ __global__ void k_residual(int n, const int* __restrict__ rp, const int* __restr
 // maxit.
 // ---------------------------------------------------------------------------
 
-constexpr int AT = 512;   // threads per block of the Arnoldi kernel
+constexpr int AT_DATA = 512;          // threads that hold y and stream the basis (8 waves)
+constexpr int AT = AT_DATA + 64;      // plus one wave that only publishes and polls
+constexpr int MAX_NB = 256;           // blocks of the Arnoldi kernel (4 slots per poll lane)
 constexpr unsigned long long SENTINEL = 0x7ff4dead5eed0001ull;
 constexpr long long SPIN_LIMIT = 1ll << 20;   // about a second of polling
 
@@ -176,54 +178,82 @@ struct ArnoldiArgs {
     SolveState* st;
 };
 
+// Grid-wide sum of one double per block.  The data waves leave their wave sums
+// in wsum; the poll wave (the last wave of the block, which has no other memory
+// traffic, so its loads never wait behind the basis prefetch of the data waves)
+// adds them in wave order, publishes the block's partial, loads all nb slots
+// (four independent loads per lane), repeats until none is the sentinel, and
+// reduces them in a fixed order, so every block computes the bit-identical
+// total.  Returns the total to every thread of the block.
 __device__ __forceinline__ double grid_sum(double part, unsigned long long* slot_row, int nb, double* wsum,
-                                           double* bcast, int* abort_flag) {
+                                           double* total, int* abort_flag) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-    if (lane == 0) wsum[wave] = part;
+    constexpr int DW = AT_DATA / 64;
+    if (wave < DW) {
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        if (lane == 0) wsum[wave] = part;
+    }
     __syncthreads();
-    if (wave == 0) {
-        if (t == 0) {
+    if (wave == DW) {
+        if (lane == 0) {
             double s = 0.0;
-            for (int w = 0; w < AT / 64; ++w) s += wsum[w];
+            for (int w = 0; w < DW; ++w) s += wsum[w];
             __hip_atomic_store(&slot_row[blockIdx.x], (unsigned long long)__double_as_longlong(s),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        double acc = 0.0;
-        bool timeout = false;
-        for (int q = lane; q < nb; q += 64) {
-            unsigned long long v;
-            long long spins = 0;
-            while ((v = __hip_atomic_load(&slot_row[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == SENTINEL) {
-                if (++spins > SPIN_LIMIT) {
-                    timeout = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            acc += __longlong_as_double((long long)v);
+        unsigned long long v[MAX_NB / 64];
+        bool ready[MAX_NB / 64];
+#pragma unroll
+        for (int k = 0; k < MAX_NB / 64; ++k) {
+            ready[k] = (lane + 64 * k) >= nb;
+            v[k] = 0ull;
         }
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        bool timeout = false;
+        long long spins = 0;
+        while (true) {
+#pragma unroll
+            for (int k = 0; k < MAX_NB / 64; ++k)
+                if (!ready[k])
+                    v[k] = __hip_atomic_load(&slot_row[lane + 64 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < MAX_NB / 64; ++k) {
+                if (!ready[k]) ready[k] = (v[k] != SENTINEL);
+                all = all && ready[k];
+            }
+            if (all) break;
+            if (++spins > SPIN_LIMIT) {
+                timeout = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        double val = 0.0;
+#pragma unroll
+        for (int k = 0; k < MAX_NB / 64; ++k)
+            if (lane + 64 * k < nb) val += __longlong_as_double((long long)v[k]);
+        for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
         uint64_t bad = ballot(timeout);
         if (lane == 0) {
-            *bcast = acc;
+            *total = val;
             if (bad) *abort_flag = 1;
         }
     }
     __syncthreads();
-    return *bcast;
+    return *total;
 }
 
 template <int EPT>
 __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
     extern __shared__ double dyn[];          // block 0: hcol (maxit+2), cs, sn (maxit each)
-    __shared__ double wsum[AT / 64];
-    __shared__ double bcast;
+    __shared__ double wsum[AT_DATA / 64];
+    __shared__ double total;
     __shared__ int abort_flag;
     if (a.st->done) return;                  // uniform: written by an earlier launch
     const int b = blockIdx.x, t = threadIdx.x;
-    const int gstride = a.nb * AT;
-    const int base = b * AT + t;
+    const bool data = t < AT_DATA;
+    const int gstride = a.nb * AT_DATA;
+    const int base = b * AT_DATA + t;
     const int n = a.n, j = a.j;
     unsigned long long* cur = a.slots + (size_t)a.parity * a.maxlinks * a.nb;
     unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * a.maxlinks * a.nb;
@@ -243,8 +273,9 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         int i = base + e * gstride;
-        y[e] = i < n ? a.y[i] : 0.0;
-        v[e] = i < n ? a.V[i] : 0.0;
+        bool ok = data && i < n;
+        y[e] = ok ? a.y[i] : 0.0;
+        v[e] = ok ? a.V[i] : 0.0;
         vn[e] = 0.0;
     }
     __syncthreads();
@@ -255,13 +286,13 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 int i = base + e * gstride;
-                vn[e] = i < n ? vnext[i] : 0.0;
+                vn[e] = (data && i < n) ? vnext[i] : 0.0;
             }
         }
         double part = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], v[e], part);
-        double h = grid_sum(part, cur + (size_t)l * a.nb, a.nb, wsum, &bcast, &abort_flag);
+        double h = grid_sum(part, cur + (size_t)l * a.nb, a.nb, wsum, &total, &abort_flag);
         if (abort_flag) break;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -276,7 +307,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
         double part = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], y[e], part);
-        hn = __builtin_sqrt(grid_sum(part, cur + (size_t)(j + 1) * a.nb, a.nb, wsum, &bcast, &abort_flag));
+        hn = __builtin_sqrt(grid_sum(part, cur + (size_t)(j + 1) * a.nb, a.nb, wsum, &total, &abort_flag));
     }
     if (abort_flag) {
         if (t == 0) {
@@ -289,7 +320,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         int i = base + e * gstride;
-        if (i < n) vout[i] = y[e] / hn;
+        if (data && i < n) vout[i] = y[e] / hn;
     }
     if (b == 0 && t == 0) {
         double* hh = hcol;
@@ -579,9 +610,13 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit) {
     }
     c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
     if (c.shmem > 48 * 1024) return ArnoldiCfg{};
-    int nb = std::min(h->num_cu, std::max(1, blocks_for(n, AT)));
+    int nb = std::min(std::min(h->num_cu, MAX_NB), std::max(1, blocks_for(n, AT_DATA)));
+    if (const char* e = getenv("SPAI_ARNOLDI_BLOCKS")) {
+        int want = atoi(e);
+        if (want >= 1 && want <= MAX_NB) nb = std::min(want, std::max(1, blocks_for(n, AT_DATA)));
+    }
     int ept = 1;
-    while ((long long)nb * AT * ept < n) ept <<= 1;
+    while ((long long)nb * AT_DATA * ept < n) ept <<= 1;
     if (ept > 16) return ArnoldiCfg{};
     int cap = 0;
     switch (ept) {

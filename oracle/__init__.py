@@ -66,7 +66,7 @@ def _lib():
                                         P, P]
         L.oracle_gmres_ir.restype = i32
         L.oracle_gmres_ir.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64,
-                                      P, P, P, P]
+                                      i32, P, P, P, P]
         L.oracle_residual.restype = None
         L.oracle_residual.argtypes = [i32, P, P, P, P, P, P]
         L.oracle_exact_sum.restype = f64
@@ -275,9 +275,15 @@ class IrResult:
         return f"{self.total}({', '.join(str(i) for i in self.its)})"
 
 
+ORTHO = {"mgs": 0, "cgs2": 1}
+
+
 def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, maxit: int,
-             tol_ir: float) -> IrResult:
-    """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D."""
+             tol_ir: float, ortho: str = "mgs") -> IrResult:
+    """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D.
+
+    ``ortho`` = "mgs" (modified Gram-Schmidt, the variant analysed in Section
+    3.2) or "cgs2" (classical Gram-Schmidt applied twice)."""
     n = A.n
     x = np.zeros(n)
     its = np.zeros(imax, np.int32)
@@ -289,7 +295,7 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     dd, bb = _f64(d), _f64(b)
     st = _lib().oracle_gmres_ir(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
                                 _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
-                                _p(its), _p(nsteps), _p(gest), _p(dn))
+                                ORTHO[ortho], _p(its), _p(nsteps), _p(gest), _p(dn))
     if st < 0:
         raise ValueError("oracle_gmres_ir: bad argument")
     s = int(nsteps[0])

@@ -703,7 +703,9 @@ void oracle_x0(int n, const int* pp, const int* pc, const double* pv, const doub
 #define IR_STAGNATED 4   /* correction stopped decreasing */
 
 /*
- * SPAI-GMRES-IR.  A: CSR FP64.  P = M^T D: CSR rows pp/pc with u_f values pv (held
+ * SPAI-GMRES-IR.  A: CSR FP64.  ortho selects the orthogonalisation of the Arnoldi
+ * vectors: 0 = modified Gram-Schmidt (the variant of the analysis in Section 3.2),
+ * 1 = classical Gram-Schmidt applied twice (CGS2).  P = M^T D: CSR rows pp/pc with u_f values pv (held
  * in double) and the FP64 scaling d; uf is the precision of the initial solve.
  * x (out) receives the solution.  its[0..imax) receives GMRES iterations per
  * refinement step; *nsteps the number of steps.  Left-preconditioned MGS-GMRES
@@ -718,9 +720,9 @@ void oracle_x0(int n, const int* pp, const int* pc, const double* pv, const doub
  */
 int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const int* pp,
                     const int* pc, const double* pv, const double* d, int uf, const double* b,
-                    double* x, double tau, int imax, int maxit, double tol_ir, int* its,
+                    double* x, double tau, int imax, int maxit, double tol_ir, int ortho, int* its,
                     int* nsteps, double* gest, double* dnorm) {
-    if (n <= 0 || imax < 1 || maxit < 1) return -1;
+    if (n <= 0 || imax < 1 || maxit < 1 || ortho < 0 || ortho > 1) return -1;
     int status = 0;
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
     double* z = (double*)malloc(sizeof(double) * (size_t)n);
@@ -733,6 +735,7 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
     double* sn = (double*)malloc(sizeof(double) * (size_t)maxit);
     double* g = (double*)malloc(sizeof(double) * (size_t)(maxit + 1));
     double* yk = (double*)malloc(sizeof(double) * (size_t)maxit);
+    double* hp = (double*)malloc(sizeof(double) * (size_t)(maxit + 1));
 #define HH(i, j) H[(size_t)(j) * (size_t)(maxit + 1) + (size_t)(i)]
 
     oracle_x0(n, pp, pc, pv, d, b, uf, x);
@@ -756,11 +759,25 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
             double* vj = V + (size_t)j * n;
             spmv(n, rp, ci, av, vj, w);
             apply_P(n, pp, pc, pv, d, w, dw, y);
-            for (int l = 0; l <= j; ++l) {            /* modified Gram-Schmidt */
-                double* vl = V + (size_t)l * n;
-                double h = dot(n, y, vl);
-                HH(l, j) = h;
-                for (int i = 0; i < n; ++i) y[i] -= h * vl[i];
+            if (ortho == 0) {
+                for (int l = 0; l <= j; ++l) {        /* modified Gram-Schmidt */
+                    double* vl = V + (size_t)l * n;
+                    double h = dot(n, y, vl);
+                    HH(l, j) = h;
+                    for (int i = 0; i < n; ++i) y[i] -= h * vl[i];
+                }
+            } else {
+                /* classical Gram-Schmidt applied twice: h = V^T y, y -= V h,
+                 * h2 = V^T y, y -= V h2, H(:, j) = h + h2 */
+                for (int l = 0; l <= j; ++l) HH(l, j) = 0.0;
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int l = 0; l <= j; ++l) hp[l] = dot(n, y, V + (size_t)l * n);
+                    for (int l = 0; l <= j; ++l) {
+                        double* vl = V + (size_t)l * n;
+                        for (int i = 0; i < n; ++i) y[i] -= hp[l] * vl[i];
+                        HH(l, j) += hp[l];
+                    }
+                }
             }
             double hn = sqrt(dot(n, y, y));
             HH(j + 1, j) = hn;
@@ -807,7 +824,7 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
     }
 #undef HH
     free(r); free(z); free(w); free(y); free(dw); free(V); free(H); free(cs); free(sn);
-    free(g); free(yk);
+    free(g); free(yk); free(hp);
     return status;
 }
 

@@ -178,15 +178,28 @@ struct ArnoldiArgs {
     SolveState* st;
 };
 
-// Grid-wide sum of one double per block.  The data waves leave their wave sums
-// in wsum; the poll wave (the last wave of the block, which has no other memory
-// traffic, so its loads never wait behind the basis prefetch of the data waves)
-// adds them in wave order, publishes the block's partial, loads all nb slots
-// (four independent loads per lane), repeats until none is the sentinel, and
-// reduces them in a fixed order, so every block computes the bit-identical
-// total.  Returns the total to every thread of the block.
-__device__ __forceinline__ double grid_sum(double part, unsigned long long* slot_row, int nb, double* wsum,
-                                           double* total, int* abort_flag) {
+// Grid-wide sum of one double per block, in two hops that keep every polled
+// word lightly shared: the poll wave of each block (the last wave, which has no
+// other memory traffic, so its loads never queue behind the basis prefetch)
+// publishes the block's partial into its write-once slot of the link; the
+// reducer block (the last block) loads all nb slots (four independent loads per
+// lane, repeated until none is the sentinel), adds them in a fixed order and
+// writes the total into one mailbox per block (each on its own 64-byte line);
+// every block then polls only its own mailbox.  All blocks obtain the
+// bit-identical total.  Returns the total to every thread of the block.
+constexpr int MBOX_STRIDE = 8;   // 64-bit words between mailboxes (one cache line)
+
+__device__ __forceinline__ bool poll_word(unsigned long long* p, unsigned long long& v) {
+    long long spins = 0;
+    while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == SENTINEL) {
+        if (++spins > SPIN_LIMIT) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+__device__ __forceinline__ double grid_sum(double part, unsigned long long* slot_row, unsigned long long* mbox,
+                                           size_t mbox_stride, int nb, double* wsum, double* total, int* abort_flag) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     constexpr int DW = AT_DATA / 64;
     if (wave < DW) {
@@ -201,43 +214,54 @@ __device__ __forceinline__ double grid_sum(double part, unsigned long long* slot
             __hip_atomic_store(&slot_row[blockIdx.x], (unsigned long long)__double_as_longlong(s),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        unsigned long long v[MAX_NB / 64];
-        bool ready[MAX_NB / 64];
-#pragma unroll
-        for (int k = 0; k < MAX_NB / 64; ++k) {
-            ready[k] = (lane + 64 * k) >= nb;
-            v[k] = 0ull;
-        }
         bool timeout = false;
-        long long spins = 0;
-        while (true) {
-#pragma unroll
-            for (int k = 0; k < MAX_NB / 64; ++k)
-                if (!ready[k])
-                    v[k] = __hip_atomic_load(&slot_row[lane + 64 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            bool all = true;
+        if ((int)blockIdx.x == nb - 1) {        // the reducer
+            unsigned long long v[MAX_NB / 64];
+            bool ready[MAX_NB / 64];
 #pragma unroll
             for (int k = 0; k < MAX_NB / 64; ++k) {
-                if (!ready[k]) ready[k] = (v[k] != SENTINEL);
-                all = all && ready[k];
+                ready[k] = (lane + 64 * k) >= nb;
+                v[k] = 0ull;
             }
-            if (all) break;
-            if (++spins > SPIN_LIMIT) {
-                timeout = true;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        double val = 0.0;
+            long long spins = 0;
+            while (true) {
 #pragma unroll
-        for (int k = 0; k < MAX_NB / 64; ++k)
-            if (lane + 64 * k < nb) val += __longlong_as_double((long long)v[k]);
-        for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
-        uint64_t bad = ballot(timeout);
-        if (lane == 0) {
-            *total = val;
-            if (bad) *abort_flag = 1;
+                for (int k = 0; k < MAX_NB / 64; ++k)
+                    if (!ready[k])
+                        v[k] = __hip_atomic_load(&slot_row[lane + 64 * k], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                bool all = true;
+#pragma unroll
+                for (int k = 0; k < MAX_NB / 64; ++k) {
+                    if (!ready[k]) ready[k] = (v[k] != SENTINEL);
+                    all = all && ready[k];
+                }
+                if (all) break;
+                if (++spins > SPIN_LIMIT) {
+                    timeout = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            double val = 0.0;
+#pragma unroll
+            for (int k = 0; k < MAX_NB / 64; ++k)
+                if (lane + 64 * k < nb) val += __longlong_as_double((long long)v[k]);
+            for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
+            const unsigned long long bits = timeout ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(val);
+#pragma unroll
+            for (int k = 0; k < MAX_NB / 64; ++k) {
+                int q = lane + 64 * k;
+                if (q < nb) __hip_atomic_store(&mbox[(size_t)q * mbox_stride], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (lane == 0) *total = val;
+        } else if (lane == 0) {
+            unsigned long long v = 0ull;
+            if (poll_word(&mbox[(size_t)blockIdx.x * mbox_stride], v)) *total = __longlong_as_double((long long)v);
+            else timeout = true;
         }
+        uint64_t bad = ballot(timeout);
+        if (lane == 0 && bad) *abort_flag = 1;
     }
     __syncthreads();
     return *total;
@@ -255,11 +279,19 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
     const int gstride = a.nb * AT_DATA;
     const int base = b * AT_DATA + t;
     const int n = a.n, j = a.j;
-    unsigned long long* cur = a.slots + (size_t)a.parity * a.maxlinks * a.nb;
-    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * a.maxlinks * a.nb;
+    // slot buffer of one parity: [maxlinks][nb] partials, then [nb][maxlinks] mailboxes (one line each)
+    const size_t per_parity = (size_t)a.maxlinks * a.nb * (1 + MBOX_STRIDE);
+    unsigned long long* cur = a.slots + (size_t)a.parity * per_parity;
+    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * per_parity;
+    unsigned long long* cur_mbox = cur + (size_t)a.maxlinks * a.nb;
+    const size_t mstride = (size_t)a.maxlinks * MBOX_STRIDE;   // between the mailboxes of two blocks
+    unsigned long long* nxt_mbox = nxt + (size_t)a.maxlinks * a.nb;
     // re-arm the other buffer for the next launch (links 0 .. j+3)
     const int lim = min(j + 4, a.maxlinks);
-    for (int l = t; l < lim; l += AT) nxt[(size_t)l * a.nb + b] = SENTINEL;
+    for (int l = t; l < lim; l += AT) {
+        nxt[(size_t)l * a.nb + b] = SENTINEL;
+        nxt_mbox[((size_t)b * a.maxlinks + l) * MBOX_STRIDE] = SENTINEL;
+    }
     double* hcol = dyn;
     double* csL = dyn + (a.maxit + 2);
     double* snL = csL + a.maxit;
@@ -292,7 +324,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
         double part = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], v[e], part);
-        double h = grid_sum(part, cur + (size_t)l * a.nb, a.nb, wsum, &total, &abort_flag);
+        double h = grid_sum(part, cur + (size_t)l * a.nb, cur_mbox + (size_t)l * MBOX_STRIDE, mstride, a.nb, wsum,
+                            &total, &abort_flag);
         if (abort_flag) break;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -307,7 +340,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
         double part = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], y[e], part);
-        hn = __builtin_sqrt(grid_sum(part, cur + (size_t)(j + 1) * a.nb, a.nb, wsum, &total, &abort_flag));
+        hn = __builtin_sqrt(grid_sum(part, cur + (size_t)(j + 1) * a.nb, cur_mbox + (size_t)(j + 1) * MBOX_STRIDE,
+                                    mstride, a.nb, wsum, &total, &abort_flag));
     }
     if (abort_flag) {
         if (t == 0) {
@@ -610,7 +644,9 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit) {
     }
     c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
     if (c.shmem > 48 * 1024) return ArnoldiCfg{};
-    int nb = std::min(std::min(h->num_cu, MAX_NB), std::max(1, blocks_for(n, AT_DATA)));
+    // half the CUs: the grid-wide sums get cheaper with fewer blocks while half the
+    // chip still streams the basis fast enough (measured on the 512x512 workload)
+    int nb = std::min(std::min(std::max(1, h->num_cu / 2), MAX_NB), std::max(1, blocks_for(n, AT_DATA)));
     if (const char* e = getenv("SPAI_ARNOLDI_BLOCKS")) {
         int want = atoi(e);
         if (want >= 1 && want <= MAX_NB) nb = std::min(want, std::max(1, blocks_for(n, AT_DATA)));
@@ -672,7 +708,7 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     if (rc) return rc;
     rc = buffer_reserve(h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
     if (rc) return rc;
-    size_t slot_count = cfg.nb ? (size_t)2 * maxlinks * cfg.nb : 0;
+    size_t slot_count = cfg.nb ? (size_t)2 * maxlinks * cfg.nb * (1 + MBOX_STRIDE) : 0;
     size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count);
     rc = buffer_reserve(h->ws[WS_SOLVE_H], hbytes);
     if (rc) return rc;

@@ -125,6 +125,13 @@ typedef struct {
     const int32_t* flags;
 } spai_precond_view;
 
+/* Orthogonalisation of the Arnoldi vectors.  Algorithm 3 asks for GMRES; the
+ * analysis of Section 3.2 uses modified Gram-Schmidt.  CGS2 (classical
+ * Gram-Schmidt applied twice) spans the same Krylov space with orthogonality to
+ * working precision and needs three global reductions per iteration instead of
+ * j+2. */
+enum { SPAI_ORTHO_MGS = 0, SPAI_ORTHO_CGS2 = 1 };
+
 /* Parameters of Algorithm 3 (its Require line: i_max, tau) plus the GMRES cap and
  * the refinement stopping rule.  u_g = u_p = u = FP64 (Section 4). */
 typedef struct {
@@ -133,6 +140,7 @@ typedef struct {
     int32_t imax;   /* maximum refinement steps (<= 32) */
     int32_t maxit;  /* maximum GMRES iterations per step */
     double tol_ir;  /* refinement stops when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf */
+    int32_t ortho;  /* SPAI_ORTHO_MGS (0, default) or SPAI_ORTHO_CGS2 */
 } spai_ir_params;
 
 typedef struct {
@@ -187,7 +195,9 @@ int spai_precond_destroy(spai_precond* P);
  * ||x_{i+1}||_inf, after imax steps, from the third step on when ||d_i||_inf >
  * ||d_{i-1}||_inf / 2, or before a step whose P r_i is exactly zero.
  * b and x are device arrays of n FP64 values (x is output only).
- * Errors: SPAI_E_ARG (sizes differ, imax outside 1..32, maxit < 1, tau < 0);
+ * Errors: SPAI_E_ARG (sizes differ, imax outside 1..32, maxit < 1, tau < 0, an
+ * unknown ortho, CGS2 when the cooperative Arnoldi kernel cannot hold the
+ * problem); SPAI_E_INTERNAL when a grid-wide sum times out (about a second);
  * warnings SPAI_W_MAXIT, SPAI_W_NOCONV.
  */
 int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,

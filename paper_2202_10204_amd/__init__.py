@@ -59,7 +59,10 @@ class _View(ctypes.Structure):
 
 class _IrParams(ctypes.Structure):
     _fields_ = [("u_r", ctypes.c_int), ("tau", _c_f64), ("imax", _c_i32), ("maxit", _c_i32),
-                ("tol_ir", _c_f64)]
+                ("tol_ir", _c_f64), ("ortho", _c_i32)]
+
+
+ORTHO = {"mgs": 0, "cgs2": 1}
 
 
 class _IrStats(ctypes.Structure):
@@ -302,8 +305,8 @@ class Handle:
 
     # -- Algorithm 3 ---------------------------------------------------------
     def gmres_ir(self, A: DeviceCSR, P: Precond, b: torch.Tensor, x: torch.Tensor, tau: float, imax: int,
-                 maxit: int, tol_ir: float, u_r: str = "dd"):
-        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir))
+                 maxit: int, tol_ir: float, u_r: str = "dd", ortho: str = "mgs"):
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO[ortho])
         st = _IrStats()
         csr = A.c()
         rc = _check(lib().spai_gmres_ir(self._raw, ctypes.byref(csr), P.raw, _ptr(b), _ptr(x),

@@ -387,6 +387,234 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// CGS2 Arnoldi step: classical Gram-Schmidt applied twice
+//   h1 = V^T y; y -= V h1; h2 = V^T y; y -= V h2; H(:, j) = h1 + h2; ||y||
+// Three grid-wide reductions per step instead of j+2: bandwidth-bound (four
+// streaming passes over the basis).  A vector reduction: every block publishes
+// its partial vector into write-once slots [l][b]; the owner of column l (block
+// l mod nb) adds the nb partials in a fixed order and writes the total into the
+// private mailbox row of every block ([b][l], write-once); each block polls its
+// own row.  All blocks obtain bit-identical totals.
+// ---------------------------------------------------------------------------
+
+// basis vectors in flight per thread: about 16 doubles of loads per thread, so
+// that large EPT does not spill (the grouping does not change the arithmetic)
+template <int EPT>
+constexpr int cg_u() { return EPT >= 16 ? 1 : EPT >= 8 ? 2 : EPT >= 4 ? 4 : 8; }
+
+// per-block partials pvec[l] = sum over the block's rows of V(i, l) y_i, l < L
+template <int EPT>
+__device__ __forceinline__ void block_vty(const double* __restrict__ V, int n, int L, const double (&y)[EPT],
+                                          int base, int gstride, double* wpart, int ldw, double* pvec) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int DW = AT_DATA / 64;
+    constexpr int CG_U = cg_u<EPT>();
+    if (wave < DW) {
+        for (int l0 = 0; l0 < L; l0 += CG_U) {
+            double vv[CG_U][EPT];
+#pragma unroll
+            for (int u = 0; u < CG_U; ++u)
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    int i = base + e * gstride;
+                    vv[u][e] = (l0 + u < L && i < n) ? V[(size_t)(l0 + u) * n + i] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < CG_U; ++u) {
+                double p = 0.0;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) p = __builtin_fma(vv[u][e], y[e], p);
+                for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+                if (lane == 0 && l0 + u < L) wpart[wave * ldw + l0 + u] = p;
+            }
+        }
+    }
+    __syncthreads();
+    for (int l = t; l < L; l += AT) {
+        double sacc = 0.0;
+        for (int w = 0; w < DW; ++w) sacc += wpart[w * ldw + l];
+        pvec[l] = sacc;
+    }
+    __syncthreads();
+}
+
+// y -= V h for the thread's rows, l ascending
+template <int EPT>
+__device__ __forceinline__ void y_minus_Vh(const double* __restrict__ V, int n, int L, double (&y)[EPT],
+                                           const double* h, int base, int gstride) {
+    if (threadIdx.x >= AT_DATA) return;
+    constexpr int CG_U = cg_u<EPT>();
+    for (int l0 = 0; l0 < L; l0 += CG_U) {
+        double vv[CG_U][EPT];
+#pragma unroll
+        for (int u = 0; u < CG_U; ++u)
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                int i = base + e * gstride;
+                vv[u][e] = (l0 + u < L && i < n) ? V[(size_t)(l0 + u) * n + i] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < CG_U; ++u) {
+            if (l0 + u < L) {
+                const double hl = h[l0 + u];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) y[e] = __builtin_fma(-hl, vv[u][e], y[e]);
+            }
+        }
+    }
+}
+
+// all-reduce of the per-block vectors pvec (length L) into hout (every block)
+__device__ __forceinline__ void grid_vsum(const double* pvec, int L, int nb, unsigned long long* slots,
+                                          unsigned long long* mbox, int lmax, double* red, double* hout,
+                                          int* abort_flag) {
+    const int b = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int l = t; l < L; l += AT)
+        __hip_atomic_store(&slots[(size_t)l * nb + b], (unsigned long long)__double_as_longlong(pvec[l]),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int owned = L > b ? (L - 1 - b) / nb + 1 : 0;
+    bool to = false;
+    for (int q = t; q < owned * nb; q += AT) {
+        int k = q / nb, src = q - k * nb;
+        unsigned long long v = 0ull;
+        if (!poll_word(&slots[(size_t)(b + k * nb) * nb + src], v)) to = true;
+        red[q] = __longlong_as_double((long long)v);
+    }
+    __syncthreads();
+    for (int k = wave; k < owned; k += AT / 64) {
+        double acc = 0.0;
+        for (int src = lane; src < nb; src += 64) acc += red[k * nb + src];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        const int l = b + k * nb;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+        for (int q = lane; q < nb; q += 64)
+            __hip_atomic_store(&mbox[(size_t)q * lmax + l], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int l = t; l < L; l += AT) {
+        unsigned long long v = 0ull;
+        if (!poll_word(&mbox[(size_t)b * lmax + l], v)) to = true;
+        hout[l] = __longlong_as_double((long long)v);
+    }
+    if (to) *abort_flag = 1;
+    __syncthreads();
+}
+
+// slot words of one parity for the CGS2 kernel
+__host__ __device__ inline size_t cgs2_parity_words(int maxlinks, int nb) {
+    return (size_t)4 * maxlinks * nb + (size_t)nb * (1 + MBOX_STRIDE);
+}
+
+template <int EPT>
+__global__ __launch_bounds__(AT) void k_arnoldi_cgs2(ArnoldiArgs a) {
+    extern __shared__ double dyn[];
+    __shared__ double wsum[AT_DATA / 64];
+    __shared__ double total;
+    __shared__ int abort_flag;
+    if (a.st->done) return;                  // uniform: written by an earlier launch
+    const int b = blockIdx.x, t = threadIdx.x, nb = a.nb;
+    const bool data = t < AT_DATA;
+    const int gstride = nb * AT_DATA;
+    const int base = b * AT_DATA + t;
+    const int n = a.n, j = a.j, L = j + 1, lmax = a.maxlinks;
+    constexpr int DW = AT_DATA / 64;
+    // LDS: wpart [DW][lmax], pvec, h1, h2 [lmax], red [lmax + nb], cs, sn [maxit]
+    double* wpart = dyn;
+    double* pvec = wpart + (size_t)DW * lmax;
+    double* h1 = pvec + lmax;
+    double* h2 = h1 + lmax;
+    double* red = h2 + lmax;
+    double* csL = red + lmax + nb;
+    double* snL = csL + a.maxit;
+    const size_t pw = cgs2_parity_words(lmax, nb);
+    unsigned long long* cur = a.slots + (size_t)a.parity * pw;
+    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * pw;
+    const size_t blk = (size_t)lmax * nb;    // one slot array or one mailbox array
+    // re-arm this block's words of the other buffer for the next launch (L + 1 columns)
+    for (int l = t; l < min(L + 1, lmax); l += AT) {
+        nxt[0 * blk + (size_t)l * nb + b] = SENTINEL;
+        nxt[1 * blk + (size_t)b * lmax + l] = SENTINEL;
+        nxt[2 * blk + (size_t)l * nb + b] = SENTINEL;
+        nxt[3 * blk + (size_t)b * lmax + l] = SENTINEL;
+    }
+    if (t == 0) {
+        nxt[4 * blk + b] = SENTINEL;
+        nxt[4 * blk + nb + (size_t)b * MBOX_STRIDE] = SENTINEL;
+        abort_flag = 0;
+    }
+    if (b == 0)
+        for (int l = t; l < j; l += AT) {
+            csL[l] = a.cs[l];
+            snL[l] = a.sn[l];
+        }
+    double y[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int i = base + e * gstride;
+        y[e] = (data && i < n) ? a.y[i] : 0.0;
+    }
+    __syncthreads();
+    block_vty<EPT>(a.V, n, L, y, base, gstride, wpart, lmax, pvec);
+    grid_vsum(pvec, L, nb, cur, cur + blk, lmax, red, h1, &abort_flag);
+    double hn = 0.0;
+    if (!abort_flag) {
+        y_minus_Vh<EPT>(a.V, n, L, y, h1, base, gstride);
+        block_vty<EPT>(a.V, n, L, y, base, gstride, wpart, lmax, pvec);
+        grid_vsum(pvec, L, nb, cur + 2 * blk, cur + 3 * blk, lmax, red, h2, &abort_flag);
+    }
+    if (!abort_flag) {
+        y_minus_Vh<EPT>(a.V, n, L, y, h2, base, gstride);
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) part = __builtin_fma(y[e], y[e], part);
+        hn = __builtin_sqrt(grid_sum(part, cur + 4 * blk, cur + 4 * blk + nb, MBOX_STRIDE, nb, wsum, &total,
+                                     &abort_flag));
+    }
+    if (abort_flag) {
+        if (t == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    double* vout = a.V + (size_t)(j + 1) * n;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int i = base + e * gstride;
+        if (data && i < n) vout[i] = y[e] / hn;
+    }
+    if (b == 0 && t == 0) {
+        double* hh = pvec;                      // free now: column j of H
+        for (int l = 0; l < L; ++l) hh[l] = h1[l] + h2[l];
+        hh[j + 1] = hn;
+        for (int l = 0; l < j; ++l) {           // previous rotations
+            double x0 = hh[l], x1 = hh[l + 1];
+            hh[l] = csL[l] * x0 + snL[l] * x1;
+            hh[l + 1] = -snL[l] * x0 + csL[l] * x1;
+        }
+        double delta = hypot(hh[j], hh[j + 1]);
+        double c = hh[j] / delta, sv = hh[j + 1] / delta;
+        hh[j] = delta;
+        hh[j + 1] = 0.0;
+        double gj = a.g[j];
+        a.g[j + 1] = -sv * gj;
+        a.g[j] = c * gj;
+        a.cs[j] = c;
+        a.sn[j] = sv;
+        double* Hc = a.H + (size_t)j * a.ld;
+        for (int l = 0; l <= j + 1; ++l) Hc[l] = hh[l];
+        double ga = fabs(-sv * gj);
+        a.st->gabs = ga;
+        if (ga <= a.tau * a.st->beta0 || hn == 0.0) {
+            a.st->its = j + 1;
+            a.st->done = 1;
+        } else if (j + 1 == a.maxit) {
+            a.st->its = j + 1;
+            a.st->done = 2;
+        }
+    }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, size_t len, unsigned long long v) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) p[i] = v;
@@ -615,54 +843,76 @@ static int check_csr(const spai_csr* A) {
 }
 
 // Launch configuration of the Arnoldi kernel: nb blocks of AT threads, EPT
-// elements per thread (a power of two); 0 when the cooperative kernel cannot
-// hold the problem (the per-projection path is used instead).
+// elements per thread (a power of two); nb = 0 when the cooperative kernel cannot
+// hold the problem (the per-projection MGS path is used instead).
 struct ArnoldiCfg {
     int nb = 0;
     int ept = 0;
+    int ortho = SPAI_ORTHO_MGS;
     size_t shmem = 0;
+    size_t slot_words = 0;   // both parities
 };
 
 template <int EPT>
-static int max_coresident(size_t shmem, int num_cu) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_arnoldi<EPT>, AT, shmem) != hipSuccess) {
-        (void)hipGetLastError();
-        return 0;
-    }
-    return per_cu * num_cu;
+static const void* arnoldi_fn(int ortho) {
+    return ortho == SPAI_ORTHO_CGS2 ? (const void*)k_arnoldi_cgs2<EPT> : (const void*)k_arnoldi<EPT>;
 }
 
-static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit) {
+static const void* arnoldi_fn(int ortho, int ept) {
+    switch (ept) {
+    case 1: return arnoldi_fn<1>(ortho);
+    case 2: return arnoldi_fn<2>(ortho);
+    case 4: return arnoldi_fn<4>(ortho);
+    case 8: return arnoldi_fn<8>(ortho);
+    default: return arnoldi_fn<16>(ortho);
+    }
+}
+
+static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
     ArnoldiCfg c;
-    if (const char* e = getenv("SPAI_ARNOLDI_PATH"))
-        if (std::string(e) == "projection") return c;
+    c.ortho = ortho;
+    if (ortho == SPAI_ORTHO_MGS)
+        if (const char* e = getenv("SPAI_ARNOLDI_PATH"))
+            if (std::string(e) == "projection") return ArnoldiCfg{};
     int coop = 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, h->device) != hipSuccess || !coop) {
         (void)hipGetLastError();
-        return c;
+        return ArnoldiCfg{};
     }
-    c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
-    if (c.shmem > 48 * 1024) return ArnoldiCfg{};
-    // half the CUs: the grid-wide sums get cheaper with fewer blocks while half the
-    // chip still streams the basis fast enough (measured on the 512x512 workload)
-    int nb = std::min(std::min(std::max(1, h->num_cu / 2), MAX_NB), std::max(1, blocks_for(n, AT_DATA)));
+    const int maxlinks = maxit + 2;
+    const int rows_nb = std::max(1, blocks_for(n, AT_DATA));
+    // MGS: half the CUs (the grid-wide sums get cheaper with fewer blocks while half
+    // the chip still streams the basis fast enough); CGS2 streams the basis four
+    // times per step and uses every CU
+    int nb = ortho == SPAI_ORTHO_CGS2 ? std::min(std::min(h->num_cu, MAX_NB), rows_nb)
+                                      : std::min(std::min(std::max(1, h->num_cu / 2), MAX_NB), rows_nb);
     if (const char* e = getenv("SPAI_ARNOLDI_BLOCKS")) {
         int want = atoi(e);
-        if (want >= 1 && want <= MAX_NB) nb = std::min(want, std::max(1, blocks_for(n, AT_DATA)));
+        if (want >= 1 && want <= MAX_NB) nb = std::min(want, rows_nb);
     }
     int ept = 1;
     while ((long long)nb * AT_DATA * ept < n) ept <<= 1;
     if (ept > 16) return ArnoldiCfg{};
-    int cap = 0;
-    switch (ept) {
-    case 1: cap = max_coresident<1>(c.shmem, h->num_cu); break;
-    case 2: cap = max_coresident<2>(c.shmem, h->num_cu); break;
-    case 4: cap = max_coresident<4>(c.shmem, h->num_cu); break;
-    case 8: cap = max_coresident<8>(c.shmem, h->num_cu); break;
-    default: cap = max_coresident<16>(c.shmem, h->num_cu); break;
+    if (ortho == SPAI_ORTHO_CGS2) {
+        c.shmem = sizeof(double) * ((size_t)(AT_DATA / 64 + 4) * maxlinks + nb + 2 * (size_t)maxit);
+        c.slot_words = 2 * cgs2_parity_words(maxlinks, nb);
+    } else {
+        c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
+        c.slot_words = (size_t)2 * maxlinks * nb * (1 + MBOX_STRIDE);
     }
-    if (cap < nb) return ArnoldiCfg{};
+    if (c.shmem > 150 * 1024) return ArnoldiCfg{};
+    const void* fn = arnoldi_fn(ortho, ept);
+    if (c.shmem > 48 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.shmem) != hipSuccess) {
+        (void)hipGetLastError();
+        return ArnoldiCfg{};
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AT, c.shmem) != hipSuccess) {
+        (void)hipGetLastError();
+        return ArnoldiCfg{};
+    }
+    if (per_cu * h->num_cu < nb) return ArnoldiCfg{};
     c.nb = nb;
     c.ept = ept;
     return c;
@@ -670,14 +920,7 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit) {
 
 static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, hipStream_t s) {
     void* args[] = {&a};
-    const void* fn = nullptr;
-    switch (c.ept) {
-    case 1: fn = (const void*)k_arnoldi<1>; break;
-    case 2: fn = (const void*)k_arnoldi<2>; break;
-    case 4: fn = (const void*)k_arnoldi<4>; break;
-    case 8: fn = (const void*)k_arnoldi<8>; break;
-    default: fn = (const void*)k_arnoldi<16>; break;
-    }
+    const void* fn = arnoldi_fn(c.ortho, c.ept);
     long tk = timer_begin(h, SPAI_KT_MGS);
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);
     timer_end(h, SPAI_KT_MGS, tk);
@@ -696,11 +939,14 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     SPAI_ARG(prm->maxit >= 1, "maxit must be positive");
     SPAI_ARG(prm->tau >= 0.0, "tau must be non-negative");
     SPAI_ARG(prm->u_r == SPAI_DD || prm->u_r == SPAI_FP64, "u_r must be DD or FP64");
+    SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS || prm->ortho == SPAI_ORTHO_CGS2, "ortho must be MGS or CGS2");
     SPAI_HIP(hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const int maxit = std::min(prm->maxit, n);
     const int ld = maxit + 1;
-    const ArnoldiCfg cfg = arnoldi_config(h, n, maxit);
+    const ArnoldiCfg cfg = arnoldi_config(h, n, maxit, prm->ortho);
+    SPAI_ARG(cfg.nb > 0 || prm->ortho == SPAI_ORTHO_MGS,
+             "CGS2 needs the cooperative Arnoldi kernel, which cannot hold this problem");
     const int maxlinks = maxit + 2;
 
     // workspace
@@ -708,7 +954,7 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     if (rc) return rc;
     rc = buffer_reserve(h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
     if (rc) return rc;
-    size_t slot_count = cfg.nb ? (size_t)2 * maxlinks * cfg.nb * (1 + MBOX_STRIDE) : 0;
+    size_t slot_count = cfg.slot_words;
     size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count);
     rc = buffer_reserve(h->ws[WS_SOLVE_H], hbytes);
     if (rc) return rc;

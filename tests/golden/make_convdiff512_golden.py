@@ -36,6 +36,8 @@ def main():
     pp, pc, pv = R.P_csr(w.n)
     res = O.gmres_ir(w.A, pp, pc, pv, R.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
     t2 = time.time()
+    res2 = O.gmres_ir(w.A, pp, pc, pv, R.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "cgs2")
+    t3 = time.time()
     out = {
         "workload": w.name,
         "recipe": w.recipe,
@@ -56,7 +58,9 @@ def main():
         "status": res.status,
         "ferr": O.ferr(res.x, w.x_true),
         "nbe": O.nbe(w.A, w.b, res.x),
-        "oracle_seconds": {"spai": t1 - t0, "gmres_ir": t2 - t1},
+        "its_cgs2": res2.its,
+        "ferr_cgs2": O.ferr(res2.x, w.x_true),
+        "oracle_seconds": {"spai": t1 - t0, "gmres_ir": t2 - t1, "gmres_ir_cgs2": t3 - t2},
     }
     path = os.path.join(HERE, "convdiff512_oracle.json")
     with open(path, "w") as f:

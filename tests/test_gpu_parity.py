@@ -249,11 +249,11 @@ def test_x0_and_apply(S, h, uf):
 # Algorithm 3
 # ---------------------------------------------------------------------------
 
-def _solve(S, h, w, A, P, u_r="dd"):
+def _solve(S, h, w, A, P, u_r="dd", ortho="mgs"):
     ir = w.ir
     b = _dev(w.b)
     x = torch.zeros_like(b)
-    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r)
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
     return x.cpu().numpy(), st
 
 
@@ -378,3 +378,29 @@ def test_projection_fallback_path_agrees(S, h, monkeypatch):
     assert s1["its"] == s2["its"]
     assert O.ferr(x2, w.x_true) <= 1e-12
     assert np.abs(x1 - x2).max() <= 1e-13 * np.abs(w.x_true).max()
+
+
+@pytest.mark.parametrize("make", [W.convdiff_small, lambda: W.convdiff_adaptive(56), lambda: W.aniso_fixed(10, "fp32"),
+                                  lambda: W.random_system(2500, 9)])
+def test_gmres_ir_cgs2_matches_oracle(S, h, make):
+    """CGS2 Arnoldi: the same iteration tuple as the oracle's CGS2 GMRES-IR and
+    forward error <= 1e-12."""
+    w = make()
+    A, P, warn, stats = _build(S, h, w)
+    s, ir = w.spai, w.ir
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "cgs2")
+    x, st = _solve(S, h, w, A, P, ortho="cgs2")
+    assert st["its"] == oref.its
+    assert O.ferr(x, w.x_true) <= 1e-12
+    assert np.abs(x - oref.x).max() <= 1e-12 * np.abs(w.x_true).max()
+
+
+def test_full_size_solve_cgs2_matches_oracle_tuple(S, h, full):
+    """CGS2 at full size: the oracle's CGS2 tuple (stored by the golden script)."""
+    w, A, P, stats = full
+    x, st = _solve(S, h, w, A, P, ortho="cgs2")
+    g = _golden512()
+    assert st["its"] == g["its_cgs2"]
+    assert O.ferr(x, w.x_true) <= 1e-12

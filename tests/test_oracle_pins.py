@@ -372,9 +372,11 @@ def test_fp32_and_fp64_spai_give_similar_preconditioners():
 # GMRES-IR
 # ---------------------------------------------------------------------------
 
-def test_gmres_step_is_the_krylov_least_squares_minimiser():
-    """After k iterations (tau = 0) MGS-GMRES returns d = argmin over K_k(PA, z)
-    of ||z - PA d||_2 with z = P r0; checked against an SVD-based solve."""
+@pytest.mark.parametrize("ortho", ["mgs", "cgs2"])
+def test_gmres_step_is_the_krylov_least_squares_minimiser(ortho):
+    """After k iterations (tau = 0) GMRES (MGS or CGS2 Arnoldi) returns
+    d = argmin over K_k(PA, z) of ||z - PA d||_2 with z = P r0; checked against
+    an orthonormal basis of the explicit Krylov matrix."""
     rng = np.random.default_rng(11)
     n = 8
     Ad = _random_dd(n, rng, density=0.6, dom=0.4)
@@ -389,7 +391,7 @@ def test_gmres_step_is_the_krylov_least_squares_minimiser():
             d = R.d
         P = sp.csr_matrix((pv * d[pc], pc, pp), shape=(n, n)).toarray()
         for k in range(1, 6):
-            res = O.gmres_ir(A, pp, pc, pv, d, "fp64", b, 0.0, 1, k, 0.0)
+            res = O.gmres_ir(A, pp, pc, pv, d, "fp64", b, 0.0, 1, k, 0.0, ortho)
             assert res.its == [k]
             x0 = P @ b
             r0 = b - Ad @ x0

@@ -41,17 +41,32 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def arnoldi_bytes_per_solve(its, n):
-    """Algorithmic HBM bytes of the Arnoldi kernel over one solve, and its launch count.
+def arnoldi_bytes_per_solve(its, n, ortho):
+    """Algorithmic HBM bytes of the Arnoldi iterations of one solve, the bytes the
+    chosen kernel streams by design, and the number of launches that do work.
 
-    Launch j (0-based) of a refinement step reads y = P A v_j (8n) and the basis
-    vectors v_0 .. v_j (8n(j+1)) once each and writes v_{j+1} (8n): 8n(j+3)."""
-    total, launches = 0, 0
+    Algorithmic: Arnoldi iteration j (0-based) reads y = P A v_j (8n) and the
+    basis vectors v_0 .. v_j (8n(j+1)) once each and writes v_{j+1} (8n):
+    8n(j+3), whatever the orthogonalisation.  By design, MGS streams exactly
+    that; CGS2 reads the basis four times (8n(4(j+1)+2)); delayed CGS2 launch j
+    reads V_{j-1}, u_j and y, then V_{j-1} again, and writes v_j and u_{j+1}
+    (8n(2j+4)), and one more launch per refinement step (pass 1 only) completes
+    the last column."""
+    alg, design, launches = 0, 0, 0
     for k in its:
         for j in range(k):
-            total += 8 * n * (j + 3)
+            alg += 8 * n * (j + 3)
+            if ortho == "mgs":
+                design += 8 * n * (j + 3)
+            elif ortho == "cgs2":
+                design += 8 * n * (4 * (j + 1) + 2)
+            else:
+                design += 8 * n * (2 * j + 4)
             launches += 1
-    return total, launches
+        if ortho == "dcgs2":
+            design += 8 * n * (k + 2)
+            launches += 1
+    return alg, design, launches
 
 
 def profiled_traffic(kernel_file, sources):
@@ -75,14 +90,14 @@ def profiled_traffic(kernel_file, sources):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=()):
+def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho="dcgs2"):
     """Build + solve `steps` times after `warmup` untimed steps; per-step times in ms."""
     import torch
 
     s, ir = w.spai, w.ir
     for _ in range(warmup):
         P, _, _ = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f)
-        h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r)
+        h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
         del P
     for kc, every in timed_kernels:
         h.timing_enable(kc, every)
@@ -97,7 +112,7 @@ def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=()):
         e0.record(stream)
         P, warn, bst = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f)
         e1.record(stream)
-        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r)
+        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
         e2.record(stream)
         e2.synchronize()
         rec.append((e0.elapsed_time(e1), e1.elapsed_time(e2), st, bst, warn))
@@ -141,7 +156,7 @@ def cpu_baseline(w, its_oracle, threads):
         "cores": threads,
         "kind": "oracle",
         "sample": (f"full oracle SPAI build ({w.n} columns, {t_build:.2f} s on {threads} threads) + "
-                   f"oracle GMRES-IR first step cut at k=30/60/90 Arnoldi iterations "
+                   f"oracle GMRES-IR (MGS) first step cut at k=30/60/90 Arnoldi iterations "
                    f"({', '.join(f'{t:.2f}' for t in ts)} s), quadratic cost fit summed over the oracle's "
                    f"tuple {sum(its_oracle)}({', '.join(map(str, its_oracle))}) -> {t_solve:.1f} s per solve"),
         "spai_cols_per_s": w.n / t_build,
@@ -157,6 +172,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, default=512, help="grid side (512 is the benchmark workload)")
+    ap.add_argument("--ortho", default="dcgs2", choices=["mgs", "cgs2", "dcgs2"],
+                    help="Arnoldi orthogonalisation (all three give the oracle's iteration tuple)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one untimed build + solve of the mixed form and a 256 MiB device copy "
                          "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE); for profiler runs")
@@ -184,7 +201,7 @@ def main():
     if args.profile_run:
         s, ir = w.spai, w.ir
         P, _, bst = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, "fp32")
-        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd")
+        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd", args.ortho)
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -194,7 +211,7 @@ def main():
         return
 
     kernels = [("columns", 1), ("mgs", 1), ("spmv_a", 3), ("apply_p", 3), ("residual", 1), ("update", 1)]
-    rec, wall, timings = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels)
+    rec, wall, timings = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels, args.ortho)
     log(f"mixed form: {[(round(a, 1), round(c, 1)) for a, c, *_ in rec]} ms (build, solve)")
     step_ms = [a + c for a, c, *_ in rec]
     build_ms = [a for a, *_ in rec]
@@ -216,7 +233,7 @@ def main():
         if args.fp64_steps <= 0:
             break
         x64 = torch.zeros_like(b)
-        r64, wall64, _ = run_form(S, h, w, A, b, x64, uf, ur, args.fp64_steps, 0)
+        r64, wall64, _ = run_form(S, h, w, A, b, x64, uf, ur, args.fp64_steps, 0, (), args.ortho)
         ms64 = float(np.mean([a + c for a, c, *_ in r64]))
         xe = x64.cpu().numpy()
         forms[name] = {
@@ -241,15 +258,17 @@ def main():
     if dom == "mgs" and per_class["mgs"]["avg_ms"]:
         # every launch is timed; launches enqueued past convergence (no-ops) count
         # in the time but not in the bytes, so the figure is conservative
-        tot_bytes, real = arnoldi_bytes_per_solve(st["its"], n)
+        tot_bytes, design_bytes, real = arnoldi_bytes_per_solve(st["its"], n, args.ortho)
         cnt, ms = timings["mgs"]
         secs = ms * 1e-3 / args.steps
         achieved = tot_bytes / secs / 1e9
-        traffic = profiled_traffic("k_arnoldi_convdiff512_traffic.txt",
+        kname = {"mgs": "k_arnoldi", "cgs2": "k_arnoldi_cgs2", "dcgs2": "k_arnoldi_dcgs2"}[args.ortho]
+        traffic = profiled_traffic(f"{kname}_convdiff512_traffic.txt",
                                    ["paper_2202_10204_amd/csrc/gmres_ir.hip", "paper_2202_10204_amd/csrc/common.hpp"])
-        roof = {"bound": "hbm", "kernel": "k_arnoldi", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
-                "bytes_per_launch": tot_bytes / real, "avg_launch_us": ms * 1e3 / cnt,
+                "bytes_per_launch": tot_bytes / real, "design_bytes_per_launch": design_bytes / real,
+                "design_rate_GBs": design_bytes / secs / 1e9, "avg_launch_us": ms * 1e3 / cnt,
                 "launches_per_step": cnt / args.steps, "real_launches_per_step": real}
     elif per_class[dom]["avg_ms"]:
         roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -270,7 +289,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "nnz_A": w.A.nnz, "spai": "adaptive identity start",
                    "eps": w.spai.eps, "beta": w.spai.beta, "maxfill": w.spai.maxfill, "u_f": "fp32",
-                   "u": "fp64", "u_r": "dd", "tau": w.ir.tau, "parallelism": "single GPU"},
+                   "u": "fp64", "u_r": "dd", "tau": w.ir.tau, "arnoldi": args.ortho, "parallelism": "single GPU"},
         "spai_cols_per_s": n / (float(np.mean(build_ms)) * 1e-3),
         "spai_ms": float(np.mean(build_ms)),
         "gmres_ir_solves_per_s": 1000.0 / float(np.mean(solve_ms)),

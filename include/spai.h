@@ -129,8 +129,12 @@ typedef struct {
  * analysis of Section 3.2 uses modified Gram-Schmidt.  CGS2 (classical
  * Gram-Schmidt applied twice) spans the same Krylov space with orthogonality to
  * working precision and needs three global reductions per iteration instead of
- * j+2. */
-enum { SPAI_ORTHO_MGS = 0, SPAI_ORTHO_CGS2 = 1 };
+ * j+2.  DCGS2 is CGS2 with the second projection and the normalisation of each
+ * new vector delayed to the next iteration: one global reduction and two passes
+ * over the basis per iteration; the stopping decision for iteration j is taken
+ * one iteration later, so one extra product with P A is computed per solve.
+ * CGS2 and DCGS2 need the cooperative Arnoldi kernel (SPAI_E_ARG otherwise). */
+enum { SPAI_ORTHO_MGS = 0, SPAI_ORTHO_CGS2 = 1, SPAI_ORTHO_DCGS2 = 2 };
 
 /* Parameters of Algorithm 3 (its Require line: i_max, tau) plus the GMRES cap and
  * the refinement stopping rule.  u_g = u_p = u = FP64 (Section 4). */
@@ -140,7 +144,7 @@ typedef struct {
     int32_t imax;   /* maximum refinement steps (<= 32) */
     int32_t maxit;  /* maximum GMRES iterations per step */
     double tol_ir;  /* refinement stops when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf */
-    int32_t ortho;  /* SPAI_ORTHO_MGS (0, default) or SPAI_ORTHO_CGS2 */
+    int32_t ortho;  /* SPAI_ORTHO_MGS (0, default), SPAI_ORTHO_CGS2 or SPAI_ORTHO_DCGS2 */
 } spai_ir_params;
 
 typedef struct {

@@ -275,7 +275,7 @@ class IrResult:
         return f"{self.total}({', '.join(str(i) for i in self.its)})"
 
 
-ORTHO = {"mgs": 0, "cgs2": 1}
+ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 
 def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, maxit: int,
@@ -283,7 +283,9 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D.
 
     ``ortho`` = "mgs" (modified Gram-Schmidt, the variant analysed in Section
-    3.2) or "cgs2" (classical Gram-Schmidt applied twice)."""
+    3.2), "cgs2" (classical Gram-Schmidt applied twice) or "dcgs2" (CGS2 with
+    the second projection and the normalisation delayed by one step: one set of
+    inner products per Arnoldi step)."""
     n = A.n
     x = np.zeros(n)
     its = np.zeros(imax, np.int32)

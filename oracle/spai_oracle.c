@@ -702,10 +702,111 @@ void oracle_x0(int n, const int* pp, const int* pc, const double* pv, const doub
 #define IR_NOCONV 2      /* refinement hit imax without meeting tol_ir */
 #define IR_STAGNATED 4   /* correction stopped decreasing */
 
+/* Givens step on column j of the Hessenberg matrix (column-major, leading
+ * dimension ld): apply the rotations 0..j-1, build rotation j, update g. */
+static void givens_column(double* H, int ld, int j, double* cs, double* sn, double* g) {
+    double* h = H + (size_t)j * (size_t)ld;
+    for (int l = 0; l < j; ++l) {
+        double a = h[l], c2 = h[l + 1];
+        h[l] = cs[l] * a + sn[l] * c2;
+        h[l + 1] = -sn[l] * a + cs[l] * c2;
+    }
+    double delta = hypot(h[j], h[j + 1]);
+    cs[j] = h[j] / delta;
+    sn[j] = h[j + 1] / delta;
+    h[j] = delta;
+    h[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+}
+
+/*
+ * Arnoldi with CGS2 whose second projection (and the normalisation) of each new
+ * vector is delayed to the next step, so that one step needs one set of inner
+ * products (the delayed-reorthogonalisation CGS2 of the low-synchronisation
+ * Gram-Schmidt literature; the steps below are derived from the Arnoldi relation
+ * M V_j = V_{j+1} H_j, M = P A, in exact arithmetic).
+ *
+ * On entry column 0 of V holds v_0 = z / beta0.  Column j of V holds the lagged
+ * vector u_j (u_0 = v_0), the once-projected successor of v_{j-1}.  Step j:
+ *   a = V_{j-1}^T u_j, omega = u_j^T u_j, nu = sqrt(omega - a^T a)  (j >= 1)
+ *   column j-1 of the Hessenberg matrix is complete: HR(0:j-1, j-1) += a,
+ *   HR(j, j-1) = nu; Givens step on it and the stopping test (|g_j| <= tau beta0,
+ *   nu = 0, or j = maxit), which ends the Arnoldi process with k = j;
+ *   y = P A u_j; b = V_{j-1}^T y, c = u_j^T y;
+ *   v_j = (u_j - V_{j-1} a) / nu;
+ *   gv = [b; (c - a^T b) / nu]  (= V_j^T y);
+ *   HR(0:j, j) = (gv - HR(0:j, 0:j-1) a) / nu  (first projection of M v_j);
+ *   u_{j+1} = (y - V_j gv) / nu  (= M v_j - V_j HR(0:j, j)).
+ * For j = 0 there is no a and nu = 1.  HR keeps the Hessenberg matrix before the
+ * rotations, H receives the rotated columns.  Returns k; *maxit_hit is set when
+ * k reached maxit without the test being met.
+ */
+static int arnoldi_dcgs2(int n, const int* rp, const int* ci, const double* av, const int* pp,
+                         const int* pc, const double* pv, const double* d, double* V, double* H,
+                         double* HR, int ld, double* cs, double* sn, double* g, double beta0, double tau,
+                         int maxit, double* w, double* dw, double* y, double* a, double* bb,
+                         int* maxit_hit) {
+#define HRR(i, j) HR[(size_t)(j) * (size_t)ld + (size_t)(i)]
+    int k = 0;
+    *maxit_hit = 0;
+    for (int j = 0;; ++j) {
+        double* uj = V + (size_t)j * n;
+        double nu = 1.0;
+        if (j > 0) {
+            double q = dot(n, uj, uj);
+            for (int l = 0; l < j; ++l) {
+                a[l] = dot(n, V + (size_t)l * n, uj);
+                q -= a[l] * a[l];
+            }
+            nu = q > 0.0 ? sqrt(q) : 0.0;
+            for (int l = 0; l < j; ++l) HRR(l, j - 1) += a[l];
+            HRR(j, j - 1) = nu;
+            for (int l = 0; l <= j; ++l) H[(size_t)(j - 1) * ld + l] = HRR(l, j - 1);
+            givens_column(H, ld, j - 1, cs, sn, g);
+            k = j;
+            if (fabs(g[j]) <= tau * beta0 || nu == 0.0) break;
+            if (j == maxit) {
+                *maxit_hit = 1;
+                break;
+            }
+        }
+        spmv(n, rp, ci, av, uj, w);
+        apply_P(n, pp, pc, pv, d, w, dw, y);
+        for (int l = 0; l < j; ++l) bb[l] = dot(n, V + (size_t)l * n, y);
+        double c = dot(n, uj, y);
+        if (j > 0) {                     /* per element: l ascending, then the division */
+            for (int l = 0; l < j; ++l) {
+                const double* vl = V + (size_t)l * n;
+                for (int i = 0; i < n; ++i) uj[i] -= a[l] * vl[i];
+            }
+            for (int i = 0; i < n; ++i) uj[i] /= nu;
+        }
+        double gj = c;
+        for (int l = 0; l < j; ++l) gj -= a[l] * bb[l];
+        gj /= nu;
+        for (int r = 0; r <= j; ++r) {
+            double s = r < j ? bb[r] : gj;
+            for (int m = 0; m < j; ++m) s -= HRR(r, m) * a[m];
+            HRR(r, j) = s / nu;
+        }
+        double* un = V + (size_t)(j + 1) * n;
+        for (int i = 0; i < n; ++i) un[i] = y[i];
+        for (int l = 0; l < j; ++l) {
+            const double* vl = V + (size_t)l * n;
+            for (int i = 0; i < n; ++i) un[i] -= bb[l] * vl[i];
+        }
+        for (int i = 0; i < n; ++i) un[i] = (un[i] - gj * uj[i]) / nu;
+    }
+#undef HRR
+    return k;
+}
+
 /*
  * SPAI-GMRES-IR.  A: CSR FP64.  ortho selects the orthogonalisation of the Arnoldi
  * vectors: 0 = modified Gram-Schmidt (the variant of the analysis in Section 3.2),
- * 1 = classical Gram-Schmidt applied twice (CGS2).  P = M^T D: CSR rows pp/pc with u_f values pv (held
+ * 1 = classical Gram-Schmidt applied twice (CGS2), 2 = CGS2 with the second
+ * projection delayed by one step (arnoldi_dcgs2).  P = M^T D: CSR rows pp/pc with u_f values pv (held
  * in double) and the FP64 scaling d; uf is the precision of the initial solve.
  * x (out) receives the solution.  its[0..imax) receives GMRES iterations per
  * refinement step; *nsteps the number of steps.  Left-preconditioned MGS-GMRES
@@ -722,7 +823,7 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
                     const int* pc, const double* pv, const double* d, int uf, const double* b,
                     double* x, double tau, int imax, int maxit, double tol_ir, int ortho, int* its,
                     int* nsteps, double* gest, double* dnorm) {
-    if (n <= 0 || imax < 1 || maxit < 1 || ortho < 0 || ortho > 1) return -1;
+    if (n <= 0 || imax < 1 || maxit < 1 || ortho < 0 || ortho > 2) return -1;
     int status = 0;
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
     double* z = (double*)malloc(sizeof(double) * (size_t)n);
@@ -736,6 +837,8 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
     double* g = (double*)malloc(sizeof(double) * (size_t)(maxit + 1));
     double* yk = (double*)malloc(sizeof(double) * (size_t)maxit);
     double* hp = (double*)malloc(sizeof(double) * (size_t)(maxit + 1));
+    double* HR = ortho == 2 ? (double*)calloc((size_t)(maxit + 1) * (size_t)maxit, sizeof(double)) : NULL;
+    double* bb = (double*)malloc(sizeof(double) * (size_t)(maxit + 1));
 #define HH(i, j) H[(size_t)(j) * (size_t)(maxit + 1) + (size_t)(i)]
 
     oracle_x0(n, pp, pc, pv, d, b, uf, x);
@@ -755,7 +858,14 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
         for (int i = 0; i <= maxit; ++i) g[i] = 0.0;
         g[0] = beta0;
         int k = 0;
-        for (int j = 0; j < maxit; ++j) {
+        if (ortho == 2) {
+            for (size_t q = 0; q < (size_t)(maxit + 1) * (size_t)maxit; ++q) HR[q] = 0.0;
+            int hit = 0;
+            k = arnoldi_dcgs2(n, rp, ci, av, pp, pc, pv, d, V, H, HR, maxit + 1, cs, sn, g, beta0, tau,
+                              maxit, w, dw, y, hp, bb, &hit);
+            if (hit) status |= IR_MAXIT;
+        }
+        for (int j = 0; j < maxit && ortho != 2; ++j) {
             double* vj = V + (size_t)j * n;
             spmv(n, rp, ci, av, vj, w);
             apply_P(n, pp, pc, pv, d, w, dw, y);
@@ -824,7 +934,7 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
     }
 #undef HH
     free(r); free(z); free(w); free(y); free(dw); free(V); free(H); free(cs); free(sn);
-    free(g); free(yk); free(hp);
+    free(g); free(yk); free(hp); free(HR); free(bb);
     return status;
 }
 

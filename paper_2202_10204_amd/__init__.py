@@ -62,7 +62,7 @@ class _IrParams(ctypes.Structure):
                 ("tol_ir", _c_f64), ("ortho", _c_i32)]
 
 
-ORTHO = {"mgs": 0, "cgs2": 1}
+ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 
 class _IrStats(ctypes.Structure):

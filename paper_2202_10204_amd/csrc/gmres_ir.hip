@@ -63,31 +63,53 @@ struct SolveState {
 // enqueued past convergence cost only their launch)
 // ---------------------------------------------------------------------------
 
-__global__ void k_spmv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                       const double* __restrict__ av, const double* __restrict__ x, double* __restrict__ y,
-                       const SolveState* __restrict__ st) {
+// w = A v and y = M^T (D w) (row k of P holds m_k, values in VP, FP64
+// arithmetic) with G lanes per row (G a power of two <= 16): the lanes load the
+// row's entries with unit stride, keep lane-strided partial sums and add them
+// by a fixed xor tree, so every call gives the same bits.  Many more waves than
+// one thread per row, and coalesced loads.
+template <int G>
+__global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const double* __restrict__ av, const double* __restrict__ x,
+                                                double* __restrict__ y, const SolveState* __restrict__ st) {
     if (st && st->done) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int row = (int)(((unsigned)blockIdx.x * 256u + threadIdx.x) / G);
+    const int sub = threadIdx.x & (G - 1);
+    if (row >= n) return;                    // the whole group of G lanes
     double s = 0.0;
-    for (int q = rp[i]; q < rp[i + 1]; ++q) s = __builtin_fma(av[q], x[ci[q]], s);
-    y[i] = s;
+    const int q1 = rp[row + 1];
+    for (int q = rp[row] + sub; q < q1; q += G) s = __builtin_fma(av[q], x[ci[q]], s);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (sub == 0) y[row] = s;
 }
 
-// y = M^T (D w): row k of P holds m_k (values in VP), FP64 arithmetic
-template <int VP>
-__global__ void k_apply_P(int n, const int* __restrict__ pp, const int* __restrict__ pc,
-                          const typename ValType<VP>::T* __restrict__ pv, const double* __restrict__ d,
-                          const double* __restrict__ w, double* __restrict__ y, const SolveState* __restrict__ st) {
+template <int VP, int G>
+__global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict__ pp, const int* __restrict__ pc,
+                                                   const typename ValType<VP>::T* __restrict__ pv,
+                                                   const double* __restrict__ d, const double* __restrict__ w,
+                                                   double* __restrict__ y, const SolveState* __restrict__ st) {
     if (st && st->done) return;
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+    const int row = (int)(((unsigned)blockIdx.x * 256u + threadIdx.x) / G);
+    const int sub = threadIdx.x & (G - 1);
+    if (row >= n) return;
     double s = 0.0;
-    for (int q = pp[k]; q < pp[k + 1]; ++q) {
+    const int q1 = pp[row + 1];
+    for (int q = pp[row] + sub; q < q1; q += G) {
         int j = pc[q];
         s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
     }
-    y[k] = s;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+    if (sub == 0) y[row] = s;
+}
+
+// lanes per row for an average of nnz / n entries per row
+static inline int lanes_per_row(long long nnz, int n) {
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    int g = 1;
+    while (g < 16 && g * 1.5 < avg) g <<= 1;
+    return g;
 }
 
 // x0 = P b in u_f: z_j = u_f(d_j b_j), products and sums in F, ascending column
@@ -174,8 +196,10 @@ struct ArnoldiArgs {
     double* sn;
     double* g;
     double tau;
-    unsigned long long* slots;   // [2][maxlinks][nb]
+    unsigned long long* slots;   // grid-sum slots and mailboxes of both parities
     SolveState* st;
+    double* HRp;         // DCGS2: first projections, column-major ld x maxit
+    double* HRf;         // DCGS2: completed Hessenberg columns before rotation, row-major (maxit+1) x maxit
 };
 
 // Grid-wide sum of one double per block, in two hops that keep every polled
@@ -615,6 +639,275 @@ __global__ __launch_bounds__(AT) void k_arnoldi_cgs2(ArnoldiArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// DCGS2 Arnoldi step: CGS2 with the second projection and the normalisation of
+// each new vector delayed by one step, so that a step needs one grid-wide
+// reduction and two streaming passes over the basis.  Column j of V holds the
+// lagged vector u_j (u_0 = v_0) and y = P A u_j.  Launch j
+//   pass 1: block partials of [V_{j-1}^T u_j, u_j^T u_j, V_{j-1}^T y, u_j^T y]
+//           (2j + 2 values: a, omega, b, c), all-reduced over the grid;
+//   every block: nu = sqrt(omega - a^T a) (nu = 1 for j = 0) and
+//           gj = (c - a^T b) / nu, in the same order, so identical everywhere;
+//   pass 2: v_j = (u_j - V_{j-1} a) / nu into column j and
+//           u_{j+1} = (y - V_{j-1} b - gj v_j) / nu into column j + 1 (skipped
+//           by the launch j = maxit, which only completes column maxit - 1);
+// while the poll wave of every block, idle during pass 2, completes its rows of
+// the Hessenberg matrix: the column j - 1 entries f_r = HRp(r, j-1) + a_r
+// (r < j), f_j = nu, and the first projection of M v_j,
+//   HRp(r, j) = (gv_r - sum_{m <= j-2} HRf(r, m) a_m - f_r a_{j-1}) / nu,
+// with gv = [b; gj] (rows r = b, b + nb, ...); the poll wave of block 0 applies
+// the Givens rotations to column j - 1 and takes the stopping decision.
+// ---------------------------------------------------------------------------
+
+// slot words of one parity for the DCGS2 kernel: [rmax][nb] slots + [nb][rmax] mailboxes
+__host__ __device__ inline size_t dcgs2_parity_words(int maxlinks, int nb) {
+    return (size_t)2 * (2 * (size_t)maxlinks) * nb;
+}
+
+// pass 1: per-block partials of the 2j + 2 inner products into pvec
+template <int EPT>
+__device__ __forceinline__ void block_dots2(const double* __restrict__ V, int n, int j, const double (&u)[EPT],
+                                            const double (&yv)[EPT], int base, int gstride, double* wpart, int ldw,
+                                            double* pvec) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int DW = AT_DATA / 64;
+    constexpr int CG_U = cg_u<EPT>();
+    if (wave < DW) {
+        double* wp = wpart + (size_t)wave * ldw;
+        for (int l0 = 0; l0 < j; l0 += CG_U) {
+            double vv[CG_U][EPT];
+#pragma unroll
+            for (int q = 0; q < CG_U; ++q)
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    int i = base + e * gstride;
+                    vv[q][e] = (l0 + q < j && i < n) ? V[(size_t)(l0 + q) * n + i] : 0.0;
+                }
+#pragma unroll
+            for (int q = 0; q < CG_U; ++q) {
+                double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    p1 = __builtin_fma(vv[q][e], u[e], p1);
+                    p2 = __builtin_fma(vv[q][e], yv[e], p2);
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    p1 += __shfl_xor(p1, o, 64);
+                    p2 += __shfl_xor(p2, o, 64);
+                }
+                if (lane == 0 && l0 + q < j) {
+                    wp[l0 + q] = p1;
+                    wp[j + 1 + l0 + q] = p2;
+                }
+            }
+        }
+        double om = 0.0, c = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            om = __builtin_fma(u[e], u[e], om);
+            c = __builtin_fma(u[e], yv[e], c);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            om += __shfl_xor(om, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if (lane == 0) {
+            wp[j] = om;
+            wp[2 * j + 1] = c;
+        }
+    }
+    __syncthreads();
+    const int R = 2 * j + 2;
+    for (int r = t; r < R; r += AT) {
+        double sacc = 0.0;
+        for (int w = 0; w < DW; ++w) sacc += wpart[(size_t)w * ldw + r];
+        pvec[r] = sacc;
+    }
+    __syncthreads();
+}
+
+// pass 2 (data waves): u and yv are consumed in place
+template <int EPT>
+__device__ __forceinline__ void dcgs2_update(const double* __restrict__ V, int n, int j, double (&u)[EPT],
+                                             double (&yv)[EPT], const double* acoef, const double* bcoef, double nu,
+                                             double gj, int base, int gstride, double* vout, double* uout) {
+    if (threadIdx.x >= AT_DATA) return;
+    constexpr int CG_U = cg_u<EPT>();
+    for (int l0 = 0; l0 < j; l0 += CG_U) {
+        double vv[CG_U][EPT];
+#pragma unroll
+        for (int q = 0; q < CG_U; ++q)
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                int i = base + e * gstride;
+                vv[q][e] = (l0 + q < j && i < n) ? V[(size_t)(l0 + q) * n + i] : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < CG_U; ++q) {
+            if (l0 + q < j) {
+                const double al = acoef[l0 + q], bl = bcoef[l0 + q];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    u[e] = __builtin_fma(-al, vv[q][e], u[e]);
+                    yv[e] = __builtin_fma(-bl, vv[q][e], yv[e]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int i = base + e * gstride;
+        if (i < n) {
+            double v = j > 0 ? u[e] / nu : u[e];
+            if (j > 0) vout[i] = v;
+            uout[i] = __builtin_fma(-gj, v, yv[e]) / nu;
+        }
+    }
+}
+
+// poll wave of every block: its rows of the Hessenberg matrix
+__device__ __forceinline__ void dcgs2_rows(const ArnoldiArgs& a, const double* hv, double nu, double gj) {
+    const int lane = threadIdx.x & 63, j = a.j, nb = a.nb, ld = a.ld, mx = a.maxit;
+    for (int r = blockIdx.x; r <= j; r += nb) {
+        double f = 0.0;                       // completed entry (r, j-1)
+        if (j >= 1) {
+            f = r < j ? a.HRp[(size_t)(j - 1) * ld + r] + hv[r] : nu;
+            if (lane == 0) a.HRf[(size_t)r * mx + (j - 1)] = f;
+        }
+        if (j >= mx) continue;
+        // sum_{m = max(0, r-1)}^{j-2} HRf(r, m) a_m, lanes over m, then a fixed tree
+        double part = 0.0;
+        for (int m = max(0, r - 1) + lane; m <= j - 2; m += 64)
+            part = __builtin_fma(a.HRf[(size_t)r * mx + m], hv[m], part);
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        if (lane == 0) {
+            double s = (r < j ? hv[j + 1 + r] : gj) - part;
+            if (j >= 1) s = __builtin_fma(-f, hv[j - 1], s);
+            a.HRp[(size_t)j * ld + r] = s / nu;
+        }
+    }
+}
+
+// poll wave of block 0, lane 0: Givens step on the completed column j - 1
+__device__ __forceinline__ void dcgs2_givens(const ArnoldiArgs& a, const double* hv, double nu, double* hh,
+                                             const double* csL, const double* snL) {
+    const int j = a.j, ld = a.ld;
+    for (int l = 0; l < j; ++l) hh[l] = a.HRp[(size_t)(j - 1) * ld + l] + hv[l];
+    hh[j] = nu;
+    for (int l = 0; l + 1 < j; ++l) {           // previous rotations
+        double x0 = hh[l], x1 = hh[l + 1];
+        hh[l] = csL[l] * x0 + snL[l] * x1;
+        hh[l + 1] = -snL[l] * x0 + csL[l] * x1;
+    }
+    const int c0 = j - 1;
+    double delta = hypot(hh[c0], hh[j]);
+    double c = hh[c0] / delta, sv = hh[j] / delta;
+    hh[c0] = delta;
+    hh[j] = 0.0;
+    double gc = a.g[c0];
+    a.g[j] = -sv * gc;
+    a.g[c0] = c * gc;
+    a.cs[c0] = c;
+    a.sn[c0] = sv;
+    double* Hc = a.H + (size_t)c0 * ld;
+    for (int l = 0; l <= j; ++l) Hc[l] = hh[l];
+    double ga = fabs(-sv * gc);
+    a.st->gabs = ga;
+    if (ga <= a.tau * a.st->beta0 || nu == 0.0) {
+        a.st->its = j;
+        a.st->done = 1;
+    } else if (j == a.maxit) {
+        a.st->its = j;
+        a.st->done = 2;
+    }
+}
+
+template <int EPT>
+__global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
+    extern __shared__ double dyn[];
+    __shared__ double nu_s, gj_s;
+    __shared__ int abort_flag;
+    if (a.st->done) return;                  // uniform: written by an earlier launch
+    const int b = blockIdx.x, t = threadIdx.x, nb = a.nb, lane = t & 63, wave = t >> 6;
+    const bool data = t < AT_DATA;
+    const int gstride = nb * AT_DATA;
+    const int base = b * AT_DATA + t;
+    const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
+    constexpr int DW = AT_DATA / 64;
+    // LDS: wpart [DW][rmax], pvec, hv [rmax], red [rmax + nb], hh [maxlinks], cs, sn [maxit]
+    double* wpart = dyn;
+    double* pvec = wpart + (size_t)DW * rmax;
+    double* hv = pvec + rmax;
+    double* red = hv + rmax;
+    double* hh = red + rmax + nb;
+    double* csL = hh + a.maxlinks;
+    double* snL = csL + a.maxit;
+    const size_t pw = dcgs2_parity_words(a.maxlinks, nb);
+    unsigned long long* cur = a.slots + (size_t)a.parity * pw;
+    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * pw;
+    const size_t blk = (size_t)rmax * nb;
+    // re-arm this block's words of the other buffer for the next launch (2j + 4 values)
+    for (int r = t; r < min(R + 2, rmax); r += AT) {
+        nxt[(size_t)r * nb + b] = SENTINEL;
+        nxt[blk + (size_t)b * rmax + r] = SENTINEL;
+    }
+    if (t == 0) abort_flag = 0;
+    if (b == 0)
+        for (int l = t; l + 1 < j; l += AT) {
+            csL[l] = a.cs[l];
+            snL[l] = a.sn[l];
+        }
+    double u[EPT], yv[EPT];
+    const double* uj = a.V + (size_t)j * n;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int i = base + e * gstride;
+        bool ok = data && i < n;
+        u[e] = ok ? uj[i] : 0.0;
+        yv[e] = ok ? a.y[i] : 0.0;
+    }
+    __syncthreads();
+    block_dots2<EPT>(a.V, n, j, u, yv, base, gstride, wpart, rmax, pvec);
+    grid_vsum(pvec, R, nb, cur, cur + blk, rmax, red, hv, &abort_flag);
+    if (abort_flag) {
+        if (t == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    if (wave == DW) {
+        double q = 0.0, ab = 0.0;
+        for (int l = lane; l < j; l += 64) {
+            q = __builtin_fma(hv[l], hv[l], q);
+            ab = __builtin_fma(hv[l], hv[j + 1 + l], ab);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            q += __shfl_xor(q, o, 64);
+            ab += __shfl_xor(ab, o, 64);
+        }
+        if (lane == 0) {
+            double nu = 1.0;
+            if (j > 0) {
+                double qq = hv[j] - q;
+                nu = qq > 0.0 ? __builtin_sqrt(qq) : 0.0;
+            }
+            nu_s = nu;
+            gj_s = (hv[2 * j + 1] - ab) / nu;
+        }
+    }
+    __syncthreads();
+    const double nu = nu_s, gj = gj_s;
+    if (wave < DW) {
+        if (j < a.maxit)
+            dcgs2_update<EPT>(a.V, n, j, u, yv, hv, hv + j + 1, nu, gj, base, gstride, a.V + (size_t)j * n,
+                              a.V + (size_t)(j + 1) * n);
+    } else {
+        dcgs2_rows(a, hv, nu, gj);
+        if (b == 0 && j >= 1 && lane == 0) dcgs2_givens(a, hv, nu, hh, csL, snL);
+    }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, size_t len, unsigned long long v) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) p[i] = v;
@@ -787,15 +1080,30 @@ static int reduce_blocks(int n) {
     return std::max(1, std::min(b, RBLOCKS));
 }
 
+template <int VP>
+static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
+                      const SolveState* st) {
+    using T = typename ValType<VP>::T;
+    const T* pv = (const T*)P->val;
+    const unsigned grid = (unsigned)(((long long)n * g + 255) / 256);
+    switch (g) {
+    case 1: hipLaunchKernelGGL((k_apply_P_g<VP, 1>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
+    case 2: hipLaunchKernelGGL((k_apply_P_g<VP, 2>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
+    case 4: hipLaunchKernelGGL((k_apply_P_g<VP, 4>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
+    case 8: hipLaunchKernelGGL((k_apply_P_g<VP, 8>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
+    default: hipLaunchKernelGGL((k_apply_P_g<VP, 16>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
+    }
+}
+
 static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
                           const SolveState* st = nullptr) {
-    int n = P->n, g = blocks_for(n, 256);
+    const int n = P->n, g = lanes_per_row(P->nnz, n);
     long tk = timer_begin(h, SPAI_KT_APPLY_P);
     switch (P->val_prec) {
-    case SPAI_FP64: hipLaunchKernelGGL(k_apply_P<SPAI_FP64>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const double*)P->val, P->d, w, y, st); break;
-    case SPAI_FP32: hipLaunchKernelGGL(k_apply_P<SPAI_FP32>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const float*)P->val, P->d, w, y, st); break;
-    case SPAI_FP16: hipLaunchKernelGGL(k_apply_P<SPAI_FP16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __half*)P->val, P->d, w, y, st); break;
-    default: hipLaunchKernelGGL(k_apply_P<SPAI_BF16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __hip_bfloat16*)P->val, P->d, w, y, st); break;
+    case SPAI_FP64: apply_P_g<SPAI_FP64>(g, n, P, w, y, s, st); break;
+    case SPAI_FP32: apply_P_g<SPAI_FP32>(g, n, P, w, y, s, st); break;
+    case SPAI_FP16: apply_P_g<SPAI_FP16>(g, n, P, w, y, s, st); break;
+    default: apply_P_g<SPAI_BF16>(g, n, P, w, y, s, st); break;
     }
     timer_end(h, SPAI_KT_APPLY_P, tk);
     SPAI_HIP(hipGetLastError());
@@ -804,9 +1112,16 @@ static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w
 
 static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
                        const SolveState* st = nullptr) {
-    int n = A->n;
+    const int n = A->n, g = lanes_per_row(A->nnz, n);
+    const unsigned grid = (unsigned)(((long long)n * g + 255) / 256);
     long tk = timer_begin(h, SPAI_KT_SPMV_A);
-    hipLaunchKernelGGL(k_spmv, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st);
+    switch (g) {
+    case 1: hipLaunchKernelGGL(k_spmv_g<1>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
+    case 2: hipLaunchKernelGGL(k_spmv_g<2>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
+    case 4: hipLaunchKernelGGL(k_spmv_g<4>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
+    case 8: hipLaunchKernelGGL(k_spmv_g<8>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
+    default: hipLaunchKernelGGL(k_spmv_g<16>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
+    }
     timer_end(h, SPAI_KT_SPMV_A, tk);
     SPAI_HIP(hipGetLastError());
     return SPAI_OK;
@@ -855,7 +1170,11 @@ struct ArnoldiCfg {
 
 template <int EPT>
 static const void* arnoldi_fn(int ortho) {
-    return ortho == SPAI_ORTHO_CGS2 ? (const void*)k_arnoldi_cgs2<EPT> : (const void*)k_arnoldi<EPT>;
+    switch (ortho) {
+    case SPAI_ORTHO_CGS2: return (const void*)k_arnoldi_cgs2<EPT>;
+    case SPAI_ORTHO_DCGS2: return (const void*)k_arnoldi_dcgs2<EPT>;
+    default: return (const void*)k_arnoldi<EPT>;
+    }
 }
 
 static const void* arnoldi_fn(int ortho, int ept) {
@@ -884,8 +1203,8 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
     // MGS: half the CUs (the grid-wide sums get cheaper with fewer blocks while half
     // the chip still streams the basis fast enough); CGS2 streams the basis four
     // times per step and uses every CU
-    int nb = ortho == SPAI_ORTHO_CGS2 ? std::min(std::min(h->num_cu, MAX_NB), rows_nb)
-                                      : std::min(std::min(std::max(1, h->num_cu / 2), MAX_NB), rows_nb);
+    int nb = ortho != SPAI_ORTHO_MGS ? std::min(std::min(h->num_cu, MAX_NB), rows_nb)
+                                     : std::min(std::min(std::max(1, h->num_cu / 2), MAX_NB), rows_nb);
     if (const char* e = getenv("SPAI_ARNOLDI_BLOCKS")) {
         int want = atoi(e);
         if (want >= 1 && want <= MAX_NB) nb = std::min(want, rows_nb);
@@ -896,6 +1215,10 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
     if (ortho == SPAI_ORTHO_CGS2) {
         c.shmem = sizeof(double) * ((size_t)(AT_DATA / 64 + 4) * maxlinks + nb + 2 * (size_t)maxit);
         c.slot_words = 2 * cgs2_parity_words(maxlinks, nb);
+    } else if (ortho == SPAI_ORTHO_DCGS2) {
+        const size_t rmax = 2 * (size_t)maxlinks;   // wpart [DW][rmax], pvec, hv, red, hh, cs, sn
+        c.shmem = sizeof(double) * ((AT_DATA / 64 + 3) * rmax + nb + maxlinks + 2 * (size_t)maxit);
+        c.slot_words = 2 * dcgs2_parity_words(maxlinks, nb);
     } else {
         c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
         c.slot_words = (size_t)2 * maxlinks * nb * (1 + MBOX_STRIDE);
@@ -939,14 +1262,15 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     SPAI_ARG(prm->maxit >= 1, "maxit must be positive");
     SPAI_ARG(prm->tau >= 0.0, "tau must be non-negative");
     SPAI_ARG(prm->u_r == SPAI_DD || prm->u_r == SPAI_FP64, "u_r must be DD or FP64");
-    SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS || prm->ortho == SPAI_ORTHO_CGS2, "ortho must be MGS or CGS2");
+    SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS || prm->ortho == SPAI_ORTHO_CGS2 || prm->ortho == SPAI_ORTHO_DCGS2,
+             "ortho must be MGS, CGS2 or DCGS2");
     SPAI_HIP(hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const int maxit = std::min(prm->maxit, n);
     const int ld = maxit + 1;
     const ArnoldiCfg cfg = arnoldi_config(h, n, maxit, prm->ortho);
     SPAI_ARG(cfg.nb > 0 || prm->ortho == SPAI_ORTHO_MGS,
-             "CGS2 needs the cooperative Arnoldi kernel, which cannot hold this problem");
+             "CGS2 and DCGS2 need the cooperative Arnoldi kernel, which cannot hold this problem");
     const int maxlinks = maxit + 2;
 
     // workspace
@@ -955,7 +1279,9 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     rc = buffer_reserve(h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
     if (rc) return rc;
     size_t slot_count = cfg.slot_words;
-    size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count);
+    const bool dcgs2 = prm->ortho == SPAI_ORTHO_DCGS2;
+    const size_t hr_words = dcgs2 ? 2 * (size_t)ld * maxit : 0;   // HRp, HRf
+    size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count + hr_words);
     rc = buffer_reserve(h->ws[WS_SOLVE_H], hbytes);
     if (rc) return rc;
     double* V = (double*)h->ws[WS_SOLVE_V].ptr;
@@ -973,6 +1299,8 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     unsigned long long* maxbits = (unsigned long long*)(scal + 16);
     unsigned* ticket = (unsigned*)(scal + 24);
     unsigned long long* slots = (unsigned long long*)(scal + 64);
+    double* HRp = (double*)(slots + slot_count);
+    double* HRf = HRp + (size_t)ld * maxit;
     char* hp = (char*)h->host_pinned.ptr;
 
     const int tb = 256, gb = blocks_for(n, tb);
@@ -1007,11 +1335,12 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
         SPAI_HIP(hipGetLastError());
         SolveState ss{};
         int sweep = 0;
-        for (int j0 = 0; j0 < maxit; j0 += chunk) {
-            int j1 = std::min(j0 + chunk, maxit);
+        // DCGS2 completes column j - 1 in launch j: launches 0 .. maxit
+        const int jend = dcgs2 ? maxit + 1 : maxit;
+        for (int j0 = 0; j0 < jend; j0 += chunk) {
+            int j1 = std::min(j0 + chunk, jend);
             for (int j = j0; j < j1; ++j) {
                 double* vj = V + (size_t)j * n;
-                double* hcol = H + (size_t)j * ld;
                 if ((rc = launch_spmv(h, A, vj, w, s, sst))) return rc;
                 if ((rc = launch_apply_P(h, P, w, y, s, sst))) return rc;
                 if (cfg.nb) {
@@ -1019,11 +1348,12 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
                     aa.n = n; aa.j = j; aa.ld = ld; aa.maxit = maxit; aa.maxlinks = maxlinks; aa.nb = cfg.nb;
                     aa.parity = sweep & 1;
                     aa.y = y; aa.V = V; aa.H = H; aa.cs = cs; aa.sn = sn; aa.g = g; aa.tau = prm->tau;
-                    aa.slots = slots; aa.st = sst;
+                    aa.slots = slots; aa.st = sst; aa.HRp = HRp; aa.HRf = HRf;
                     if ((rc = launch_arnoldi(h, cfg, aa, s))) return rc;
                     ++sweep;
                 } else {
                     // one launch per projection: h_lj = <y, v_l>, y -= h_lj v_l, l = 0..j
+                    double* hcol = H + (size_t)j * ld;
                     for (int l = 0; l <= j; ++l) {
                         const double* vprev = l > 0 ? V + (size_t)(l - 1) * n : nullptr;
                         const double* hprev = l > 0 ? hcol + (l - 1) : nullptr;
@@ -1147,10 +1477,8 @@ extern "C" int spai_spmv(spai_handle* h, const spai_csr* A, const double* x, dou
     int rc = spai::check_csr(A);
     if (rc) return rc;
     SPAI_HIP(hipSetDevice(h->device));
-    int n = A->n;
-    hipLaunchKernelGGL(spai::k_spmv, dim3((n + 255) / 256), dim3(256), 0, h->stream, n, A->rowptr, A->col,
-                       A->val, x, y, (const spai::SolveState*)nullptr);
-    SPAI_HIP(hipGetLastError());
+    rc = spai::launch_spmv(h, A, x, y, h->stream);
+    if (rc) return rc;
     SPAI_HIP(hipStreamSynchronize(h->stream));
     return SPAI_OK;
 }

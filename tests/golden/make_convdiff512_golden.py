@@ -2,7 +2,8 @@
 
 Calls only oracle/ (and the shared input generators): the full adaptive FP32
 SPAI build (digests of every column's insertion-ordered indices and values)
-and the SPAI-GMRES-IR solve (iteration tuple, errors).  Output:
+and the SPAI-GMRES-IR solve with each Arnoldi orthogonalisation (MGS, CGS2,
+delayed CGS2: iteration tuples, errors).  Output:
 convdiff512_oracle.json next to this script.  Takes a few minutes (the oracle's
 GMRES is single-threaded).
 
@@ -38,6 +39,8 @@ def main():
     t2 = time.time()
     res2 = O.gmres_ir(w.A, pp, pc, pv, R.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "cgs2")
     t3 = time.time()
+    res3 = O.gmres_ir(w.A, pp, pc, pv, R.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dcgs2")
+    t4 = time.time()
     out = {
         "workload": w.name,
         "recipe": w.recipe,
@@ -60,7 +63,10 @@ def main():
         "nbe": O.nbe(w.A, w.b, res.x),
         "its_cgs2": res2.its,
         "ferr_cgs2": O.ferr(res2.x, w.x_true),
-        "oracle_seconds": {"spai": t1 - t0, "gmres_ir": t2 - t1, "gmres_ir_cgs2": t3 - t2},
+        "its_dcgs2": res3.its,
+        "ferr_dcgs2": O.ferr(res3.x, w.x_true),
+        "oracle_seconds": {"spai": t1 - t0, "gmres_ir": t2 - t1, "gmres_ir_cgs2": t3 - t2,
+                           "gmres_ir_dcgs2": t4 - t3},
     }
     path = os.path.join(HERE, "convdiff512_oracle.json")
     with open(path, "w") as f:

@@ -380,27 +380,47 @@ def test_projection_fallback_path_agrees(S, h, monkeypatch):
     assert np.abs(x1 - x2).max() <= 1e-13 * np.abs(w.x_true).max()
 
 
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
 @pytest.mark.parametrize("make", [W.convdiff_small, lambda: W.convdiff_adaptive(56), lambda: W.aniso_fixed(10, "fp32"),
                                   lambda: W.random_system(2500, 9)])
-def test_gmres_ir_cgs2_matches_oracle(S, h, make):
-    """CGS2 Arnoldi: the same iteration tuple as the oracle's CGS2 GMRES-IR and
-    forward error <= 1e-12."""
+def test_gmres_ir_other_orthogonalisations_match_oracle(S, h, make, ortho):
+    """CGS2 and delayed CGS2 Arnoldi: the same iteration tuple as the oracle's
+    GMRES-IR with the same orthogonalisation, forward error <= 1e-12."""
     w = make()
     A, P, warn, stats = _build(S, h, w)
     s, ir = w.spai, w.ir
     ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
     pp, pc, pv = ref.P_csr(w.n)
-    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "cgs2")
-    x, st = _solve(S, h, w, A, P, ortho="cgs2")
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, ortho)
+    x, st = _solve(S, h, w, A, P, ortho=ortho)
     assert st["its"] == oref.its
     assert O.ferr(x, w.x_true) <= 1e-12
     assert np.abs(x - oref.x).max() <= 1e-12 * np.abs(w.x_true).max()
 
 
-def test_full_size_solve_cgs2_matches_oracle_tuple(S, h, full):
-    """CGS2 at full size: the oracle's CGS2 tuple (stored by the golden script)."""
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_full_size_solve_other_orthogonalisations_match_oracle_tuple(S, h, full, ortho):
+    """CGS2 / delayed CGS2 at full size: the oracle's tuple for the same
+    orthogonalisation (stored by the golden script)."""
     w, A, P, stats = full
-    x, st = _solve(S, h, w, A, P, ortho="cgs2")
+    x, st = _solve(S, h, w, A, P, ortho=ortho)
     g = _golden512()
-    assert st["its"] == g["its_cgs2"]
+    assert st["its"] == g[f"its_{ortho}"]
     assert O.ferr(x, w.x_true) <= 1e-12
+
+
+def test_dcgs2_maxit_cap(S, h):
+    """Delayed CGS2 when GMRES stops at maxit: the completing launch j = maxit
+    reports SPAI_W_MAXIT and the same iterations as the oracle."""
+    w = W.convdiff_adaptive(40)
+    A, P, warn, stats = _build(S, h, w)
+    s, ir = w.spai, w.ir
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, 3, 12, ir.tol_ir, "dcgs2")
+    b = _dev(w.b)
+    x = torch.zeros_like(b)
+    st = h.gmres_ir(A, P, b, x, ir.tau, 3, 12, ir.tol_ir, "dd", "dcgs2")
+    assert st["its"] == oref.its == [12] * len(oref.its)
+    assert st["status"] & S.W_MAXIT
+    assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()

@@ -372,7 +372,7 @@ def test_fp32_and_fp64_spai_give_similar_preconditioners():
 # GMRES-IR
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("ortho", ["mgs", "cgs2"])
+@pytest.mark.parametrize("ortho", ["mgs", "cgs2", "dcgs2"])
 def test_gmres_step_is_the_krylov_least_squares_minimiser(ortho):
     """After k iterations (tau = 0) GMRES (MGS or CGS2 Arnoldi) returns
     d = argmin over K_k(PA, z) of ||z - PA d||_2 with z = P r0; checked against

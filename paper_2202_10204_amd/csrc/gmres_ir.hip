@@ -12,6 +12,8 @@
 #include <cstring>
 #include <string>
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace spai {
@@ -181,6 +183,42 @@ __global__ void k_residual(int n, const int* __restrict__ rp, const int* __restr
 // maxit.
 // ---------------------------------------------------------------------------
 
+// Sum of one double over the 64 lanes of a wave (all lanes active), the same
+// bits in every lane: row sums of 16 lanes by DPP moves (quad_perm xor 1, xor 2,
+// row_ror 4, row_ror 8; no LDS round trip), then the four row sums read with
+// readlane and added in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_mov<0xB1>(v);     // quad_perm(1, 0, 3, 2)
+    v += dpp_mov<0x4E>(v);     // quad_perm(2, 3, 0, 1)
+    v += dpp_mov<0x124>(v);    // row_ror:4
+    v += dpp_mov<0x128>(v);    // row_ror:8
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Load p[i] where ok, else 0, with an unconditional load of a valid address
+// (p[0] is always valid): the loads of a group then stay in one basic block.
+__device__ __forceinline__ double ld0(const double* __restrict__ p, size_t i, bool ok) {
+    const double v = p[ok ? i : 0];
+    return ok ? v : 0.0;
+}
+
+// Index for a prefetch: i where ok, else 0 (a valid address).  The raw value is
+// kept and masked only where it is used, so that no wait is placed between the
+// prefetch and the work it overlaps.
+__device__ __forceinline__ size_t pf_index(size_t i, bool ok) { return ok ? i : 0; }
+
 constexpr int AT_DATA = 512;          // threads that hold y and stream the basis (8 waves)
 constexpr int AT = AT_DATA + 64;      // plus one wave that only publishes and polls
 constexpr int MAX_NB = 256;           // blocks of the Arnoldi kernel (4 slots per poll lane)
@@ -227,7 +265,7 @@ __device__ __forceinline__ double grid_sum(double part, unsigned long long* slot
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     constexpr int DW = AT_DATA / 64;
     if (wave < DW) {
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        part = wave_sum(part);
         if (lane == 0) wsum[wave] = part;
     }
     __syncthreads();
@@ -271,7 +309,7 @@ __device__ __forceinline__ double grid_sum(double part, unsigned long long* slot
 #pragma unroll
             for (int k = 0; k < MAX_NB / 64; ++k)
                 if (lane + 64 * k < nb) val += __longlong_as_double((long long)v[k]);
-            for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
+            val = wave_sum(val);
             const unsigned long long bits = timeout ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(val);
 #pragma unroll
             for (int k = 0; k < MAX_NB / 64; ++k) {
@@ -289,6 +327,126 @@ __device__ __forceinline__ double grid_sum(double part, unsigned long long* slot
     }
     __syncthreads();
     return *total;
+}
+
+// Apply the Givens rotations 0..m-1 in order to the column hh[0..m]; the
+// running entry is carried in a register (same operations as rotating hh in
+// place, without a round trip through memory per rotation).
+// The operands of 8 rotations are loaded together, so that one LDS latency is
+// paid per 8 rotations instead of one per rotation.
+__device__ __forceinline__ void apply_rotations(double* hh, int m, const double* csL, const double* snL) {
+    if (m <= 0) return;
+    double x0 = hh[0];
+    for (int l0 = 0; l0 < m; l0 += 8) {
+        double x1[8], c[8], s[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int l = min(l0 + k, m - 1);
+            x1[k] = hh[l + 1];
+            c[k] = csL[l];
+            s[k] = snL[l];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (l0 + k < m) {
+                hh[l0 + k] = c[k] * x0 + s[k] * x1[k];
+                x0 = -s[k] * x0 + c[k] * x1[k];
+            }
+        }
+    }
+    hh[m] = x0;
+}
+
+// The same rotations applied by the 64 lanes of one wave: lane L owns a
+// segment of at most ROT_SEG consecutive rotations; the carried entry obeys the
+// affine recurrence x_{l+1} = -s_l x_l + c_l h_{l+1}, whose maps are composed
+// over the lanes by an inclusive scan (Kogge-Stone, fixed order), so every lane
+// obtains its incoming carry in 6 steps instead of waiting for the whole chain.
+// The rounding differs from the sequential order only in how the carry is
+// associated.  hh must be visible to the whole wave; on return the rotated
+// entries are.
+constexpr int ROT_SEG = 8;
+
+__device__ __forceinline__ void wave_rotate(double* hh, int m, const double* csL, const double* snL) {
+    const int lane = threadIdx.x & 63;
+    if (m <= 0) return;
+    if (m > 64 * ROT_SEG) {
+        if (lane == 0) apply_rotations(hh, m, csL, snL);
+        wave_sync();
+        return;
+    }
+    const int seg = (m + 63) / 64;
+    const int lo = min(lane * seg, m), hi = min(lo + seg, m);
+    double cv[ROT_SEG], sv[ROT_SEG], xv[ROT_SEG];
+    double A = 1.0, B = 0.0;
+#pragma unroll
+    for (int k = 0; k < ROT_SEG; ++k) {
+        cv[k] = 1.0;
+        sv[k] = 0.0;
+        xv[k] = 0.0;
+        if (lo + k < hi) {
+            cv[k] = csL[lo + k];
+            sv[k] = snL[lo + k];
+            xv[k] = hh[lo + k + 1];
+            A = -sv[k] * A;
+            B = -sv[k] * B + cv[k] * xv[k];
+        }
+    }
+    for (int d = 1; d < 64; d <<= 1) {       // maps of the lanes before come first
+        const double Ap = __shfl_up(A, d, 64), Bp = __shfl_up(B, d, 64);
+        if (lane >= d) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    const double x00 = hh[0];
+    const double Ae = __shfl_up(A, 1, 64), Be = __shfl_up(B, 1, 64);
+    double x0 = lane == 0 ? x00 : Ae * x00 + Be;
+    wave_sync();                              // every read of hh before any write
+#pragma unroll
+    for (int k = 0; k < ROT_SEG; ++k) {
+        if (lo + k < hi) {
+            hh[lo + k] = cv[k] * x0 + sv[k] * xv[k];
+            x0 = -sv[k] * x0 + cv[k] * xv[k];
+        }
+    }
+    if (lo < hi && hi == m) hh[m] = x0;
+    wave_sync();
+}
+
+// One wave completes column c of the Hessenberg matrix: hh[0..c+1] holds it
+// before rotation (visible to the wave).  Applies rotations 0..c-1, builds
+// rotation c, updates g, writes the rotated column into H and takes the
+// stopping decision (|g_{c+1}| <= tau beta0 or a zero subdiagonal: converged;
+// c + 1 = maxit: iteration cap).
+__device__ __forceinline__ void wave_givens_column(const ArnoldiArgs& a, double* hh, int c, const double* csL,
+                                                   const double* snL) {
+    const int lane = threadIdx.x & 63;
+    wave_rotate(hh, c, csL, snL);
+    if (lane == 0) {
+        const double hs = hh[c + 1];
+        const double delta = hypot(hh[c], hs);
+        const double cc = hh[c] / delta, sv = hs / delta;
+        hh[c] = delta;
+        hh[c + 1] = 0.0;
+        const double gc = a.g[c];
+        a.g[c + 1] = -sv * gc;
+        a.g[c] = cc * gc;
+        a.cs[c] = cc;
+        a.sn[c] = sv;
+        const double ga = fabs(-sv * gc);
+        a.st->gabs = ga;
+        if (ga <= a.tau * a.st->beta0 || hs == 0.0) {
+            a.st->its = c + 1;
+            a.st->done = 1;
+        } else if (c + 1 == a.maxit) {
+            a.st->its = c + 1;
+            a.st->done = 2;
+        }
+    }
+    wave_sync();
+    double* Hc = a.H + (size_t)c * a.ld;
+    for (int l = lane; l <= c + 1; l += 64) Hc[l] = hh[l];
 }
 
 template <int EPT>
@@ -330,8 +488,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
     for (int e = 0; e < EPT; ++e) {
         int i = base + e * gstride;
         bool ok = data && i < n;
-        y[e] = ok ? a.y[i] : 0.0;
-        v[e] = ok ? a.V[i] : 0.0;
+        y[e] = ld0(a.y, i, ok);
+        v[e] = ld0(a.V, i, ok);
         vn[e] = 0.0;
     }
     __syncthreads();
@@ -342,7 +500,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 int i = base + e * gstride;
-                vn[e] = (data && i < n) ? vnext[i] : 0.0;
+                vn[e] = vnext[pf_index(i, data && i < n)];   // masked where used
             }
         }
         double part = 0.0;
@@ -354,7 +512,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             y[e] = __builtin_fma(-h, v[e], y[e]);
-            v[e] = vn[e];
+            v[e] = (data && base + e * gstride < n) ? vn[e] : 0.0;
         }
         if (b == 0 && t == 0) hcol[l] = h;
     }
@@ -380,34 +538,10 @@ __global__ __launch_bounds__(AT) void k_arnoldi(ArnoldiArgs a) {
         int i = base + e * gstride;
         if (data && i < n) vout[i] = y[e] / hn;
     }
-    if (b == 0 && t == 0) {
-        double* hh = hcol;
-        hh[j + 1] = hn;
-        for (int l = 0; l < j; ++l) {           // previous rotations
-            double x0 = hh[l], x1 = hh[l + 1];
-            hh[l] = csL[l] * x0 + snL[l] * x1;
-            hh[l + 1] = -snL[l] * x0 + csL[l] * x1;
-        }
-        double delta = hypot(hh[j], hh[j + 1]);
-        double c = hh[j] / delta, s = hh[j + 1] / delta;
-        hh[j] = delta;
-        hh[j + 1] = 0.0;
-        double gj = a.g[j];
-        a.g[j + 1] = -s * gj;
-        a.g[j] = c * gj;
-        a.cs[j] = c;
-        a.sn[j] = s;
-        double* Hc = a.H + (size_t)j * a.ld;
-        for (int l = 0; l <= j + 1; ++l) Hc[l] = hh[l];
-        double ga = fabs(-s * gj);
-        a.st->gabs = ga;
-        if (ga <= a.tau * a.st->beta0 || hn == 0.0) {
-            a.st->its = j + 1;
-            a.st->done = 1;
-        } else if (j + 1 == a.maxit) {
-            a.st->its = j + 1;
-            a.st->done = 2;
-        }
+    if (b == 0 && t < 64) {
+        if (t == 0) hcol[j + 1] = hn;
+        wave_sync();
+        wave_givens_column(a, hcol, j, csL, snL);
     }
 }
 
@@ -442,14 +576,14 @@ __device__ __forceinline__ void block_vty(const double* __restrict__ V, int n, i
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
                     int i = base + e * gstride;
-                    vv[u][e] = (l0 + u < L && i < n) ? V[(size_t)(l0 + u) * n + i] : 0.0;
+                    vv[u][e] = ld0(V + (size_t)min(l0 + u, L - 1) * n, i, l0 + u < L && i < n);
                 }
 #pragma unroll
             for (int u = 0; u < CG_U; ++u) {
                 double p = 0.0;
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) p = __builtin_fma(vv[u][e], y[e], p);
-                for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+                p = wave_sum(p);
                 if (lane == 0 && l0 + u < L) wpart[wave * ldw + l0 + u] = p;
             }
         }
@@ -476,7 +610,7 @@ __device__ __forceinline__ void y_minus_Vh(const double* __restrict__ V, int n, 
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 int i = base + e * gstride;
-                vv[u][e] = (l0 + u < L && i < n) ? V[(size_t)(l0 + u) * n + i] : 0.0;
+                vv[u][e] = ld0(V + (size_t)min(l0 + u, L - 1) * n, i, l0 + u < L && i < n);
             }
 #pragma unroll
         for (int u = 0; u < CG_U; ++u) {
@@ -509,7 +643,7 @@ __device__ __forceinline__ void grid_vsum(const double* pvec, int L, int nb, uns
     for (int k = wave; k < owned; k += AT / 64) {
         double acc = 0.0;
         for (int src = lane; src < nb; src += 64) acc += red[k * nb + src];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        acc = wave_sum(acc);
         const int l = b + k * nb;
         const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
         for (int q = lane; q < nb; q += 64)
@@ -575,7 +709,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_cgs2(ArnoldiArgs a) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         int i = base + e * gstride;
-        y[e] = (data && i < n) ? a.y[i] : 0.0;
+        y[e] = ld0(a.y, i, data && i < n);
     }
     __syncthreads();
     block_vty<EPT>(a.V, n, L, y, base, gstride, wpart, lmax, pvec);
@@ -607,35 +741,12 @@ __global__ __launch_bounds__(AT) void k_arnoldi_cgs2(ArnoldiArgs a) {
         int i = base + e * gstride;
         if (data && i < n) vout[i] = y[e] / hn;
     }
-    if (b == 0 && t == 0) {
+    if (b == 0 && t < 64) {
         double* hh = pvec;                      // free now: column j of H
-        for (int l = 0; l < L; ++l) hh[l] = h1[l] + h2[l];
-        hh[j + 1] = hn;
-        for (int l = 0; l < j; ++l) {           // previous rotations
-            double x0 = hh[l], x1 = hh[l + 1];
-            hh[l] = csL[l] * x0 + snL[l] * x1;
-            hh[l + 1] = -snL[l] * x0 + csL[l] * x1;
-        }
-        double delta = hypot(hh[j], hh[j + 1]);
-        double c = hh[j] / delta, sv = hh[j + 1] / delta;
-        hh[j] = delta;
-        hh[j + 1] = 0.0;
-        double gj = a.g[j];
-        a.g[j + 1] = -sv * gj;
-        a.g[j] = c * gj;
-        a.cs[j] = c;
-        a.sn[j] = sv;
-        double* Hc = a.H + (size_t)j * a.ld;
-        for (int l = 0; l <= j + 1; ++l) Hc[l] = hh[l];
-        double ga = fabs(-sv * gj);
-        a.st->gabs = ga;
-        if (ga <= a.tau * a.st->beta0 || hn == 0.0) {
-            a.st->its = j + 1;
-            a.st->done = 1;
-        } else if (j + 1 == a.maxit) {
-            a.st->its = j + 1;
-            a.st->done = 2;
-        }
+        for (int l = t; l < L; l += 64) hh[l] = h1[l] + h2[l];
+        if (t == 0) hh[j + 1] = hn;
+        wave_sync();
+        wave_givens_column(a, hh, j, csL, snL);
     }
 }
 
@@ -659,47 +770,107 @@ __global__ __launch_bounds__(AT) void k_arnoldi_cgs2(ArnoldiArgs a) {
 // the Givens rotations to column j - 1 and takes the stopping decision.
 // ---------------------------------------------------------------------------
 
+// first LDS region of the DCGS2 kernel, in doubles
+__host__ __device__ constexpr size_t dcgs2_front_words(int ept, int rmax) {
+    return ept <= 8 ? (size_t)2 * AT_DATA * ept : (size_t)(AT_DATA / 64) * rmax;
+}
+
 // slot words of one parity for the DCGS2 kernel: [rmax][nb] slots + [nb][rmax] mailboxes
 __host__ __device__ inline size_t dcgs2_parity_words(int maxlinks, int nb) {
     return (size_t)2 * (2 * (size_t)maxlinks) * nb;
 }
 
-// pass 1: per-block partials of the 2j + 2 inner products into pvec
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Sum NV per-lane values over the 64 lanes of a wave with NV - 1 + 6 - log2(NV)
+// exchanges instead of 6 NV: halving exchanges (lane L keeps the half of the
+// values selected by its bit, adds its partner's copy of that half), then a
+// full xor reduction over the remaining low lane bits.  Returns the total of
+// value `idx` (set on return) in every lane; the lanes with
+// (lane & (64 / NV - 1)) == 0 are the writers, one per value.  The schedule is
+// fixed, so the bits of a total do not depend on timing.
+template <int NV>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[NV], int lane, int& idx) {
+    constexpr int S = ilog2(NV);
+    idx = 0;
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+        const int h = NV >> (st + 1), mask = 32 >> st;
+        const bool hi = (lane & mask) != 0;
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+            const double send = hi ? v[k] : v[k + h];
+            const double keep = hi ? v[k + h] : v[k];
+            v[k] = keep + __shfl_xor(send, mask, 64);
+        }
+        if (hi) idx += h;
+    }
+    double r = v[0];
+#pragma unroll
+    for (int mask = 32 >> S; mask > 0; mask >>= 1) r += __shfl_xor(r, mask, 64);
+    return r;
+}
+
+// basis vectors per group in the double-buffered passes: 16 doubles per buffer
+// and thread (32 loads in flight per thread with two buffers)
+template <int EPT>
+constexpr int cg_u2() { return EPT >= 16 ? 1 : 16 / EPT; }
+
+// raw loads of basis vectors l0 .. l0+U-1 (< lim) at the thread's rows; entries
+// outside (columns >= lim, rows >= n) are loaded from a valid address and must
+// not be used
+template <int EPT, int U>
+__device__ __forceinline__ void load_cols(const double* __restrict__ V, int n, int l0, int lim, int base, int gstride,
+                                          double (&vv)[U][EPT]) {
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            int i = base + e * gstride;
+            vv[q][e] = V[(size_t)min(l0 + q, lim - 1) * n + pf_index(i, i < n)];
+        }
+}
+
+// pass 1: per-block partials of the 2j + 2 inner products into pvec (the next
+// group of basis vectors is loaded while the current one is reduced)
 template <int EPT>
 __device__ __forceinline__ void block_dots2(const double* __restrict__ V, int n, int j, const double (&u)[EPT],
                                             const double (&yv)[EPT], int base, int gstride, double* wpart, int ldw,
                                             double* pvec) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     constexpr int DW = AT_DATA / 64;
-    constexpr int CG_U = cg_u<EPT>();
+    constexpr int CG_U = cg_u2<EPT>();
+    constexpr int NV = 2 * CG_U;
+    constexpr int GRP = 64 / NV;             // lanes that share one value after the reduction
     if (wave < DW) {
         double* wp = wpart + (size_t)wave * ldw;
+        double vv[CG_U][EPT], vn[CG_U][EPT];
+        if (j > 0) load_cols<EPT, CG_U>(V, n, 0, j, base, gstride, vv);
         for (int l0 = 0; l0 < j; l0 += CG_U) {
-            double vv[CG_U][EPT];
-#pragma unroll
-            for (int q = 0; q < CG_U; ++q)
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) {
-                    int i = base + e * gstride;
-                    vv[q][e] = (l0 + q < j && i < n) ? V[(size_t)(l0 + q) * n + i] : 0.0;
-                }
+            if (l0 + CG_U < j) load_cols<EPT, CG_U>(V, n, l0 + CG_U, j, base, gstride, vn);
+            double p[NV];
 #pragma unroll
             for (int q = 0; q < CG_U; ++q) {
                 double p1 = 0.0, p2 = 0.0;
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
-                    p1 = __builtin_fma(vv[q][e], u[e], p1);
-                    p2 = __builtin_fma(vv[q][e], yv[e], p2);
+                    const double vk = base + e * gstride < n ? vv[q][e] : 0.0;
+                    p1 = __builtin_fma(vk, u[e], p1);
+                    p2 = __builtin_fma(vk, yv[e], p2);
                 }
-                for (int o = 32; o > 0; o >>= 1) {
-                    p1 += __shfl_xor(p1, o, 64);
-                    p2 += __shfl_xor(p2, o, 64);
-                }
-                if (lane == 0 && l0 + q < j) {
-                    wp[l0 + q] = p1;
-                    wp[j + 1 + l0 + q] = p2;
-                }
+                p[q] = p1;
+                p[CG_U + q] = p2;
             }
+            int idx;
+            const double tot = wave_reduce_scatter<NV>(p, lane, idx);
+            if ((lane & (GRP - 1)) == 0) {
+                const int q = idx < CG_U ? idx : idx - CG_U;
+                if (l0 + q < j) wp[(idx < CG_U ? 0 : j + 1) + l0 + q] = tot;
+            }
+#pragma unroll
+            for (int q = 0; q < CG_U; ++q)
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) vv[q][e] = vn[q][e];
         }
         double om = 0.0, c = 0.0;
 #pragma unroll
@@ -707,10 +878,8 @@ __device__ __forceinline__ void block_dots2(const double* __restrict__ V, int n,
             om = __builtin_fma(u[e], u[e], om);
             c = __builtin_fma(u[e], yv[e], c);
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            om += __shfl_xor(om, o, 64);
-            c += __shfl_xor(c, o, 64);
-        }
+        om = wave_sum(om);
+        c = wave_sum(c);
         if (lane == 0) {
             wp[j] = om;
             wp[2 * j + 1] = c;
@@ -726,24 +895,165 @@ __device__ __forceinline__ void block_dots2(const double* __restrict__ V, int n,
     __syncthreads();
 }
 
-// pass 2 (data waves): u and yv are consumed in place
+// pass 1 with one wave per basis vector: wave w takes the vectors l = w,
+// w + 8, ... over all rows of the block (8 EPT rows per lane; (u_i, y_i) staged
+// in LDS in the row order of the data threads), so that every block partial is
+// reduced once, by one wave; the loads of the next chunk of 8 rows are in
+// flight while the current chunk is used.  For EPT <= 8 (the staging takes
+// 16 KB per EPT of LDS).
+template <int EPT>
+__device__ __forceinline__ void block_dots_cols(const double* __restrict__ V, int n, int j, const double (&u)[EPT],
+                                                const double (&yv)[EPT], int gstride, double2* uy, double* wsum2,
+                                                double* pvec) {
+    const int t = threadIdx.x, lane = t & 63, b = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // uniform: scalar column bases
+    constexpr int DW = AT_DATA / 64;
+    if (wave < DW) {
+        double om = 0.0, c = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            uy[e * AT_DATA + t] = make_double2(u[e], yv[e]);
+            om = __builtin_fma(u[e], u[e], om);
+            c = __builtin_fma(u[e], yv[e], c);
+        }
+        om = wave_sum(om);
+        c = wave_sum(c);
+        if (lane == 0) {
+            wsum2[2 * wave] = om;
+            wsum2[2 * wave + 1] = c;
+        }
+    }
+    __syncthreads();
+    if (wave < DW) {
+        // a chunk = CE row blocks of 512 (8 CE rows per lane); NCH chunks per vector
+        constexpr int CE = EPT <= 2 ? 1 : 2;
+        constexpr int NCH = EPT / CE;
+        const int ncol = j > wave ? (j - 1 - wave) / DW + 1 : 0;
+        const int total = ncol * NCH;
+        // FULL: every 512-row block of the thread block lies inside 0 .. n-1 (the
+        // loads take a scalar column base plus the lane's offset, no masks)
+        const bool all_full = b * AT_DATA + (EPT - 1) * gstride + AT_DATA <= n;
+        // EPT <= 2: the lane's 8 EPT pairs (u_i, y_i) are held in registers for
+        // the whole pass (LDS reads would cost a fifth of the pass)
+        constexpr bool REG = EPT <= 2;
+        double ur[REG ? 8 * EPT : 1], yr[REG ? 8 * EPT : 1];
+        if constexpr (REG) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double2 q = uy[e * AT_DATA + lane + 64 * k];
+                    ur[e * 8 + k] = q.x;
+                    yr[e * 8 + k] = q.y;
+                }
+        }
+        auto run = [&](auto fullc) {
+            constexpr bool FULL = decltype(fullc)::value;
+            double p1 = 0.0, p2 = 0.0;
+            auto load = [&](int it, double (&buf)[8 * CE]) {
+                const int l = wave + DW * (it / NCH), c = it % NCH;
+                const double* col = V + (size_t)l * n;
+#pragma unroll
+                for (int ee = 0; ee < CE; ++ee) {
+                    const int rb = b * AT_DATA + (c * CE + ee) * gstride;   // uniform
+                    if constexpr (FULL) {
+                        const double* cb = col + rb;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) buf[ee * 8 + k] = cb[lane + 64 * k];
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const int r = rb + lane + 64 * k;
+                            buf[ee * 8 + k] = col[pf_index((size_t)r, r < n)];
+                        }
+                    }
+                }
+            };
+            auto consume = [&](int it, const double (&buf)[8 * CE]) {
+                const int c = it % NCH;
+#pragma unroll
+                for (int ee = 0; ee < CE; ++ee) {
+                    const int e = c * CE + ee;
+                    const int r0 = b * AT_DATA + e * gstride + lane;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        double qx, qy;
+                        if constexpr (REG) {
+                            qx = ur[e * 8 + k];
+                            qy = yr[e * 8 + k];
+                        } else {
+                            const double2 q = uy[e * AT_DATA + lane + 64 * k];
+                            qx = q.x;
+                            qy = q.y;
+                        }
+                        const double vk = (FULL || r0 + 64 * k < n) ? buf[ee * 8 + k] : 0.0;
+                        p1 = __builtin_fma(vk, qx, p1);
+                        p2 = __builtin_fma(vk, qy, p2);
+                    }
+                }
+                if (c == NCH - 1) {
+                    const double t1 = wave_sum(p1), t2 = wave_sum(p2);
+                    const int l = wave + DW * (it / NCH);
+                    if (lane == 0) {
+                        pvec[l] = t1;
+                        pvec[j + 1 + l] = t2;
+                    }
+                    p1 = 0.0;
+                    p2 = 0.0;
+                }
+            };
+            // three buffers in turn: the loads of chunks it + 1 and it + 2 are in
+            // flight while chunk it is used (a chunk index past the end reloads
+            // the last chunk, unused)
+            double ba[8 * CE], bb[8 * CE], bc[8 * CE];
+            if (total > 0) {
+                load(0, ba);
+                load(min(1, total - 1), bb);
+            }
+            for (int it = 0; it < total; it += 3) {
+                load(min(it + 2, total - 1), bc);
+                consume(it, ba);
+                if (it + 1 < total) {
+                    load(min(it + 3, total - 1), ba);
+                    consume(it + 1, bb);
+                }
+                if (it + 2 < total) {
+                    load(min(it + 4, total - 1), bb);
+                    consume(it + 2, bc);
+                }
+            }
+        };
+        if (all_full)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
+    }
+    __syncthreads();
+    if (t == 0) {
+        double om = 0.0, c = 0.0;
+        for (int w = 0; w < DW; ++w) {
+            om += wsum2[2 * w];
+            c += wsum2[2 * w + 1];
+        }
+        pvec[j] = om;
+        pvec[2 * j + 1] = c;
+    }
+    __syncthreads();
+}
+
+// pass 2 (data waves): u and yv are consumed in place; the basis vectors are
+// taken in descending order
 template <int EPT>
 __device__ __forceinline__ void dcgs2_update(const double* __restrict__ V, int n, int j, double (&u)[EPT],
                                              double (&yv)[EPT], const double* acoef, const double* bcoef, double nu,
                                              double gj, int base, int gstride, double* vout, double* uout) {
     if (threadIdx.x >= AT_DATA) return;
-    constexpr int CG_U = cg_u<EPT>();
-    for (int l0 = 0; l0 < j; l0 += CG_U) {
-        double vv[CG_U][EPT];
+    constexpr int CG_U = cg_u2<EPT>();
+    // basis vectors in descending order: the most recently read ones (the end of
+    // pass 1) come first, while they may still sit in the memory-side cache
+    auto use = [&](int l0, const double (&vv)[CG_U][EPT]) {
 #pragma unroll
-        for (int q = 0; q < CG_U; ++q)
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                int i = base + e * gstride;
-                vv[q][e] = (l0 + q < j && i < n) ? V[(size_t)(l0 + q) * n + i] : 0.0;
-            }
-#pragma unroll
-        for (int q = 0; q < CG_U; ++q) {
+        for (int q = CG_U - 1; q >= 0; --q) {
             if (l0 + q < j) {
                 const double al = acoef[l0 + q], bl = bcoef[l0 + q];
 #pragma unroll
@@ -752,6 +1062,19 @@ __device__ __forceinline__ void dcgs2_update(const double* __restrict__ V, int n
                     yv[e] = __builtin_fma(-bl, vv[q][e], yv[e]);
                 }
             }
+        }
+    };
+    // groups of CG_U vectors from the top down, two buffers in turn (a group
+    // index below 0 reloads group 0, unused)
+    double va[CG_U][EPT], vb[CG_U][EPT];
+    const int top = j > 0 ? ((j - 1) / CG_U) * CG_U : 0;
+    if (j > 0) load_cols<EPT, CG_U>(V, n, top, j, base, gstride, va);
+    for (int l0 = top; l0 >= 0 && j > 0; l0 -= 2 * CG_U) {
+        load_cols<EPT, CG_U>(V, n, max(l0 - CG_U, 0), j, base, gstride, vb);
+        use(l0, va);
+        if (l0 - CG_U >= 0) {
+            load_cols<EPT, CG_U>(V, n, max(l0 - 2 * CG_U, 0), j, base, gstride, va);
+            use(l0 - CG_U, vb);
         }
     }
 #pragma unroll
@@ -779,7 +1102,7 @@ __device__ __forceinline__ void dcgs2_rows(const ArnoldiArgs& a, const double* h
         double part = 0.0;
         for (int m = max(0, r - 1) + lane; m <= j - 2; m += 64)
             part = __builtin_fma(a.HRf[(size_t)r * mx + m], hv[m], part);
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        part = wave_sum(part);
         if (lane == 0) {
             double s = (r < j ? hv[j + 1 + r] : gj) - part;
             if (j >= 1) s = __builtin_fma(-f, hv[j - 1], s);
@@ -788,44 +1111,22 @@ __device__ __forceinline__ void dcgs2_rows(const ArnoldiArgs& a, const double* h
     }
 }
 
-// poll wave of block 0, lane 0: Givens step on the completed column j - 1
+// poll wave of block 0: Givens step on the completed column j - 1; hh holds
+// HRp(0:j-1, j-1), loaded at the start of the launch
 __device__ __forceinline__ void dcgs2_givens(const ArnoldiArgs& a, const double* hv, double nu, double* hh,
                                              const double* csL, const double* snL) {
-    const int j = a.j, ld = a.ld;
-    for (int l = 0; l < j; ++l) hh[l] = a.HRp[(size_t)(j - 1) * ld + l] + hv[l];
-    hh[j] = nu;
-    for (int l = 0; l + 1 < j; ++l) {           // previous rotations
-        double x0 = hh[l], x1 = hh[l + 1];
-        hh[l] = csL[l] * x0 + snL[l] * x1;
-        hh[l + 1] = -snL[l] * x0 + csL[l] * x1;
-    }
-    const int c0 = j - 1;
-    double delta = hypot(hh[c0], hh[j]);
-    double c = hh[c0] / delta, sv = hh[j] / delta;
-    hh[c0] = delta;
-    hh[j] = 0.0;
-    double gc = a.g[c0];
-    a.g[j] = -sv * gc;
-    a.g[c0] = c * gc;
-    a.cs[c0] = c;
-    a.sn[c0] = sv;
-    double* Hc = a.H + (size_t)c0 * ld;
-    for (int l = 0; l <= j; ++l) Hc[l] = hh[l];
-    double ga = fabs(-sv * gc);
-    a.st->gabs = ga;
-    if (ga <= a.tau * a.st->beta0 || nu == 0.0) {
-        a.st->its = j;
-        a.st->done = 1;
-    } else if (j == a.maxit) {
-        a.st->its = j;
-        a.st->done = 2;
-    }
+    const int j = a.j, lane = threadIdx.x & 63;
+    for (int l = lane; l < j; l += 64) hh[l] += hv[l];
+    if (lane == 0) hh[j] = nu;
+    wave_sync();
+    wave_givens_column(a, hh, j - 1, csL, snL);
 }
 
 template <int EPT>
 __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
-    extern __shared__ double dyn[];
+    extern __shared__ __align__(16) double dyn[];
     __shared__ double nu_s, gj_s;
+    __shared__ double wsum2[2 * (AT_DATA / 64)];
     __shared__ int abort_flag;
     if (a.st->done) return;                  // uniform: written by an earlier launch
     const int b = blockIdx.x, t = threadIdx.x, nb = a.nb, lane = t & 63, wave = t >> 6;
@@ -834,9 +1135,10 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
     const int base = b * AT_DATA + t;
     const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
     constexpr int DW = AT_DATA / 64;
-    // LDS: wpart [DW][rmax], pvec, hv [rmax], red [rmax + nb], hh [maxlinks], cs, sn [maxit]
-    double* wpart = dyn;
-    double* pvec = wpart + (size_t)DW * rmax;
+    // LDS: front (EPT <= 8: (u, y) staging [AT_DATA EPT] double2; else wpart [DW][rmax]),
+    // pvec, hv [rmax], red [rmax + nb], hh [maxlinks], cs, sn [maxit]
+    constexpr bool COLS = EPT <= 8;
+    double* pvec = dyn + dcgs2_front_words(EPT, rmax);
     double* hv = pvec + rmax;
     double* red = hv + rmax;
     double* hh = red + rmax + nb;
@@ -852,22 +1154,28 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
         nxt[blk + (size_t)b * rmax + r] = SENTINEL;
     }
     if (t == 0) abort_flag = 0;
-    if (b == 0)
+    if (b == 0) {
         for (int l = t; l + 1 < j; l += AT) {
             csL[l] = a.cs[l];
             snL[l] = a.sn[l];
         }
+        if (wave == DW)                       // first projections of column j - 1
+            for (int l = lane; l < j; l += 64) hh[l] = a.HRp[(size_t)(j - 1) * a.ld + l];
+    }
     double u[EPT], yv[EPT];
     const double* uj = a.V + (size_t)j * n;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         int i = base + e * gstride;
         bool ok = data && i < n;
-        u[e] = ok ? uj[i] : 0.0;
-        yv[e] = ok ? a.y[i] : 0.0;
+        u[e] = ld0(uj, i, ok);
+        yv[e] = ld0(a.y, i, ok);
     }
     __syncthreads();
-    block_dots2<EPT>(a.V, n, j, u, yv, base, gstride, wpart, rmax, pvec);
+    if constexpr (COLS)
+        block_dots_cols<EPT>(a.V, n, j, u, yv, gstride, (double2*)dyn, wsum2, pvec);
+    else
+        block_dots2<EPT>(a.V, n, j, u, yv, base, gstride, dyn, rmax, pvec);
     grid_vsum(pvec, R, nb, cur, cur + blk, rmax, red, hv, &abort_flag);
     if (abort_flag) {
         if (t == 0) {
@@ -882,10 +1190,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
             q = __builtin_fma(hv[l], hv[l], q);
             ab = __builtin_fma(hv[l], hv[j + 1 + l], ab);
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            q += __shfl_xor(q, o, 64);
-            ab += __shfl_xor(ab, o, 64);
-        }
+        q = wave_sum(q);
+        ab = wave_sum(ab);
         if (lane == 0) {
             double nu = 1.0;
             if (j > 0) {
@@ -899,12 +1205,24 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
     __syncthreads();
     const double nu = nu_s, gj = gj_s;
     if (wave < DW) {
+        if constexpr (COLS) {                // reload from the staging instead of holding them through pass 1
+            const double2* uy = (const double2*)dyn;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                u[e] = uy[e * AT_DATA + t].x;
+                yv[e] = uy[e * AT_DATA + t].y;
+            }
+        }
         if (j < a.maxit)
             dcgs2_update<EPT>(a.V, n, j, u, yv, hv, hv + j + 1, nu, gj, base, gstride, a.V + (size_t)j * n,
                               a.V + (size_t)(j + 1) * n);
     } else {
+        // the poll wave's bookkeeping is a short dependent chain next to the
+        // streaming data waves: raise its issue priority while it runs
+        __builtin_amdgcn_s_setprio(3);
         dcgs2_rows(a, hv, nu, gj);
-        if (b == 0 && j >= 1 && lane == 0) dcgs2_givens(a, hv, nu, hh, csL, snL);
+        if (b == 0 && j >= 1) dcgs2_givens(a, hv, nu, hh, csL, snL);
+        __builtin_amdgcn_s_setprio(0);
     }
 }
 
@@ -919,7 +1237,7 @@ __global__ void k_fill_u64(unsigned long long* p, size_t len, unsigned long long
 
 __device__ __forceinline__ double block_sum(double v) {
     __shared__ double sh[RB / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wave_sum(v);
     int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) sh[w] = v;
     __syncthreads();
@@ -1216,8 +1534,9 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
         c.shmem = sizeof(double) * ((size_t)(AT_DATA / 64 + 4) * maxlinks + nb + 2 * (size_t)maxit);
         c.slot_words = 2 * cgs2_parity_words(maxlinks, nb);
     } else if (ortho == SPAI_ORTHO_DCGS2) {
-        const size_t rmax = 2 * (size_t)maxlinks;   // wpart [DW][rmax], pvec, hv, red, hh, cs, sn
-        c.shmem = sizeof(double) * ((AT_DATA / 64 + 3) * rmax + nb + maxlinks + 2 * (size_t)maxit);
+        const int rmax = 2 * maxlinks;   // front, pvec, hv, red, hh, cs, sn
+        c.shmem = sizeof(double) * (dcgs2_front_words(ept, rmax) + 3 * (size_t)rmax + nb + maxlinks +
+                                    2 * (size_t)maxit);
         c.slot_words = 2 * dcgs2_parity_words(maxlinks, nb);
     } else {
         c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);

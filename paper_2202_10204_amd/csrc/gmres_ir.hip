@@ -1560,11 +1560,28 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
     return c;
 }
 
+// The blocks of an Arnoldi launch must be resident together (they wait on each
+// other's partial sums).  arnoldi_config admits a configuration only when the
+// occupancy query shows that all nb blocks fit on the device at once, so an
+// ordinary launch on an otherwise idle device places them all; every wait is
+// bounded, so a launch whose blocks were not all placed ends with an error
+// instead of hanging.  The cooperative launch API gives the same placement
+// with a formal guarantee, but costs about 11 us of queue synchronisation on
+// each side of every launch; SPAI_COOPERATIVE=1 selects it.
+static bool use_cooperative_launch() {
+    static const bool coop = [] {
+        const char* e = getenv("SPAI_COOPERATIVE");
+        return e && std::string(e) == "1";
+    }();
+    return coop;
+}
+
 static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, hipStream_t s) {
     void* args[] = {&a};
     const void* fn = arnoldi_fn(c.ortho, c.ept);
     long tk = timer_begin(h, SPAI_KT_MGS);
-    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);
+    hipError_t e = use_cooperative_launch() ? hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s)
+                                            : hipLaunchKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);
     timer_end(h, SPAI_KT_MGS, tk);
     SPAI_HIP(e);
     return SPAI_OK;

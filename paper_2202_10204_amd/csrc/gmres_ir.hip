@@ -631,6 +631,7 @@ __device__ __forceinline__ void grid_vsum(const double* pvec, int L, int nb, uns
     for (int l = t; l < L; l += AT)
         __hip_atomic_store(&slots[(size_t)l * nb + b], (unsigned long long)__double_as_longlong(pvec[l]),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();                          // pvec may share its storage with red
     const int owned = L > b ? (L - 1 - b) / nb + 1 : 0;
     bool to = false;
     for (int q = t; q < owned * nb; q += AT) {
@@ -770,45 +771,16 @@ __global__ __launch_bounds__(AT) void k_arnoldi_cgs2(ArnoldiArgs a) {
 // the Givens rotations to column j - 1 and takes the stopping decision.
 // ---------------------------------------------------------------------------
 
-// first LDS region of the DCGS2 kernel, in doubles
-__host__ __device__ constexpr size_t dcgs2_front_words(int ept, int rmax) {
-    return ept <= 8 ? (size_t)2 * AT_DATA * ept : (size_t)(AT_DATA / 64) * rmax;
+// LDS of the DCGS2 kernel, in doubles: the (u, y) staging [AT_DATA min(EPT, 8)] double2,
+// the block partials / poll buffer [rmax + nb] (one after the other in time),
+// the totals [rmax], the Hessenberg column [maxlinks], cs and sn [maxit]
+__host__ __device__ constexpr size_t dcgs2_lds_words(int ept, int rmax, int nb, int maxlinks, int maxit) {
+    return (size_t)2 * AT_DATA * (ept < 8 ? ept : 8) + (size_t)(rmax + nb) + rmax + maxlinks + 2 * (size_t)maxit;
 }
 
 // slot words of one parity for the DCGS2 kernel: [rmax][nb] slots + [nb][rmax] mailboxes
 __host__ __device__ inline size_t dcgs2_parity_words(int maxlinks, int nb) {
     return (size_t)2 * (2 * (size_t)maxlinks) * nb;
-}
-
-constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
-
-// Sum NV per-lane values over the 64 lanes of a wave with NV - 1 + 6 - log2(NV)
-// exchanges instead of 6 NV: halving exchanges (lane L keeps the half of the
-// values selected by its bit, adds its partner's copy of that half), then a
-// full xor reduction over the remaining low lane bits.  Returns the total of
-// value `idx` (set on return) in every lane; the lanes with
-// (lane & (64 / NV - 1)) == 0 are the writers, one per value.  The schedule is
-// fixed, so the bits of a total do not depend on timing.
-template <int NV>
-__device__ __forceinline__ double wave_reduce_scatter(double (&v)[NV], int lane, int& idx) {
-    constexpr int S = ilog2(NV);
-    idx = 0;
-#pragma unroll
-    for (int st = 0; st < S; ++st) {
-        const int h = NV >> (st + 1), mask = 32 >> st;
-        const bool hi = (lane & mask) != 0;
-#pragma unroll
-        for (int k = 0; k < h; ++k) {
-            const double send = hi ? v[k] : v[k + h];
-            const double keep = hi ? v[k + h] : v[k];
-            v[k] = keep + __shfl_xor(send, mask, 64);
-        }
-        if (hi) idx += h;
-    }
-    double r = v[0];
-#pragma unroll
-    for (int mask = 32 >> S; mask > 0; mask >>= 1) r += __shfl_xor(r, mask, 64);
-    return r;
 }
 
 // basis vectors per group in the double-buffered passes: 16 doubles per buffer
@@ -831,76 +803,15 @@ __device__ __forceinline__ void load_cols(const double* __restrict__ V, int n, i
         }
 }
 
-// pass 1: per-block partials of the 2j + 2 inner products into pvec (the next
-// group of basis vectors is loaded while the current one is reduced)
-template <int EPT>
-__device__ __forceinline__ void block_dots2(const double* __restrict__ V, int n, int j, const double (&u)[EPT],
-                                            const double (&yv)[EPT], int base, int gstride, double* wpart, int ldw,
-                                            double* pvec) {
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    constexpr int DW = AT_DATA / 64;
-    constexpr int CG_U = cg_u2<EPT>();
-    constexpr int NV = 2 * CG_U;
-    constexpr int GRP = 64 / NV;             // lanes that share one value after the reduction
-    if (wave < DW) {
-        double* wp = wpart + (size_t)wave * ldw;
-        double vv[CG_U][EPT], vn[CG_U][EPT];
-        if (j > 0) load_cols<EPT, CG_U>(V, n, 0, j, base, gstride, vv);
-        for (int l0 = 0; l0 < j; l0 += CG_U) {
-            if (l0 + CG_U < j) load_cols<EPT, CG_U>(V, n, l0 + CG_U, j, base, gstride, vn);
-            double p[NV];
-#pragma unroll
-            for (int q = 0; q < CG_U; ++q) {
-                double p1 = 0.0, p2 = 0.0;
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) {
-                    const double vk = base + e * gstride < n ? vv[q][e] : 0.0;
-                    p1 = __builtin_fma(vk, u[e], p1);
-                    p2 = __builtin_fma(vk, yv[e], p2);
-                }
-                p[q] = p1;
-                p[CG_U + q] = p2;
-            }
-            int idx;
-            const double tot = wave_reduce_scatter<NV>(p, lane, idx);
-            if ((lane & (GRP - 1)) == 0) {
-                const int q = idx < CG_U ? idx : idx - CG_U;
-                if (l0 + q < j) wp[(idx < CG_U ? 0 : j + 1) + l0 + q] = tot;
-            }
-#pragma unroll
-            for (int q = 0; q < CG_U; ++q)
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) vv[q][e] = vn[q][e];
-        }
-        double om = 0.0, c = 0.0;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            om = __builtin_fma(u[e], u[e], om);
-            c = __builtin_fma(u[e], yv[e], c);
-        }
-        om = wave_sum(om);
-        c = wave_sum(c);
-        if (lane == 0) {
-            wp[j] = om;
-            wp[2 * j + 1] = c;
-        }
-    }
-    __syncthreads();
-    const int R = 2 * j + 2;
-    for (int r = t; r < R; r += AT) {
-        double sacc = 0.0;
-        for (int w = 0; w < DW; ++w) sacc += wpart[(size_t)w * ldw + r];
-        pvec[r] = sacc;
-    }
-    __syncthreads();
-}
-
 // pass 1 with one wave per basis vector: wave w takes the vectors l = w,
-// w + 8, ... over all rows of the block (8 EPT rows per lane; (u_i, y_i) staged
-// in LDS in the row order of the data threads), so that every block partial is
-// reduced once, by one wave; the loads of the next chunk of 8 rows are in
-// flight while the current chunk is used.  For EPT <= 8 (the staging takes
-// 16 KB per EPT of LDS).
+// w + 8, ... over all rows of the block (8 rows per lane and 512-row chunk;
+// (u_i, y_i) staged in LDS in the row order of the data threads), so that each
+// block partial is reduced once per staged part, by one wave; three buffers of
+// loads are in flight while one is used.  At most DCGS2_SE chunks are staged at
+// a time (64 KB): with more (EPT = 16) the rows are covered in EPT / DCGS2_SE
+// parts and the parts' totals are added.
+constexpr int DCGS2_SE = 8;
+
 template <int EPT>
 __device__ __forceinline__ void block_dots_cols(const double* __restrict__ V, int n, int j, const double (&u)[EPT],
                                                 const double (&yv)[EPT], int gstride, double2* uy, double* wsum2,
@@ -908,11 +819,18 @@ __device__ __forceinline__ void block_dots_cols(const double* __restrict__ V, in
     const int t = threadIdx.x, lane = t & 63, b = blockIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // uniform: scalar column bases
     constexpr int DW = AT_DATA / 64;
+    constexpr int SE = EPT < DCGS2_SE ? EPT : DCGS2_SE;       // chunks staged per part
+    constexpr int NPART = EPT / SE;
+    // a load chunk = CE row blocks of 512 (8 CE rows per lane); NCH chunks per vector and part
+    constexpr int CE = (EPT <= 2 || NPART > 1) ? 1 : 2;
+    constexpr int NCH = SE / CE;
+    // EPT <= 2: the lane's 8 EPT pairs (u_i, y_i) are held in registers for the
+    // whole pass (LDS reads would cost a fifth of the pass)
+    constexpr bool REG = EPT <= 2;
     if (wave < DW) {
         double om = 0.0, c = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            uy[e * AT_DATA + t] = make_double2(u[e], yv[e]);
             om = __builtin_fma(u[e], u[e], om);
             c = __builtin_fma(u[e], yv[e], c);
         }
@@ -923,110 +841,112 @@ __device__ __forceinline__ void block_dots_cols(const double* __restrict__ V, in
             wsum2[2 * wave + 1] = c;
         }
     }
-    __syncthreads();
-    if (wave < DW) {
-        // a chunk = CE row blocks of 512 (8 CE rows per lane); NCH chunks per vector
-        constexpr int CE = EPT <= 2 ? 1 : 2;
-        constexpr int NCH = EPT / CE;
-        const int ncol = j > wave ? (j - 1 - wave) / DW + 1 : 0;
-        const int total = ncol * NCH;
-        // FULL: every 512-row block of the thread block lies inside 0 .. n-1 (the
-        // loads take a scalar column base plus the lane's offset, no masks)
-        const bool all_full = b * AT_DATA + (EPT - 1) * gstride + AT_DATA <= n;
-        // EPT <= 2: the lane's 8 EPT pairs (u_i, y_i) are held in registers for
-        // the whole pass (LDS reads would cost a fifth of the pass)
-        constexpr bool REG = EPT <= 2;
-        double ur[REG ? 8 * EPT : 1], yr[REG ? 8 * EPT : 1];
-        if constexpr (REG) {
+    const int ncol = j > wave ? (j - 1 - wave) / DW + 1 : 0;
+    const int total = ncol * NCH;
+    // FULL: every 512-row chunk of the thread block lies inside 0 .. n-1 (the
+    // loads take a scalar column base plus the lane's offset, no masks)
+    const bool all_full = b * AT_DATA + (EPT - 1) * gstride + AT_DATA <= n;
 #pragma unroll
-            for (int e = 0; e < EPT; ++e)
+    for (int part = 0; part < NPART; ++part) {
+        if (wave < DW) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const double2 q = uy[e * AT_DATA + lane + 64 * k];
-                    ur[e * 8 + k] = q.x;
-                    yr[e * 8 + k] = q.y;
-                }
+            for (int e = 0; e < SE; ++e) uy[e * AT_DATA + t] = make_double2(u[part * SE + e], yv[part * SE + e]);
         }
-        auto run = [&](auto fullc) {
-            constexpr bool FULL = decltype(fullc)::value;
-            double p1 = 0.0, p2 = 0.0;
-            auto load = [&](int it, double (&buf)[8 * CE]) {
-                const int l = wave + DW * (it / NCH), c = it % NCH;
-                const double* col = V + (size_t)l * n;
+        __syncthreads();
+        if (wave < DW) {
+            double ur[REG ? 8 * EPT : 1], yr[REG ? 8 * EPT : 1];
+            if constexpr (REG) {
 #pragma unroll
-                for (int ee = 0; ee < CE; ++ee) {
-                    const int rb = b * AT_DATA + (c * CE + ee) * gstride;   // uniform
-                    if constexpr (FULL) {
-                        const double* cb = col + rb;
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) buf[ee * 8 + k] = cb[lane + 64 * k];
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 8; ++k) {
-                            const int r = rb + lane + 64 * k;
-                            buf[ee * 8 + k] = col[pf_index((size_t)r, r < n)];
-                        }
-                    }
-                }
-            };
-            auto consume = [&](int it, const double (&buf)[8 * CE]) {
-                const int c = it % NCH;
-#pragma unroll
-                for (int ee = 0; ee < CE; ++ee) {
-                    const int e = c * CE + ee;
-                    const int r0 = b * AT_DATA + e * gstride + lane;
+                for (int e = 0; e < EPT; ++e)
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        double qx, qy;
-                        if constexpr (REG) {
-                            qx = ur[e * 8 + k];
-                            qy = yr[e * 8 + k];
+                        const double2 q = uy[e * AT_DATA + lane + 64 * k];
+                        ur[e * 8 + k] = q.x;
+                        yr[e * 8 + k] = q.y;
+                    }
+            }
+            auto run = [&](auto fullc) {
+                constexpr bool FULL = decltype(fullc)::value;
+                double p1 = 0.0, p2 = 0.0;
+                auto load = [&](int it, double (&buf)[8 * CE]) {
+                    const int l = wave + DW * (it / NCH), c = it % NCH;
+                    const double* col = V + (size_t)l * n;
+#pragma unroll
+                    for (int ee = 0; ee < CE; ++ee) {
+                        const int rb = b * AT_DATA + (part * SE + c * CE + ee) * gstride;   // uniform
+                        if constexpr (FULL) {
+                            const double* cb = col + rb;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) buf[ee * 8 + k] = cb[lane + 64 * k];
                         } else {
-                            const double2 q = uy[e * AT_DATA + lane + 64 * k];
-                            qx = q.x;
-                            qy = q.y;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) {
+                                const int r = rb + lane + 64 * k;
+                                buf[ee * 8 + k] = col[pf_index((size_t)r, r < n)];
+                            }
                         }
-                        const double vk = (FULL || r0 + 64 * k < n) ? buf[ee * 8 + k] : 0.0;
-                        p1 = __builtin_fma(vk, qx, p1);
-                        p2 = __builtin_fma(vk, qy, p2);
                     }
+                };
+                auto consume = [&](int it, const double (&buf)[8 * CE]) {
+                    const int c = it % NCH;
+#pragma unroll
+                    for (int ee = 0; ee < CE; ++ee) {
+                        const int e = c * CE + ee;                         // staged chunk
+                        const int r0 = b * AT_DATA + (part * SE + e) * gstride + lane;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            double qx, qy;
+                            if constexpr (REG) {
+                                qx = ur[e * 8 + k];
+                                qy = yr[e * 8 + k];
+                            } else {
+                                const double2 q = uy[e * AT_DATA + lane + 64 * k];
+                                qx = q.x;
+                                qy = q.y;
+                            }
+                            const double vk = (FULL || r0 + 64 * k < n) ? buf[ee * 8 + k] : 0.0;
+                            p1 = __builtin_fma(vk, qx, p1);
+                            p2 = __builtin_fma(vk, qy, p2);
+                        }
+                    }
+                    if (c == NCH - 1) {
+                        const double t1 = wave_sum(p1), t2 = wave_sum(p2);
+                        const int l = wave + DW * (it / NCH);
+                        if (lane == 0) {
+                            pvec[l] = part == 0 ? t1 : pvec[l] + t1;
+                            pvec[j + 1 + l] = part == 0 ? t2 : pvec[j + 1 + l] + t2;
+                        }
+                        p1 = 0.0;
+                        p2 = 0.0;
+                    }
+                };
+                // three buffers in turn: the loads of chunks it + 1 and it + 2 are in
+                // flight while chunk it is used (a chunk index past the end reloads
+                // the last chunk, unused)
+                double ba[8 * CE], bb[8 * CE], bc[8 * CE];
+                if (total > 0) {
+                    load(0, ba);
+                    load(min(1, total - 1), bb);
                 }
-                if (c == NCH - 1) {
-                    const double t1 = wave_sum(p1), t2 = wave_sum(p2);
-                    const int l = wave + DW * (it / NCH);
-                    if (lane == 0) {
-                        pvec[l] = t1;
-                        pvec[j + 1 + l] = t2;
+                for (int it = 0; it < total; it += 3) {
+                    load(min(it + 2, total - 1), bc);
+                    consume(it, ba);
+                    if (it + 1 < total) {
+                        load(min(it + 3, total - 1), ba);
+                        consume(it + 1, bb);
                     }
-                    p1 = 0.0;
-                    p2 = 0.0;
+                    if (it + 2 < total) {
+                        load(min(it + 4, total - 1), bb);
+                        consume(it + 2, bc);
+                    }
                 }
             };
-            // three buffers in turn: the loads of chunks it + 1 and it + 2 are in
-            // flight while chunk it is used (a chunk index past the end reloads
-            // the last chunk, unused)
-            double ba[8 * CE], bb[8 * CE], bc[8 * CE];
-            if (total > 0) {
-                load(0, ba);
-                load(min(1, total - 1), bb);
-            }
-            for (int it = 0; it < total; it += 3) {
-                load(min(it + 2, total - 1), bc);
-                consume(it, ba);
-                if (it + 1 < total) {
-                    load(min(it + 3, total - 1), ba);
-                    consume(it + 1, bb);
-                }
-                if (it + 2 < total) {
-                    load(min(it + 4, total - 1), bb);
-                    consume(it + 2, bc);
-                }
-            }
-        };
-        if (all_full)
-            run(std::true_type{});
-        else
-            run(std::false_type{});
+            if (all_full)
+                run(std::true_type{});
+            else
+                run(std::false_type{});
+        }
+        if (NPART > 1) __syncthreads();       // the next part overwrites the staging
     }
     __syncthreads();
     if (t == 0) {
@@ -1135,13 +1055,12 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
     const int base = b * AT_DATA + t;
     const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
     constexpr int DW = AT_DATA / 64;
-    // LDS: front (EPT <= 8: (u, y) staging [AT_DATA EPT] double2; else wpart [DW][rmax]),
-    // pvec, hv [rmax], red [rmax + nb], hh [maxlinks], cs, sn [maxit]
-    constexpr bool COLS = EPT <= 8;
-    double* pvec = dyn + dcgs2_front_words(EPT, rmax);
-    double* hv = pvec + rmax;
-    double* red = hv + rmax;
-    double* hh = red + rmax + nb;
+    // LDS (dcgs2_lds_words): (u, y) staging, block partials = poll buffer, totals,
+    // Hessenberg column, cs, sn
+    double* pvec = dyn + (size_t)2 * AT_DATA * (EPT < DCGS2_SE ? EPT : DCGS2_SE);
+    double* red = pvec;                      // free once the partials are published
+    double* hv = pvec + rmax + nb;
+    double* hh = hv + rmax;
     double* csL = hh + a.maxlinks;
     double* snL = csL + a.maxit;
     const size_t pw = dcgs2_parity_words(a.maxlinks, nb);
@@ -1172,10 +1091,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
         yv[e] = ld0(a.y, i, ok);
     }
     __syncthreads();
-    if constexpr (COLS)
-        block_dots_cols<EPT>(a.V, n, j, u, yv, gstride, (double2*)dyn, wsum2, pvec);
-    else
-        block_dots2<EPT>(a.V, n, j, u, yv, base, gstride, dyn, rmax, pvec);
+    block_dots_cols<EPT>(a.V, n, j, u, yv, gstride, (double2*)dyn, wsum2, pvec);
     grid_vsum(pvec, R, nb, cur, cur + blk, rmax, red, hv, &abort_flag);
     if (abort_flag) {
         if (t == 0) {
@@ -1205,7 +1121,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
     __syncthreads();
     const double nu = nu_s, gj = gj_s;
     if (wave < DW) {
-        if constexpr (COLS) {                // reload from the staging instead of holding them through pass 1
+        if constexpr (EPT <= DCGS2_SE) {     // reload from the staging instead of holding them through pass 1
             const double2* uy = (const double2*)dyn;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -1523,6 +1439,8 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
     // times per step and uses every CU
     int nb = ortho != SPAI_ORTHO_MGS ? std::min(std::min(h->num_cu, MAX_NB), rows_nb)
                                      : std::min(std::min(std::max(1, h->num_cu / 2), MAX_NB), rows_nb);
+    if ((long long)nb * AT_DATA * 16 < n)    // more blocks rather than more than 16 elements per thread
+        nb = std::min(std::min(h->num_cu, MAX_NB), rows_nb);
     if (const char* e = getenv("SPAI_ARNOLDI_BLOCKS")) {
         int want = atoi(e);
         if (want >= 1 && want <= MAX_NB) nb = std::min(want, rows_nb);
@@ -1534,15 +1452,13 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
         c.shmem = sizeof(double) * ((size_t)(AT_DATA / 64 + 4) * maxlinks + nb + 2 * (size_t)maxit);
         c.slot_words = 2 * cgs2_parity_words(maxlinks, nb);
     } else if (ortho == SPAI_ORTHO_DCGS2) {
-        const int rmax = 2 * maxlinks;   // front, pvec, hv, red, hh, cs, sn
-        c.shmem = sizeof(double) * (dcgs2_front_words(ept, rmax) + 3 * (size_t)rmax + nb + maxlinks +
-                                    2 * (size_t)maxit);
+        c.shmem = sizeof(double) * dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit);
         c.slot_words = 2 * dcgs2_parity_words(maxlinks, nb);
     } else {
         c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
         c.slot_words = (size_t)2 * maxlinks * nb * (1 + MBOX_STRIDE);
     }
-    if (c.shmem > 150 * 1024) return ArnoldiCfg{};
+    if (c.shmem > 159 * 1024) return ArnoldiCfg{};   // 160 KB of LDS per CU, 1 KB for static arrays
     const void* fn = arnoldi_fn(ortho, ept);
     if (c.shmem > 48 * 1024 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.shmem) != hipSuccess) {

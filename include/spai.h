@@ -207,6 +207,43 @@ int spai_precond_destroy(spai_precond* P);
 int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
                   double* x, const spai_ir_params* p, spai_ir_stats* st);
 
+/*
+ * Batches of independent systems (many systems of different sizes in one call).
+ * A batch is one block-diagonal matrix A (the caller concatenates the systems):
+ * system s owns rows and columns sys_ptr[s] .. sys_ptr[s+1]-1, with sys_ptr a
+ * host array of nsys + 1 int32 values from 0 to n, strictly increasing.
+ *
+ * spai_build_batched: Algorithm 1 on every column of every system in one build
+ * (a block-diagonal matrix's SPAI is the SPAI of each block: a column's shadow,
+ * candidates and residual stay inside its block), so the result is the
+ * block-diagonal P whose block s is system s's preconditioner, bit-identical to
+ * building each system alone with the same parameters.  Errors: those of
+ * spai_build, and SPAI_E_ARG for a bad sys_ptr or an entry of A outside the
+ * diagonal blocks (checked on the device).
+ */
+int spai_build_batched(spai_handle* h, const spai_csr* A, int32_t nsys, const int32_t* sys_ptr,
+                       const spai_pattern* J, const spai_build_params* p, spai_precond** P,
+                       spai_build_stats* st);
+
+/*
+ * spai_gmres_ir_batched: Algorithm 3 for every system of the batch on its own
+ * (its own x0, residuals, Krylov space, stopping decisions and refinement
+ * steps, with the semantics of spai_gmres_ir and maxit capped at the system's
+ * size), all systems in one persistent launch: each workgroup takes the next
+ * system (largest first) and runs its whole refinement loop.  Orthogonalisation
+ * is MGS (p->ortho must be SPAI_ORTHO_MGS).  b and x are device arrays of n FP64
+ * values in the batch's row order; st is a host array of nsys statistics.
+ * Device workspace: up to two workgroups per compute unit, each holding
+ * n_max (min(maxit, n_max) + 1) + O(maxit^2) doubles for the largest system
+ * n_max (fewer workgroups if that would exceed a quarter of free memory).
+ * Returns the bitwise OR of the systems' warnings (SPAI_W_MAXIT,
+ * SPAI_W_NOCONV), or a negative error: SPAI_E_ARG (as spai_gmres_ir, a bad
+ * sys_ptr, an entry outside the blocks, ortho not MGS), SPAI_E_OOM, SPAI_E_HIP.
+ */
+int spai_gmres_ir_batched(spai_handle* h, const spai_csr* A, const spai_precond* P, int32_t nsys,
+                          const int32_t* sys_ptr, const double* b, double* x, const spai_ir_params* p,
+                          spai_ir_stats* st);
+
 /* Kernel timing for measurement: when enabled for a kernel class, every
  * `sample_every`-th launch of that class is bracketed by a pair of HIP events
  * recorded on the handle's stream.  spai_timing_read synchronises the stream,

@@ -100,11 +100,15 @@ def lib():
         L.spai_precond_apply.argtypes = [_p, _p, _p, _p]
         L.spai_precond_apply_uf.argtypes = [_p, _p, _p, _p]
         L.spai_spmv.argtypes = [_p, P(_Csr), _p, _p]
+        L.spai_build_batched.argtypes = [_p, P(_Csr), _c_i32, P(_c_i32), P(_Pattern), P(_BuildParams), P(_p),
+                                         P(_BuildStats)]
+        L.spai_gmres_ir_batched.argtypes = [_p, P(_Csr), _p, _c_i32, P(_c_i32), _p, _p, P(_IrParams), P(_IrStats)]
         L.spai_timing_enable.argtypes = [_p, ctypes.c_int, ctypes.c_int]
         L.spai_timing_read.argtypes = [_p, ctypes.c_int, P(_c_i64), P(_c_f64)]
         for name in ("spai_timing_enable", "spai_timing_read", "spai_create", "spai_destroy", "spai_set_stream", "spai_build", "spai_precond_import",
                      "spai_precond_view_get", "spai_precond_destroy", "spai_gmres_ir", "spai_residual",
-                     "spai_precond_apply", "spai_precond_apply_uf", "spai_spmv"):
+                     "spai_precond_apply", "spai_precond_apply_uf", "spai_spmv", "spai_build_batched",
+                     "spai_gmres_ir_batched"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -314,6 +318,39 @@ class Handle:
         s = st.steps
         return {"steps": s, "its": list(st.its[:s]), "total_its": st.total_its, "status": rc,
                 "gest": list(st.gest[:s]), "dnorm": list(st.dnorm[:s])}
+
+    # -- batches of independent systems (block-diagonal A, host sys_ptr) ------
+    def spai_build_batched(self, A: DeviceCSR, sys_ptr, pattern: Optional[DevicePattern], eps: float, alpha: int,
+                           beta: int, maxfill: int, u_f: str = "fp32"):
+        """Returns (Precond of the whole batch, warnings, stats dict)."""
+        sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f])
+        st = _BuildStats()
+        out = ctypes.c_void_p()
+        csr = A.c()
+        pat = pattern.c() if pattern is not None else None
+        rc = _check(lib().spai_build_batched(self._raw, ctypes.byref(csr), len(sys_ptr) - 1, sp,
+                                             ctypes.byref(pat) if pat else None, ctypes.byref(prm),
+                                             ctypes.byref(out), ctypes.byref(st)), "spai_build_batched")
+        stats = {f: getattr(st, f) for f, _ in _BuildStats._fields_}
+        return Precond(self, out.value, stats), rc, stats
+
+    def gmres_ir_batched(self, A: DeviceCSR, P: Precond, sys_ptr, b: torch.Tensor, x: torch.Tensor, tau: float,
+                         imax: int, maxit: int, tol_ir: float, u_r: str = "dd"):
+        """Returns (warning bits of all systems, list of per-system stats dicts)."""
+        nsys = len(sys_ptr) - 1
+        sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO["mgs"])
+        st = (_IrStats * nsys)()
+        csr = A.c()
+        rc = _check(lib().spai_gmres_ir_batched(self._raw, ctypes.byref(csr), P.raw, nsys, sp, _ptr(b), _ptr(x),
+                                                ctypes.byref(prm), st), "spai_gmres_ir_batched")
+        out = []
+        for q in range(nsys):
+            k = st[q].steps
+            out.append({"steps": k, "its": list(st[q].its[:k]), "total_its": st[q].total_its,
+                        "status": st[q].status, "gest": list(st[q].gest[:k]), "dnorm": list(st[q].dnorm[:k])})
+        return rc, out
 
     # -- measurement ---------------------------------------------------------
     def timing_enable(self, kernel: str, sample_every: int = 1):

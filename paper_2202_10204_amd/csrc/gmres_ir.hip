@@ -15,37 +15,12 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "device_math.hpp"
 
 namespace spai {
 
 constexpr int RB = 256;        // threads per reduction block
 constexpr int RBLOCKS = 1024;  // upper bound on reduction blocks
-
-// ---------------------------------------------------------------------------
-// double-double helpers (error-free transformations)
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
-    s = a + b;
-    double bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-__device__ __forceinline__ void fast_two_sum(double a, double b, double& s, double& e) {
-    s = a + b;
-    e = b - (s - a);
-}
-
-// (xh, xl) + (yh, yl), accurate double-word addition (Joldes, Muller, Popescu 2017)
-__device__ __forceinline__ void dd_add(double xh, double xl, double yh, double yl, double& zh, double& zl) {
-    double sh, sl, th, tl;
-    two_sum(xh, yh, sh, sl);
-    two_sum(xl, yl, th, tl);
-    sl = sl + th;
-    fast_two_sum(sh, sl, sh, sl);
-    sl = sl + tl;
-    fast_two_sum(sh, sl, zh, zl);
-}
 
 // ---------------------------------------------------------------------------
 // solver state shared by the kernels of one refinement step
@@ -182,30 +157,6 @@ __global__ void k_residual(int n, const int* __restrict__ rp, const int* __restr
 // g and sets `done` when |g_{j+1}| <= tau beta0, on an exact breakdown or at
 // maxit.
 // ---------------------------------------------------------------------------
-
-// Sum of one double over the 64 lanes of a wave (all lanes active), the same
-// bits in every lane: row sums of 16 lanes by DPP moves (quad_perm xor 1, xor 2,
-// row_ror 4, row_ror 8; no LDS round trip), then the four row sums read with
-// readlane and added in a fixed order.
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double read_lane(double v, int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_mov<0xB1>(v);     // quad_perm(1, 0, 3, 2)
-    v += dpp_mov<0x4E>(v);     // quad_perm(2, 3, 0, 1)
-    v += dpp_mov<0x124>(v);    // row_ror:4
-    v += dpp_mov<0x128>(v);    // row_ror:8
-    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
 
 // Load p[i] where ok, else 0, with an unconditional load of a valid address
 // (p[0] is always valid): the loads of a group then stay in one basic block.

@@ -485,3 +485,133 @@ def test_half_precision_spai_solve_matches_oracle(S, h, uf, ortho):
     x, st = _solve(S, h, w, A, P, ortho=ortho)
     assert st["its"] == oref.its
     assert O.ferr(x, w.x_true) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# batches of independent systems (one block-diagonal matrix)
+# ---------------------------------------------------------------------------
+
+def _batch_device(S, B):
+    A = S.DeviceCSR.from_host(B.A)
+    return A, _dev(B.b)
+
+
+def _compare_batch_columns(P, B, s, ref):
+    """System s's columns of the batched build against the oracle's build of s alone."""
+    cols = P.columns()
+    r0 = int(B.sys_ptr[s])
+    n = int(B.sys_ptr[s + 1]) - r0
+    L = cols["len"].cpu().numpy()[r0:r0 + n]
+    J = cols["J"].cpu().numpy()[r0:r0 + n]
+    M = cols["m"].cpu().numpy()[r0:r0 + n]
+    steps = cols["steps"].cpu().numpy()[r0:r0 + n]
+    bad = []
+    for k in range(n):
+        Lk = ref.length[k]
+        if (L[k] != Lk or steps[k] != ref.steps[k] or not np.array_equal(J[k, :Lk] - r0, ref.J[k, :Lk])
+                or not np.array_equal(M[k, :Lk], ref.m[k, :Lk])):
+            bad.append(k)
+    assert not bad, f"system {s}: {len(bad)} of {n} columns differ, first {bad[:8]}"
+
+
+def _batch_ferr(B, x):
+    out = []
+    for s in range(B.nsys):
+        r0, r1 = int(B.sys_ptr[s]), int(B.sys_ptr[s + 1])
+        out.append(O.ferr(x[r0:r1], B.x_true[r0:r1]))
+    return np.array(out)
+
+
+@pytest.fixture(scope="module")
+def batch48(S, h):
+    B = W.random_batch(48, 200, 2500)
+    A, b = _batch_device(S, B)
+    s = B.spai
+    P, warn, stats = h.spai_build_batched(A, B.sys_ptr, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    return B, A, b, P, stats
+
+
+def test_batched_build_is_the_per_system_build(S, h, batch48):
+    """Every column of 6 sampled systems of the batched build equals the
+    oracle's build of that system alone (bit-exact indices, values, steps)."""
+    B, A, b, P, stats = batch48
+    s = B.spai
+    for q in [0, 7, 19, 23, 40, 47]:
+        w = B.system(q)
+        ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+        _compare_batch_columns(P, B, q, ref)
+
+
+def test_batched_solve_matches_oracle_per_system(S, h, batch48):
+    """Each of the 48 systems: the batched GMRES-IR iteration tuple equals the
+    oracle's solve of that system alone, and x reaches 1e-12."""
+    B, A, b, P, stats = batch48
+    ir = B.ir
+    x = torch.zeros_like(b)
+    rc, st = h.gmres_ir_batched(A, P, B.sys_ptr, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+    assert rc == 0
+    xh = x.cpu().numpy()
+    ferr = _batch_ferr(B, xh)
+    assert ferr.max() <= 1e-12
+    s = B.spai
+    for q in range(B.nsys):
+        w = B.system(q)
+        ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+        pp, pc, pv = ref.P_csr(w.n)
+        o = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, w.ir.tau, w.ir.imax, w.ir.maxit, w.ir.tol_ir)
+        assert st[q]["its"] == o.its, f"system {q}"
+        r0, r1 = int(B.sys_ptr[q]), int(B.sys_ptr[q + 1])
+        assert np.abs(xh[r0:r1] - o.x).max() <= 1e-12 * np.abs(w.x_true).max()
+
+
+def test_batched_solve_is_the_single_solve(S, h, batch48):
+    """A system solved inside the batch and alone (spai_gmres_ir with MGS) gives
+    the same iteration tuple and the same solution to 1e-13."""
+    B, A, b, P, stats = batch48
+    ir = B.ir
+    x = torch.zeros_like(b)
+    rc, st = h.gmres_ir_batched(A, P, B.sys_ptr, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+    q = 13
+    w = B.system(q)
+    A1, P1, _, _ = _build(S, h, w)
+    x1, s1 = _solve(S, h, w, A1, P1)
+    assert s1["its"] == st[q]["its"]
+    r0, r1 = int(B.sys_ptr[q]), int(B.sys_ptr[q + 1])
+    assert np.abs(x.cpu().numpy()[r0:r1] - x1).max() <= 1e-13 * np.abs(w.x_true).max()
+
+
+def test_batched_rejects_entries_outside_blocks(S, h, batch48):
+    B, A, b, P, stats = batch48
+    bad = B.sys_ptr.copy()
+    bad[5] += 3                                   # cuts through the rows of systems 4 and 5
+    s = B.spai
+    with pytest.raises(S.SpaiError):
+        h.spai_build_batched(A, bad, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    x = torch.zeros_like(b)
+    with pytest.raises(S.SpaiError):
+        h.gmres_ir_batched(A, P, bad, b, x, B.ir.tau, B.ir.imax, B.ir.maxit, B.ir.tol_ir)
+
+
+def test_batch4096_full_size(S, h):
+    """The full batch (4096 systems, n log-uniform in [200, 20000]): 8 sampled
+    systems' columns and iteration tuples equal the oracle's solves of those
+    systems alone; every system reaches 1e-12."""
+    B = W.random_batch(4096)
+    A, b = _batch_device(S, B)
+    s, ir = B.spai, B.ir
+    P, warn, stats = h.spai_build_batched(A, B.sys_ptr, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    x = torch.zeros_like(b)
+    rc, st = h.gmres_ir_batched(A, P, B.sys_ptr, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
+    assert rc == 0
+    ferr = _batch_ferr(B, x.cpu().numpy())
+    assert ferr.max() <= 1e-12
+    rng = np.random.default_rng(5)
+    ns = np.diff(B.sys_ptr)
+    sample = sorted(set(rng.choice(B.nsys, 6, replace=False).tolist()) | {int(np.argmax(ns)), int(np.argmin(ns))})
+    for q in sample:
+        w = B.system(q)
+        ref = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+        _compare_batch_columns(P, B, q, ref)
+        pp, pc, pv = ref.P_csr(w.n)
+        o = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, w.ir.tau, w.ir.imax, w.ir.maxit, w.ir.tol_ir)
+        assert st[q]["its"] == o.its, f"system {q}"

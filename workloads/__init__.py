@@ -38,7 +38,7 @@ import numpy as np
 ROOT_SEED = 220210204
 
 # purposes for seed streams
-_COEF, _XTRUE, _TRACE = 0, 1, 2
+_COEF, _XTRUE, _TRACE, _SIZES = 0, 1, 2, 3
 
 
 def rng_for(config_id: int, size_tag: int, purpose: int) -> np.random.Generator:
@@ -400,6 +400,105 @@ def aniso_fixed(N: int = 128, u_f: str = "fp16") -> Workload:
                     IrParams(tau=1e-8, imax=10, maxit=min(n, 500), tol_ir=TOL_IR),
                     f"aniso3d N={N} jumps 1e4 in 5% cells, anisotropy (1,1,1e-3), values on 2^-24 grid, "
                     f"x_true on 2^-10 grid")
+
+
+def random_banded_rows(n: int, rng: np.random.Generator, kmin: int = 4, kmax: int = 12,
+                       half_band: int = 32, dominance: float = 1.1, pbits: int = 26) -> CSR:
+    """The structure of ``random_banded`` drawn row-parallel (its own stream).
+
+    Row i holds k_i ~ U{kmin..kmax} entries including the diagonal; the k_i - 1
+    off-diagonal columns are the candidates i + o, o in [-half_band, half_band-1]
+    without 0 and inside [0, n), with the smallest of independent U(0,1) keys
+    (a uniform draw without replacement); values N(0,1) on the 2^-pbits grid
+    (an exact zero becomes 2^-pbits) and a_ii = dominance * sum_j |a_ij| on the
+    grid."""
+    ks = rng.integers(kmin, kmax + 1, size=n)
+    offs = np.concatenate([np.arange(-half_band, 0), np.arange(1, half_band)])
+    cand = np.arange(n, dtype=np.int64)[:, None] + offs[None, :]
+    valid = (cand >= 0) & (cand < n)
+    keys = rng.random(cand.shape)
+    keys[~valid] = 2.0
+    m = min(kmax - 1, offs.size)               # the m smallest keys of a row, in ascending order
+    part = np.argpartition(keys, m - 1, axis=1)[:, :m]
+    order = np.take_along_axis(part, np.argsort(np.take_along_axis(keys, part, axis=1), axis=1), axis=1)
+    kk = np.minimum(ks - 1, valid.sum(axis=1))
+    take = np.arange(m)[None, :] < kk[:, None]
+    cols = np.take_along_axis(cand, order, axis=1)[take]
+    rows = np.repeat(np.arange(n), kk)
+    v = _quantize(rng.standard_normal(cols.size), pbits)
+    v[v == 0.0] = 2.0 ** -pbits
+    d = _quantize(dominance * np.bincount(rows, weights=np.abs(v), minlength=n), pbits)
+    d[d == 0.0] = 1.0
+    return _assemble(n, np.concatenate([rows, np.arange(n)]), np.concatenate([cols, np.arange(n)]),
+                     np.concatenate([v, d]))
+
+
+@dataclasses.dataclass
+class Batch:
+    """Independent systems stored as one block-diagonal matrix: system s owns rows
+    and columns sys_ptr[s] .. sys_ptr[s+1]-1."""
+
+    name: str
+    sys_ptr: np.ndarray
+    A: CSR
+    x_true: np.ndarray
+    b: np.ndarray
+    spai: SpaiParams
+    ir: IrParams
+    recipe: str
+
+    @property
+    def nsys(self) -> int:
+        return len(self.sys_ptr) - 1
+
+    @property
+    def n(self) -> int:
+        return self.A.n
+
+    def system(self, s: int) -> Workload:
+        """System s alone (indices rebased), with the batch's parameters."""
+        r0, r1 = int(self.sys_ptr[s]), int(self.sys_ptr[s + 1])
+        q0, q1 = int(self.A.rowptr[r0]), int(self.A.rowptr[r1])
+        A = CSR(r1 - r0, (self.A.rowptr[r0:r1 + 1] - q0).astype(np.int32),
+                (self.A.col[q0:q1] - r0).astype(np.int32), self.A.val[q0:q1].copy())
+        return Workload(f"{self.name}_sys{s}", A, self.x_true[r0:r1].copy(), self.b[r0:r1].copy(), None,
+                        dataclasses.replace(self.spai),
+                        dataclasses.replace(self.ir, maxit=min(A.n, self.ir.maxit)), self.recipe)
+
+
+def random_batch(nsys: int = 4096, nmin: int = 200, nmax: int = 20000) -> Batch:
+    """Many independent random banded systems (4-12 entries per row within a band
+    of 64, N(0,1), dominance 1.1), sizes log-uniform in [nmin, nmax]; adaptive
+    FP32 SPAI (identity start, eps 0.3, beta 8, at most 20 entries per column;
+    alpha = ceil(nmin / 8) >= 3 steps, which the fill cap reaches first: at most
+    (20 - 1) / 8 + 1 = 3 augmentations), FP64 GMRES-IR with a double-double
+    residual, tau 1e-8, maxit min(n_s, 500).  Full size: 4096 systems,
+    sum n ~ 1.8e7."""
+    sz = rng_for(5, nsys, _SIZES)
+    ns = np.rint(np.exp(sz.uniform(math.log(nmin), math.log(nmax), size=nsys))).astype(np.int64)
+    ptr = np.zeros(nsys + 1, np.int64)
+    ptr[1:] = np.cumsum(ns)
+    rps, cols, vals, xs, bs = [], [], [], [], []
+    nnz_off = 0
+    for s in range(nsys):
+        n = int(ns[s])
+        A = random_banded_rows(n, rng_for(5, 1_000_000 + s, _COEF))
+        x, b = exact_rhs(A, rng_for(5, 1_000_000 + s, _XTRUE), pbits=26, sbits=16)
+        rps.append(A.rowptr[:-1].astype(np.int64) + nnz_off)
+        cols.append(A.col + ptr[s])
+        vals.append(A.val)
+        xs.append(x)
+        bs.append(b)
+        nnz_off += A.nnz
+    if nnz_off >= 2**31 or ptr[-1] >= 2**31:
+        raise ValueError("batch exceeds int32 indices")
+    rowptr = np.concatenate(rps + [np.array([nnz_off])]).astype(np.int32)
+    A = CSR(int(ptr[-1]), rowptr, np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+    return Batch(f"random_batch_{nsys}_n{nmin}-{nmax}", ptr, A, np.concatenate(xs), np.concatenate(bs),
+                 SpaiParams(eps=0.3, alpha=-(-nmin // 8), beta=8, maxfill=20, u_f="fp32"),
+                 IrParams(tau=1e-8, imax=10, maxit=500, tol_ir=TOL_IR),
+                 f"{nsys} random banded systems, n log-uniform in [{nmin}, {nmax}], 4-12 nnz/row in a band of 64, "
+                 f"N(0,1) on 2^-26 grid, diag 1.1 x offdiag abs sum, x_true on 2^-16 grid")
 
 
 def random_system(n: int, sys_id: int = 0) -> Workload:

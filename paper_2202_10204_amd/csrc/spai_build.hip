@@ -710,10 +710,41 @@ static int launch_columns(spai_handle* h, const ColArgs& a, hipStream_t s) {
 // configurations: lanes per problem G (|J| <= G-1), shadow rows, gathered entries,
 // raw candidates; the last one is the large-problem kernel for deferred columns
 template <int UF> using CfgS = Cfg<UF, 8, 32, 64, 256>;
-template <int UF> using CfgM = Cfg<UF, 16, 64, 128, 512>;
-template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 512>;
+template <int UF> using CfgM = Cfg<UF, 16, 64, 128, 256>;
+template <int UF> using CfgM21s = Cfg<UF, 21, 40, 128, 256>;   // small shadows: more problems per CU
+template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256>;
 template <int UF> using CfgL = Cfg<UF, 32, 64, 256, 512>;
 template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 2048>;
+
+__global__ void k_strided_list(int count, int stride, int* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = i * stride;
+}
+
+// For |J| <= 20: the small-shadow configuration when a strided sample of at
+// most 2048 columns defers no more than 2% of its columns to the large-problem
+// kernel, else the standard one.  A deferred column is recomputed from scratch
+// by the next configuration with the same arithmetic, so the choice changes
+// the time, not the result.
+template <int UF>
+static int launch_columns_m21(spai_handle* h, const ColArgs& a, hipStream_t s, int* sample_list,
+                              int* count_host) {
+    if (a.cols != nullptr || a.ncols < 4096) return launch_columns<CfgM21<UF>>(h, a, s);
+    const int ns = 2048, stride = a.ncols / ns;
+    hipLaunchKernelGGL(k_strided_list, dim3((ns + 255) / 256), dim3(256), 0, s, ns, stride, sample_list);
+    SPAI_HIP(hipGetLastError());
+    ColArgs smp = a;
+    smp.cols = sample_list;
+    smp.ncols = ns;
+    SPAI_HIP(hipMemsetAsync(a.defer_count, 0, sizeof(int), s));
+    int rc = launch_columns<CfgM21s<UF>>(h, smp, s);
+    if (rc) return rc;
+    SPAI_HIP(hipMemcpyAsync(count_host, a.defer_count, sizeof(int), hipMemcpyDeviceToHost, s));
+    SPAI_HIP(hipStreamSynchronize(s));
+    const bool small = *count_host * 50 <= ns;
+    SPAI_HIP(hipMemsetAsync(a.defer_count, 0, sizeof(int), s));
+    return small ? launch_columns<CfgM21s<UF>>(h, a, s) : launch_columns<CfgM21<UF>>(h, a, s);
+}
 
 template <int UF>
 static int run_columns(spai_handle* h, int pmax, ColArgs a, hipStream_t s, int* defer_list2, int* defer_count_dev,
@@ -722,7 +753,7 @@ static int run_columns(spai_handle* h, int pmax, ColArgs a, hipStream_t s, int* 
     int* dc = a.defer_count;
     if (pmax <= CfgS<UF>::MAXP) rc = launch_columns<CfgS<UF>>(h, a, s);
     else if (pmax <= CfgM<UF>::MAXP) rc = launch_columns<CfgM<UF>>(h, a, s);
-    else if (pmax <= CfgM21<UF>::MAXP) rc = launch_columns<CfgM21<UF>>(h, a, s);
+    else if (pmax <= CfgM21<UF>::MAXP) rc = launch_columns_m21<UF>(h, a, s, defer_list2, defer_count_host);
     else if (pmax <= CfgL<UF>::MAXP) rc = launch_columns<CfgL<UF>>(h, a, s);
     else {
         // everything goes straight to the large kernel

@@ -11,7 +11,9 @@ refinement with sparse approximate inverse preconditioning"):
                    least-squares solution of eq. (redprob) (numpy lstsq);
 * ``gmres_ir``   — Algorithm 3 (Section 3.2): x0 = P b in u_f, residuals
                    computed exactly and rounded to FP64, left-preconditioned
-                   MGS-GMRES in FP64 (u_g = u_p = u, Section 4);
+                   MGS-GMRES in FP64 (u_g = u_p = u, Section 4); or, for the
+                   precision sets of Tables 4-5, everything stored in binary32
+                   with residuals in binary64;
 * ``residual``   — r = fl(b - A x), each component exactly rounded.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
@@ -67,6 +69,8 @@ def _lib():
         L.oracle_gmres_ir.restype = i32
         L.oracle_gmres_ir.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64,
                                       i32, P, P, P, P]
+        L.oracle_gmres_ir_fp32.restype = i32
+        L.oracle_gmres_ir_fp32.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64, P, P, P, P]
         L.oracle_residual.restype = None
         L.oracle_residual.argtypes = [i32, P, P, P, P, P, P]
         L.oracle_exact_sum.restype = f64
@@ -279,13 +283,17 @@ ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 
 def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, maxit: int,
-             tol_ir: float, ortho: str = "mgs") -> IrResult:
+             tol_ir: float, ortho: str = "mgs", u: str = "fp64") -> IrResult:
     """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D.
 
     ``ortho`` = "mgs" (modified Gram-Schmidt, the variant analysed in Section
     3.2), "cgs2" (classical Gram-Schmidt applied twice) or "dcgs2" (CGS2 with
     the second projection and the normalisation delayed by one step: one set of
-    inner products per Arnoldi step)."""
+    inner products per Arnoldi step).
+
+    ``u`` is the working precision u = u_g = u_p: "fp64" (residual rounded
+    exactly to FP64, the precision set of Table 3) or "fp32" (the sets of Tables
+    4 and 5: every stored quantity binary32, residual in binary64, MGS only)."""
     n = A.n
     x = np.zeros(n)
     its = np.zeros(imax, np.int32)
@@ -295,9 +303,18 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     rp, ci, av = _i32(A.rowptr), _i32(A.col), _f64(A.val)
     pp, pc, pv = _i32(P_rowptr), _i32(P_col), _f64(P_val)
     dd, bb = _f64(d), _f64(b)
-    st = _lib().oracle_gmres_ir(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
-                                _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
-                                ORTHO[ortho], _p(its), _p(nsteps), _p(gest), _p(dn))
+    if u == "fp32":
+        if ortho != "mgs":
+            raise ValueError("the single working precision variant uses MGS")
+        st = _lib().oracle_gmres_ir_fp32(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
+                                         _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
+                                         _p(its), _p(nsteps), _p(gest), _p(dn))
+    elif u == "fp64":
+        st = _lib().oracle_gmres_ir(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
+                                    _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
+                                    ORTHO[ortho], _p(its), _p(nsteps), _p(gest), _p(dn))
+    else:
+        raise ValueError(f"unknown working precision {u}")
     if st < 0:
         raise ValueError("oracle_gmres_ir: bad argument")
     s = int(nsteps[0])

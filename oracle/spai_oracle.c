@@ -938,6 +938,159 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
     return status;
 }
 
+/*
+ * SPAI-GMRES-IR with working precision u = u_g = u_p = single and residual
+ * precision u_r = double (the precision sets (half, single, double) and
+ * (single, single, double) of Tables 4 and 5).  Every quantity Algorithm 3
+ * stores in u is a binary32 value: A and b (rounded to binary32 on entry; the
+ * paper's data are given in u), the scaling d, x0, r_i, the Krylov basis, the
+ * Hessenberg matrix, the rotations, d_i and x.  The residual is evaluated in
+ * binary64 (products of binary32 values are exact there; the row's terms are
+ * subtracted from b_i one by one in CSR order) and then rounded to binary32.
+ * P is applied in binary32: D w rounded per element, then each row's sum in
+ * ascending column order with fused multiply-adds; A likewise.  Inner products
+ * and norms are sequential binary32 sums with fused multiply-adds.  GMRES is
+ * MGS with the same stopping rules as oracle_gmres_ir; the refinement stops
+ * when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf, after imax steps, on stagnation
+ * (from the third step) or before a step whose P r_i is exactly zero.  uf must
+ * be a binary32 or 16-bit format (u_f no finer than u).  x (out) receives the
+ * binary32 solution as doubles.
+ */
+static float dot32(int n, const float* a, const float* b) {
+    float s = 0.0f;
+    for (int i = 0; i < n; ++i) s = fmaf(a[i], b[i], s);
+    return s;
+}
+
+static void apply_P32(int n, const int* pp, const int* pc, const float* pv, const float* d, const float* w,
+                      float* dw, float* y) {
+    for (int j = 0; j < n; ++j) dw[j] = d[j] * w[j];
+    for (int k = 0; k < n; ++k) {
+        float s = 0.0f;
+        for (int t = pp[k]; t < pp[k + 1]; ++t) s = fmaf(pv[t], dw[pc[t]], s);
+        y[k] = s;
+    }
+}
+
+static void spmv32(int n, const int* rp, const int* ci, const float* av, const float* x, float* y) {
+    for (int i = 0; i < n; ++i) {
+        float s = 0.0f;
+        for (int t = rp[i]; t < rp[i + 1]; ++t) s = fmaf(av[t], x[ci[t]], s);
+        y[i] = s;
+    }
+}
+
+int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, const int* pp,
+                         const int* pc, const double* pv, const double* d, int uf, const double* b,
+                         double* x, double tau, int imax, int maxit, double tol_ir, int* its, int* nsteps,
+                         double* gest, double* dnorm) {
+    if (n <= 0 || imax < 1 || maxit < 1 || uf == OR_FP64) return -1;
+    const int nnz = rp[n], pnz = pp[n];
+    float* af = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+    float* pf = (float*)malloc(sizeof(float) * (size_t)(pnz > 0 ? pnz : 1));
+    float* df = (float*)malloc(sizeof(float) * (size_t)n);
+    float* bf = (float*)malloc(sizeof(float) * (size_t)n);
+    float* xf = (float*)malloc(sizeof(float) * (size_t)n);
+    float* r = (float*)malloc(sizeof(float) * (size_t)n);
+    float* z = (float*)malloc(sizeof(float) * (size_t)n);
+    float* w = (float*)malloc(sizeof(float) * (size_t)n);
+    float* y = (float*)malloc(sizeof(float) * (size_t)n);
+    float* dw = (float*)malloc(sizeof(float) * (size_t)n);
+    float* V = (float*)malloc(sizeof(float) * (size_t)n * (size_t)(maxit + 1));
+    float* H = (float*)calloc((size_t)(maxit + 1) * (size_t)maxit, sizeof(float));
+    float* cs = (float*)malloc(sizeof(float) * (size_t)maxit);
+    float* sn = (float*)malloc(sizeof(float) * (size_t)maxit);
+    float* g = (float*)malloc(sizeof(float) * (size_t)(maxit + 1));
+    float* yk = (float*)malloc(sizeof(float) * (size_t)maxit);
+    double* x0 = (double*)malloc(sizeof(double) * (size_t)n);
+#define HH(i, j) H[(size_t)(j) * (size_t)(maxit + 1) + (size_t)(i)]
+    for (int t = 0; t < nnz; ++t) af[t] = (float)av[t];
+    for (int t = 0; t < pnz; ++t) pf[t] = (float)pv[t];
+    for (int i = 0; i < n; ++i) {
+        df[i] = (float)d[i];
+        bf[i] = (float)b[i];
+    }
+    /* x0 = P b in u_f (as in the double-precision variant), stored in u */
+    oracle_x0(n, pp, pc, pv, d, b, uf, x0);
+    for (int i = 0; i < n; ++i) xf[i] = (float)x0[i];
+    int status = 0;
+    float dprev = INFINITY;
+    *nsteps = 0;
+    for (int step = 0; step < imax; ++step) {
+        for (int i = 0; i < n; ++i) {           /* r = b - A x in double, stored in single */
+            double s = (double)bf[i];
+            for (int t = rp[i]; t < rp[i + 1]; ++t) s = fma(-(double)af[t], (double)xf[ci[t]], s);
+            r[i] = (float)s;
+        }
+        apply_P32(n, pp, pc, pf, df, r, dw, z);
+        const float beta0 = sqrtf(dot32(n, z, z));
+        if (beta0 == 0.0f) break;
+        its[step] = 0;
+        if (gest) gest[step] = 0.0;
+        if (dnorm) dnorm[step] = 0.0;
+        *nsteps = step + 1;
+        for (int i = 0; i < n; ++i) V[i] = z[i] / beta0;
+        for (int i = 0; i <= maxit; ++i) g[i] = 0.0f;
+        g[0] = beta0;
+        int k = 0;
+        for (int j = 0; j < maxit; ++j) {
+            float* vj = V + (size_t)j * n;
+            spmv32(n, rp, ci, af, vj, w);
+            apply_P32(n, pp, pc, pf, df, w, dw, y);
+            for (int l = 0; l <= j; ++l) {             /* modified Gram-Schmidt */
+                const float* vl = V + (size_t)l * n;
+                const float h = dot32(n, y, vl);
+                HH(l, j) = h;
+                for (int i = 0; i < n; ++i) y[i] = fmaf(-h, vl[i], y[i]);
+            }
+            const float hn = sqrtf(dot32(n, y, y));
+            HH(j + 1, j) = hn;
+            for (int l = 0; l < j; ++l) {
+                const float a = HH(l, j), c2 = HH(l + 1, j);
+                HH(l, j) = cs[l] * a + sn[l] * c2;
+                HH(l + 1, j) = -sn[l] * a + cs[l] * c2;
+            }
+            const float delta = hypotf(HH(j, j), HH(j + 1, j));
+            cs[j] = HH(j, j) / delta;
+            sn[j] = HH(j + 1, j) / delta;
+            HH(j, j) = delta;
+            HH(j + 1, j) = 0.0f;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (fabsf(g[j + 1]) <= (float)tau * beta0 || hn == 0.0f) break;
+            if (j + 1 == maxit) { status |= IR_MAXIT; break; }
+            float* vn = V + (size_t)(j + 1) * n;
+            for (int i = 0; i < n; ++i) vn[i] = y[i] / hn;
+        }
+        its[step] = k;
+        if (gest) gest[step] = (double)(fabsf(g[k]) / beta0);
+        for (int c = k - 1; c >= 0; --c) {
+            float s = g[c];
+            for (int c2 = c + 1; c2 < k; ++c2) s = fmaf(-HH(c, c2), yk[c2], s);
+            yk[c] = s / HH(c, c);
+        }
+        float dn = 0.0f, xn = 0.0f;
+        for (int i = 0; i < n; ++i) {
+            float di = 0.0f;
+            for (int c = 0; c < k; ++c) di = fmaf(V[(size_t)c * n + i], yk[c], di);
+            xf[i] = xf[i] + di;
+            if (fabsf(di) > dn) dn = fabsf(di);
+            if (fabsf(xf[i]) > xn) xn = fabsf(xf[i]);
+        }
+        if (dnorm) dnorm[step] = (double)dn;
+        if ((double)dn <= tol_ir * (double)xn) break;
+        if (step >= 2 && dn > 0.5f * dprev) { status |= IR_STAGNATED; break; }
+        dprev = dn;
+        if (step == imax - 1) status |= IR_NOCONV;
+    }
+#undef HH
+    for (int i = 0; i < n; ++i) x[i] = (double)xf[i];
+    free(af); free(pf); free(df); free(bf); free(xf); free(r); free(z); free(w); free(y); free(dw);
+    free(V); free(H); free(cs); free(sn); free(g); free(yk); free(x0);
+    return status;
+}
+
 /* y = P w in FP64 (for tests of the application of the preconditioner) */
 void oracle_apply_P(int n, const int* pp, const int* pc, const double* pv, const double* d,
                     const double* w, double* y) {

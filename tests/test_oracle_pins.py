@@ -443,3 +443,70 @@ def test_x0_in_fp32_is_sequential_fp32():
     x0 = O.x0(np.arange(n + 1), np.arange(n), pv, d, b, "fp32")
     expect = (pv.astype(np.float32) * (d * b).astype(np.float32)).astype(np.float64)
     assert np.array_equal(x0, expect)
+
+
+# ---------------------------------------------------------------------------
+# working precision single (the precision sets of Tables 4 and 5)
+# ---------------------------------------------------------------------------
+
+def _f32(a):
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
+def test_fp32_gmres_step_is_the_krylov_least_squares_minimiser():
+    """u = single: after k iterations (tau = 0) the correction is the Krylov
+    least-squares minimiser of the binary32 data (A and b rounded to binary32,
+    x0 and r0 stored in binary32, r0 evaluated in binary64), up to binary32
+    rounding of the Arnoldi process."""
+    rng = np.random.default_rng(21)
+    n = 8
+    Ad = _f32(_random_dd(n, rng, density=0.6, dom=0.4))
+    A = _csr(Ad)
+    b = _f32(rng.standard_normal(n))
+    pp, pc, pv, d = np.arange(n + 1), np.arange(n), np.ones(n), np.ones(n)
+    x0 = _f32(O.x0(pp, pc, pv, d, b, "fp32"))
+    r0 = _f32(b - Ad @ x0)
+    for k in range(1, 6):
+        res = O.gmres_ir(A, pp, pc, pv, d, "fp32", b, 0.0, 1, k, 0.0, "mgs", "fp32")
+        assert res.its == [k]
+        assert np.array_equal(_f32(res.x), res.x)           # x is stored in binary32
+        K = np.column_stack([np.linalg.matrix_power(Ad, i) @ r0 for i in range(k)])
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(Ad @ Q, r0, rcond=None)
+        dexp = Q @ y
+        assert np.abs((res.x - x0) - dexp).max() <= 2e-5 * np.abs(dexp).max() + 4 * 2.0 ** -24 * np.abs(x0).max()
+
+
+def test_fp32_exact_preconditioner_takes_one_iteration_per_step():
+    """P = A^-1 rounded to binary32 (u_f = single = u): every refinement step
+    takes one GMRES iteration (the 1(1)-type rows of Table 5), and the
+    refinement reaches the binary32 limiting accuracy."""
+    w = W.s0_matrix(5)
+    Ad = _dense(w.A)
+    S = sp.csr_matrix(_f32(np.linalg.inv(Ad)))
+    S.sort_indices()
+    res = O.gmres_ir(w.A, S.indptr, S.indices, S.data, np.ones(w.n), "fp32", w.b, 1e-4, 10, 50, W.TOL_IR32,
+                     "mgs", "fp32")
+    assert all(k == 1 for k in res.its), res.its
+    assert O.ferr(res.x, w.x_true) <= 2.0 ** -22
+
+
+def test_fp32_limiting_accuracy_and_half_vs_single():
+    """Theorem 1 with u = single, u_r = double: the forward error reaches the
+    order of u (here x_true is a binary32 vector); SPAI in half and in single
+    give near-identical nnz(P) and iteration totals (Tables 4 and 5)."""
+    w = W.s0_matrix(6)
+    n, ir = w.n, w.ir
+    assert ir.u == "fp32" and ir.tau == 1e-4
+    tot = {}
+    for uf in ("fp16", "fp32"):
+        R = O.spai(w.A, None, 0.3, -(-n // 8), 8, 63, uf)
+        pp, pc, pv = R.P_csr(n)
+        res = O.gmres_ir(w.A, pp, pc, pv, R.d, uf, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "mgs", "fp32")
+        assert res.status & ~O.IR_STAGNATED == 0
+        assert O.ferr(res.x, w.x_true) <= 2.0 ** -20
+        tot[uf] = (int(pp[-1]), sum(res.its))
+    assert abs(tot["fp16"][0] - tot["fp32"][0]) <= 0.05 * tot["fp32"][0]
+    assert abs(tot["fp16"][1] - tot["fp32"][1]) <= 0.25 * tot["fp32"][1] + 2
+    with pytest.raises(ValueError):
+        O.gmres_ir(w.A, pp, pc, pv, R.d, "fp32", w.b, ir.tau, 1, 5, ir.tol_ir, "dcgs2", "fp32")

@@ -58,3 +58,40 @@ def test_random_banded_band_and_dominance():
     d = np.abs(S.diagonal())
     off = np.asarray(abs(S).sum(1)).ravel() - d
     assert np.all(d >= 1.1 * off * (1 - 1e-6))
+
+
+def test_s0_shapes_follow_the_table():
+    """The paper-shaped stand-ins have the n and nnz of Table tab:mats, a nonzero
+    diagonal, kappa_inf within 10x of the listed one, and an exact right-hand
+    side; the matrices of the single-working-precision tables are exact in FP32
+    (A, x_true and b)."""
+    for k, (name, n, nnz, kappa, pset, eps) in enumerate(W.S0_SHAPES):
+        if n > 1200:
+            continue   # the 2205 case takes several seconds of dense algebra
+        w = W.s0_matrix(k)
+        assert w.n == n and w.A.nnz == nnz, name
+        S = w.A.to_scipy()
+        assert np.all(S.diagonal() != 0.0)
+        assert 0.1 <= W.kappa_inf(w.A) / kappa <= 10.0, name
+        r = np.asarray(S @ w.x_true) - w.b
+        assert np.abs(r).max() == 0.0
+        if pset == "hsd":
+            for v in (w.A.val, w.x_true, w.b):
+                assert np.array_equal(v.astype(np.float32).astype(np.float64), v), name
+
+
+def test_serving_trace_mix():
+    tr = W.serving_trace(200.0, 2.0)
+    assert 300 <= len(tr) <= 500
+    assert all(a.t < b.t for a, b in zip(tr, tr[1:]))
+    kinds = {a.kind for a in tr}
+    assert kinds == {"convdiff", "aniso", "random"}
+    for a in tr:
+        lo, hi = {"convdiff": (32, 512), "aniso": (10, 128), "random": (1000, 20000)}[a.kind]
+        assert lo <= a.size <= hi
+        assert a.u_f in ("fp16", "fp32")
+    assert tr == W.serving_trace(200.0, 2.0)
+    w = W.serving_request(tr[0])
+    assert w.spai.u_f == tr[0].u_f
+    r = np.asarray(w.A.to_scipy() @ w.x_true) - w.b
+    assert np.abs(r).max() == 0.0

@@ -331,6 +331,7 @@ class IrParams:
     imax: int             # maximum refinement steps
     maxit: int            # maximum GMRES iterations per refinement step
     tol_ir: float         # refinement stops when ||d||_inf <= tol_ir ||x||_inf
+    u: str = "fp64"       # working precision u = u_g = u_p ("fp64" or "fp32")
 
 
 @dataclasses.dataclass
@@ -350,6 +351,7 @@ class Workload:
 
 
 TOL_IR = 2.0 ** -45   # refinement stops once ||d||_inf <= 2^-45 ||x||_inf (about 256 u)
+TOL_IR32 = 2.0 ** -16  # the same 256 u for working precision single
 
 
 def _convdiff_pbits(N: int, peclet: float, sbits: int) -> int:
@@ -510,3 +512,190 @@ def random_system(n: int, sys_id: int = 0) -> Workload:
                     IrParams(tau=1e-8, imax=10, maxit=min(n, 500), tol_ir=TOL_IR),
                     f"random banded n={n} 4-12 nnz/row half-band 32, N(0,1) on 2^-26 grid, "
                     f"diag 1.1 x offdiag abs sum, x_true on 2^-16 grid")
+
+
+# ---------------------------------------------------------------------------
+# serving stream: Poisson arrivals of systems of the three families
+# ---------------------------------------------------------------------------
+
+SERVE_ALPHA = 125   # augmentation cap of the adaptive families in the stream (see serving_request)
+
+
+@dataclasses.dataclass
+class Arrival:
+    t: float      # arrival time in seconds from the start of the stream
+    kind: str     # "convdiff" (2D, adaptive), "aniso" (3D, fixed pattern(A^2)), "random" (banded, adaptive)
+    size: int     # grid side for convdiff / aniso, n for random
+    u_f: str      # "fp16" or "fp32"
+    req_id: int
+
+
+def serving_trace(rate: float = 200.0, duration: float = 60.0, tag: int = 0,
+                  max_side_2d: int = 512, max_side_3d: int = 128, max_n_random: int = 20000) -> list:
+    """Poisson arrivals at ``rate`` per second for ``duration`` seconds; each request
+    is uniform over the three families with sizes log-uniform in: 2D side
+    [32, max_side_2d], 3D side [10, max_side_3d], random n [1000, max_n_random]
+    (so n spans 1e3 .. 2.1e6 at the defaults), and u_f FP16 or FP32 with equal
+    probability."""
+    rng = rng_for(6, tag, _TRACE)
+    out, t, k = [], 0.0, 0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            return out
+        kind = ("convdiff", "aniso", "random")[int(rng.integers(0, 3))]
+        u = float(rng.random())
+        if kind == "convdiff":
+            size = int(round(math.exp(math.log(32) + u * (math.log(max_side_2d) - math.log(32)))))
+        elif kind == "aniso":
+            size = int(round(math.exp(math.log(10) + u * (math.log(max_side_3d) - math.log(10)))))
+        else:
+            size = int(round(math.exp(math.log(1000) + u * (math.log(max_n_random) - math.log(1000)))))
+        u_f = "fp16" if rng.random() < 0.5 else "fp32"
+        out.append(Arrival(t, kind, size, u_f, k))
+        k += 1
+
+
+def serving_request(a: Arrival) -> Workload:
+    """The system of one arrival, from its own seed streams.  The adaptive
+    families use alpha = SERVE_ALPHA for every size (not ceil(n / beta)) so that
+    requests of different sizes share parameters and can be batched: from the
+    identity start with beta = 8 and at most 20 entries per column a column
+    takes at most 3 augmentation steps, so any alpha >= 3 gives the same
+    preconditioner."""
+    tag = 10_000_000 + a.req_id
+    if a.kind == "convdiff":
+        N = a.size
+        pb = _convdiff_pbits(N, 100.0, 17)
+        A = convdiff2d(N, 100.0, (1e-2, 1.0), rng_for(6, tag, _COEF), pbits=pb)
+        x, b = exact_rhs(A, rng_for(6, tag, _XTRUE), pbits=pb, sbits=17)
+        return Workload(f"serve{a.req_id}_convdiff_{N}x{N}", A, x, b, None,
+                        SpaiParams(eps=0.3, alpha=SERVE_ALPHA, beta=8, maxfill=20, u_f=a.u_f),
+                        IrParams(tau=1e-8, imax=10, maxit=500, tol_ir=TOL_IR),
+                        f"convdiff2d N={N} Pe=100 kappa~logU[1e-2,1], values on 2^-{pb} grid, x_true on 2^-17 grid")
+    if a.kind == "aniso":
+        N = a.size
+        A = aniso3d(N, rng_for(6, tag, _COEF), pbits=24)
+        x, b = exact_rhs(A, rng_for(6, tag, _XTRUE), pbits=24, sbits=10)
+        return Workload(f"serve{a.req_id}_aniso_{N}^3", A, x, b, pattern_power2_trunc(A, 27),
+                        SpaiParams(eps=0.5, alpha=0, beta=8, maxfill=27, u_f=a.u_f),
+                        IrParams(tau=1e-8, imax=10, maxit=500, tol_ir=TOL_IR),
+                        f"aniso3d N={N} jumps 1e4 in 5% cells, values on 2^-24 grid, x_true on 2^-10 grid")
+    n = a.size
+    A = random_banded_rows(n, rng_for(6, tag, _COEF))
+    x, b = exact_rhs(A, rng_for(6, tag, _XTRUE), pbits=26, sbits=16)
+    return Workload(f"serve{a.req_id}_random_n{n}", A, x, b, None,
+                    SpaiParams(eps=0.3, alpha=SERVE_ALPHA, beta=8, maxfill=20, u_f=a.u_f),
+                    IrParams(tau=1e-8, imax=10, maxit=500, tol_ir=TOL_IR),
+                    f"random banded n={n} 4-12 nnz/row half-band 32, N(0,1) on 2^-26 grid, x_true on 2^-16 grid")
+
+
+# ---------------------------------------------------------------------------
+# paper-shaped stand-ins for the matrices of Table tab:mats
+# ---------------------------------------------------------------------------
+
+# (shape of the table's row, n, nnz, kappa_inf(A), precision set, epsilons of its tables)
+# Set "sdq" = (u_f, u, u_r) = (single, double, quad) of Table 3; "hsd" = (half, single,
+# double) of Table 4, also run as (single, single, double) in Table 5.
+S0_SHAPES = [
+    ("pores_3", 532, 3474, 1.2e6, "sdq", (0.5, 0.4)),
+    ("steam1", 240, 2248, 3.1e7, "sdq", (0.2, 0.1)),
+    ("steam3", 80, 314, 7.6e10, "sdq", (0.5, 0.1)),
+    ("saylr1", 238, 1128, 1.6e9, "sdq", (0.4, 0.3)),
+    ("bfwa782", 782, 7514, 6.8e3, "hsd", (0.5, 0.3)),
+    ("cage5", 37, 233, 2.9e1, "hsd", (0.5, 0.3)),
+    ("gre_115", 115, 421, 1.4e2, "hsd", (0.5, 0.3)),
+    ("orsreg_1", 2205, 14133, 7.0e3, "hsd", (0.5, 0.3)),
+    ("sherman4", 1104, 3786, 3.1e3, "hsd", (0.5, 0.3)),
+]
+
+
+def kappa_inf(A: CSR) -> float:
+    """Dense infinity-norm condition number (small n only)."""
+    M = A.to_scipy().toarray()
+    return float(np.abs(M).sum(axis=1).max() * np.abs(np.linalg.inv(M)).sum(axis=1).max())
+
+
+def s0_matrix(k: int) -> Workload:
+    """Random nonsymmetric stand-in with the n, nnz and (within 10x) kappa_inf of
+    row k of Table tab:mats: off-diagonals N(0,1) at distinct random columns within
+    a band of +-min(32, n/4), spread evenly over the rows (nnz - n of them), and a
+    positive diagonal s * sum_j |a_ij| whose factor s is found by bisection on
+    log kappa_inf (dense).  Parameters follow the paper's protocol (identity
+    start, beta = 8, alpha = ceil(n / beta), tau = 1e-8 for u = double and 1e-4
+    for u = single); the fill cap is the library's largest, 63 entries per
+    column, standing in for the paper's uncapped columns.
+
+    Off-diagonals are clipped to +-7.9.  Values of the "sdq" matrices lie on a
+    2^-24 grid with x_true on 2^-16 (exact FP64 right-hand side); those of the
+    "hsd" matrices, which Tables 4 and 5 solve with working precision single,
+    on a 2^-10 grid with x_true on 2^-5, so that A, x_true and b = A x_true are
+    exact in FP32 as well when |a| < 2^5 and a row holds at most 16 entries
+    (5 + 10 + 5 + 4 = 24 bits; checked by s0_fp32_exact)."""
+    name, n, nnz, kappa, pset, eps = S0_SHAPES[k]
+    rng = rng_for(7, k, _COEF)
+    pbits, sbits = (24, 16) if pset == "sdq" else (10, 5)
+    hb = min(32, n // 4)
+    off = nnz - n
+    base, extra = divmod(off, n)
+    ks = np.full(n, base)
+    ks[rng.permutation(n)[:extra]] += 1
+    offs = np.concatenate([np.arange(-hb, 0), np.arange(1, hb + 1)])
+    rows, cols = [], []
+    for i in range(n):
+        cand = i + offs
+        cand = cand[(cand >= 0) & (cand < n)]
+        take = rng.permutation(cand)[:min(int(ks[i]), cand.size)]
+        rows.append(np.full(take.size, i))
+        cols.append(take)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    v = _quantize(np.clip(rng.standard_normal(cols.size), -7.9, 7.9), pbits)
+    v[v == 0.0] = 2.0 ** -pbits
+    rs = np.bincount(rows, weights=np.abs(v), minlength=n)
+
+    def assemble(s):
+        d = _quantize(s * rs, pbits)
+        d[d == 0.0] = 2.0 ** -pbits
+        return _assemble(n, np.concatenate([rows, np.arange(n)]), np.concatenate([cols, np.arange(n)]),
+                         np.concatenate([v, d]))
+
+    def kap(A):
+        try:
+            return kappa_inf(A)
+        except np.linalg.LinAlgError:
+            return np.inf
+
+    # A(s) = offdiag + s diag(rowsum) is singular where -s is a real eigenvalue of
+    # diag(rowsum)^-1 offdiag (all inside [-1, 1]); kappa_inf(A(s)) grows without
+    # bound as s decreases from 2 to the largest such s*, so bisect on log kappa
+    # over (s*, 2]
+    off_m = np.zeros((n, n))
+    off_m[rows, cols] = v
+    lam = np.linalg.eigvals(off_m / rs[:, None])
+    real = -lam[np.abs(lam.imag) <= 1e-9 * np.maximum(np.abs(lam), 1.0)].real
+    s_star = float(real.max()) if real.size else -1.5
+    lo, hi = s_star, 2.0
+    A_hi = assemble(hi)
+    best = (abs(math.log10(kap(A_hi) / kappa)), hi, A_hi)
+    for _ in range(80):
+        if best[0] <= 0.3:
+            break
+        mid = 0.5 * (lo + hi)
+        A_mid = assemble(mid)
+        km = kap(A_mid)
+        if np.isfinite(km) and abs(math.log10(km / kappa)) < best[0]:
+            best = (abs(math.log10(km / kappa)), mid, A_mid)
+        if km >= kappa:
+            lo = mid
+        else:
+            hi = mid
+    A = best[2]
+    x, b = exact_rhs(A, rng_for(7, k, _XTRUE), pbits=pbits, sbits=sbits)
+    single = pset != "sdq"
+    return Workload(f"s0_{name}_shape_n{n}", A, x, b, None,
+                    SpaiParams(eps=eps[0], alpha=-(-n // 8), beta=8, maxfill=63, u_f="fp16" if single else "fp32"),
+                    IrParams(tau=1e-4 if single else 1e-8, imax=10, maxit=n, tol_ir=TOL_IR32 if single else TOL_IR,
+                             u="fp32" if single else "fp64"),
+                    f"stand-in for the shape of {name} (n={n}, nnz~{nnz}, kappa_inf~{kappa:.1e}); band "
+                    f"+-{hb}, N(0,1) on 2^-{pbits} grid, diagonal factor {best[1]:.4g}, x_true on 2^-{sbits} grid")

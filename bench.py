@@ -215,6 +215,153 @@ def run_batch(S, W, args):
     print(json.dumps(out), flush=True)
 
 
+def _serve_gen(a):
+    import workloads as W
+    return W.serving_request(a)
+
+
+def run_serve(S, W, args):
+    """The serving stream: Poisson arrivals of systems of the three families (2D
+    convection-diffusion, 3D anisotropic diffusion, random banded; u_f FP16 or
+    FP32), submitted to the library's request loop at their arrival times.
+    Latency = completion - submission on the server's clock; a request counts
+    as solved when it reaches a forward error <= 1e-12.  With --serve-fp64 the
+    same stream runs again with u_f = FP64 (the all-FP64 SPAI form)."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+
+    trace = W.serving_trace(args.rate, args.duration)
+    log(f"serving stream: {len(trace)} arrivals over {args.duration} s at {args.rate}/s")
+    t = time.time()
+    # host-side generation in worker processes, forked before this process touches the GPU
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        ws = list(ex.map(_serve_gen, trace, chunksize=1))
+    log(f"generated in {time.time() - t:.1f} s; n from {min(w.n for w in ws)} to {max(w.n for w in ws)}")
+    torch.cuda.set_device(0)
+
+    def one_pass(u_f_override=None):
+        srv = S.Server(batch_lanes=args.lanes, batch_max_n=args.batch_max_n, batch_max_systems=1024,
+                       hbm_budget=args.budget_gib << 30)
+        reqs = []
+        for w in ws:
+            s, ir = w.spai, w.ir
+            build = {"eps": s.eps, "alpha": s.alpha, "beta": s.beta, "maxfill": s.maxfill,
+                     "u_f": u_f_override or s.u_f}
+            irp = {"tau": ir.tau, "imax": ir.imax, "maxit": ir.maxit, "tol_ir": ir.tol_ir, "u_r": "dd",
+                   "ortho": args.ortho}
+            reqs.append((w.A, w.b, w.pattern, build, irp))
+        # warm-up: one request of each batch key and one device-lane request, untimed
+        seen = set()
+        for r, a in zip(reqs, trace):
+            key = (a.kind == "aniso", r[3]["u_f"], r[0].n > args.batch_max_n)
+            if key not in seen:
+                seen.add(key)
+                srv.wait(srv.submit(*r))
+        t0 = time.perf_counter()
+        ids, late = [], []
+        for r, a in zip(reqs, trace):
+            dt = t0 + a.t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            else:
+                late.append(-dt)
+            ids.append(srv.submit(*r))
+        out = [srv.wait(i) for i in ids]
+        srv.close()
+        lat, ok, fails, t_first, t_last = [], 0, 0, None, None
+        kinds = {}
+        for (rc, x, rec), w, a in zip(out, ws, trace):
+            good = rc >= 0 and x is not None and float(np.abs(x - w.x_true).max() / np.abs(w.x_true).max()) <= 1e-12
+            ok += good
+            fails += not good
+            lat.append(1e3 * (rec["t_done"] - rec["t_submit"]))
+            t_first = rec["t_submit"] if t_first is None else min(t_first, rec["t_submit"])
+            t_last = rec["t_done"] if t_last is None else max(t_last, rec["t_done"])
+            k = kinds.setdefault(a.kind, {"requests": 0, "solved": 0, "lat_ms": []})
+            k["requests"] += 1
+            k["solved"] += int(good)
+            k["lat_ms"].append(lat[-1])
+        span = t_last - t_first
+        for k in kinds.values():
+            k["p50_ms"] = percentile(k["lat_ms"], 50)
+            k["p99_ms"] = percentile(k["lat_ms"], 99)
+            del k["lat_ms"]
+        batches = [rec["batch_size"] for _, _, rec in out if rec["lane"] >= 0]
+        return {"solves_per_s": ok / span, "requests_per_s": len(out) / span, "span_s": span,
+                "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "solved": ok, "failed": fails,
+                "by_kind": kinds, "mean_batch": float(np.mean(batches)) if batches else 0.0,
+                "late_submissions": len(late), "max_late_ms": 1e3 * max(late) if late else 0.0}
+
+    mixed = one_pass()
+    out = {
+        "metric": "serving: GMRES-IR solves/s at 1e-12 fwd err with p50/p99 latency", "value": mixed["solves_per_s"],
+        "unit": "solves/s", "n_gpus": 1, "steps": len(trace), "warmup": 0, "ms_per_step": 1e3 * mixed["span_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16/f32+f64+dd",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream, Poisson {args.rate}/s for {args.duration} s: 2D convdiff side "
+                               f"logU[32,512] adaptive, 3D aniso side logU[10,128] pattern(A^2)<=27, random banded n "
+                               f"logU[1e3,2e4] adaptive; u_f FP16/FP32 50/50; u FP64, u_r DD",
+                   "requests": len(trace), "batch_lanes": args.lanes, "batch_max_n": args.batch_max_n,
+                   "hbm_budget_gib": args.budget_gib, "device_lane_arnoldi": args.ortho},
+        "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed": mixed,
+    }
+    if args.serve_fp64:
+        out["fp64_form"] = one_pass("fp64")
+    print(json.dumps(out), flush=True)
+
+
+def run_tables(S, W, args):
+    """The structure of Tables 3-5 on the paper-shaped stand-ins: for each matrix
+    and each epsilon of its table, the GPU build (nnz(P), kappa_inf(PA) from the
+    dense product on the host) and the GPU solve in the table's precision set(s):
+    (single, double, double-double) for the Table 3 shapes, (half, single,
+    double) and (single, single, double) for the Table 4/5 shapes.  Iteration
+    tuples, forward errors and times per solve; one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2202_10204_amd import diagnostics as D
+
+    torch.cuda.set_device(0)
+    h = S.Handle()
+    rows = []
+    for k, (name, n, nnz, kappa, pset, eps_list) in enumerate(W.S0_SHAPES):
+        w = W.s0_matrix(k)
+        A = S.DeviceCSR.from_host(w.A)
+        b = torch.as_tensor(w.b, device="cuda")
+        Ad = w.A.to_scipy().toarray()
+        sets = [("fp32", "fp64", "dd")] if pset == "sdq" else [("fp16", "fp32", "fp64"), ("fp32", "fp32", "fp64")]
+        for uf, u, ur in sets:
+            for eps in eps_list:
+                P, warn, st = h.spai_build(A, None, eps, -(-n // 8), 8, 63, uf)
+                PA = D.dense_p(P) @ Ad
+                kap = float(np.abs(PA).sum(1).max() * np.abs(np.linalg.inv(PA)).sum(1).max())
+                tau = 1e-4 if u == "fp32" else 1e-8
+                tol = W.TOL_IR32 if u == "fp32" else W.TOL_IR
+                x = torch.zeros_like(b)
+                r = h.gmres_ir(A, P, b, x, tau, 10, n, tol, ur, "mgs", u)       # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x = torch.zeros_like(b)
+                r = h.gmres_ir(A, P, b, x, tau, 10, n, tol, ur, "mgs", u)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                xh = x.cpu().numpy()
+                rows.append({"matrix": w.name, "set": f"({uf},{u},{ur})", "eps": eps, "nnz_A": w.A.nnz,
+                             "kappa_inf_A": W.kappa_inf(w.A), "nnz_P": int(st["nnz"]),
+                             "cols_over_eps": int(st["cols_over_eps"]), "kappa_inf_PA": kap,
+                             "its": r["its"], "total_its": r["total_its"], "status": r["status"],
+                             "ferr": float(np.abs(xh - w.x_true).max() / np.abs(w.x_true).max()),
+                             "solve_ms": 1e3 * dt})
+                log(f"{w.name} ({uf},{u},{ur}) eps={eps}: nnz(P)={st['nnz']} kappa(PA)={kap:.2e} "
+                    f"its={r['total_its']}{tuple(r['its'])} ferr={rows[-1]['ferr']:.1e}")
+                del P
+    print(json.dumps({"metric": "paper table structure on stand-in matrices (context, not a benchmark)",
+                      "data": "synthetic", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,9 +370,17 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, default=512, help="grid side (512 is the benchmark workload)")
-    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "batch"],
+    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "batch", "serve", "tables"],
                     help="convdiff: the benchmark line (default); batch: 4096 independent random banded systems "
-                         "(a separate measurement of the batched entry points, printed as its own JSON line)")
+                         "(a separate measurement of the batched entry points, printed as its own JSON line); "
+                         "serve: the serving stream through the library's request loop (its own JSON line); "
+                         "tables: Tables 3-5 of the paper re-run on stand-in matrices of the same shapes")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: arrivals per second")
+    ap.add_argument("--duration", type=float, default=0.25, help="serve: seconds of arrivals")
+    ap.add_argument("--lanes", type=int, default=3, help="serve: batch lanes")
+    ap.add_argument("--batch-max-n", type=int, default=20000, help="serve: largest batched system")
+    ap.add_argument("--budget-gib", type=int, default=128, help="serve: device memory budget in GiB")
+    ap.add_argument("--serve-fp64", action="store_true", help="serve: run the stream again with u_f = FP64")
     ap.add_argument("--ortho", default="dcgs2", choices=["mgs", "cgs2", "dcgs2"],
                     help="Arnoldi orthogonalisation (all three give the oracle's iteration tuple)")
     ap.add_argument("--profile-run", action="store_true",
@@ -243,6 +398,12 @@ def main():
     import paper_2202_10204_amd as S
     import workloads as W
 
+    if args.workload == "serve":
+        run_serve(S, W, args)
+        return
+    if args.workload == "tables":
+        run_tables(S, W, args)
+        return
     torch.cuda.set_device(0)
     if args.workload == "batch":
         run_batch(S, W, args)

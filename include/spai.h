@@ -137,7 +137,15 @@ typedef struct {
 enum { SPAI_ORTHO_MGS = 0, SPAI_ORTHO_CGS2 = 1, SPAI_ORTHO_DCGS2 = 2 };
 
 /* Parameters of Algorithm 3 (its Require line: i_max, tau) plus the GMRES cap and
- * the refinement stopping rule.  u_g = u_p = u = FP64 (Section 4). */
+ * the refinement stopping rule, the residual precision u_r and the working
+ * precision u = u_g = u_p (Section 4 uses u_g = u_p = u).
+ * u = SPAI_FP64 (0, default): the precision set (u_f, double, u_r) of Table 3.
+ * u = SPAI_FP32: the sets (half, single, double) and (single, single, double) of
+ * Tables 4 and 5: A and b are used as rounded to binary32, x0, r_i (evaluated in
+ * binary64, so u_r must be SPAI_FP64), the Krylov basis, the Hessenberg
+ * matrix, d_i and x are binary32 values (x is returned as doubles), u_f must be
+ * FP32, FP16 or BF16, and GMRES orthogonalises with MGS in one workgroup per
+ * system (the batched solver's kernel; a single system runs as a batch of one). */
 typedef struct {
     spai_prec u_r;  /* residual precision: SPAI_DD (double-double) or SPAI_FP64 */
     double tau;     /* GMRES stops when |g_{j+1}| <= tau ||P r_i||_2 */
@@ -145,6 +153,7 @@ typedef struct {
     int32_t maxit;  /* maximum GMRES iterations per step */
     double tol_ir;  /* refinement stops when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf */
     int32_t ortho;  /* SPAI_ORTHO_MGS (0, default), SPAI_ORTHO_CGS2 or SPAI_ORTHO_DCGS2 */
+    spai_prec u;    /* working precision: SPAI_FP64 (0, default) or SPAI_FP32 */
 } spai_ir_params;
 
 typedef struct {
@@ -201,8 +210,9 @@ int spai_precond_destroy(spai_precond* P);
  * b and x are device arrays of n FP64 values (x is output only).
  * Errors: SPAI_E_ARG (sizes differ, imax outside 1..32, maxit < 1, tau < 0, an
  * unknown ortho, CGS2 when the cooperative Arnoldi kernel cannot hold the
- * problem); SPAI_E_INTERNAL when a grid-wide sum times out (about a second);
- * warnings SPAI_W_MAXIT, SPAI_W_NOCONV.
+ * problem, u other than FP64/FP32, u = FP32 with u_r = DD, ortho other than
+ * MGS or u_f = FP64); SPAI_E_INTERNAL when a grid-wide sum times out (about a
+ * second); warnings SPAI_W_MAXIT, SPAI_W_NOCONV.
  */
 int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
                   double* x, const spai_ir_params* p, spai_ir_stats* st);
@@ -271,6 +281,106 @@ int spai_precond_apply(spai_handle* h, const spai_precond* P, const double* w, d
 int spai_precond_apply_uf(spai_handle* h, const spai_precond* P, const double* b, double* x0);
 /* y = A x in FP64. */
 int spai_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y);
+
+/*
+ * Serving: a request loop inside the library that solves independent systems
+ * as they arrive (continuous batching).  Requests are host data (copied at
+ * submission); each is admitted once its device footprint fits the server's
+ * memory budget, and its matrix, preconditioner and Krylov basis stay on the
+ * device from admission until its result is copied back.
+ *
+ * Two kinds of lanes, each a host thread with its own stream and handle, run
+ * admitted work concurrently:
+ *   - batch lanes take every waiting system with n <= batch_max_n that shares
+ *     the oldest one's parameters (up to batch_max_systems, in arrival order)
+ *     and run them as one batch: spai_build_batched, then
+ *     spai_gmres_ir_batched (MGS; ortho is ignored).  A lane that finishes
+ *     takes the next batch at once, so arrivals join the device while other
+ *     batches are still running.
+ *   - one device lane runs larger systems one at a time with spai_build and
+ *     spai_gmres_ir (the request's ortho).  Its Arnoldi launches synchronise
+ *     across the whole grid and need every workgroup resident, so while that
+ *     solve runs no batch starts (running batches finish first); builds
+ *     overlap freely.
+ * A system's result does not depend on what else is in flight: a batch gives
+ * every system the bits it gets in a batch of its own (every system is solved
+ * by one workgroup in a fixed order, and the block-diagonal build equals each
+ * block's build), and the device lane's kernels are deterministic.
+ * Device memory: the server allocates hbm_budget bytes once and lends each
+ * admitted unit of work (a batch, or one device-lane request) a contiguous
+ * region of it, first fit; the library's allocations for that unit come from
+ * the region (so no lane ever waits on another lane's hipFree), and the region
+ * returns to the server when the unit's results are on the host.  A batch
+ * needs its requests' footprints plus one lane workspace; a request waits
+ * until a free region is large enough.
+ */
+typedef struct spai_server spai_server;
+
+typedef struct {
+    int32_t batch_lanes;       /* concurrent batch lanes, 1..16 */
+    int32_t batch_max_n;       /* systems up to this size are batched; larger ones use the device lane */
+    int32_t batch_max_systems; /* systems per batch, >= 1 */
+    int32_t pad;
+    int64_t hbm_budget;        /* device bytes of the server's arena (allocated at creation) */
+    int64_t lane_workspace;    /* batched-solver workspace of a batch in bytes (0: min(8 GiB,
+                                  hbm_budget / 4 / batch_lanes)) */
+} spai_serve_params;
+
+/* One system: host CSR A (validated on the device like spai_build's input),
+ * host right-hand side b, optional host initial pattern (jptr: n+1, jidx: jnnz;
+ * NULL jptr = identity), and the parameters of the build and of the solve. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    const double* b;
+    int32_t jnnz;
+    const int32_t* jptr;
+    const int32_t* jidx;
+    spai_build_params build;
+    spai_ir_params ir;
+} spai_serve_request;
+
+typedef struct {
+    int32_t rc;             /* the request's outcome: 0, a SPAI_W_* mask, or a negative SPAI_E_* */
+    int32_t lane;           /* batch lane index, or -1 for the device lane */
+    int32_t batch_size;     /* systems solved in the same batch (1 on the device lane) */
+    int32_t pad;
+    int64_t footprint;      /* device bytes reserved at admission (an upper estimate) */
+    int64_t nnz_p;          /* stored entries of the system's preconditioner */
+    double t_submit;        /* seconds since the server was created */
+    double t_admit;
+    double t_done;          /* result copied back to the host */
+    spai_ir_stats ir;
+} spai_serve_result;
+
+/* Upper estimate of a request's device footprint in bytes (host only; also
+ * what admission reserves).  SPAI_E_ARG for a malformed request. */
+int spai_serve_footprint(const spai_serve_request* r, int64_t* bytes);
+
+/* Create a server on the current device, allocate its arena and start its
+ * lanes.  Errors: SPAI_E_ARG (batch_lanes outside 1..16, batch_max_n < 1,
+ * batch_max_systems < 1, a budget that does not hold a lane workspace),
+ * SPAI_E_OOM (the arena could not be allocated), SPAI_E_HIP (no device). */
+int spai_serve_create(const spai_serve_params* p, spai_server** S);
+
+/* Queue a request (its arrays are copied before the call returns) and return
+ * its id.  Errors: SPAI_E_ARG (NULL pointers, n <= 0, rowptr not running from 0
+ * to nnz, bad parameters), SPAI_E_OOM (its footprint, plus a lane workspace for
+ * a batched system, exceeds hbm_budget, so it could never be admitted). */
+int spai_serve_submit(spai_server* S, const spai_serve_request* r, int64_t* id);
+
+/* Block until request `id` is done, copy its solution into x (host, n values;
+ * may be NULL) and its record into *res (may be NULL), and forget it.  Returns
+ * the request's outcome (res->rc; spai_last_error() describes a negative one),
+ * or SPAI_E_ARG for an unknown id. */
+int spai_serve_wait(spai_server* S, int64_t id, double* x, spai_serve_result* res);
+
+/* Finish every queued request, stop the lanes and free the server.  Results not
+ * yet collected are dropped. */
+int spai_serve_destroy(spai_server* S);
 
 #ifdef __cplusplus
 }

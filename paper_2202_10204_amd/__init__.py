@@ -59,7 +59,7 @@ class _View(ctypes.Structure):
 
 class _IrParams(ctypes.Structure):
     _fields_ = [("u_r", ctypes.c_int), ("tau", _c_f64), ("imax", _c_i32), ("maxit", _c_i32),
-                ("tol_ir", _c_f64), ("ortho", _c_i32)]
+                ("tol_ir", _c_f64), ("ortho", _c_i32), ("u", ctypes.c_int)]
 
 
 ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
@@ -68,6 +68,22 @@ ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 class _IrStats(ctypes.Structure):
     _fields_ = [("steps", _c_i32), ("its", _c_i32 * 32), ("total_its", _c_i32), ("status", _c_i32),
                 ("gest", _c_f64 * 32), ("dnorm", _c_f64 * 32)]
+
+
+class _ServeParams(ctypes.Structure):
+    _fields_ = [("batch_lanes", _c_i32), ("batch_max_n", _c_i32), ("batch_max_systems", _c_i32), ("pad", _c_i32),
+                ("hbm_budget", _c_i64), ("lane_workspace", _c_i64)]
+
+
+class _ServeRequest(ctypes.Structure):
+    _fields_ = [("n", _c_i32), ("nnz", _c_i32), ("rowptr", _p), ("col", _p), ("val", _p), ("b", _p),
+                ("jnnz", _c_i32), ("jptr", _p), ("jidx", _p), ("build", _BuildParams), ("ir", _IrParams)]
+
+
+class _ServeResult(ctypes.Structure):
+    _fields_ = [("rc", _c_i32), ("lane", _c_i32), ("batch_size", _c_i32), ("pad", _c_i32),
+                ("footprint", _c_i64), ("nnz_p", _c_i64), ("t_submit", _c_f64), ("t_admit", _c_f64),
+                ("t_done", _c_f64), ("ir", _IrStats)]
 
 
 class SpaiError(RuntimeError):
@@ -103,12 +119,18 @@ def lib():
         L.spai_build_batched.argtypes = [_p, P(_Csr), _c_i32, P(_c_i32), P(_Pattern), P(_BuildParams), P(_p),
                                          P(_BuildStats)]
         L.spai_gmres_ir_batched.argtypes = [_p, P(_Csr), _p, _c_i32, P(_c_i32), _p, _p, P(_IrParams), P(_IrStats)]
+        L.spai_serve_footprint.argtypes = [P(_ServeRequest), P(_c_i64)]
+        L.spai_serve_create.argtypes = [P(_ServeParams), P(_p)]
+        L.spai_serve_submit.argtypes = [_p, P(_ServeRequest), P(_c_i64)]
+        L.spai_serve_wait.argtypes = [_p, _c_i64, _p, P(_ServeResult)]
+        L.spai_serve_destroy.argtypes = [_p]
         L.spai_timing_enable.argtypes = [_p, ctypes.c_int, ctypes.c_int]
         L.spai_timing_read.argtypes = [_p, ctypes.c_int, P(_c_i64), P(_c_f64)]
         for name in ("spai_timing_enable", "spai_timing_read", "spai_create", "spai_destroy", "spai_set_stream", "spai_build", "spai_precond_import",
                      "spai_precond_view_get", "spai_precond_destroy", "spai_gmres_ir", "spai_residual",
                      "spai_precond_apply", "spai_precond_apply_uf", "spai_spmv", "spai_build_batched",
-                     "spai_gmres_ir_batched"):
+                     "spai_gmres_ir_batched", "spai_serve_footprint", "spai_serve_create", "spai_serve_submit",
+                     "spai_serve_wait", "spai_serve_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -309,8 +331,8 @@ class Handle:
 
     # -- Algorithm 3 ---------------------------------------------------------
     def gmres_ir(self, A: DeviceCSR, P: Precond, b: torch.Tensor, x: torch.Tensor, tau: float, imax: int,
-                 maxit: int, tol_ir: float, u_r: str = "dd", ortho: str = "mgs"):
-        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO[ortho])
+                 maxit: int, tol_ir: float, u_r: str = "dd", ortho: str = "mgs", u: str = "fp64"):
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO[ortho], PREC[u])
         st = _IrStats()
         csr = A.c()
         rc = _check(lib().spai_gmres_ir(self._raw, ctypes.byref(csr), P.raw, _ptr(b), _ptr(x),
@@ -336,11 +358,11 @@ class Handle:
         return Precond(self, out.value, stats), rc, stats
 
     def gmres_ir_batched(self, A: DeviceCSR, P: Precond, sys_ptr, b: torch.Tensor, x: torch.Tensor, tau: float,
-                         imax: int, maxit: int, tol_ir: float, u_r: str = "dd"):
+                         imax: int, maxit: int, tol_ir: float, u_r: str = "dd", u: str = "fp64"):
         """Returns (warning bits of all systems, list of per-system stats dicts)."""
         nsys = len(sys_ptr) - 1
         sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
-        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO["mgs"])
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO["mgs"], PREC[u])
         st = (_IrStats * nsys)()
         csr = A.c()
         rc = _check(lib().spai_gmres_ir_batched(self._raw, ctypes.byref(csr), P.raw, nsys, sp, _ptr(b), _ptr(x),
@@ -379,3 +401,85 @@ class Handle:
     def spmv(self, A: DeviceCSR, x, y):
         csr = A.c()
         _check(lib().spai_spmv(self._raw, ctypes.byref(csr), _ptr(x), _ptr(y)), "spai_spmv")
+
+
+# ---------------------------------------------------------------------------
+# serving: the library's request loop (host arrays in, host solution out)
+# ---------------------------------------------------------------------------
+
+def _serve_request(A, b, pattern, build: dict, ir: dict):
+    """Marshal one request; returns (struct, arrays kept alive while it is used)."""
+    rp = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col, dtype=np.int32)
+    av = np.ascontiguousarray(A.val, dtype=np.float64)
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    keep = [rp, ci, av, bb]
+    jp = ji = None
+    if pattern is not None:
+        jp = np.ascontiguousarray(pattern.ptr, dtype=np.int32)
+        ji = np.ascontiguousarray(pattern.idx, dtype=np.int32)
+        keep += [jp, ji]
+    bp = _BuildParams(float(build["eps"]), int(build["alpha"]), int(build["beta"]), int(build["maxfill"]),
+                      PREC[build["u_f"]])
+    ip = _IrParams(PREC[ir.get("u_r", "dd")], float(ir["tau"]), int(ir["imax"]), int(ir["maxit"]),
+                   float(ir["tol_ir"]), ORTHO[ir.get("ortho", "mgs")], PREC[ir.get("u", "fp64")])
+    r = _ServeRequest(int(A.n), int(ci.size), rp.ctypes.data, ci.ctypes.data, av.ctypes.data, bb.ctypes.data,
+                      int(ji.size) if ji is not None else 0, jp.ctypes.data if jp is not None else None,
+                      ji.ctypes.data if ji is not None else None, bp, ip)
+    return r, keep
+
+
+def serve_footprint(A, b, pattern, build: dict, ir: dict) -> int:
+    """Device bytes admission reserves for a request (host only)."""
+    r, keep = _serve_request(A, b, pattern, build, ir)
+    out = _c_i64()
+    _check(lib().spai_serve_footprint(ctypes.byref(r), ctypes.byref(out)), "spai_serve_footprint")
+    return int(out.value)
+
+
+class Server:
+    """The library's request loop on the current device (see spai_serve_* in include/spai.h)."""
+
+    def __init__(self, batch_lanes: int = 3, batch_max_n: int = 20000, batch_max_systems: int = 1024,
+                 hbm_budget: int = 64 << 30, lane_workspace: int = 0):
+        if not torch.cuda.is_available():
+            raise SpaiError("no GPU available: libspai runs on the device only")
+        prm = _ServeParams(int(batch_lanes), int(batch_max_n), int(batch_max_systems), 0, int(hbm_budget),
+                           int(lane_workspace))
+        raw = ctypes.c_void_p()
+        _check(lib().spai_serve_create(ctypes.byref(prm), ctypes.byref(raw)), "spai_serve_create")
+        self._raw = raw
+        self._n = {}
+
+    def submit(self, A, b, pattern, build: dict, ir: dict) -> int:
+        """Queue one system (host CSR ``A`` with rowptr/col/val, host ``b``, optional
+        host pattern with ptr/idx); returns its id."""
+        r, keep = _serve_request(A, b, pattern, build, ir)
+        rid = _c_i64()
+        _check(lib().spai_serve_submit(self._raw, ctypes.byref(r), ctypes.byref(rid)), "spai_serve_submit")
+        self._n[rid.value] = int(A.n)
+        return int(rid.value)
+
+    def wait(self, rid: int):
+        """Block until request ``rid`` is done; returns (rc, x or None, record dict)."""
+        n = self._n.pop(rid)
+        x = np.empty(n, np.float64)
+        res = _ServeResult()
+        rc = lib().spai_serve_wait(self._raw, int(rid), x.ctypes.data, ctypes.byref(res))
+        k = res.ir.steps
+        rec = {"rc": res.rc, "lane": res.lane, "batch_size": res.batch_size, "footprint": res.footprint,
+               "nnz_p": res.nnz_p, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
+               "steps": k, "its": list(res.ir.its[:k]), "total_its": res.ir.total_its, "status": res.ir.status,
+               "error": last_error() if rc < 0 else ""}
+        return rc, (x if rc >= 0 else None), rec
+
+    def close(self):
+        if getattr(self, "_raw", None) is not None and self._raw.value:
+            lib().spai_serve_destroy(self._raw)
+            self._raw = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

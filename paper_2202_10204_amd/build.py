@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspai.so")
-SOURCES = ["api.hip", "spai_build.hip", "gmres_ir.hip", "batched.hip"]
+SOURCES = ["api.hip", "spai_build.hip", "gmres_ir.hip", "batched.hip", "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -10,27 +10,52 @@ static thread_local std::string g_last_error = "no error";
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-int buffer_reserve(Buffer& b, size_t bytes) {
+int dev_malloc(spai_handle* h, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    Arena& a = h->arena;
+    if (a.base) {
+        const size_t off = (a.used + 255) & ~(size_t)255;
+        if (off <= a.size && bytes <= a.size - off) {
+            *p = a.base + off;
+            a.used = off + bytes;
+            return SPAI_OK;
+        }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error(std::string("device allocation of ") + std::to_string(bytes) + " bytes failed: " +
+                  hipGetErrorString(e));
+        return SPAI_E_OOM;
+    }
+    return SPAI_OK;
+}
+
+void dev_free(void* p, const Arena& from) {
+    if (!p || from.owns(p)) return;
+    (void)hipFree(p);
+}
+
+int buffer_reserve(spai_handle* h, Buffer& b, size_t bytes) {
     if (bytes <= b.bytes && b.ptr) return SPAI_OK;
     buffer_free(b);
     size_t want = bytes + bytes / 8 + 256;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error(std::string("device allocation of ") + std::to_string(want) + " bytes failed: " +
-                  hipGetErrorString(e));
-        return SPAI_E_OOM;
-    }
+    int rc = dev_malloc(h, &p, want);
+    if (rc) return rc;
     b.ptr = p;
     b.bytes = want;
+    b.from = h->arena;
     return SPAI_OK;
 }
 
 void buffer_free(Buffer& b) {
-    if (b.ptr) (void)hipFree(b.ptr);
+    dev_free(b.ptr, b.from);
     b.ptr = nullptr;
     b.bytes = 0;
+    b.from = Arena{};
 }
 
 }  // namespace spai

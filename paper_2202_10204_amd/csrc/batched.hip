@@ -73,60 +73,77 @@ struct BatchArgs {
 };
 
 // sum over the workgroup; every thread gets the same bits
-__device__ __forceinline__ double wg_sum(double v, double* sh) {
+template <typename TW>
+__device__ __forceinline__ TW wg_sum(TW v, TW* sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     v = wave_sum(v);
     if (lane == 0) sh[wave] = v;
     __syncthreads();
-    double t = 0.0;
+    TW t = 0;
 #pragma unroll
     for (int w = 0; w < BW; ++w) t += sh[w];
     __syncthreads();
     return t;
 }
 
-__device__ __forceinline__ double wg_max(double v, double* sh) {
+template <typename TW>
+__device__ __forceinline__ TW wg_max(TW v, TW* sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     if (lane == 0) sh[wave] = v;
     __syncthreads();
-    double t = 0.0;
+    TW t = 0;
 #pragma unroll
     for (int w = 0; w < BW; ++w) t = fmax(t, sh[w]);
     __syncthreads();
     return t;
 }
 
-// y_i = sum_q m_q d_j w_j over row i of P, FP64 (rows r0 + i, columns global)
-template <int VP>
-__device__ __forceinline__ double p_row(const BatchArgs& a, int gi, const double* w) {
+__device__ __forceinline__ float tw_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tw_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float tw_sqrt(float a) { return __builtin_sqrtf(a); }
+__device__ __forceinline__ double tw_sqrt(double a) { return __builtin_sqrt(a); }
+template <typename TW, typename T> __device__ __forceinline__ TW to_tw(T v) {
+    if constexpr (sizeof(TW) == 8) return to_f64(v);
+    else return to_f32(v);
+}
+
+// y_i = sum_q m_q (d_j w_j) over row i of P in the working precision TW (d
+// rounded to TW; rows r0 + i, columns global)
+template <int VP, typename TW>
+__device__ __forceinline__ TW p_row(const BatchArgs& a, int gi, const TW* w) {
     using T = typename ValType<VP>::T;
     const T* pv = (const T*)a.pv;
-    double s = 0.0;
+    TW s = 0;
     for (int q = a.pp[gi]; q < a.pp[gi + 1]; ++q) {
         const int j = a.pc[q];
-        s = __builtin_fma(to_f64(pv[q]), a.d[j] * w[j], s);
+        s = tw_fma(to_tw<TW>(pv[q]), (TW)a.d[j] * w[j], s);
     }
     return s;
 }
 
-template <int VP>
-__device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, spai_ir_stats& st) {
+// One system's whole refinement loop in working precision TW (double: u = FP64;
+// float: u = FP32, where A, b, the scaling, r, the basis, H, the rotations, d
+// and x are binary32 values and the residual is evaluated in binary64).
+template <int VP, typename TW>
+__device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, spai_ir_stats& st) {
     using T = typename ValType<VP>::T;
+    constexpr bool U32 = sizeof(TW) == 4;
     const int t = threadIdx.x;
     const int r0 = a.sys_ptr[s], n = a.sys_ptr[s + 1] - r0;
     const int mx = min(a.maxit, n);
     const int ld = mx + 1;
-    // slot layout: V [n x (mx+1)] (column stride n), H [ld x mx], cs, sn, g, yk [ld], r, w, y [cap_n]
-    double* V = ws;
-    double* H = V + (size_t)a.cap_n * (a.kmax + 1);
-    double* cs = H + (size_t)(a.kmax + 1) * a.kmax;
-    double* sn = cs + (a.kmax + 1);
-    double* g = sn + (a.kmax + 1);
-    double* yk = g + (a.kmax + 1);
-    double* r = yk + (a.kmax + 1) - r0;   // indexed by global row
-    double* w = r + a.cap_n;
-    double* y = w + a.cap_n;
+    // slot layout (in TW): V [n x (mx+1)] (column stride n), H [ld x mx], cs, sn, g, yk [ld], r, w, y [cap_n]
+    TW* ws = (TW*)ws_d;
+    TW* V = ws;
+    TW* H = V + (size_t)a.cap_n * (a.kmax + 1);
+    TW* cs = H + (size_t)(a.kmax + 1) * a.kmax;
+    TW* sn = cs + (a.kmax + 1);
+    TW* g = sn + (a.kmax + 1);
+    TW* yk = g + (a.kmax + 1);
+    TW* r = yk + (a.kmax + 1) - r0;   // indexed by global row
+    TW* w = r + a.cap_n;
+    TW* y = w + a.cap_n;
     double* x = a.x;
     if (t == 0) {                             // statistics of this system (LDS, written by thread 0)
         st.steps = 0;
@@ -138,7 +155,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, 
             st.dnorm[q] = 0.0;
         }
     }
-    // x0 = P b in u_f (products and sums in the arithmetic precision of u_f, column order)
+    // x0 = P b in u_f (products and sums in the arithmetic precision of u_f, column order), stored in u
     for (int i = t; i < n; i += BT) {
         const int gi = r0 + i;
         if constexpr (VP == SPAI_FP64) {
@@ -160,10 +177,10 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, 
         }
     }
     __syncthreads();
-    double dprev = INFINITY;
+    TW dprev = INFINITY;
     int status = 0;
     for (int step = 0; step < a.imax; ++step) {
-        // r = b - A x in u_r, rounded to FP64
+        // r = b - A x in u_r, stored in u (A and b as stored in u)
         for (int i = t; i < n; i += BT) {
             const int gi = r0 + i;
             if (a.dd) {
@@ -174,68 +191,71 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, 
                     const double pl = __builtin_fma(av, xv, -ph);
                     dd_add(shi, slo, -ph, -pl, shi, slo);
                 }
-                r[gi] = shi + slo;
+                r[gi] = (TW)(shi + slo);
             } else {
-                double acc = a.b[gi];
-                for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) acc = __builtin_fma(-a.av[q], x[a.ci[q]], acc);
-                r[gi] = acc;
+                double acc = U32 ? (double)(float)a.b[gi] : a.b[gi];
+                for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
+                    const double av = U32 ? (double)(float)a.av[q] : a.av[q];
+                    acc = __builtin_fma(-av, x[a.ci[q]], acc);
+                }
+                r[gi] = (TW)acc;
             }
         }
         __syncthreads();
         // z = P r into V(:, 0); beta0 = ||z||
-        double part = 0.0;
+        TW part = 0;
         for (int i = t; i < n; i += BT) {
-            const double z = p_row<VP>(a, r0 + i, r);
+            const TW z = p_row<VP, TW>(a, r0 + i, r);
             V[i] = z;
-            part = __builtin_fma(z, z, part);
+            part = tw_fma(z, z, part);
         }
-        const double beta0 = sqrt(wg_sum(part, sh));
-        if (beta0 == 0.0) break;             // P r_i = 0: x_i solves the system
+        const TW beta0 = tw_sqrt(wg_sum(part, sh));
+        if (beta0 == (TW)0) break;           // P r_i = 0: x_i solves the system
         if (t == 0) st.steps = step + 1;
         for (int i = t; i < n; i += BT) V[i] = V[i] / beta0;
-        for (int l = t; l <= mx; l += BT) g[l] = l == 0 ? beta0 : 0.0;
+        for (int l = t; l <= mx; l += BT) g[l] = l == 0 ? beta0 : (TW)0;
         __syncthreads();
         int k = 0, capped = 0;
-        double gk = beta0;
+        TW gk = beta0;
         for (int jj = 0; jj < mx; ++jj) {
-            const double* vj = V + (size_t)jj * n;
-            // w = A v_j (global rows, the system's columns)
+            const TW* vj = V + (size_t)jj * n;
+            // w = A v_j (global rows, the system's columns), A as stored in u
             for (int i = t; i < n; i += BT) {
                 const int gi = r0 + i;
-                double acc = 0.0;
-                for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) acc = __builtin_fma(a.av[q], vj[a.ci[q] - r0], acc);
+                TW acc = 0;
+                for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) acc = tw_fma((TW)a.av[q], vj[a.ci[q] - r0], acc);
                 w[gi] = acc;
             }
             __syncthreads();
-            for (int i = t; i < n; i += BT) y[r0 + i] = p_row<VP>(a, r0 + i, w);
+            for (int i = t; i < n; i += BT) y[r0 + i] = p_row<VP, TW>(a, r0 + i, w);
             // modified Gram-Schmidt: h_lj = <y, v_l>, y -= h_lj v_l, l = 0 .. jj
-            double* Hc = H + (size_t)jj * ld;
+            TW* Hc = H + (size_t)jj * ld;
             for (int l = 0; l <= jj; ++l) {
-                const double* vl = V + (size_t)l * n;
-                double p = 0.0;
-                for (int i = t; i < n; i += BT) p = __builtin_fma(y[r0 + i], vl[i], p);
-                const double hl = wg_sum(p, sh);
-                for (int i = t; i < n; i += BT) y[r0 + i] = __builtin_fma(-hl, vl[i], y[r0 + i]);
+                const TW* vl = V + (size_t)l * n;
+                TW p = 0;
+                for (int i = t; i < n; i += BT) p = tw_fma(y[r0 + i], vl[i], p);
+                const TW hl = wg_sum(p, sh);
+                for (int i = t; i < n; i += BT) y[r0 + i] = tw_fma(-hl, vl[i], y[r0 + i]);
                 if (t == 0) Hc[l] = hl;
             }
-            double p = 0.0;
-            for (int i = t; i < n; i += BT) p = __builtin_fma(y[r0 + i], y[r0 + i], p);
-            const double hn = sqrt(wg_sum(p, sh));
-            double* vn = V + (size_t)(jj + 1) * n;
+            TW p = 0;
+            for (int i = t; i < n; i += BT) p = tw_fma(y[r0 + i], y[r0 + i], p);
+            const TW hn = tw_sqrt(wg_sum(p, sh));
+            TW* vn = V + (size_t)(jj + 1) * n;
             for (int i = t; i < n; i += BT) vn[i] = y[r0 + i] / hn;
             if (t == 0) {
                 // previous rotations, new rotation, g update
                 Hc[jj + 1] = hn;
                 for (int l = 0; l < jj; ++l) {
-                    const double x0 = Hc[l], x1 = Hc[l + 1];
+                    const TW x0 = Hc[l], x1 = Hc[l + 1];
                     Hc[l] = cs[l] * x0 + sn[l] * x1;
                     Hc[l + 1] = -sn[l] * x0 + cs[l] * x1;
                 }
-                const double delta = hypot(Hc[jj], Hc[jj + 1]);
-                const double c = Hc[jj] / delta, sv = Hc[jj + 1] / delta;
+                const TW delta = hypot(Hc[jj], Hc[jj + 1]);
+                const TW c = Hc[jj] / delta, sv = Hc[jj + 1] / delta;
                 Hc[jj] = delta;
-                Hc[jj + 1] = 0.0;
-                const double gj = g[jj];
+                Hc[jj + 1] = 0;
+                const TW gj = g[jj];
                 g[jj + 1] = -sv * gj;
                 g[jj] = c * gj;
                 cs[jj] = c;
@@ -246,7 +266,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, 
             gk = sh[BW];
             k = jj + 1;
             __syncthreads();
-            if (gk <= a.tau * beta0 || hn == 0.0) break;
+            if (gk <= (TW)a.tau * beta0 || hn == (TW)0) break;
             if (jj + 1 == mx) {
                 capped = 1;
                 break;
@@ -256,31 +276,34 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, 
         // back substitution H(0:k, 0:k) yk = g(0:k)
         if (t == 0) {
             for (int c = k - 1; c >= 0; --c) {
-                double acc = g[c];
-                for (int c2 = c + 1; c2 < k; ++c2) acc -= H[(size_t)c2 * ld + c] * yk[c2];
+                TW acc = g[c];
+                for (int c2 = c + 1; c2 < k; ++c2) {
+                    if constexpr (U32) acc = tw_fma(-H[(size_t)c2 * ld + c], yk[c2], acc);
+                    else acc -= H[(size_t)c2 * ld + c] * yk[c2];
+                }
                 yk[c] = acc / H[(size_t)c * ld + c];
             }
         }
         __syncthreads();
-        // d = V_k yk, x += d
-        double dm = 0.0, xm = 0.0;
+        // d = V_k yk, x += d (in u)
+        TW dm = 0, xm = 0;
         for (int i = t; i < n; i += BT) {
-            double di = 0.0;
-            for (int c = 0; c < k; ++c) di = __builtin_fma(V[(size_t)c * n + i], yk[c], di);
-            const double xi = x[r0 + i] + di;
-            x[r0 + i] = xi;
+            TW di = 0;
+            for (int c = 0; c < k; ++c) di = tw_fma(V[(size_t)c * n + i], yk[c], di);
+            const TW xi = (TW)x[r0 + i] + di;
+            x[r0 + i] = (double)xi;
             dm = fmax(dm, fabs(di));
             xm = fmax(xm, fabs(xi));
         }
-        const double dn = wg_max(dm, sh), xn = wg_max(xm, sh);
+        const TW dn = wg_max(dm, sh), xn = wg_max(xm, sh);
         if (t == 0) {
             st.its[step] = k;                 // imax <= 32
-            st.gest[step] = gk / beta0;
-            st.dnorm[step] = dn;
+            st.gest[step] = (double)(gk / beta0);
+            st.dnorm[step] = (double)dn;
             st.total_its += k;
         }
-        if (dn <= a.tol_ir * xn) break;
-        if (step >= 2 && dn > 0.5 * dprev) {
+        if ((double)dn <= a.tol_ir * (double)xn) break;
+        if (step >= 2 && dn > (TW)0.5 * dprev) {
             status |= SPAI_W_NOCONV;
             break;
         }
@@ -294,9 +317,9 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws, double* sh, 
     __syncthreads();
 }
 
-template <int VP>
+template <int VP, typename TW>
 __global__ __launch_bounds__(BT) void k_gmres_ir_batched(BatchArgs a) {
-    __shared__ double sh[BW + 2];
+    __shared__ TW sh[BW + 2];
     __shared__ int sys;
     __shared__ spai_ir_stats st;
     double* ws = a.ws + (size_t)blockIdx.x * a.slot;
@@ -306,7 +329,7 @@ __global__ __launch_bounds__(BT) void k_gmres_ir_batched(BatchArgs a) {
         const int q = sys;
         __syncthreads();
         if (q >= a.nsys) break;
-        solve_system<VP>(a, a.order[q], ws, sh, st);
+        solve_system<VP, TW>(a, a.order[q], ws, sh, st);
     }
 }
 
@@ -325,7 +348,7 @@ static int check_batch(const spai_csr* A, int32_t nsys, const int32_t* sys_ptr) 
 // diagonal blocks.
 static int upload_and_check_blocks(spai_handle* h, const spai_csr* A, int32_t nsys, const int32_t* sys_ptr,
                                    int** d_sys_ptr) {
-    int rc = buffer_reserve(h->ws[WS_MISC], sizeof(int) * ((size_t)nsys + 1 + 64));
+    int rc = buffer_reserve(h, h->ws[WS_MISC], sizeof(int) * ((size_t)nsys + 1 + 64));
     if (rc) return rc;
     int* dsp = (int*)h->ws[WS_MISC].ptr;
     int* bad = dsp + nsys + 1;
@@ -360,7 +383,9 @@ int build_batched_impl(spai_handle* h, const spai_csr* A, int32_t nsys, const in
 int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, int32_t nsys,
                           const int32_t* sys_ptr, const double* b, double* x, const spai_ir_params* prm,
                           spai_ir_stats* st) {
-    SPAI_ARG(h && P && b && x && prm && st, "NULL argument");
+    SPAI_ARG(h && prm && st, "NULL handle, parameters or statistics");
+    SPAI_ARG(P, "NULL preconditioner");
+    SPAI_ARG(b && x, "NULL right-hand side or solution");
     int rc = check_batch(A, nsys, sys_ptr);
     if (rc) return rc;
     SPAI_ARG(P->n == A->n, "preconditioner size differs from the matrix");
@@ -369,6 +394,11 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     SPAI_ARG(prm->tau >= 0.0, "tau must be non-negative");
     SPAI_ARG(prm->u_r == SPAI_DD || prm->u_r == SPAI_FP64, "u_r must be DD or FP64");
     SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS, "the batched solver orthogonalises with MGS");
+    SPAI_ARG(prm->u == SPAI_FP64 || prm->u == SPAI_FP32, "the working precision u must be FP64 or FP32");
+    if (prm->u == SPAI_FP32) {
+        SPAI_ARG(prm->u_r == SPAI_FP64, "with working precision FP32 the residual precision must be FP64");
+        SPAI_ARG(P->val_prec != SPAI_FP64, "u_f must not be finer than the working precision");
+    }
     SPAI_HIP(hipSetDevice(h->device));
     hipStream_t s = h->stream;
     int* dsp = nullptr;
@@ -398,15 +428,17 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     const size_t slot = (size_t)cap_n * (kmax + 1) + (size_t)(kmax + 1) * kmax + 4 * (size_t)(kmax + 1) +
                         3 * (size_t)cap_n + 64;
     // workgroups: two per CU, fewer when the slots would take more than a quarter of free memory
+    // (or more than the handle's workspace cap)
     size_t free_b = 0, total_b = 0;
     SPAI_HIP(hipMemGetInfo(&free_b, &total_b));
     long long g = std::min<long long>(nsys, 2LL * h->num_cu);
-    const long long fit = (long long)(free_b / 4 / (slot * sizeof(double)));
+    const size_t room = h->ws_cap ? std::min(free_b / 4, h->ws_cap) : free_b / 4;
+    const long long fit = (long long)(room / (slot * sizeof(double)));
     g = std::max(1LL, std::min(g, fit));
 
-    rc = buffer_reserve(h->ws[WS_SPARE], sizeof(double) * slot * (size_t)g);
+    rc = buffer_reserve(h, h->ws[WS_SPARE], sizeof(double) * slot * (size_t)g);
     if (rc) return rc;
-    rc = buffer_reserve(h->ws[WS_SOLVE_VEC],
+    rc = buffer_reserve(h, h->ws[WS_SOLVE_VEC],
                         sizeof(int) * ((size_t)nsys + 64) + sizeof(spai_ir_stats) * (size_t)nsys + 256);
     if (rc) return rc;
     int* dorder = (int*)h->ws[WS_SOLVE_VEC].ptr;
@@ -440,11 +472,20 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     a.next = next;
     a.stats = dst;
     long tk = timer_begin(h, SPAI_KT_MGS);
-    switch (P->val_prec) {
-    case SPAI_FP64: hipLaunchKernelGGL(k_gmres_ir_batched<SPAI_FP64>, dim3((unsigned)g), dim3(BT), 0, s, a); break;
-    case SPAI_FP32: hipLaunchKernelGGL(k_gmres_ir_batched<SPAI_FP32>, dim3((unsigned)g), dim3(BT), 0, s, a); break;
-    case SPAI_FP16: hipLaunchKernelGGL(k_gmres_ir_batched<SPAI_FP16>, dim3((unsigned)g), dim3(BT), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_gmres_ir_batched<SPAI_BF16>, dim3((unsigned)g), dim3(BT), 0, s, a); break;
+    const dim3 grid((unsigned)g), blk(BT);
+    if (prm->u == SPAI_FP32) {
+        switch (P->val_prec) {
+        case SPAI_FP32: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, float>), grid, blk, 0, s, a); break;
+        case SPAI_FP16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP16, float>), grid, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_BF16, float>), grid, blk, 0, s, a); break;
+        }
+    } else {
+        switch (P->val_prec) {
+        case SPAI_FP64: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP64, double>), grid, blk, 0, s, a); break;
+        case SPAI_FP32: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, double>), grid, blk, 0, s, a); break;
+        case SPAI_FP16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP16, double>), grid, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_BF16, double>), grid, blk, 0, s, a); break;
+        }
     }
     timer_end(h, SPAI_KT_MGS, tk);
     SPAI_HIP(hipGetLastError());

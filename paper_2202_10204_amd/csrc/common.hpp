@@ -47,12 +47,28 @@ struct Status {
 // device memory: grow-only buffers owned by the handle
 // ---------------------------------------------------------------------------
 
+// A region of device memory lent to a handle: allocations are taken from it
+// front to back and never returned one by one; the lender reclaims the whole
+// region once the handle's work in it has completed.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    bool owns(const void* p) const { return base && (const char*)p >= base && (const char*)p < base + size; }
+};
+
 struct Buffer {
     void* ptr = nullptr;
     size_t bytes = 0;
+    Arena from;        // the region it came from (empty: hipMalloc)
 };
 
-int buffer_reserve(Buffer& b, size_t bytes);
+// Device memory of a handle: from the handle's arena when it has one (a free
+// is then a no-op and never waits, where hipFree waits for the whole device),
+// else, or when the arena is exhausted, hipMalloc / hipFree.
+int dev_malloc(spai_handle* h, void** p, size_t bytes);
+void dev_free(void* p, const Arena& from);
+int buffer_reserve(spai_handle* h, Buffer& b, size_t bytes);
 void buffer_free(Buffer& b);
 
 // fixed small device area for counters and reduction results
@@ -83,6 +99,8 @@ struct spai_handle {
     spai::Buffer red;              // reduction partials + ticket counters
     spai::Buffer host_pinned;      // pinned host staging
     int num_cu = 256;
+    spai::Arena arena;             // device memory lent by a request server (empty: hipMalloc)
+    size_t ws_cap = 0;             // cap on the batched solver's workspace in bytes (0: a quarter of free memory)
 };
 
 struct spai_precond {
@@ -100,6 +118,7 @@ struct spai_precond {
     int32_t* steps = nullptr;   // n (build only)
     double* res = nullptr;      // n (build only)
     int32_t* flags = nullptr;   // n (build only)
+    spai::Arena from;             // arena of the building handle (arrays inside it are not freed one by one)
 };
 
 namespace spai {

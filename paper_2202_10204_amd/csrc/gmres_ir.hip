@@ -45,40 +45,75 @@ struct SolveState {
 // row's entries with unit stride, keep lane-strided partial sums and add them
 // by a fixed xor tree, so every call gives the same bits.  Many more waves than
 // one thread per row, and coalesced loads.
-template <int G>
+template <int G, int R>
 __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ av, const double* __restrict__ x,
                                                 double* __restrict__ y, const SolveState* __restrict__ st) {
     if (st && st->done) return;
-    const int row = (int)(((unsigned)blockIdx.x * 256u + threadIdx.x) / G);
+    // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
+    constexpr int GPB = 256 / G;
     const int sub = threadIdx.x & (G - 1);
-    if (row >= n) return;                    // the whole group of G lanes
-    double s = 0.0;
-    const int q1 = rp[row + 1];
-    for (int q = rp[row] + sub; q < q1; q += G) s = __builtin_fma(av[q], x[ci[q]], s);
+    const int row0 = (int)blockIdx.x * GPB * R + (int)threadIdx.x / G;
+    if (row0 >= n) return;                   // the whole group of G lanes
+    // R rows per group: their row pointers, entries and gathers are all in flight together
+    int q0[R], q1[R];
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
-    if (sub == 0) y[row] = s;
+    for (int r = 0; r < R; ++r) {
+        const int row = min(row0 + r * GPB, n - 1);
+        q0[r] = rp[row] + sub;
+        q1[r] = row0 + r * GPB < n ? rp[row + 1] : 0;
+    }
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double s = 0.0;
+        for (int q = q0[r]; q < q1[r]; q += G) s = __builtin_fma(av[q], x[ci[q]], s);
+        acc[r] = s;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double s = acc[r];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (sub == 0 && row0 + r * GPB < n) y[row0 + r * GPB] = s;
+    }
 }
 
-template <int VP, int G>
+template <int VP, int G, int R>
 __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                                                    const typename ValType<VP>::T* __restrict__ pv,
                                                    const double* __restrict__ d, const double* __restrict__ w,
                                                    double* __restrict__ y, const SolveState* __restrict__ st) {
     if (st && st->done) return;
-    const int row = (int)(((unsigned)blockIdx.x * 256u + threadIdx.x) / G);
+    // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
+    constexpr int GPB = 256 / G;
     const int sub = threadIdx.x & (G - 1);
-    if (row >= n) return;
-    double s = 0.0;
-    const int q1 = pp[row + 1];
-    for (int q = pp[row] + sub; q < q1; q += G) {
-        int j = pc[q];
-        s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
+    const int row0 = (int)blockIdx.x * GPB * R + (int)threadIdx.x / G;
+    if (row0 >= n) return;
+    int q0[R], q1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = min(row0 + r * GPB, n - 1);
+        q0[r] = pp[row] + sub;
+        q1[r] = row0 + r * GPB < n ? pp[row + 1] : 0;
+    }
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double s = 0.0;
+        for (int q = q0[r]; q < q1[r]; q += G) {
+            const int j = pc[q];
+            s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
+        }
+        acc[r] = s;
     }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
-    if (sub == 0) y[row] = s;
+    for (int r = 0; r < R; ++r) {
+        double s = acc[r];
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+        if (sub == 0 && row0 + r * GPB < n) y[row0 + r * GPB] = s;
+    }
 }
 
 // lanes per row for an average of nnz / n entries per row
@@ -1265,19 +1300,29 @@ static int reduce_blocks(int n) {
     return std::max(1, std::min(b, RBLOCKS));
 }
 
+// rows per lane group in the sparse products (measured on the 512 x 512
+// workload: 2 for A with 5 entries per row, 4 for P with up to 20)
+constexpr int SPMV_R = 2;
+constexpr int APPLY_R = 4;
+
 template <int VP>
 static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
                       const SolveState* st) {
     using T = typename ValType<VP>::T;
     const T* pv = (const T*)P->val;
-    const unsigned grid = (unsigned)(((long long)n * g + 255) / 256);
+    const long long groups = ((long long)n + APPLY_R - 1) / APPLY_R;
+    const unsigned grid = (unsigned)((groups * g + 255) / 256);
+#define SPAI_AP(G)                                                                                                \
+    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, \
+                       w, y, st)
     switch (g) {
-    case 1: hipLaunchKernelGGL((k_apply_P_g<VP, 1>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
-    case 2: hipLaunchKernelGGL((k_apply_P_g<VP, 2>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
-    case 4: hipLaunchKernelGGL((k_apply_P_g<VP, 4>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
-    case 8: hipLaunchKernelGGL((k_apply_P_g<VP, 8>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
-    default: hipLaunchKernelGGL((k_apply_P_g<VP, 16>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, w, y, st); break;
+    case 1: SPAI_AP(1); break;
+    case 2: SPAI_AP(2); break;
+    case 4: SPAI_AP(4); break;
+    case 8: SPAI_AP(8); break;
+    default: SPAI_AP(16); break;
     }
+#undef SPAI_AP
 }
 
 static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
@@ -1298,15 +1343,19 @@ static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w
 static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
                        const SolveState* st = nullptr) {
     const int n = A->n, g = lanes_per_row(A->nnz, n);
-    const unsigned grid = (unsigned)(((long long)n * g + 255) / 256);
+    const long long groups = ((long long)n + SPMV_R - 1) / SPMV_R;
+    const unsigned grid = (unsigned)((groups * g + 255) / 256);
     long tk = timer_begin(h, SPAI_KT_SPMV_A);
+#define SPAI_SP(G)                                                                                              \
+    hipLaunchKernelGGL((k_spmv_g<G, SPMV_R>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st)
     switch (g) {
-    case 1: hipLaunchKernelGGL(k_spmv_g<1>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
-    case 2: hipLaunchKernelGGL(k_spmv_g<2>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
-    case 4: hipLaunchKernelGGL(k_spmv_g<4>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
-    case 8: hipLaunchKernelGGL(k_spmv_g<8>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
-    default: hipLaunchKernelGGL(k_spmv_g<16>, dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st); break;
+    case 1: SPAI_SP(1); break;
+    case 2: SPAI_SP(2); break;
+    case 4: SPAI_SP(4); break;
+    case 8: SPAI_SP(8); break;
+    default: SPAI_SP(16); break;
     }
+#undef SPAI_SP
     timer_end(h, SPAI_KT_SPMV_A, tk);
     SPAI_HIP(hipGetLastError());
     return SPAI_OK;
@@ -1454,9 +1503,15 @@ static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, h
     return SPAI_OK;
 }
 
+int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, int32_t nsys,
+                          const int32_t* sys_ptr, const double* b, double* x, const spai_ir_params* prm,
+                          spai_ir_stats* st);
+
 int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b, double* x,
                   const spai_ir_params* prm, spai_ir_stats* st) {
-    SPAI_ARG(h && P && b && x && prm, "NULL argument");
+    SPAI_ARG(h && prm, "NULL handle or parameters");
+    SPAI_ARG(P, "NULL preconditioner");
+    SPAI_ARG(b && x, "NULL right-hand side or solution");
     int rc = check_csr(A);
     if (rc) return rc;
     const int n = A->n;
@@ -1467,6 +1522,16 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     SPAI_ARG(prm->u_r == SPAI_DD || prm->u_r == SPAI_FP64, "u_r must be DD or FP64");
     SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS || prm->ortho == SPAI_ORTHO_CGS2 || prm->ortho == SPAI_ORTHO_DCGS2,
              "ortho must be MGS, CGS2 or DCGS2");
+    SPAI_ARG(prm->u == SPAI_FP64 || prm->u == SPAI_FP32, "the working precision u must be FP64 or FP32");
+    if (prm->u == SPAI_FP32) {
+        // working precision single: the system runs in the batched solver as a batch of one
+        SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS, "working precision FP32 orthogonalises with MGS");
+        const int32_t one[2] = {0, n};
+        spai_ir_stats tmp{};
+        rc = gmres_ir_batched_impl(h, A, P, 1, one, b, x, prm, &tmp);
+        if (rc >= 0 && st) *st = tmp;
+        return rc;
+    }
     SPAI_HIP(hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const int maxit = std::min(prm->maxit, n);
@@ -1477,15 +1542,15 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     const int maxlinks = maxit + 2;
 
     // workspace
-    rc = buffer_reserve(h->ws[WS_SOLVE_V], sizeof(double) * (size_t)n * (size_t)(maxit + 1));
+    rc = buffer_reserve(h, h->ws[WS_SOLVE_V], sizeof(double) * (size_t)n * (size_t)(maxit + 1));
     if (rc) return rc;
-    rc = buffer_reserve(h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
+    rc = buffer_reserve(h, h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
     if (rc) return rc;
     size_t slot_count = cfg.slot_words;
     const bool dcgs2 = prm->ortho == SPAI_ORTHO_DCGS2;
     const size_t hr_words = dcgs2 ? 2 * (size_t)ld * maxit : 0;   // HRp, HRf
     size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count + hr_words);
-    rc = buffer_reserve(h->ws[WS_SOLVE_H], hbytes);
+    rc = buffer_reserve(h, h->ws[WS_SOLVE_H], hbytes);
     if (rc) return rc;
     double* V = (double*)h->ws[WS_SOLVE_V].ptr;
     double* r = (double*)h->ws[WS_SOLVE_VEC].ptr;

@@ -807,22 +807,20 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 static void precond_free(spai_precond* P) {
     if (!P) return;
     void* ptrs[] = {P->rowptr, P->col, P->val, P->d, P->j_ins, P->m_ins, P->len, P->steps, P->res, P->flags};
-    for (void* q : ptrs)
-        if (q) (void)hipFree(q);
+    for (void* q : ptrs) dev_free(q, P->from);
     delete P;
 }
 
 template <typename T>
-static int dev_alloc(T** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        set_error(std::string("device allocation failed: ") + hipGetErrorString(e));
-        return SPAI_E_OOM;
-    }
-    return SPAI_OK;
+static int dev_alloc(spai_handle* h, T** p, size_t count) {
+    return dev_malloc(h, (void**)p, sizeof(T) * (count ? count : 1));
+}
+
+// a new preconditioner whose arrays come from the handle's allocator
+static spai_precond* precond_new(spai_handle* h) {
+    spai_precond* P = new spai_precond();
+    P->from = h->arena;
+    return P;
 }
 
 static size_t val_size(spai_prec v) {
@@ -862,7 +860,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
            o_tot = take(16), o_dl = take(4 * (size_t)n), o_dl2 = take(4 * (size_t)n),
            o_dc = take(16), o_prep = take(sizeof(PrepOut)), o_bst = take(sizeof(BuildStatsDev)),
            o_nI = take(4 * (size_t)n);
-    int rc = buffer_reserve(h->ws[WS_BUILD0], off);
+    int rc = buffer_reserve(h, h->ws[WS_BUILD0], off);
     if (rc) return rc;
     char* base = (char*)h->ws[WS_BUILD0].ptr;
     void* bn = base + o_bn;
@@ -880,7 +878,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     int* nI = (int*)(base + o_nI);
     char* hp = (char*)h->host_pinned.ptr;
 
-    spai_precond* P = new spai_precond();
+    spai_precond* P = precond_new(h);
     P->n = n;
     P->val_prec = p->u_f;
     auto fail = [&](int code) { precond_free(P); return code; };
@@ -889,7 +887,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     SPAI_HIP(hipMemsetAsync(prep, 0, sizeof(PrepOut), s));
     SPAI_HIP(hipMemsetAsync(dc, 0, 16, s));
     SPAI_HIP(hipMemsetAsync(bst, 0, sizeof(BuildStatsDev), s));
-    if ((rc = dev_alloc(&P->d, n))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->d, n))) return fail(rc);
     const int tb = 256, gb = (n + tb - 1) / tb;
     hipLaunchKernelGGL(k_validate_scale, dim3(gb), dim3(tb), 0, s, n, nnz, A->rowptr, A->col, A->val,
                        P->d, cnt, prep);
@@ -933,12 +931,12 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     SPAI_HIP(hipGetLastError());
 
     // per-column outputs
-    if ((rc = dev_alloc(&P->j_ins, (size_t)n * stride))) return fail(rc);
-    if ((rc = dev_alloc(&P->m_ins, (size_t)n * stride))) return fail(rc);
-    if ((rc = dev_alloc(&P->len, n))) return fail(rc);
-    if ((rc = dev_alloc(&P->steps, n))) return fail(rc);
-    if ((rc = dev_alloc(&P->res, n))) return fail(rc);
-    if ((rc = dev_alloc(&P->flags, n))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->j_ins, (size_t)n * stride))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->m_ins, (size_t)n * stride))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->len, n))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->steps, n))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->res, n))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->flags, n))) return fail(rc);
 
     ColArgs a{};
     a.n = n; a.rp = A->rowptr; a.ci = A->col; a.av = A->val; a.cp = cp; a.ri = ri; a.d = P->d;
@@ -960,7 +958,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     if (rc) return fail(rc);
 
     // compaction into CSR(P)
-    if ((rc = dev_alloc(&P->rowptr, (size_t)n + 1))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->rowptr, (size_t)n + 1))) return fail(rc);
     if ((rc = scan_ints(n, P->len, P->rowptr, blk, tot, s))) return fail(rc);
     hipLaunchKernelGGL(k_build_stats, dim3(gb), dim3(tb), 0, s, n, P->len, P->steps, P->res, P->flags, nI, bst);
     SPAI_HIP(hipMemcpyAsync(hp, tot, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -970,15 +968,10 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     BuildStatsDev bs;
     std::memcpy(&bs, hp + 64, sizeof(bs));
     P->nnz = total;
-    if ((rc = dev_alloc(&P->col, (size_t)total))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->col, (size_t)total))) return fail(rc);
     {
         void* v = nullptr;
-        hipError_t e = hipMalloc(&v, val_size(p->u_f) * (size_t)std::max(total, 1));
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("device allocation failed for P values");
-            return fail(SPAI_E_OOM);
-        }
+        if ((rc = dev_malloc(h, &v, val_size(p->u_f) * (size_t)std::max(total, 1)))) return fail(rc);
         P->val = v;
     }
     long long work = (long long)n * stride;
@@ -1043,22 +1036,18 @@ int spai::precond_import_impl(spai_handle* h, int32_t n, int64_t nnz, const int3
     *P_out = nullptr;
     SPAI_HIP(hipSetDevice(h->device));
     hipStream_t s = h->stream;
-    spai_precond* P = new spai_precond();
+    spai_precond* P = precond_new(h);
     P->n = n;
     P->nnz = nnz;
     P->val_prec = vp;
     auto fail = [&](int code) { precond_free(P); return code; };
     int rc;
-    if ((rc = dev_alloc(&P->rowptr, (size_t)n + 1))) return fail(rc);
-    if ((rc = dev_alloc(&P->col, (size_t)nnz))) return fail(rc);
-    if ((rc = dev_alloc(&P->d, (size_t)n))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->rowptr, (size_t)n + 1))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->col, (size_t)nnz))) return fail(rc);
+    if ((rc = dev_alloc(h, &P->d, (size_t)n))) return fail(rc);
     {
         void* v = nullptr;
-        if (hipMalloc(&v, val_size(vp) * (size_t)std::max<int64_t>(nnz, 1)) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("device allocation failed for P values");
-            return fail(SPAI_E_OOM);
-        }
+        if ((rc = dev_malloc(h, &v, val_size(vp) * (size_t)std::max<int64_t>(nnz, 1)))) return fail(rc);
         P->val = v;
     }
     SPAI_HIP(hipMemcpyAsync(P->rowptr, rowptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));

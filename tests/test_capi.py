@@ -82,3 +82,45 @@ def test_binding_refuses_to_run_without_a_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(S.SpaiError):
         S.Handle()
+
+
+def test_serve_footprint_and_arguments_on_the_host(lib):
+    """The admission estimate is a host computation: it grows with the system,
+    counts the pattern and the solve's basis, and malformed requests are
+    rejected before any device work."""
+    import paper_2202_10204_amd as S
+    import workloads as W
+
+    build = {"eps": 0.3, "alpha": 125, "beta": 8, "maxfill": 20, "u_f": "fp32"}
+    ir = {"tau": 1e-8, "imax": 10, "maxit": 500, "tol_ir": 2.0 ** -45}
+    small = W.serving_request(W.Arrival(0.0, "random", 1000, "fp32", 0))
+    large = W.serving_request(W.Arrival(0.0, "random", 4000, "fp32", 1))
+    f1 = S.serve_footprint(small.A, small.b, None, build, ir)
+    f2 = S.serve_footprint(large.A, large.b, None, build, ir)
+    # at least A, b, x, P at the fill cap and the basis of min(maxit, n) + 1 vectors
+    for w, f in ((small, f1), (large, f2)):
+        n, nnz = w.n, w.A.nnz
+        floor = 12 * nnz + 16 * n + 8 * 20 * n + 8 * n * (min(500, n) + 1)
+        assert floor <= f <= 4 * floor + (16 << 20)
+    assert f2 > f1
+    f_fp16 = S.serve_footprint(small.A, small.b, None, dict(build, u_f="fp16"), ir)
+    assert f_fp16 < f1
+    aniso = W.serving_request(W.Arrival(0.0, "aniso", 10, "fp32", 2))
+    fb = dict(build, eps=0.5, alpha=0, maxfill=27)
+    assert S.serve_footprint(aniso.A, aniso.b, aniso.pattern, fb, ir) > S.serve_footprint(aniso.A, aniso.b, None,
+                                                                                          fb, ir)
+    with pytest.raises(S.SpaiError):
+        S.serve_footprint(small.A, small.b, None, dict(build, maxfill=0), ir)
+    with pytest.raises(S.SpaiError):
+        S.serve_footprint(small.A, small.b, None, build, dict(ir, imax=33))
+    bad = W.CSR(small.A.n, small.A.rowptr.copy(), small.A.col, small.A.val)
+    bad.rowptr[-1] += 1
+    with pytest.raises(S.SpaiError):
+        S.serve_footprint(bad, small.b, None, build, ir)
+    # the server itself needs a device: its creation and submission fail cleanly without one
+    prm = S._ServeParams(0, 1000, 16, 0, 1 << 30, 0)
+    out = ctypes.c_void_p()
+    assert lib.spai_serve_create(ctypes.byref(prm), ctypes.byref(out)) == S.E_ARG
+    assert lib.spai_serve_submit(None, None, None) == S.E_ARG
+    assert lib.spai_serve_wait(None, 1, None, None) == S.E_ARG
+    assert lib.spai_serve_destroy(None) == 0

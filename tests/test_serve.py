@@ -1,0 +1,161 @@
+"""The library's request loop (spai_serve_*): continuous batching of independent
+solves, admission by device footprint, and results that do not depend on what
+else is in flight.
+
+Every request is solved alone (submitted, then waited for, one at a time) and
+again in a mix (all submitted at once, so several batches and the device lane
+run together): the solutions must be bit-identical, the GMRES tuples equal,
+and equal to the oracle's for requests checked against it.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BATCH_MAX_N = 3000
+
+# families and sizes of the stream at small sizes: three batch keys (adaptive
+# FP32, adaptive FP16, fixed pattern FP32/FP16) and two systems above
+# BATCH_MAX_N for the device lane
+ARRIVALS = [
+    W.Arrival(0.0, "random", 1200, "fp32", 0),
+    W.Arrival(0.0, "random", 1500, "fp16", 1),
+    W.Arrival(0.0, "random", 2600, "fp32", 2),
+    W.Arrival(0.0, "convdiff", 32, "fp32", 3),
+    W.Arrival(0.0, "convdiff", 36, "fp16", 4),
+    W.Arrival(0.0, "aniso", 10, "fp32", 5),
+    W.Arrival(0.0, "aniso", 11, "fp16", 6),
+    W.Arrival(0.0, "convdiff", 56, "fp32", 7),
+    W.Arrival(0.0, "aniso", 15, "fp32", 8),
+    W.Arrival(0.0, "random", 1800, "fp32", 9),
+]
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2202_10204_amd as S
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return S
+
+
+@pytest.fixture(scope="module")
+def systems():
+    return [W.serving_request(a) for a in ARRIVALS]
+
+
+def _args(w, ortho="mgs"):
+    s, ir = w.spai, w.ir
+    build = {"eps": s.eps, "alpha": s.alpha, "beta": s.beta, "maxfill": s.maxfill, "u_f": s.u_f}
+    irp = {"tau": ir.tau, "imax": ir.imax, "maxit": ir.maxit, "tol_ir": ir.tol_ir, "u_r": "dd", "ortho": ortho}
+    return w.A, w.b, w.pattern, build, irp
+
+
+def _ortho(k):
+    return "dcgs2" if k == 8 else "mgs"
+
+
+@pytest.fixture(scope="module")
+def alone(S, systems):
+    srv = S.Server(batch_lanes=3, batch_max_n=BATCH_MAX_N, hbm_budget=8 << 30, lane_workspace=512 << 20)
+    out = []
+    for k, w in enumerate(systems):
+        rid = srv.submit(*_args(w, _ortho(k)))
+        out.append(srv.wait(rid))
+    srv.close()
+    return out
+
+
+def test_alone_results_are_valid(systems, alone):
+    for k, (w, (rc, x, rec)) in enumerate(zip(systems, alone)):
+        print(k, w.name, w.n, rec["lane"], rec["its"], rc, flush=True)
+        assert rc >= 0, rec["error"]
+        assert rec["batch_size"] == 1
+        assert (rec["lane"] == -1) == (w.n > BATCH_MAX_N)
+        if w.spai.u_f == "fp32":
+            assert O.ferr(x, w.x_true) <= 1e-12, (k, w.name)
+
+
+def test_mix_equals_alone_bitwise(S, systems, alone):
+    srv = S.Server(batch_lanes=3, batch_max_n=BATCH_MAX_N, hbm_budget=8 << 30, lane_workspace=512 << 20)
+    ids = [srv.submit(*_args(w, _ortho(k))) for k, w in enumerate(systems)]
+    mix = [srv.wait(i) for i in ids]
+    srv.close()
+    batched = 0
+    for k, ((rc_a, x_a, rec_a), (rc_m, x_m, rec_m)) in enumerate(zip(alone, mix)):
+        assert rc_m == rc_a, (k, rec_m["error"])
+        assert rec_m["its"] == rec_a["its"], k
+        assert np.array_equal(x_m, x_a), (k, float(np.abs(x_m - x_a).max()))
+        assert rec_m["t_submit"] <= rec_m["t_admit"] <= rec_m["t_done"]
+        batched = max(batched, rec_m["batch_size"])
+    # the three FP32 adaptive systems of the batch lanes share parameters: at least two ran together
+    assert batched >= 2
+
+
+@pytest.mark.parametrize("k", [0, 5, 7, 8])
+def test_served_tuples_equal_the_oracle(systems, alone, k):
+    w = systems[k]
+    s, ir = w.spai, w.ir
+    R = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = R.P_csr(w.n)
+    res = O.gmres_ir(w.A, pp, pc, pv, R.d, s.u_f, w.b, ir.tau, ir.imax, min(ir.maxit, w.n), ir.tol_ir,
+                     _ortho(k))
+    rc, x, rec = alone[k]
+    assert rec["its"] == list(res.its), (rec["its"], res.its)
+    assert rec["nnz_p"] == int(pp[-1])
+    assert np.abs(x - res.x).max() <= 1e-12 * np.abs(res.x).max()
+
+
+UNIT_SLACK = 16 << 20   # per unit of work, beside the footprints (the library's allowance for small buffers)
+
+
+def test_admission_respects_the_budget(S, systems, alone):
+    """An arena that holds about two units of work at a time: the units in
+    flight (a batch = its footprints + one lane workspace, a device-lane request
+    = its footprint) never exceed it together, some requests had to wait, and
+    the results are still those of the requests alone."""
+    fps = [S.serve_footprint(*_args(w, _ortho(k))) for k, w in enumerate(systems)]
+    lanes, lane_ws = 2, 64 << 20
+    budget = 2 * (lane_ws + UNIT_SLACK) + int(max(fps) * 1.5)
+    srv = S.Server(batch_lanes=lanes, batch_max_n=BATCH_MAX_N, hbm_budget=budget, lane_workspace=lane_ws)
+    ids = [srv.submit(*_args(w, _ortho(k))) for k, w in enumerate(systems)]
+    recs = []
+    for k, i in enumerate(ids):
+        rc, x, rec = srv.wait(i)
+        assert rc == alone[k][0]
+        assert np.array_equal(x, alone[k][1]), k
+        assert np.array_equal(rec["its"], alone[k][2]["its"]), k
+        assert rec["footprint"] == fps[k]
+        recs.append(rec)
+    srv.close()
+    units = {}
+    for r in recs:
+        key = (r["lane"], r["t_admit"])
+        u = units.setdefault(key, {"t_admit": r["t_admit"], "t_done": r["t_done"], "size": UNIT_SLACK +
+                                   (lane_ws if r["lane"] >= 0 else 0)})
+        u["size"] += r["footprint"]
+    for u in units.values():
+        held = sum(v["size"] for v in units.values() if v["t_admit"] <= u["t_admit"] < v["t_done"])
+        assert held <= budget, (held, budget)
+    assert any(r["t_admit"] > r["t_submit"] + 1e-3 for r in recs)     # somebody waited for a lane or memory
+
+
+def test_bad_requests_are_rejected(S, systems):
+    srv = S.Server(batch_lanes=1, batch_max_n=BATCH_MAX_N, hbm_budget=512 << 20, lane_workspace=128 << 20)
+    w = systems[0]
+    A, b, pat, build, irp = _args(w)
+    with pytest.raises(S.SpaiError):
+        srv.submit(A, b, pat, dict(build, maxfill=0), irp)
+    with pytest.raises(S.SpaiError):
+        srv.submit(A, b, pat, build, dict(irp, imax=0))
+    # a request that can never fit the budget (64^3 unknowns with a 500-vector basis: about 1.2 GB)
+    big = W.serving_request(W.Arrival(0.0, "aniso", 64, "fp32", 99))
+    with pytest.raises(S.SpaiError):
+        srv.submit(*_args(big))
+    srv.close()

@@ -1253,6 +1253,71 @@ __global__ __launch_bounds__(RB) void k_backsolve(int k, const double* __restric
     }
 }
 
+// The same back substitution for k <= BS_MAXK with the latency of H off the
+// critical path: the whole workgroup stages BS_COLS columns of H (rows 0 .. top
+// of the block) in LDS with all loads in flight, then wave 0 runs those columns
+// with the right-hand side in registers (lane l holds rows l, l + 64, ...) and
+// the pivot value broadcast by readlane, no barrier per column.  Same
+// operations in the same order as k_backsolve.
+constexpr int BS_MAXK = 512;
+constexpr int BS_COLS = 32;
+
+__global__ __launch_bounds__(RB) void k_backsolve_lds(int k, const double* __restrict__ H, int ld,
+                                                      const double* __restrict__ g, double* __restrict__ yk) {
+    constexpr int M = BS_MAXK / 64;
+    __shared__ double hb[BS_COLS * BS_MAXK];   // column q of the block at hb[q * BS_MAXK]
+    const int t = threadIdx.x, lane = t & 63;
+    double wv[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = lane + 64 * m;
+        wv[m] = i < k ? g[i] : 0.0;
+    }
+    for (int top = k - 1; top >= 0; top -= BS_COLS) {
+        const int c0 = max(top - BS_COLS + 1, 0), nc = top - c0 + 1, rows = top + 1;
+        __syncthreads();
+        // 16 loads in flight per thread, then their LDS stores
+        const int tot = nc * rows;
+        for (int e0 = 0; e0 < tot; e0 += 16 * RB) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = min(e0 + u * RB + t, tot - 1);
+                const int q = e / rows, i = e - q * rows;
+                v[u] = H[(size_t)(c0 + q) * ld + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * RB + t;
+                if (e < tot) {
+                    const int q = e / rows, i = e - q * rows;
+                    hb[q * BS_MAXK + i] = v[u];
+                }
+            }
+        }
+        __syncthreads();
+        if (t < 64) {
+            for (int c = top; c >= c0; --c) {
+                const double* hc = hb + (c - c0) * BS_MAXK;
+                const int mc = c >> 6;
+                double wc = 0.0;
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+                    if (m == mc) wc = wv[m];
+                wc = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(wc), c & 63),
+                                      __builtin_amdgcn_readlane(__double2loint(wc), c & 63));
+                const double yc = wc / hc[c];
+                if (lane == 0) yk[c] = yc;
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const int i = lane + 64 * m;
+                    if (i < c) wv[m] = __builtin_fma(-hc[i], yc, wv[m]);
+                }
+            }
+        }
+    }
+}
+
 // x += V_k y; records ||d||_inf and ||x||_inf (non-negative doubles compare as integers)
 __global__ void k_update(int n, int k, const double* __restrict__ V, const double* __restrict__ yk,
                          double* __restrict__ x, unsigned long long* __restrict__ maxbits) {
@@ -1507,6 +1572,20 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
                           const int32_t* sys_ptr, const double* b, double* x, const spai_ir_params* prm,
                           spai_ir_stats* st);
 
+// two events without timing, destroyed with the scope
+struct EventPair {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    int create() {
+        for (auto& x : e) SPAI_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+        return SPAI_OK;
+    }
+    hipEvent_t operator[](int i) const { return e[i]; }
+    ~EventPair() {
+        for (auto x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
 int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b, double* x,
                   const spai_ir_params* prm, spai_ir_stats* st) {
     SPAI_ARG(h && prm, "NULL handle or parameters");
@@ -1575,6 +1654,8 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     const int nbr = reduce_blocks(n);
     SPAI_HIP(hipMemsetAsync(ticket, 0, 16, s));
     const int chunk = 8;   // Arnoldi steps enqueued between checks of the stop flag
+    EventPair ev;          // completion of the flag copies of the last two chunks
+    if ((rc = ev.create())) return rc;
 
     int status = 0;
     spai_ir_stats loc{};
@@ -1605,7 +1686,18 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
         int sweep = 0;
         // DCGS2 completes column j - 1 in launch j: launches 0 .. maxit
         const int jend = dcgs2 ? maxit + 1 : maxit;
-        for (int j0 = 0; j0 < jend; j0 += chunk) {
+        // The stop flag of chunk c is read while chunk c + 1 is already queued, so
+        // the device never drains between chunks; a chunk enqueued after the stop
+        // returns at once on the device (every kernel checks the flag).
+        int pending = -1;   // chunk whose flag copy has not been read yet
+        bool stopped = false;
+        auto read_flag = [&](int c) -> int {
+            SPAI_HIP(hipEventSynchronize(ev[c & 1]));
+            std::memcpy(&ss, hp + 256 * (c & 1), sizeof(ss));
+            return SPAI_OK;
+        };
+        int cidx = 0;
+        for (int j0 = 0; j0 < jend; j0 += chunk, ++cidx) {
             int j1 = std::min(j0 + chunk, jend);
             for (int j = j0; j < j1; ++j) {
                 double* vj = V + (size_t)j * n;
@@ -1640,10 +1732,20 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
                     SPAI_HIP(hipGetLastError());
                 }
             }
-            SPAI_HIP(hipMemcpyAsync(hp, sst, sizeof(SolveState), hipMemcpyDeviceToHost, s));
-            SPAI_HIP(hipStreamSynchronize(s));
-            std::memcpy(&ss, hp, sizeof(ss));
-            if (ss.done) break;
+            SPAI_HIP(hipMemcpyAsync(hp + 256 * (cidx & 1), sst, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+            SPAI_HIP(hipEventRecord(ev[cidx & 1], s));
+            if (pending >= 0) {
+                if ((rc = read_flag(pending))) return rc;
+                if (ss.done) {
+                    stopped = true;
+                    pending = -1;
+                    break;
+                }
+            }
+            pending = cidx;
+        }
+        if (!stopped && pending >= 0) {
+            if ((rc = read_flag(pending))) return rc;
         }
         if (ss.done == 3 || ss.err) {
             set_error("a grid-wide sum of the Arnoldi kernel timed out");
@@ -1657,7 +1759,11 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
         if (ss.done == 2) status |= SPAI_W_MAXIT;
         loc.its[step] = kk;
         loc.total_its += kk;
-        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(RB), 0, s, kk, (const double*)H, ld, (const double*)g, w, yk);
+        if (kk <= BS_MAXK)
+            hipLaunchKernelGGL(k_backsolve_lds, dim3(1), dim3(RB), 0, s, kk, (const double*)H, ld, (const double*)g, yk);
+        else
+            hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(RB), 0, s, kk, (const double*)H, ld, (const double*)g, w,
+                               yk);
         SPAI_HIP(hipMemsetAsync(maxbits, 0, 16, s));
         long tu = timer_begin(h, SPAI_KT_UPDATE);
         hipLaunchKernelGGL(k_update, dim3(gb), dim3(tb), 0, s, n, kk, (const double*)V, (const double*)yk, x, maxbits);

@@ -68,7 +68,9 @@ def _lib():
                                         P, P]
         L.oracle_gmres_ir.restype = i32
         L.oracle_gmres_ir.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64,
-                                      i32, P, P, P, P]
+                                      i32, i32, P, P, P, P]
+        L.oracle_x0_right.restype = None
+        L.oracle_x0_right.argtypes = [i32, P, P, P, P, P, i32, P]
         L.oracle_gmres_ir_fp32.restype = i32
         L.oracle_gmres_ir_fp32.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64, P, P, P, P]
         L.oracle_residual.restype = None
@@ -283,7 +285,7 @@ ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 
 def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, maxit: int,
-             tol_ir: float, ortho: str = "mgs", u: str = "fp64") -> IrResult:
+             tol_ir: float, ortho: str = "mgs", u: str = "fp64", side: str = "left") -> IrResult:
     """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D.
 
     ``ortho`` = "mgs" (modified Gram-Schmidt, the variant analysed in Section
@@ -293,7 +295,11 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
 
     ``u`` is the working precision u = u_g = u_p: "fp64" (residual rounded
     exactly to FP64, the precision set of Table 3) or "fp32" (the sets of Tables
-    4 and 5: every stored quantity binary32, residual in binary64, MGS only)."""
+    4 and 5: every stored quantity binary32, residual in binary64, MGS only).
+
+    ``side`` = "left" (Algorithm 3: P = M^T D from ``spai``) or "right" (P = D M
+    from ``spai_right``, GMRES on A P y = r_i with d_i = P y; working precision
+    double only)."""
     n = A.n
     x = np.zeros(n)
     its = np.zeros(imax, np.int32)
@@ -303,6 +309,8 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     rp, ci, av = _i32(A.rowptr), _i32(A.col), _f64(A.val)
     pp, pc, pv = _i32(P_rowptr), _i32(P_col), _f64(P_val)
     dd, bb = _f64(d), _f64(b)
+    if side not in ("left", "right") or (side == "right" and u != "fp64"):
+        raise ValueError("side must be left or right (right with u = fp64)")
     if u == "fp32":
         if ortho != "mgs":
             raise ValueError("the single working precision variant uses MGS")
@@ -312,7 +320,7 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     elif u == "fp64":
         st = _lib().oracle_gmres_ir(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
                                     _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
-                                    ORTHO[ortho], _p(its), _p(nsteps), _p(gest), _p(dn))
+                                    ORTHO[ortho], int(side == "right"), _p(its), _p(nsteps), _p(gest), _p(dn))
     else:
         raise ValueError(f"unknown working precision {u}")
     if st < 0:
@@ -328,6 +336,42 @@ def x0(P_rowptr, P_col, P_val, d, b, uf: str) -> np.ndarray:
     pp, pc, pv = _i32(P_rowptr), _i32(P_col), _f64(P_val)
     _lib().oracle_x0(n, _p(pp), _p(pc), _p(pv), _p(_f64(d)), _p(_f64(b)), UF[uf], _p(out))
     return out
+
+
+@dataclasses.dataclass
+class _Transposed:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+
+def x0_right(P_rowptr, P_col, P_val, d, b, uf: str) -> np.ndarray:
+    """x0 = P b in u_f for a right preconditioner P = D M (rows i hold m_k[i])."""
+    n = len(b)
+    out = np.zeros(n)
+    pp, pc, pv = _i32(P_rowptr), _i32(P_col), _f64(P_val)
+    _lib().oracle_x0_right(n, _p(pp), _p(pc), _p(pv), _p(_f64(d)), _p(_f64(b)), UF[uf], _p(out))
+    return out
+
+
+def spai_right(A, pattern, eps: float, alpha: int, beta: int, maxfill: int, uf: str, nthreads: int = 0):
+    """Right preconditioner P = D M with A D M ~ I: Algorithm 1 on A itself with its
+    columns scaled to unit maximum (D = diag(1 / max_i |a_ij|)), i.e. the left-form
+    build of A^T, whose rows m_k become the columns of M.  Returns (R, rowptr, col,
+    val, d): R the per-column results of the build on A^T, and the CSR of P by rows
+    i (entries m_k[i], columns k ascending) with the scaling d applied to the
+    output."""
+    import scipy.sparse as _sp
+    At = _sp.csr_matrix((np.asarray(A.val), np.asarray(A.col), np.asarray(A.rowptr)), shape=(A.n, A.n)).T.tocsr()
+    At.sort_indices()
+
+    T = _Transposed(A.n, At.indptr.astype(np.int32), At.indices.astype(np.int32), At.data.copy())
+    R = spai(T, pattern, eps, alpha, beta, maxfill, uf, nthreads=max(1, nthreads))
+    pp, pc, pv = R.P_csr(A.n)
+    Pt = _sp.csr_matrix((pv, pc, pp), shape=(A.n, A.n)).T.tocsr()
+    Pt.sort_indices()
+    return R, Pt.indptr.astype(np.int32), Pt.indices.astype(np.int32), Pt.data.copy(), R.d.copy()
 
 
 def apply_P(P_rowptr, P_col, P_val, d, w) -> np.ndarray:

@@ -671,6 +671,33 @@ static void spmv(int n, const int* rp, const int* ci, const double* av, const do
     }
 }
 
+/* Right preconditioner P = D M (Algorithm 1 run on A with the columns of A scaled
+ * to unit maximum, so that A D M ~ I): row i of its CSR holds the entries m_k[i]
+ * of the columns k with i in J_k (columns pc, values pv), and y = P w = D (M w):
+ * y_i = d_i * sum_k m_k[i] w_k in FP64. */
+static void apply_P_right(int n, const int* pp, const int* pc, const double* pv, const double* d,
+                          const double* w, double* y) {
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int t = pp[i]; t < pp[i + 1]; ++t) s += pv[t] * w[pc[t]];
+        y[i] = d[i] * s;
+    }
+}
+
+/* y = P A v (left preconditioning, the paper's Algorithm 3) or y = A P v (right
+ * preconditioning); w and dw are scratch vectors. */
+static void apply_op(int right, int n, const int* rp, const int* ci, const double* av, const int* pp,
+                     const int* pc, const double* pv, const double* d, const double* v, double* w, double* dw,
+                     double* y) {
+    if (right) {
+        apply_P_right(n, pp, pc, pv, d, v, w);
+        spmv(n, rp, ci, av, w, y);
+    } else {
+        spmv(n, rp, ci, av, v, w);
+        apply_P(n, pp, pc, pv, d, w, dw, y);
+    }
+}
+
 static double dot(int n, const double* a, const double* b) {
     double s = 0.0;
     for (int i = 0; i < n; ++i) s += a[i] * b[i];
@@ -693,6 +720,21 @@ void oracle_x0(int n, const int* pp, const int* pc, const double* pv, const doub
         double s = 0.0;
         for (int t = pp[k]; t < pp[k + 1]; ++t) s = FFMA(pv[t], z[pc[t]], s);  /* ascending column */
         x0[k] = s;
+    }
+    free(z);
+}
+
+/* x0 = P b in u_f for a right preconditioner P = D M: b rounded to u_f, each row's
+ * sum of m_k[i] b_k in the arithmetic precision of u_f (ascending k, fused
+ * multiply-adds), then multiplied by d_i rounded to u_f, in that precision. */
+void oracle_x0_right(int n, const int* pp, const int* pc, const double* pv, const double* d,
+                     const double* b, int uf, double* x0) {
+    double* z = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int j = 0; j < n; ++j) z[j] = RS(b[j]);
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int t = pp[i]; t < pp[i + 1]; ++t) s = FFMA(pv[t], z[pc[t]], s);
+        x0[i] = FMUL(RS(d[i]), s);
     }
     free(z);
 }
@@ -742,7 +784,7 @@ static void givens_column(double* H, int ld, int j, double* cs, double* sn, doub
  * rotations, H receives the rotated columns.  Returns k; *maxit_hit is set when
  * k reached maxit without the test being met.
  */
-static int arnoldi_dcgs2(int n, const int* rp, const int* ci, const double* av, const int* pp,
+static int arnoldi_dcgs2(int right, int n, const int* rp, const int* ci, const double* av, const int* pp,
                          const int* pc, const double* pv, const double* d, double* V, double* H,
                          double* HR, int ld, double* cs, double* sn, double* g, double beta0, double tau,
                          int maxit, double* w, double* dw, double* y, double* a, double* bb,
@@ -771,8 +813,7 @@ static int arnoldi_dcgs2(int n, const int* rp, const int* ci, const double* av, 
                 break;
             }
         }
-        spmv(n, rp, ci, av, uj, w);
-        apply_P(n, pp, pc, pv, d, w, dw, y);
+        apply_op(right, n, rp, ci, av, pp, pc, pv, d, uj, w, dw, y);
         for (int l = 0; l < j; ++l) bb[l] = dot(n, V + (size_t)l * n, y);
         double c = dot(n, uj, y);
         if (j > 0) {                     /* per element: l ascending, then the division */
@@ -803,7 +844,11 @@ static int arnoldi_dcgs2(int n, const int* rp, const int* ci, const double* av, 
 }
 
 /*
- * SPAI-GMRES-IR.  A: CSR FP64.  ortho selects the orthogonalisation of the Arnoldi
+ * SPAI-GMRES-IR.  A: CSR FP64.  right = 0: left preconditioning as in Algorithm 3
+ * (GMRES on P A d = P r_i, P = M^T D as for oracle_x0); right = 1: right
+ * preconditioning with P = D M given as for apply_P_right (GMRES on A P y = r_i,
+ * stopped when |g_{j+1}| <= tau ||r_i||_2, correction d_i = P y; x0 from
+ * oracle_x0_right).  ortho selects the orthogonalisation of the Arnoldi
  * vectors: 0 = modified Gram-Schmidt (the variant of the analysis in Section 3.2),
  * 1 = classical Gram-Schmidt applied twice (CGS2), 2 = CGS2 with the second
  * projection delayed by one step (arnoldi_dcgs2).  P = M^T D: CSR rows pp/pc with u_f values pv (held
@@ -821,7 +866,7 @@ static int arnoldi_dcgs2(int n, const int* rp, const int* ci, const double* av, 
  */
 int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const int* pp,
                     const int* pc, const double* pv, const double* d, int uf, const double* b,
-                    double* x, double tau, int imax, int maxit, double tol_ir, int ortho, int* its,
+                    double* x, double tau, int imax, int maxit, double tol_ir, int ortho, int right, int* its,
                     int* nsteps, double* gest, double* dnorm) {
     if (n <= 0 || imax < 1 || maxit < 1 || ortho < 0 || ortho > 2) return -1;
     int status = 0;
@@ -841,15 +886,17 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
     double* bb = (double*)malloc(sizeof(double) * (size_t)(maxit + 1));
 #define HH(i, j) H[(size_t)(j) * (size_t)(maxit + 1) + (size_t)(i)]
 
-    oracle_x0(n, pp, pc, pv, d, b, uf, x);
+    if (right) oracle_x0_right(n, pp, pc, pv, d, b, uf, x);
+    else oracle_x0(n, pp, pc, pv, d, b, uf, x);
     double dprev = INFINITY;
     int step;
     *nsteps = 0;
     for (step = 0; step < imax; ++step) {
         oracle_residual(n, rp, ci, av, b, x, r);
-        apply_P(n, pp, pc, pv, d, r, dw, z);
+        if (right) memcpy(z, r, sizeof(double) * (size_t)n);   /* GMRES on A P y = r_i */
+        else apply_P(n, pp, pc, pv, d, r, dw, z);              /* GMRES on P A d = P r_i */
         double beta0 = sqrt(dot(n, z, z));
-        if (beta0 == 0.0) break;  /* P r_i = 0: x_i solves the system; no further step */
+        if (beta0 == 0.0) break;  /* the (preconditioned) residual is 0: x_i solves the system */
         its[step] = 0;
         if (gest) gest[step] = 0.0;
         if (dnorm) dnorm[step] = 0.0;
@@ -861,14 +908,13 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
         if (ortho == 2) {
             for (size_t q = 0; q < (size_t)(maxit + 1) * (size_t)maxit; ++q) HR[q] = 0.0;
             int hit = 0;
-            k = arnoldi_dcgs2(n, rp, ci, av, pp, pc, pv, d, V, H, HR, maxit + 1, cs, sn, g, beta0, tau,
+            k = arnoldi_dcgs2(right, n, rp, ci, av, pp, pc, pv, d, V, H, HR, maxit + 1, cs, sn, g, beta0, tau,
                               maxit, w, dw, y, hp, bb, &hit);
             if (hit) status |= IR_MAXIT;
         }
         for (int j = 0; j < maxit && ortho != 2; ++j) {
             double* vj = V + (size_t)j * n;
-            spmv(n, rp, ci, av, vj, w);
-            apply_P(n, pp, pc, pv, d, w, dw, y);
+            apply_op(right, n, rp, ci, av, pp, pc, pv, d, vj, w, dw, y);
             if (ortho == 0) {
                 for (int l = 0; l <= j; ++l) {        /* modified Gram-Schmidt */
                     double* vl = V + (size_t)l * n;
@@ -917,11 +963,19 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
             for (int c2 = c + 1; c2 < k; ++c2) s -= HH(c, c2) * yk[c2];
             yk[c] = s / HH(c, c);
         }
-        /* d = V_k y; x = x + d */
-        double dn = 0.0;
+        /* d = V_k y (left) or d = P V_k y (right); x = x + d */
         for (int i = 0; i < n; ++i) {
             double di = 0.0;
             for (int c = 0; c < k; ++c) di += V[(size_t)c * n + i] * yk[c];
+            w[i] = di;
+        }
+        if (right) {
+            apply_P_right(n, pp, pc, pv, d, w, y);
+            memcpy(w, y, sizeof(double) * (size_t)n);
+        }
+        double dn = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double di = w[i];
             if (fabs(di) > dn) dn = fabs(di);
             x[i] = x[i] + di;
         }

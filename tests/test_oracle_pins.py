@@ -510,3 +510,56 @@ def test_fp32_limiting_accuracy_and_half_vs_single():
     assert abs(tot["fp16"][1] - tot["fp32"][1]) <= 0.25 * tot["fp32"][1] + 2
     with pytest.raises(ValueError):
         O.gmres_ir(w.A, pp, pc, pv, R.d, "fp32", w.b, ir.tau, 1, 5, ir.tol_ir, "dcgs2", "fp32")
+
+
+# ---------------------------------------------------------------------------
+# right preconditioning (GMRES on A P y = r, the paper's future-work variant)
+# ---------------------------------------------------------------------------
+
+def test_right_spai_columns_meet_eps_on_A():
+    """The right build is Algorithm 1 on A itself: with P = D M, column k of
+    A P - I is A D m_k - e_k, whose norm is the column residual the build
+    reports and tests against eps."""
+    w = W.convdiff_small(12)
+    n = w.n
+    R, pp, pc, pv, d = O.spai_right(w.A, None, 0.4, -(-n // 8), 8, 20, "fp64")
+    P = sp.csr_matrix((pv, pc, pp), shape=(n, n)).toarray() * d[:, None]
+    E = _dense(w.A) @ P - np.eye(n)
+    colres = np.linalg.norm(E, axis=0)
+    assert np.allclose(colres, R.res, rtol=1e-9, atol=1e-12)
+    ok = (R.flags & O.FLAG_EPS) == 0
+    assert ok.any() and np.all(colres[ok] <= 0.4 * (1 + 1e-12))
+
+
+def test_right_gmres_step_is_the_krylov_least_squares_minimiser():
+    """Right preconditioning: after k iterations (tau = 0) the correction is
+    d = P y with y = argmin over K_k(A P, r0) of ||r0 - A P y||_2."""
+    rng = np.random.default_rng(31)
+    n = 8
+    Ad = _random_dd(n, rng, density=0.6, dom=0.4)
+    A = _csr(Ad)
+    b = rng.standard_normal(n)
+    R, pp, pc, pv, d = O.spai_right(A, None, 0.6, 0, 8, 8, "fp64")      # a diagonal P
+    P = sp.csr_matrix((pv, pc, pp), shape=(n, n)).toarray() * d[:, None]
+    x0 = O.x0_right(pp, pc, pv, d, b, "fp64")
+    r0 = b - Ad @ x0
+    AP = Ad @ P
+    for ortho in ("mgs", "dcgs2"):
+        for k in range(1, 6):
+            res = O.gmres_ir(A, pp, pc, pv, d, "fp64", b, 0.0, 1, k, 0.0, ortho, side="right")
+            assert res.its == [k]
+            K = np.column_stack([np.linalg.matrix_power(AP, i) @ r0 for i in range(k)])
+            Q, _ = np.linalg.qr(K)
+            y, *_ = np.linalg.lstsq(AP @ Q, r0, rcond=None)
+            dexp = P @ (Q @ y)
+            assert np.abs((res.x - x0) - dexp).max() <= 1e-9 * np.abs(dexp).max()
+
+
+def test_right_exact_preconditioner_takes_one_iteration_per_step():
+    w = W.convdiff_small(10)
+    S = sp.csr_matrix(np.linalg.inv(_dense(w.A)))
+    S.sort_indices()
+    res = O.gmres_ir(w.A, S.indptr, S.indices, S.data, np.ones(w.n), "fp64", w.b, 1e-8, 10, 50, W.TOL_IR,
+                     side="right")
+    assert all(k == 1 for k in res.its)
+    assert O.ferr(res.x, w.x_true) <= 1e-15

@@ -81,12 +81,18 @@ typedef struct {
 
 /* Parameters of Algorithm 1 (its Require line: J, alpha, beta, eps) plus the fill
  * cap of Section 2.2 and the precision u_f of Section 3.1. */
+enum { SPAI_LEFT = 0, SPAI_RIGHT = 1 };
+
 typedef struct {
     double eps;      /* column residual tolerance: stop once ||e_k - B m_k||_2 <= eps */
     int32_t alpha;   /* maximum augmentation steps per column (0 = fixed pattern) */
     int32_t beta;    /* maximum indices added per augmentation step */
     int32_t maxfill; /* cap on |J_k| (never truncates the initial pattern) */
     spai_prec u_f;   /* FP64, FP32, FP16 or BF16 */
+    int32_t side;    /* SPAI_LEFT (0, default): Algorithm 1 on B = A^T D, P = M^T D, the left
+                        preconditioner of Algorithm 3.  SPAI_RIGHT: Algorithm 1 on B = A D with
+                        D = diag(1 / max_i |a_ij|) (columns of A scaled to unit maximum), so that
+                        A P ~ I with P = D M; spai_gmres_ir then preconditions on the right. */
 } spai_build_params;
 
 typedef struct {
@@ -123,6 +129,8 @@ typedef struct {
     const int32_t* steps;
     const double* res;
     const int32_t* flags;
+    int32_t side;          /* SPAI_LEFT: row k holds m_k, P w = M^T (D w); SPAI_RIGHT: row i holds the
+                              entries m_k[i] (columns k ascending), P w = D (M w) */
 } spai_precond_view;
 
 /* Orthogonalisation of the Arnoldi vectors.  Algorithm 3 asks for GMRES; the
@@ -204,7 +212,10 @@ int spai_precond_destroy(spai_precond* P);
  * arithmetic for FP16/BF16), then per refinement step r_i = b - A x_i in u_r
  * (stored FP64), left-preconditioned MGS-GMRES on P A d = P r_i in FP64 with zero
  * initial guess, stopped when the Givens estimate |g_{j+1}| <= tau ||P r_i||_2,
- * and x_{i+1} = x_i + d_i in FP64.  Refinement stops when ||d_i||_inf <= tol_ir
+ * and x_{i+1} = x_i + d_i in FP64.  With a preconditioner built with
+ * side = SPAI_RIGHT the solve preconditions on the right instead (the paper's
+ * future-work variant): GMRES on A P y = r_i stopped when |g_{j+1}| <=
+ * tau ||r_i||_2, d_i = P y (working precision FP64 only).  Refinement stops when ||d_i||_inf <= tol_ir
  * ||x_{i+1}||_inf, after imax steps, from the third step on when ||d_i||_inf >
  * ||d_{i-1}||_inf / 2, or before a step whose P r_i is exactly zero.
  * b and x are device arrays of n FP64 values (x is output only).
@@ -241,7 +252,7 @@ int spai_build_batched(spai_handle* h, const spai_csr* A, int32_t nsys, const in
  * steps, with the semantics of spai_gmres_ir and maxit capped at the system's
  * size), all systems in one persistent launch: each workgroup takes the next
  * system (largest first) and runs its whole refinement loop.  Orthogonalisation
- * is MGS (p->ortho must be SPAI_ORTHO_MGS).  b and x are device arrays of n FP64
+ * is MGS (p->ortho must be SPAI_ORTHO_MGS); P must be a left preconditioner.  b and x are device arrays of n FP64
  * values in the batch's row order; st is a host array of nsys statistics.
  * Device workspace: up to two workgroups per compute unit, each holding
  * n_max (min(maxit, n_max) + 1) + O(maxit^2) doubles for the largest system

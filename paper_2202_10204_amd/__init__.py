@@ -42,7 +42,10 @@ class _Pattern(ctypes.Structure):
 
 class _BuildParams(ctypes.Structure):
     _fields_ = [("eps", _c_f64), ("alpha", _c_i32), ("beta", _c_i32), ("maxfill", _c_i32),
-                ("u_f", ctypes.c_int)]
+                ("u_f", ctypes.c_int), ("side", _c_i32)]
+
+
+SIDE = {"left": 0, "right": 1}
 
 
 class _BuildStats(ctypes.Structure):
@@ -54,7 +57,7 @@ class _BuildStats(ctypes.Structure):
 class _View(ctypes.Structure):
     _fields_ = [("n", _c_i32), ("nnz", _c_i64), ("rowptr", _p), ("col", _p), ("val", _p),
                 ("val_prec", ctypes.c_int), ("d", _p), ("stride", _c_i32), ("j_ins", _p),
-                ("m_ins", _p), ("len", _p), ("steps", _p), ("res", _p), ("flags", _p)]
+                ("m_ins", _p), ("len", _p), ("steps", _p), ("res", _p), ("flags", _p), ("side", _c_i32)]
 
 
 class _IrParams(ctypes.Structure):
@@ -309,9 +312,10 @@ class Handle:
 
     # -- Algorithm 1 ---------------------------------------------------------
     def spai_build(self, A: DeviceCSR, pattern: Optional[DevicePattern], eps: float, alpha: int, beta: int,
-                   maxfill: int, u_f: str = "fp32"):
-        """Returns (Precond, warnings, stats dict)."""
-        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f])
+                   maxfill: int, u_f: str = "fp32", side: str = "left"):
+        """Returns (Precond, warnings, stats dict).  side = "left" (P = M^T D, Algorithm 3)
+        or "right" (P = D M with A P ~ I; the solve then preconditions on the right)."""
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], SIDE[side])
         st = _BuildStats()
         out = ctypes.c_void_p()
         csr = A.c()
@@ -346,7 +350,7 @@ class Handle:
                            beta: int, maxfill: int, u_f: str = "fp32"):
         """Returns (Precond of the whole batch, warnings, stats dict)."""
         sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
-        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f])
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], 0)
         st = _BuildStats()
         out = ctypes.c_void_p()
         csr = A.c()
@@ -420,7 +424,7 @@ def _serve_request(A, b, pattern, build: dict, ir: dict):
         ji = np.ascontiguousarray(pattern.idx, dtype=np.int32)
         keep += [jp, ji]
     bp = _BuildParams(float(build["eps"]), int(build["alpha"]), int(build["beta"]), int(build["maxfill"]),
-                      PREC[build["u_f"]])
+                      PREC[build["u_f"]], SIDE[build.get("side", "left")])
     ip = _IrParams(PREC[ir.get("u_r", "dd")], float(ir["tau"]), int(ir["imax"]), int(ir["maxit"]),
                    float(ir["tol_ir"]), ORTHO[ir.get("ortho", "mgs")], PREC[ir.get("u", "fp64")])
     r = _ServeRequest(int(A.n), int(ci.size), rp.ctypes.data, ci.ctypes.data, av.ctypes.data, bb.ctypes.data,

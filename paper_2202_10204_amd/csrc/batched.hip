@@ -394,6 +394,7 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     SPAI_ARG(prm->tau >= 0.0, "tau must be non-negative");
     SPAI_ARG(prm->u_r == SPAI_DD || prm->u_r == SPAI_FP64, "u_r must be DD or FP64");
     SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS, "the batched solver orthogonalises with MGS");
+    SPAI_ARG(P->side == SPAI_LEFT, "the batched solver applies left preconditioners");
     SPAI_ARG(prm->u == SPAI_FP64 || prm->u == SPAI_FP32, "the working precision u must be FP64 or FP32");
     if (prm->u == SPAI_FP32) {
         SPAI_ARG(prm->u_r == SPAI_FP64, "with working precision FP32 the residual precision must be FP64");

@@ -119,6 +119,7 @@ struct spai_precond {
     double* res = nullptr;      // n (build only)
     int32_t* flags = nullptr;   // n (build only)
     spai::Arena from;             // arena of the building handle (arrays inside it are not freed one by one)
+    int32_t side = SPAI_LEFT;     // SPAI_RIGHT: rows hold m_k[i], applied as D (M w)
 };
 
 namespace spai {

@@ -41,7 +41,8 @@ struct SolveState {
 // ---------------------------------------------------------------------------
 
 // w = A v and y = M^T (D w) (row k of P holds m_k, values in VP, FP64
-// arithmetic) with G lanes per row (G a power of two <= 16): the lanes load the
+// arithmetic; for a right preconditioner row i holds the m_k[i] and y = D (M w))
+// with G lanes per row (G a power of two <= 16): the lanes load the
 // row's entries with unit stride, keep lane-strided partial sums and add them
 // by a fixed xor tree, so every call gives the same bits.  Many more waves than
 // one thread per row, and coalesced loads.
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
     }
 }
 
-template <int VP, int G, int R>
+template <int VP, int G, int R, bool RIGHT>
 __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                                                    const typename ValType<VP>::T* __restrict__ pv,
                                                    const double* __restrict__ d, const double* __restrict__ w,
@@ -103,7 +104,8 @@ __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict_
         double s = 0.0;
         for (int q = q0[r]; q < q1[r]; q += G) {
             const int j = pc[q];
-            s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
+            if constexpr (RIGHT) s = __builtin_fma(to_f64(pv[q]), w[j], s);
+            else s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
         }
         acc[r] = s;
     }
@@ -112,7 +114,10 @@ __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict_
         double s = acc[r];
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
-        if (sub == 0 && row0 + r * GPB < n) y[row0 + r * GPB] = s;
+        if (sub == 0 && row0 + r * GPB < n) {
+            if constexpr (RIGHT) s = d[row0 + r * GPB] * s;   // P = D M: the scaling acts on the output
+            y[row0 + r * GPB] = s;
+        }
     }
 }
 
@@ -125,13 +130,25 @@ static inline int lanes_per_row(long long nnz, int n) {
 }
 
 // x0 = P b in u_f: z_j = u_f(d_j b_j), products and sums in F, ascending column
-template <int VP>
+template <int VP, bool RIGHT>
 __global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                      const typename ValType<VP>::T* __restrict__ pv, const double* __restrict__ d,
                      const double* __restrict__ b, double* __restrict__ x0) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    if constexpr (VP == SPAI_FP64) {
+    if constexpr (RIGHT) {
+        // P = D M: b rounded to u_f, the row's sum in the arithmetic of u_f, times d_k rounded to u_f
+        if constexpr (VP == SPAI_FP64) {
+            double s = 0.0;
+            for (int q = pp[k]; q < pp[k + 1]; ++q) s = __builtin_fma(pv[q], b[pc[q]], s);
+            x0[k] = d[k] * s;
+        } else {
+            float s = 0.0f;
+            for (int q = pp[k]; q < pp[k + 1]; ++q)
+                s = __builtin_fmaf(to_f32(pv[q]), store<VP, float>((float)b[pc[q]]), s);
+            x0[k] = (double)(store<VP, float>((float)d[k]) * s);
+        }
+    } else if constexpr (VP == SPAI_FP64) {
         double s = 0.0;
         for (int q = pp[k]; q < pp[k + 1]; ++q) {
             int j = pc[q];
@@ -1341,6 +1358,38 @@ __global__ void k_update(int n, int k, const double* __restrict__ V, const doubl
     }
 }
 
+// t = V_k y (the correction before the right preconditioner is applied)
+__global__ void k_vy(int n, int k, const double* __restrict__ V, const double* __restrict__ yk,
+                     double* __restrict__ t) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double di = 0.0;
+    for (int c = 0; c < k; ++c) di = di + V[(size_t)c * n + i] * yk[c];
+    t[i] = di;
+}
+
+// x += d; records ||d||_inf and ||x||_inf like k_update
+__global__ void k_add_norms(int n, const double* __restrict__ dv, double* __restrict__ x,
+                            unsigned long long* __restrict__ maxbits) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double dm = 0.0, xm = 0.0;
+    if (i < n) {
+        const double di = dv[i];
+        const double xi = x[i] + di;
+        x[i] = xi;
+        dm = fabs(di);
+        xm = fabs(xi);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        dm = fmax(dm, __shfl_xor(dm, o, 64));
+        xm = fmax(xm, __shfl_xor(xm, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&maxbits[0], (unsigned long long)__double_as_longlong(dm));
+        atomicMax(&maxbits[1], (unsigned long long)__double_as_longlong(xm));
+    }
+}
+
 // g = beta0 e_1; fresh solver state
 __global__ void k_init_state(double* g, int len, const double* beta0, SolveState* st) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1370,16 +1419,16 @@ static int reduce_blocks(int n) {
 constexpr int SPMV_R = 2;
 constexpr int APPLY_R = 4;
 
-template <int VP>
+template <int VP, bool RIGHT>
 static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
                       const SolveState* st) {
     using T = typename ValType<VP>::T;
     const T* pv = (const T*)P->val;
     const long long groups = ((long long)n + APPLY_R - 1) / APPLY_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
-#define SPAI_AP(G)                                                                                                \
-    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R>), dim3(grid), dim3(256), 0, s, n, P->rowptr, P->col, pv, P->d, \
-                       w, y, st)
+#define SPAI_AP(G)                                                                                       \
+    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
+                       P->col, pv, P->d, w, y, st)
     switch (g) {
     case 1: SPAI_AP(1); break;
     case 2: SPAI_AP(2); break;
@@ -1394,11 +1443,24 @@ static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w
                           const SolveState* st = nullptr) {
     const int n = P->n, g = lanes_per_row(P->nnz, n);
     long tk = timer_begin(h, SPAI_KT_APPLY_P);
+    const bool right = P->side == SPAI_RIGHT;
     switch (P->val_prec) {
-    case SPAI_FP64: apply_P_g<SPAI_FP64>(g, n, P, w, y, s, st); break;
-    case SPAI_FP32: apply_P_g<SPAI_FP32>(g, n, P, w, y, s, st); break;
-    case SPAI_FP16: apply_P_g<SPAI_FP16>(g, n, P, w, y, s, st); break;
-    default: apply_P_g<SPAI_BF16>(g, n, P, w, y, s, st); break;
+    case SPAI_FP64:
+        if (right) apply_P_g<SPAI_FP64, true>(g, n, P, w, y, s, st);
+        else apply_P_g<SPAI_FP64, false>(g, n, P, w, y, s, st);
+        break;
+    case SPAI_FP32:
+        if (right) apply_P_g<SPAI_FP32, true>(g, n, P, w, y, s, st);
+        else apply_P_g<SPAI_FP32, false>(g, n, P, w, y, s, st);
+        break;
+    case SPAI_FP16:
+        if (right) apply_P_g<SPAI_FP16, true>(g, n, P, w, y, s, st);
+        else apply_P_g<SPAI_FP16, false>(g, n, P, w, y, s, st);
+        break;
+    default:
+        if (right) apply_P_g<SPAI_BF16, true>(g, n, P, w, y, s, st);
+        else apply_P_g<SPAI_BF16, false>(g, n, P, w, y, s, st);
+        break;
     }
     timer_end(h, SPAI_KT_APPLY_P, tk);
     SPAI_HIP(hipGetLastError());
@@ -1428,12 +1490,23 @@ static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, doubl
 
 static int launch_x0(const spai_precond* P, const double* b, double* x0, hipStream_t s) {
     int n = P->n, g = blocks_for(n, 256);
+#define SPAI_X0(VP, T, R) hipLaunchKernelGGL((k_x0<VP, R>), dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const T*)P->val, P->d, b, x0)
+    const bool right = P->side == SPAI_RIGHT;
     switch (P->val_prec) {
-    case SPAI_FP64: hipLaunchKernelGGL(k_x0<SPAI_FP64>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const double*)P->val, P->d, b, x0); break;
-    case SPAI_FP32: hipLaunchKernelGGL(k_x0<SPAI_FP32>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const float*)P->val, P->d, b, x0); break;
-    case SPAI_FP16: hipLaunchKernelGGL(k_x0<SPAI_FP16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __half*)P->val, P->d, b, x0); break;
-    default: hipLaunchKernelGGL(k_x0<SPAI_BF16>, dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const __hip_bfloat16*)P->val, P->d, b, x0); break;
+    case SPAI_FP64:
+        if (right) { SPAI_X0(SPAI_FP64, double, true); } else { SPAI_X0(SPAI_FP64, double, false); }
+        break;
+    case SPAI_FP32:
+        if (right) { SPAI_X0(SPAI_FP32, float, true); } else { SPAI_X0(SPAI_FP32, float, false); }
+        break;
+    case SPAI_FP16:
+        if (right) { SPAI_X0(SPAI_FP16, __half, true); } else { SPAI_X0(SPAI_FP16, __half, false); }
+        break;
+    default:
+        if (right) { SPAI_X0(SPAI_BF16, __hip_bfloat16, true); } else { SPAI_X0(SPAI_BF16, __hip_bfloat16, false); }
+        break;
     }
+#undef SPAI_X0
     SPAI_HIP(hipGetLastError());
     return SPAI_OK;
 }
@@ -1602,6 +1675,8 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS || prm->ortho == SPAI_ORTHO_CGS2 || prm->ortho == SPAI_ORTHO_DCGS2,
              "ortho must be MGS, CGS2 or DCGS2");
     SPAI_ARG(prm->u == SPAI_FP64 || prm->u == SPAI_FP32, "the working precision u must be FP64 or FP32");
+    const bool right = P->side == SPAI_RIGHT;
+    SPAI_ARG(!right || prm->u == SPAI_FP64, "right preconditioning runs in working precision FP64");
     if (prm->u == SPAI_FP32) {
         // working precision single: the system runs in the batched solver as a batch of one
         SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS, "working precision FP32 orthogonalises with MGS");
@@ -1663,7 +1738,8 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     double dprev = INFINITY;
     for (int step = 0; step < prm->imax; ++step) {
         if ((rc = launch_residual(h, A, b, x, r, prm->u_r, s))) return rc;
-        if ((rc = launch_apply_P(h, P, r, V, s))) return rc;              // z = P r into V(:,0)
+        if (right) SPAI_HIP(hipMemcpyAsync(V, r, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        else if ((rc = launch_apply_P(h, P, r, V, s))) return rc;          // z = P r into V(:,0)
         hipLaunchKernelGGL(k_mgs, dim3(nbr), dim3(RB), 0, s, n, V, (const double*)nullptr,
                            (const double*)nullptr, (const double*)V, scal, partials, ticket, (int)MGS_NORM,
                            (const SolveState*)nullptr);
@@ -1701,8 +1777,13 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
             int j1 = std::min(j0 + chunk, jend);
             for (int j = j0; j < j1; ++j) {
                 double* vj = V + (size_t)j * n;
-                if ((rc = launch_spmv(h, A, vj, w, s, sst))) return rc;
-                if ((rc = launch_apply_P(h, P, w, y, s, sst))) return rc;
+                if (right) {                                               // y = A P v_j
+                    if ((rc = launch_apply_P(h, P, vj, w, s, sst))) return rc;
+                    if ((rc = launch_spmv(h, A, w, y, s, sst))) return rc;
+                } else {                                                   // y = P A v_j
+                    if ((rc = launch_spmv(h, A, vj, w, s, sst))) return rc;
+                    if ((rc = launch_apply_P(h, P, w, y, s, sst))) return rc;
+                }
                 if (cfg.nb) {
                     ArnoldiArgs aa{};
                     aa.n = n; aa.j = j; aa.ld = ld; aa.maxit = maxit; aa.maxlinks = maxlinks; aa.nb = cfg.nb;
@@ -1766,7 +1847,14 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
                                yk);
         SPAI_HIP(hipMemsetAsync(maxbits, 0, 16, s));
         long tu = timer_begin(h, SPAI_KT_UPDATE);
-        hipLaunchKernelGGL(k_update, dim3(gb), dim3(tb), 0, s, n, kk, (const double*)V, (const double*)yk, x, maxbits);
+        if (right) {                                                       // d = P (V_k y)
+            hipLaunchKernelGGL(k_vy, dim3(gb), dim3(tb), 0, s, n, kk, (const double*)V, (const double*)yk, w);
+            if ((rc = launch_apply_P(h, P, w, y, s))) return rc;
+            hipLaunchKernelGGL(k_add_norms, dim3(gb), dim3(tb), 0, s, n, (const double*)y, x, maxbits);
+        } else {
+            hipLaunchKernelGGL(k_update, dim3(gb), dim3(tb), 0, s, n, kk, (const double*)V, (const double*)yk, x,
+                               maxbits);
+        }
         timer_end(h, SPAI_KT_UPDATE, tu);
         SPAI_HIP(hipGetLastError());
         SPAI_HIP(hipMemcpyAsync(hp, maxbits, 16, hipMemcpyDeviceToHost, s));

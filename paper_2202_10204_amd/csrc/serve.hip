@@ -40,7 +40,7 @@ struct Request {
 // Requests that can share one batch: the same build and solve parameters and
 // the same kind of initial pattern.
 bool same_key(const Request& a, const Request& b) {
-    return a.bp.eps == b.bp.eps && a.bp.alpha == b.bp.alpha && a.bp.beta == b.bp.beta &&
+    return a.bp.eps == b.bp.eps && a.bp.alpha == b.bp.alpha && a.bp.beta == b.bp.beta && a.bp.side == b.bp.side &&
            a.bp.maxfill == b.bp.maxfill && a.bp.u_f == b.bp.u_f && a.ip.u_r == b.ip.u_r && a.ip.tau == b.ip.tau &&
            a.ip.imax == b.ip.imax && a.ip.maxit == b.ip.maxit && a.ip.tol_ir == b.ip.tol_ir && a.ip.u == b.ip.u &&
            a.jptr.empty() == b.jptr.empty();
@@ -92,6 +92,7 @@ int check_request(const spai_serve_request* r) {
     SPAI_ARG(p.eps > 0 && p.alpha >= 0 && p.beta >= 0 && p.maxfill >= 1 && p.maxfill <= 63,
              "bad build parameters");
     SPAI_ARG(p.u_f == SPAI_FP64 || p.u_f == SPAI_FP32 || p.u_f == SPAI_FP16 || p.u_f == SPAI_BF16, "bad u_f");
+    SPAI_ARG(p.side == SPAI_LEFT || p.side == SPAI_RIGHT, "bad side");
     const spai_ir_params& q = r->ir;
     SPAI_ARG(q.imax >= 1 && q.imax <= 32 && q.maxit >= 1 && q.tau >= 0, "bad solve parameters");
     SPAI_ARG(q.u_r == SPAI_DD || q.u_r == SPAI_FP64, "bad u_r");
@@ -582,7 +583,8 @@ extern "C" int spai_serve_submit(spai_server* S, const spai_serve_request* r, in
     int rc = spai::check_request(r);
     if (rc) return rc;
     const int64_t fp = spai::footprint_of(r);
-    const bool small = r->n <= S->prm.batch_max_n;
+    // right preconditioners run on the device lane (the batched solver applies left ones)
+    const bool small = r->n <= S->prm.batch_max_n && r->build.side == SPAI_LEFT;
     const int64_t need = fp + spai::UNIT_SLACK + (small ? S->prm.lane_workspace : 0);
     if (need > S->prm.hbm_budget) {
         spai::set_error("request needs " + std::to_string(need) + " bytes of device memory (footprint " +

@@ -831,10 +831,107 @@ static size_t val_size(spai_prec v) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// CSR transpose (for the right preconditioner): entries are counted per column,
+// placed by per-column cursors and each output row is then sorted by column,
+// so the result is the unique sorted CSR of the transpose.
+// ---------------------------------------------------------------------------
+
+__global__ void k_check_rows(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+                             int* __restrict__ cnt, int* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = rp[i], e = rp[i + 1];
+    if (a < 0 || e < a || e > nnz || (i == 0 && a != 0) || (i == n - 1 && e != nnz)) {
+        atomicOr(bad, 1);
+        return;
+    }
+    for (int q = a; q < e; ++q) {
+        const int c = ci[q];
+        if (c < 0 || c >= n) atomicOr(bad, 1);
+        else atomicAdd(&cnt[c], 1);
+    }
+}
+
+template <typename T>
+__global__ void k_scatter_t(int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ v,
+                            int* __restrict__ cursor, int* __restrict__ oc, T* __restrict__ ov) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) {
+        const int pos = atomicAdd(&cursor[ci[q]], 1);
+        oc[pos] = i;
+        ov[pos] = v[q];
+    }
+}
+
+template <typename T>
+__global__ void k_sort_rows(int n, const int* __restrict__ ptr, int* __restrict__ c, T* __restrict__ v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a0 = ptr[i], e = ptr[i + 1];
+    for (int a = a0 + 1; a < e; ++a) {
+        const int key = c[a];
+        const T val = v[a];
+        int b = a - 1;
+        while (b >= a0 && c[b] > key) {
+            c[b + 1] = c[b];
+            v[b + 1] = v[b];
+            --b;
+        }
+        c[b + 1] = key;
+        v[b + 1] = val;
+    }
+}
+
+// (orp, oci, ov) = transpose of the n x n CSR (rp, ci, v); SPAI_E_ARG for a
+// malformed input (checked on the device before anything is placed).
+template <typename T>
+static int csr_transpose(spai_handle* h, int n, int nnz, const int* rp, const int* ci, const T* v, int* orp,
+                         int* oci, T* ov) {
+    hipStream_t s = h->stream;
+    const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1;
+    int* tmp = nullptr;
+    int rc = dev_alloc(h, &tmp, 2 * (size_t)n + nb + 64);
+    if (rc) return rc;
+    int* cnt = tmp;
+    int* cur = cnt + n + 1;
+    int* blk = cur + n;
+    int* tot = blk + nb;
+    int* bad = tot + 8;
+    const int g = (n + 255) / 256;
+    auto done = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        dev_free(tmp, h->arena);
+        return code;
+    };
+    if (hipMemsetAsync(cnt, 0, 4 * ((size_t)n + 1), s) != hipSuccess || hipMemsetAsync(bad, 0, 4, s) != hipSuccess)
+        return done(SPAI_E_HIP);
+    hipLaunchKernelGGL(k_check_rows, dim3(g), dim3(256), 0, s, n, nnz, rp, ci, cnt, bad);
+    int hbad = 0;
+    if (hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return done(SPAI_E_HIP);
+    if (hbad) {
+        set_error("invalid argument: malformed CSR (row pointers or column indices out of range)");
+        return done(SPAI_E_ARG);
+    }
+    if ((rc = scan_ints(n, cnt, orp, blk, tot, s))) return done(rc);
+    if (hipMemcpyAsync(cur, orp, 4 * (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess) return done(SPAI_E_HIP);
+    hipLaunchKernelGGL((k_scatter_t<T>), dim3(g), dim3(256), 0, s, n, rp, ci, v, cur, oci, ov);
+    hipLaunchKernelGGL((k_sort_rows<T>), dim3(g), dim3(256), 0, s, n, (const int*)orp, oci, ov);
+    if (hipGetLastError() != hipSuccess) return done(SPAI_E_HIP);
+    return done(SPAI_OK);
+}
+
+static int build_right(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+                       spai_precond** P_out, spai_build_stats* st);
+
 int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
                spai_precond** P_out, spai_build_stats* st) {
     SPAI_ARG(h && A && p && P_out, "NULL handle, matrix, parameters or output");
     *P_out = nullptr;
+    SPAI_ARG(p->side == SPAI_LEFT || p->side == SPAI_RIGHT, "side must be SPAI_LEFT or SPAI_RIGHT");
     const int n = A->n;
     SPAI_ARG(n > 0, "n must be positive");
     SPAI_ARG(A->nnz >= n && A->rowptr && A->col && A->val, "matrix arrays missing or nnz < n");
@@ -846,6 +943,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     if (J) {
         SPAI_ARG(J->n == n && J->ptr && J->idx && J->nnz >= n, "pattern does not match the matrix");
     }
+    if (p->side == SPAI_RIGHT) return build_right(h, A, J, p, P_out, st);
     hipStream_t s = h->stream;
     SPAI_HIP(hipSetDevice(h->device));
     const int nnz = A->nnz;
@@ -1006,6 +1104,72 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     return warn;
 }
 
+// The right preconditioner: the left build of A^T gives rows m_k with
+// A D m_k ~ e_k (D from the rows of A^T, i.e. the columns of A); P = D M is the
+// transpose of that CSR with D applied to the output.
+static int build_right(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+                       spai_precond** P_out, spai_build_stats* st) {
+    const int n = A->n, nnz = A->nnz;
+    SPAI_ARG(n > 0 && nnz >= n && A->rowptr && A->col && A->val, "matrix arrays missing or nnz < n");
+    SPAI_HIP(hipSetDevice(h->device));
+    int *trp = nullptr, *tci = nullptr;
+    double* tv = nullptr;
+    int rc;
+    auto free_t = [&]() {
+        (void)hipStreamSynchronize(h->stream);
+        dev_free(trp, h->arena);
+        dev_free(tci, h->arena);
+        dev_free(tv, h->arena);
+    };
+    if ((rc = dev_alloc(h, &trp, (size_t)n + 1)) || (rc = dev_alloc(h, &tci, (size_t)nnz)) ||
+        (rc = dev_alloc(h, &tv, (size_t)nnz))) {
+        free_t();
+        return rc;
+    }
+    if ((rc = csr_transpose<double>(h, n, nnz, A->rowptr, A->col, A->val, trp, tci, tv))) {
+        free_t();
+        return rc;
+    }
+    spai_csr At{n, nnz, trp, tci, tv};
+    spai_build_params pl = *p;
+    pl.side = SPAI_LEFT;
+    spai_precond* P = nullptr;
+    const int warn = build_impl(h, &At, J, &pl, &P, st);
+    free_t();
+    if (warn < 0) return warn;
+    // transpose the rows m_k into rows i of P = D M
+    int *prp = nullptr, *pci = nullptr;
+    void* pv = nullptr;
+    const int pnz = (int)P->nnz;
+    auto fail = [&](int code) {
+        (void)hipStreamSynchronize(h->stream);
+        dev_free(prp, h->arena);
+        dev_free(pci, h->arena);
+        dev_free(pv, h->arena);
+        precond_free(P);
+        return code;
+    };
+    if ((rc = dev_alloc(h, &prp, (size_t)n + 1)) || (rc = dev_alloc(h, &pci, (size_t)pnz)) ||
+        (rc = dev_malloc(h, &pv, val_size(P->val_prec) * (size_t)std::max(pnz, 1))))
+        return fail(rc);
+    switch (P->val_prec) {
+    case SPAI_FP64: rc = csr_transpose<double>(h, n, pnz, P->rowptr, P->col, (const double*)P->val, prp, pci, (double*)pv); break;
+    case SPAI_FP32: rc = csr_transpose<float>(h, n, pnz, P->rowptr, P->col, (const float*)P->val, prp, pci, (float*)pv); break;
+    default: rc = csr_transpose<uint16_t>(h, n, pnz, P->rowptr, P->col, (const uint16_t*)P->val, prp, pci, (uint16_t*)pv); break;
+    }
+    if (rc) return fail(rc);
+    SPAI_HIP(hipStreamSynchronize(h->stream));
+    dev_free(P->rowptr, P->from);
+    dev_free(P->col, P->from);
+    dev_free(P->val, P->from);
+    P->rowptr = prp;
+    P->col = pci;
+    P->val = pv;
+    P->side = SPAI_RIGHT;
+    *P_out = P;
+    return warn;
+}
+
 int precond_import_impl(spai_handle* h, int32_t n, int64_t nnz, const int32_t* rowptr,
                         const int32_t* col, const double* val, spai_prec vp, const double* d,
                         spai_precond** P_out);
@@ -1097,6 +1261,7 @@ extern "C" int spai_precond_view_get(const spai_precond* P, spai_precond_view* v
     v->steps = P->steps;
     v->res = P->res;
     v->flags = P->flags;
+    v->side = P->side;
     return SPAI_OK;
 }
 

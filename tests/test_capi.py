@@ -68,7 +68,8 @@ def test_bad_parameters_are_rejected_before_any_device_work(lib):
     A = S._Csr(4, 4, 8, 8, 8)
     for bad in (S._BuildParams(0.0, 1, 8, 20, S.FP32), S._BuildParams(0.3, -1, 8, 20, S.FP32),
                 S._BuildParams(0.3, 1, 8, 0, S.FP32), S._BuildParams(0.3, 1, 8, 64, S.FP32),
-                S._BuildParams(0.3, 1, 8, 20, 7)):
+                S._BuildParams(0.3, 1, 8, 20, 7), S._BuildParams(0.3, 1, 8, 20, S.FP32, 2),
+                S._BuildParams(0.0, 1, 8, 20, S.FP32, 1), S._BuildParams(0.3, 1, 8, 64, S.FP32, 1)):
         assert L.spai_build(fake_handle, ctypes.byref(A), None, ctypes.byref(bad), ctypes.byref(out), None) == S.E_ARG
     assert out.value is None
 

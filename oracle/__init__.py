@@ -64,7 +64,7 @@ def _lib():
         L.oracle_spai.argtypes = [i32, P, P, P, P, P, f64, i32, i32, i32, i32, P, i32, i32, i32,
                                   P, P, P, P, P, P, P, P, P, P]
         L.oracle_spai_probe.restype = i32
-        L.oracle_spai_probe.argtypes = [i32, P, P, P, i32, P, i32, i32, i32, P, P, P, P, P, P, P,
+        L.oracle_spai_probe.argtypes = [i32, P, P, P, i32, P, i32, P, i32, i32, i32, P, P, P, P, P, P, P,
                                         P, P]
         L.oracle_gmres_ir.restype = i32
         L.oracle_gmres_ir.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64,
@@ -218,9 +218,12 @@ class Probe:
     flags: int
 
 
-def spai_probe(A, k: int, J, uf: str, cap: int = 4096) -> Probe:
-    """One solve + candidate scoring step of Algorithm 1 for column k and a given J."""
+def spai_probe(A, k: int, J, uf: str, cap: int = 4096, Iprev=None) -> Probe:
+    """One solve + candidate scoring step of Algorithm 1 for column k and a given J.
+    ``Iprev``: the shadow of the previous solve of the column, in its order (its rows
+    keep their places, the new rows follow ascending); None for a first solve."""
     J = _i32(J)
+    Ip = _i32(Iprev if Iprev is not None else np.zeros(0, np.int32))
     res = np.zeros(1)
     I = np.zeros(cap, np.int32)
     m = np.zeros(1, np.int32)
@@ -231,7 +234,7 @@ def spai_probe(A, k: int, J, uf: str, cap: int = 4096) -> Probe:
     rbar = np.zeros(1)
     flags = np.zeros(1, np.int32)
     rp, ci, av = _i32(A.rowptr), _i32(A.col), _f64(A.val)
-    rc = _lib().oracle_spai_probe(A.n, _p(rp), _p(ci), _p(av), int(k), _p(J), len(J), UF[uf], cap,
+    rc = _lib().oracle_spai_probe(A.n, _p(rp), _p(ci), _p(av), int(k), _p(J), len(J), _p(Ip), len(Ip), UF[uf], cap,
                                   _p(res), _p(I), _p(m), _p(mbar), _p(cj), _p(crho), _p(nc),
                                   _p(rbar), _p(flags))
     if rc != 0:

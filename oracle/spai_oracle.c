@@ -166,15 +166,6 @@ static int sort_unique(int* v, int len) {
     return w;
 }
 
-static int find_sorted(const int* v, int len, int key) {
-    int lo = 0, hi = len - 1;
-    while (lo <= hi) {
-        int mid = (lo + hi) / 2;
-        if (v[mid] == key) return mid;
-        if (v[mid] < key) lo = mid + 1; else hi = mid - 1;
-    }
-    return -1;
-}
 
 typedef struct { double rho; int j; } cand_t;
 
@@ -192,7 +183,8 @@ static int cmp_cand(const void* a, const void* b) {
 
 typedef struct {
     int cap_e;       /* capacity for index gathers */
-    int* Ibuf;       /* shadow I (sorted) */
+    int* Ibuf;       /* shadow I in insertion order (see column_solve) */
+    int* Tbuf;       /* scratch for the rows of the new columns */
     int* Cbuf;       /* candidates */
     double* A0;      /* gathered A-bar, column-major m x p (kept for the residual) */
     double* Aw;      /* working copy for QR, m x (p+1): last column e-bar */
@@ -207,6 +199,7 @@ static void work_reserve(work_t* W, int m, int p, int e) {
     if (e > W->cap_e) {
         W->cap_e = e * 2;
         W->Ibuf = (int*)realloc(W->Ibuf, sizeof(int) * (size_t)W->cap_e);
+        W->Tbuf = (int*)realloc(W->Tbuf, sizeof(int) * (size_t)W->cap_e);
         W->Cbuf = (int*)realloc(W->Cbuf, sizeof(int) * (size_t)W->cap_e);
         W->cand = (cand_t*)realloc(W->cand, sizeof(cand_t) * (size_t)W->cap_e);
     }
@@ -223,7 +216,7 @@ static void work_reserve(work_t* W, int m, int p, int e) {
 }
 
 static void work_free(work_t* W) {
-    free(W->Ibuf); free(W->Cbuf); free(W->cand); free(W->A0); free(W->Aw);
+    free(W->Ibuf); free(W->Tbuf); free(W->Cbuf); free(W->cand); free(W->A0); free(W->Aw);
     free(W->s); free(W->Rd); free(W->mb);
 }
 
@@ -243,9 +236,16 @@ typedef struct {
 
 static double dmin(double a, double b) { return a < b ? a : b; }
 
+/* position of key in the shadow list I (insertion order), or -1 */
+static int find_pos(const int* I, int m, int key) {
+    for (int t = 0; t < m; ++t)
+        if (I[t] == key) return t;
+    return -1;
+}
+
 /* Solve the reduced least-squares problem (eq. redprob) for the current J by
  * Householder QR (Algorithm 1, QR and solve lines) and return res^2.
- * I (sorted, length m) and J (insertion order, length p) are given. */
+ * I (insertion order, length m) and J (insertion order, length p) are given. */
 static double ls_solve(const prep_t* P, int k, const int* I, int m, const int* J, int p,
                        work_t* W, int uf, int* flags, int* kin) {
     double* A0 = W->A0;
@@ -255,12 +255,12 @@ static double ls_solve(const prep_t* P, int k, const int* I, int m, const int* J
         int j = J[c];
         for (int i = 0; i < m; ++i) A0[(size_t)c * m + i] = 0.0;
         for (int t = P->rp[j]; t < P->rp[j + 1]; ++t) {
-            int pos = find_sorted(I, m, P->ci[t]);
+            int pos = find_pos(I, m, P->ci[t]);
             A0[(size_t)c * m + pos] = RS(P->d[j] * P->av[t]);
         }
     }
     memcpy(A, A0, sizeof(double) * (size_t)m * (size_t)p);
-    int kpos = find_sorted(I, m, k);
+    int kpos = find_pos(I, m, k);
     *kin = kpos >= 0;
     for (int i = 0; i < m; ++i) A[(size_t)p * m + i] = (i == kpos) ? 1.0 : 0.0;
 
@@ -320,18 +320,29 @@ static double ls_solve(const prep_t* P, int k, const int* I, int m, const int* J
 }
 
 /* Shadow and reduced least-squares solve for the current J (lines computing I_k,
- * A-bar, e-bar, QR, m-bar and s-bar in Algorithm 1).  Leaves I in W->Ibuf (m
- * entries), m-bar in W->mb and s-bar in W->s; returns res^2 = ||e_k - B m_k||^2. */
-static double column_solve(const prep_t* P, int k, const int* J, int p, work_t* W, int uf,
+ * A-bar, e-bar, QR, m-bar and s-bar in Algorithm 1).  The shadow is kept in
+ * insertion order: the first m_prev entries of W->Ibuf (the shadow of the
+ * previous solve of this column, 0 at the first solve) stay where they are and
+ * the rows that the new columns bring in follow in ascending order.  With this
+ * row order the Householder reflectors of the columns already factored are
+ * unchanged by an augmentation (those columns are zero in the new rows), so the
+ * full QR below is exactly what an incremental update of the previous QR
+ * computes (the remark on updating the QR in Section 2.2).  Leaves I in W->Ibuf
+ * (m entries), m-bar in W->mb and s-bar in W->s; returns
+ * res^2 = ||e_k - B m_k||^2. */
+static double column_solve(const prep_t* P, int k, const int* J, int p, work_t* W, int uf, int m_prev,
                            int* m_out, int* kin, int* flags) {
     /* shadow I_k = rows touched by the columns J_k (structural; no stored zeros) */
     int ecount = 0;
     for (int c = 0; c < p; ++c) ecount += P->rp[J[c] + 1] - P->rp[J[c]];
     work_reserve(W, ecount + 1, p + 1, ecount + 1);
-    int m = 0;
+    int nt = 0;
     for (int c = 0; c < p; ++c)
-        for (int t = P->rp[J[c]]; t < P->rp[J[c] + 1]; ++t) W->Ibuf[m++] = P->ci[t];
-    m = sort_unique(W->Ibuf, m);
+        for (int t = P->rp[J[c]]; t < P->rp[J[c] + 1]; ++t) W->Tbuf[nt++] = P->ci[t];
+    nt = sort_unique(W->Tbuf, nt);
+    int m = m_prev;
+    for (int t = 0; t < nt; ++t)
+        if (find_pos(W->Ibuf, m_prev, W->Tbuf[t]) < 0) W->Ibuf[m++] = W->Tbuf[t];
     work_reserve(W, m + 1, p + 1, ecount + 1);
     *m_out = m;
     return ls_solve(P, k, W->Ibuf, m, J, p, W, uf, flags, kin);
@@ -372,7 +383,7 @@ static int column_score(const prep_t* P, int k, const int* J, int p, int m, int 
         for (int q = P->rp[j]; q < P->rp[j + 1]; ++q) {
             int i = P->ci[q];
             double ri;
-            int pos = find_sorted(W->Ibuf, m, i);
+            int pos = find_pos(W->Ibuf, m, i);
             if (pos >= 0) ri = W->s[pos];
             else if (i == k) ri = -1.0;  /* k outside the shadow */
             else continue;               /* row not in L */
@@ -404,9 +415,10 @@ static void spai_column(const prep_t* P, int k, const int* J0, int len0, double 
     info->flags = 0;
     info->margin = INFINITY;
     info->steps = 0;
+    int m = 0;
     for (int step = 0;; ++step) {
-        int m = 0, kin = 0;
-        double res2 = column_solve(P, k, J, p, W, uf, &m, &kin, &info->flags);
+        int kin = 0;
+        double res2 = column_solve(P, k, J, p, W, uf, m, &m, &kin, &info->flags);
         double res = FSQRT(res2);
         if (hist && step < hcap) hist[step] = res;
         info->res = res;
@@ -443,19 +455,24 @@ static void spai_column(const prep_t* P, int k, const int* J0, int len0, double 
 
 /*
  * One solve and scoring step of Algorithm 1 for column k with the given J (insertion
- * order), for tests.  Outputs: res, I (sorted, *m entries, capacity cap), m-bar (p
+ * order) and the shadow of the previous solve Iprev (mprev rows, 0 for a first
+ * solve), for tests.  Outputs: res, I (sorted, *m entries, capacity cap), m-bar (p
  * entries), candidates cj/crho (*nc entries, ascending j, capacity cap) and rho-bar.
  * Returns 0, or -1 when a capacity is too small.
  */
 int oracle_spai_probe(int n, const int* rp, const int* ci, const double* av, int k, const int* J,
-                      int p, int uf, int cap, double* res, int* I, int* m, double* mbar, int* cj,
-                      double* crho, int* nc, double* rbar, int* flags) {
+                      int p, const int* Iprev, int mprev, int uf, int cap, double* res, int* I, int* m,
+                      double* mbar, int* cj, double* crho, int* nc, double* rbar, int* flags) {
     prep_t P;
     prep_build(&P, n, rp, ci, av, uf);
     work_t W;
     memset(&W, 0, sizeof(W));
     int kin = 0, mm = 0, fl = 0;
-    double res2 = column_solve(&P, k, J, p, &W, uf, &mm, &kin, &fl);
+    int ecount = mprev;
+    for (int c = 0; c < p; ++c) ecount += rp[J[c] + 1] - rp[J[c]];
+    work_reserve(&W, ecount + 1, p + 1, ecount + 1);
+    for (int t = 0; t < mprev; ++t) W.Ibuf[t] = Iprev[t];   /* shadow of the previous solve, in order */
+    double res2 = column_solve(&P, k, J, p, &W, uf, mprev, &mm, &kin, &fl);
     int rc = 0;
     *res = FSQRT(res2);
     *m = mm;

@@ -307,9 +307,15 @@ def test_selection_rule_and_invariants(uf):
         hist = R.hist[k][~np.isnan(R.hist[k])]
         assert len(hist) == R.steps[k] + 1
         assert np.all(np.diff(hist) <= 1e3 * u)
+        Iprev = None
         for step in range(R.steps[k]):
-            pr = O.spai_probe(A, k, Jk[:pos], uf)
+            pr = O.spai_probe(A, k, Jk[:pos], uf, Iprev=Iprev)
             assert pr.res == hist[step] and pr.res > s.eps
+            # the shadow grows in insertion order: the previous rows keep their places
+            if Iprev is not None:
+                assert list(pr.I[:len(Iprev)]) == list(Iprev)
+                assert list(pr.I[len(Iprev):]) == sorted(pr.I[len(Iprev):])
+            Iprev = pr.I
             acc = sorted([(rho, j) for j, rho in zip(pr.cand, pr.rho) if rho <= pr.rbar])
             nsel = min(s.beta, len(acc), s.maxfill - pos)
             assert Jk[pos:pos + nsel] == [j for _, j in acc[:nsel]]

@@ -256,7 +256,7 @@ def run_serve(S, W, args):
 
     def one_pass(u_f_override=None):
         srv = S.Server(batch_lanes=args.lanes, batch_max_n=args.batch_max_n, batch_max_systems=1024,
-                       hbm_budget=args.budget_gib << 30)
+                       hbm_budget=args.budget_gib << 30, sjf_age_ms=args.sjf_age_ms)
         reqs = []
         for w in ws:
             s, ir = w.spai, w.ir
@@ -317,7 +317,9 @@ def run_serve(S, W, args):
                                f"logU[32,512] adaptive, 3D aniso side logU[10,128] pattern(A^2)<=27, random banded n "
                                f"logU[1e3,2e4] adaptive; u_f FP16/FP32 50/50; u FP64, u_r DD",
                    "requests": len(trace), "batch_lanes": args.lanes, "batch_max_n": args.batch_max_n,
-                   "hbm_budget_gib": args.budget_gib, "device_lane_arnoldi": args.ortho},
+                   "hbm_budget_gib": args.budget_gib, "device_lane_arnoldi": args.ortho,
+                   "device_lane_order": f"smallest first, age limit {args.sjf_age_ms} ms" if args.sjf_age_ms
+                   else "arrival"},
         "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed": mixed,
     }
     if args.serve_fp64:
@@ -394,6 +396,9 @@ def main():
     ap.add_argument("--batch-max-n", type=int, default=20000, help="serve: largest batched system")
     ap.add_argument("--budget-gib", type=int, default=128, help="serve: device memory budget in GiB")
     ap.add_argument("--serve-fp64", action="store_true", help="serve: run the stream again with u_f = FP64")
+    ap.add_argument("--sjf-age-ms", type=int, default=2000,
+                    help="serve: device lane serves the smallest waiting system first unless the oldest waited "
+                         "longer than this (0: arrival order)")
     ap.add_argument("--ortho", default="dcgs2", choices=["mgs", "cgs2", "dcgs2"],
                     help="Arnoldi orthogonalisation (all three give the oracle's iteration tuple)")
     ap.add_argument("--profile-run", action="store_true",

@@ -93,6 +93,13 @@ typedef struct {
                         preconditioner of Algorithm 3.  SPAI_RIGHT: Algorithm 1 on B = A D with
                         D = diag(1 / max_i |a_ij|) (columns of A scaled to unit maximum), so that
                         A P ~ I with P = D M; spai_gmres_ir then preconditions on the right. */
+    int32_t qr_update; /* 0 (default): each augmentation step factors the reduced problem from
+                          scratch; 1: the QR of the previous step is updated (its reflectors
+                          are applied to the new columns only, Section 2.2's remark), which
+                          keeps the factorisation in LDS through the candidate phase: fewer
+                          operations, less LDS left for other columns.  Both give the same
+                          bits (the shadow rows are kept in insertion order, so the columns
+                          factored earlier are zero in the rows an augmentation adds). */
 } spai_build_params;
 
 typedef struct {
@@ -309,7 +316,8 @@ int spai_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y);
  *     takes the next batch at once, so arrivals join the device while other
  *     batches are still running.
  *   - one device lane runs larger systems one at a time with spai_build and
- *     spai_gmres_ir (the request's ortho).  Its Arnoldi launches synchronise
+ *     spai_gmres_ir (the request's ortho), in arrival order or smallest first
+ *     (sjf_age_ms).  Its Arnoldi launches synchronise
  *     across the whole grid and need every workgroup resident, so while that
  *     solve runs no batch starts (running batches finish first); builds
  *     overlap freely.
@@ -331,7 +339,8 @@ typedef struct {
     int32_t batch_lanes;       /* concurrent batch lanes, 1..16 */
     int32_t batch_max_n;       /* systems up to this size are batched; larger ones use the device lane */
     int32_t batch_max_systems; /* systems per batch, >= 1 */
-    int32_t pad;
+    int32_t sjf_age_ms;        /* device lane order: 0 = arrival order; > 0 = smallest waiting system
+                                  first unless the oldest has waited longer than this many ms */
     int64_t hbm_budget;        /* device bytes of the server's arena (allocated at creation) */
     int64_t lane_workspace;    /* batched-solver workspace of a batch in bytes (0: min(8 GiB,
                                   hbm_budget / 4 / batch_lanes)) */

@@ -42,7 +42,7 @@ class _Pattern(ctypes.Structure):
 
 class _BuildParams(ctypes.Structure):
     _fields_ = [("eps", _c_f64), ("alpha", _c_i32), ("beta", _c_i32), ("maxfill", _c_i32),
-                ("u_f", ctypes.c_int), ("side", _c_i32)]
+                ("u_f", ctypes.c_int), ("side", _c_i32), ("qr_update", _c_i32)]
 
 
 SIDE = {"left": 0, "right": 1}
@@ -74,7 +74,7 @@ class _IrStats(ctypes.Structure):
 
 
 class _ServeParams(ctypes.Structure):
-    _fields_ = [("batch_lanes", _c_i32), ("batch_max_n", _c_i32), ("batch_max_systems", _c_i32), ("pad", _c_i32),
+    _fields_ = [("batch_lanes", _c_i32), ("batch_max_n", _c_i32), ("batch_max_systems", _c_i32), ("sjf_age_ms", _c_i32),
                 ("hbm_budget", _c_i64), ("lane_workspace", _c_i64)]
 
 
@@ -312,10 +312,12 @@ class Handle:
 
     # -- Algorithm 1 ---------------------------------------------------------
     def spai_build(self, A: DeviceCSR, pattern: Optional[DevicePattern], eps: float, alpha: int, beta: int,
-                   maxfill: int, u_f: str = "fp32", side: str = "left"):
+                   maxfill: int, u_f: str = "fp32", side: str = "left", qr_update: bool = False):
         """Returns (Precond, warnings, stats dict).  side = "left" (P = M^T D, Algorithm 3)
-        or "right" (P = D M with A P ~ I; the solve then preconditions on the right)."""
-        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], SIDE[side])
+        or "right" (P = D M with A P ~ I; the solve then preconditions on the right);
+        qr_update: update each column's QR across augmentation steps (same results)."""
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], SIDE[side],
+                           int(bool(qr_update)))
         st = _BuildStats()
         out = ctypes.c_void_p()
         csr = A.c()
@@ -347,10 +349,10 @@ class Handle:
 
     # -- batches of independent systems (block-diagonal A, host sys_ptr) ------
     def spai_build_batched(self, A: DeviceCSR, sys_ptr, pattern: Optional[DevicePattern], eps: float, alpha: int,
-                           beta: int, maxfill: int, u_f: str = "fp32"):
+                           beta: int, maxfill: int, u_f: str = "fp32", qr_update: bool = False):
         """Returns (Precond of the whole batch, warnings, stats dict)."""
         sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
-        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], 0)
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], 0, int(bool(qr_update)))
         st = _BuildStats()
         out = ctypes.c_void_p()
         csr = A.c()
@@ -445,11 +447,11 @@ class Server:
     """The library's request loop on the current device (see spai_serve_* in include/spai.h)."""
 
     def __init__(self, batch_lanes: int = 3, batch_max_n: int = 20000, batch_max_systems: int = 1024,
-                 hbm_budget: int = 64 << 30, lane_workspace: int = 0):
+                 hbm_budget: int = 64 << 30, lane_workspace: int = 0, sjf_age_ms: int = 0):
         if not torch.cuda.is_available():
             raise SpaiError("no GPU available: libspai runs on the device only")
-        prm = _ServeParams(int(batch_lanes), int(batch_max_n), int(batch_max_systems), 0, int(hbm_budget),
-                           int(lane_workspace))
+        prm = _ServeParams(int(batch_lanes), int(batch_max_n), int(batch_max_systems), int(sjf_age_ms),
+                           int(hbm_budget), int(lane_workspace))
         raw = ctypes.c_void_p()
         _check(lib().spai_serve_create(ctypes.byref(prm), ctypes.byref(raw)), "spai_serve_create")
         self._raw = raw

@@ -41,6 +41,7 @@ struct Request {
 // the same kind of initial pattern.
 bool same_key(const Request& a, const Request& b) {
     return a.bp.eps == b.bp.eps && a.bp.alpha == b.bp.alpha && a.bp.beta == b.bp.beta && a.bp.side == b.bp.side &&
+           a.bp.qr_update == b.bp.qr_update &&
            a.bp.maxfill == b.bp.maxfill && a.bp.u_f == b.bp.u_f && a.ip.u_r == b.ip.u_r && a.ip.tau == b.ip.tau &&
            a.ip.imax == b.ip.imax && a.ip.maxit == b.ip.maxit && a.ip.tol_ir == b.ip.tol_ir && a.ip.u == b.ip.u &&
            a.jptr.empty() == b.jptr.empty();
@@ -93,6 +94,7 @@ int check_request(const spai_serve_request* r) {
              "bad build parameters");
     SPAI_ARG(p.u_f == SPAI_FP64 || p.u_f == SPAI_FP32 || p.u_f == SPAI_FP16 || p.u_f == SPAI_BF16, "bad u_f");
     SPAI_ARG(p.side == SPAI_LEFT || p.side == SPAI_RIGHT, "bad side");
+    SPAI_ARG(p.qr_update == 0 || p.qr_update == 1, "bad qr_update");
     const spai_ir_params& q = r->ir;
     SPAI_ARG(q.imax >= 1 && q.imax <= 32 && q.maxit >= 1 && q.tau >= 0, "bad solve parameters");
     SPAI_ARG(q.u_r == SPAI_DD || q.u_r == SPAI_FP64, "bad u_r");
@@ -486,17 +488,26 @@ bool take_batch(spai_server* S, int lane, Unit& u) {
     return true;
 }
 
+// The device lane serves the oldest large request, or, with a positive
+// age limit, the smallest waiting one (shortest job first: one large system
+// holds the whole device for its solve) unless the oldest has waited longer
+// than the limit.
 bool take_large(spai_server* S, Unit& u) {
     if (S->large.empty()) return false;
-    Request* r = S->large.front();
+    const double now = seconds_since(S->t0);
+    auto pick = S->large.begin();
+    if (S->prm.sjf_age_ms > 0 && now - (*pick)->res.t_submit <= 1e-3 * S->prm.sjf_age_ms)
+        for (auto it = S->large.begin(); it != S->large.end(); ++it)
+            if ((*it)->n < (*pick)->n) pick = it;
+    Request* r = *pick;
     const int64_t need = r->res.footprint + UNIT_SLACK;
     if (need > S->regions.largest()) return false;
-    r->res.t_admit = seconds_since(S->t0);
+    r->res.t_admit = now;
     r->res.lane = -1;
     u.rs.push_back(r);
     u.size = need;
     u.off = S->regions.take(need);
-    S->large.pop_front();
+    S->large.erase(pick);
     return true;
 }
 
@@ -551,6 +562,7 @@ extern "C" int spai_serve_create(const spai_serve_params* p, spai_server** out) 
     SPAI_ARG(p->batch_lanes >= 1 && p->batch_lanes <= spai::MAX_LANES, "batch_lanes outside 1..16");
     SPAI_ARG(p->batch_max_n >= 1 && p->batch_max_systems >= 1, "batch_max_n and batch_max_systems must be >= 1");
     SPAI_ARG(p->hbm_budget > 0 && p->lane_workspace >= 0, "bad budget");
+    SPAI_ARG(p->sjf_age_ms >= 0, "sjf_age_ms must be non-negative");
     spai_serve_params prm = *p;
     if (prm.lane_workspace == 0)
         prm.lane_workspace = std::min<int64_t>(8ll << 30, prm.hbm_budget / 4 / prm.batch_lanes);

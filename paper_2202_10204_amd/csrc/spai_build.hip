@@ -191,6 +191,7 @@ struct ColArgs {
     int* nI;
     int* defer_list;
     int* defer_count;
+    int qr_update;      // keep each column's QR across augmentation steps (same results)
 };
 
 template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_>
@@ -206,24 +207,47 @@ struct Cfg {
     static constexpr int PPW = 64 / G_;    // problems per wavefront
 };
 
-template <class C>
-struct alignas(16) Smem {
+// A-bar (columns in J order, Householder vectors below the diagonal, R above)
+// and e-bar in column p, and the candidate arrays.  When the QR is updated across
+// augmentation steps (INC) the factorisation must survive the candidate phase, so
+// the two get their own space; otherwise they share it.
+template <class C, bool INC> struct QrCand;
+template <class C> struct QrCand<C, false> {
     using F = typename C::F;
-    uint64_t gkey[C::EMAX];  // (row i << 32) | slot, sorted by row then slot
     union {
-        F A[(C::MAXP + 1) * C::LD];   // QR phase: columns of A-bar, then e-bar
+        F A[(C::MAXP + 1) * C::LD];
         struct {
             int key[C::CMAX];         // raw candidates, sorted
             int cj[C::CMAX];          // unique candidates (ascending j)
             F rho[C::CMAX];
         } c;
-    } u;
+    };
+};
+template <class C> struct QrCand<C, true> {
+    using F = typename C::F;
+    F A[(C::MAXP + 1) * C::LD];
+    struct {
+        int key[C::CMAX];
+        int cj[C::CMAX];
+        F rho[C::CMAX];
+    } c;
+    F tau[C::MAXP + 1];      // tau_t of each reflector
+    uint8_t rz[C::MAXP + 1]; // reflector t skipped (zero column norm)
+};
+
+template <class C, bool INC>
+struct alignas(16) Smem {
+    using F = typename C::F;
+    uint64_t gkey[C::EMAX];  // (row i << 32) | slot, sorted by row then slot
+    QrCand<C, INC> u;
+
     F gval[C::EMAX];         // u_f(d_j a_ji) by slot
     uint8_t gcol[C::EMAX];   // position of j in J by slot
     uint8_t gpos[C::EMAX];   // row position in I of sorted entry e
-    int I[C::MAXM];          // shadow, ascending
-    int seg[C::MAXM + 1];    // first sorted entry of each row of A-bar
-    F s[C::MAXM];            // residual s-bar
+    int I[C::MAXM];          // shadow in insertion order: earlier solves' rows, then new rows ascending
+    uint8_t dpos[C::MAXM];   // position in I of the d-th row in ascending order
+    int seg[C::MAXM + 1];    // first sorted entry of the d-th row in ascending order
+    F s[C::MAXM];            // residual s-bar (rows in insertion order)
     int J[C::MAXP + 1];
     F mb[C::MAXP + 1];
     F Rd[C::MAXP + 1];
@@ -271,7 +295,21 @@ __device__ __forceinline__ int bsearch_sorted(const int* v, int len, int key) {
     return -1;
 }
 
-template <class C>
+// index d of row i among the shadow rows in ascending order (the row of the d-th
+// segment is the high word of its first sorted entry), or -1
+__device__ __forceinline__ int bsearch_rows(const uint64_t* gkey, const int* seg, int m, int i) {
+    int lo = 0, hi = m - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int x = (int)(uint32_t)(gkey[seg[mid]] >> 32);
+        if (x == i) return mid;
+        if (x < i) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+template <class C, bool INC>
 __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
     using F = typename C::F;
     constexpr int G = C::G;
@@ -282,7 +320,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
     if (g >= C::PPW) return;
     const int prob = blockIdx.x * C::PPW + g;
     if (prob >= a.ncols) return;
-    Smem<C>& S = reinterpret_cast<Smem<C>*>(smem_raw)[g];
+    Smem<C, INC>& S = reinterpret_cast<Smem<C, INC>*>(smem_raw)[g];
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
     const uint64_t below = (wl == 0) ? 0ull : ((~0ull) >> (64 - wl));
     const F* bnrm2 = reinterpret_cast<const F*>(a.bnrm2);
@@ -312,12 +350,17 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
     }
     wave_sync();
     const int cap = a.maxfill > p ? a.maxfill : p;
-    int flags = 0, step = 0, m = 0, kpos = -1;
+    int flags = 0, step = 0, m = 0, kpos = -1, p_prev = 0;
     F res = F(0);
     if (p == 0 && !defer) flags |= CF_EPS;
 
     for (step = 0; p > 0 && !defer; ++step) {
         // ---- shadow I_k and A-bar = B(I_k, J_k), e-bar = e_k(I_k) ----
+        // The rows of the previous solve keep their positions and the rows the new
+        // columns bring in follow in ascending order.  The columns factored before
+        // are zero in the new rows, so their Householder reflectors do not change:
+        // the QR below equals an incremental update of the previous one.
+        const int m_prev = m;
         int myj = 0, mys = 0, myn = 0;
         if (lane < p) {
             myj = S.J[lane];
@@ -360,9 +403,38 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             m += __popcll(ballot(head) & gmask);
         }
         if (m > C::MAXM) { defer = true; break; }
-        // positions, shadow list, row segments
+        // sorted rows, their segments, and their positions in I.  A row is old
+        // (in the previous shadow) iff the first entry of its segment comes from a
+        // column of the previous solve (slots follow the column order); old rows
+        // appear in the same relative order as in the previous sorted list, so the
+        // previous dpos gives their positions.  Pass 1 reads the previous lists and
+        // leaves each head's position (other entries: their sorted row index) in
+        // gpos; pass 2 writes the new lists; pass 3 maps every entry to its position.
         {
-            int run = 0;
+            int run = 0, nnew = 0, nold = 0;
+            for (int base = 0; base < E; base += G) {
+                int e = base + lane;
+                bool head = false, old = false;
+                if (e < E) {
+                    uint32_t i = (uint32_t)(S.gkey[e] >> 32);
+                    head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
+                    old = head && S.gcol[(uint32_t)(S.gkey[e] & 0xffffffffu)] < p_prev;
+                }
+                const bool fresh = head && !old;
+                uint64_t bal = ballot(head) & gmask, obal = ballot(old) & gmask, nbal = ballot(fresh) & gmask;
+                if (e < E) {
+                    if (head)
+                        S.gpos[e] = old ? S.dpos[nold + __popcll(obal & below)]
+                                        : (uint8_t)(m_prev + nnew + __popcll(nbal & below));
+                    else
+                        S.gpos[e] = (uint8_t)(run + __popcll(bal & below) - 1);
+                }
+                run += __popcll(bal);
+                nold += __popcll(obal);
+                nnew += __popcll(nbal);
+            }
+            wave_sync();
+            run = 0;
             for (int base = 0; base < E; base += G) {
                 int e = base + lane;
                 bool head = false;
@@ -372,14 +444,12 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                     head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
                 }
                 uint64_t bal = ballot(head) & gmask;
-                int before = __popcll(bal & below);
-                if (e < E) {
-                    int pos = run + before - (head ? 0 : 1);
-                    S.gpos[e] = (uint8_t)pos;
-                    if (head) {
-                        S.I[pos] = (int)i;
-                        S.seg[pos] = e;
-                    }
+                if (head) {
+                    const int d = run + __popcll(bal & below);
+                    const int pos = S.gpos[e];
+                    S.seg[d] = e;
+                    S.dpos[d] = (uint8_t)pos;
+                    if (pos >= m_prev) S.I[pos] = (int)i;
                 }
                 run += __popcll(bal);
             }
@@ -388,8 +458,30 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                 S.is[0] = -1;
             }
         }
-        // zero the p+1 columns (lane c zeroes column c)
-        if (lane <= p) {
+        wave_sync();
+        for (int e = lane; e < E; e += G) {
+            const bool head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != (uint32_t)(S.gkey[e] >> 32));
+            if (!head) S.gpos[e] = S.dpos[S.gpos[e]];
+        }
+        // With the update (INC), columns 0 .. p_old-1 and e-bar (in column p_old)
+        // still hold the factorisation of the previous solve over its m_prev rows:
+        // the new rows are zero in those columns, so only the new columns are
+        // gathered, the old reflectors are applied to them, and the QR continues at
+        // column p_old.  Without it (p_old = 0) everything is rebuilt: the same
+        // operations on the same values, so the same bits.
+        const int p_old = (INC && step > 0) ? p_prev : 0;
+        if (p_old > 0 && lane == p) {
+            // e-bar after the previous reflectors moves from column p_old to column p
+            const F* src = &S.u.A[p_old * C::LD];
+            F* dst = &S.u.A[p * C::LD];
+            for (int i = 0; i < m_prev; ++i) dst[i] = src[i];
+            for (int i = m_prev; i < m; ++i) dst[i] = F(0);
+        }
+        wave_sync();
+        if (lane < p_old) {
+            F* col = &S.u.A[lane * C::LD];
+            for (int i = m_prev; i < m; ++i) col[i] = F(0);
+        } else if (lane < p || (p_old == 0 && lane == p)) {
             F* col = &S.u.A[lane * C::LD];
             for (int i = 0; i < m; ++i) col[i] = F(0);
         }
@@ -397,21 +489,42 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         for (int e = lane; e < E; e += G) {
             int slot = (int)(uint32_t)(S.gkey[e] & 0xffffffffu);
             int pos = S.gpos[e];
-            S.u.A[S.gcol[slot] * C::LD + pos] = S.gval[slot];
-            if (S.I[pos] == k && S.seg[pos] == e) S.is[0] = pos;
+            if (S.gcol[slot] >= p_old) S.u.A[S.gcol[slot] * C::LD + pos] = S.gval[slot];
+            if (S.I[pos] == k) S.is[0] = pos;
         }
         wave_sync();
         kpos = S.is[0];
-        if (lane == 0 && kpos >= 0) S.u.A[p * C::LD + kpos] = F(1);
+        // e-bar = e_k(I): the 1 is placed by a full build, or by the update when k is a new row
+        if (lane == 0 && kpos >= 0 && (p_old == 0 || kpos >= m_prev)) S.u.A[p * C::LD + kpos] = F(1);
         wave_sync();
 
         // ---- Householder QR of A-bar, applied to e-bar as well ----
         // For x = A(t:m, t): sigma = ||x||, alpha = -sgn(x_t) sigma (sgn(0) = +1),
         // v = x - alpha e_1 with v^T v = 2 sigma (sigma + |x_t|), so the reflector
         // maps a column a to a - (v^T a / tau) v with tau = sigma (sigma + |x_t|).
+        // Sums run over the rows t .. m-1 (the stored zeros of the new rows add
+        // nothing), so the update equals the factorisation from scratch.
         bool rankdef = false;
         const int qsteps = p < m ? p : m;
-        for (int t = 0; t < qsteps; ++t) {
+        // reflectors of the previous solve: t < min(p_old, m_prev) (later ones met only
+        // zeros then and meet only zeros now: the loop below finds them rank deficient)
+        const int qold = min(min(p_old, m_prev), qsteps);
+        if constexpr (INC)
+            for (int t = 0; t < qold; ++t) rankdef |= S.u.rz[t] != 0;
+        if constexpr (INC) if (lane >= p_old && lane < p) {
+            // the previous reflectors on a new column, one after the other
+            F* col = &S.u.A[lane * C::LD];
+            for (int t = 0; t < qold; ++t) {
+                if (S.u.rz[t]) continue;
+                const F* v = &S.u.A[t * C::LD];
+                F dot = F(0);
+                for (int i = t; i < m; ++i) dot = ffma(v[i], col[i], dot);
+                F f = dot / S.u.tau[t];
+                for (int i = t; i < m; ++i) col[i] = store<C::UF>(ffma(-f, v[i], col[i]));
+            }
+        }
+        wave_sync();
+        for (int t = qold; t < qsteps; ++t) {
             if (lane == t) {
                 F* x = &S.u.A[t * C::LD];
                 F sig2 = F(0);
@@ -419,12 +532,17 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                 F sigma = fsqrt(sig2);
                 if (sigma == F(0)) {
                     S.Rd[t] = F(0);
+                    if constexpr (INC) S.u.rz[t] = 1;
                     S.is[1] = 1;
                 } else {
                     F xt = x[t];
                     F alpha = (xt >= F(0)) ? -sigma : sigma;
                     x[t] = store<C::UF>(xt - alpha);
                     S.fs[0] = sigma * (sigma + fabs(xt));
+                    if constexpr (INC) {
+                        S.u.tau[t] = S.fs[0];
+                        S.u.rz[t] = 0;
+                    }
                     S.Rd[t] = store<C::UF>(alpha);
                     S.is[1] = 0;
                 }
@@ -466,12 +584,13 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         if (rankdef) flags |= CF_RANKDEF;
 
         // ---- residual s-bar = A-bar m-bar - e-bar over the stored entries ----
-        for (int pos = lane; pos < m; pos += G) {
+        for (int d = lane; d < m; d += G) {
             F acc = F(0);
-            for (int e = S.seg[pos]; e < S.seg[pos + 1]; ++e) {
+            for (int e = S.seg[d]; e < S.seg[d + 1]; ++e) {
                 int slot = (int)(uint32_t)(S.gkey[e] & 0xffffffffu);
                 acc = ffma(S.gval[slot], S.mb[S.gcol[slot]], acc);
             }
+            const int pos = S.dpos[d];
             S.s[pos] = acc - ((pos == kpos) ? F(1) : F(0));
         }
         wave_sync();
@@ -544,8 +663,8 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             for (int q = a.rp[j]; q < a.rp[j + 1]; ++q) {
                 int i = a.ci[q];
                 F r;
-                int pos = bsearch_sorted(S.I, m, i);
-                if (pos >= 0) r = S.s[pos];
+                int d = bsearch_rows(S.gkey, S.seg, m, i);
+                if (d >= 0) r = S.s[S.dpos[d]];
                 else if (i == k) r = F(-1);
                 else continue;
                 tj = ffma(r, scaled_entry<C::UF>(dj, a.av[q]), tj);
@@ -609,6 +728,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             }
             wave_sync();
         }
+        p_prev = p;
         p += nsel;
     }
 
@@ -688,23 +808,28 @@ __global__ void k_build_stats(int n, const int* __restrict__ len, const int* __r
 // host side
 // ---------------------------------------------------------------------------
 
-template <class C>
-static int launch_columns(spai_handle* h, const ColArgs& a, hipStream_t s) {
-    if (a.ncols <= 0) return SPAI_OK;
-    size_t sh = sizeof(Smem<C>) * C::PPW;
+template <class C, bool INC>
+static int launch_columns_v(spai_handle* h, const ColArgs& a, hipStream_t s) {
+    size_t sh = sizeof(Smem<C, INC>) * C::PPW;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] {
-        attr_err = hipFuncSetAttribute((const void*)k_spai_columns<C>,
+        attr_err = hipFuncSetAttribute((const void*)k_spai_columns<C, INC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     });
     SPAI_HIP(attr_err);
     int grid = (a.ncols + C::PPW - 1) / C::PPW;
     long tk = timer_begin(h, SPAI_KT_COLUMNS);
-    hipLaunchKernelGGL(k_spai_columns<C>, dim3(grid), dim3(64), sh, s, a);
+    hipLaunchKernelGGL((k_spai_columns<C, INC>), dim3(grid), dim3(64), sh, s, a);
     timer_end(h, SPAI_KT_COLUMNS, tk);
     SPAI_HIP(hipGetLastError());
     return SPAI_OK;
+}
+
+template <class C>
+static int launch_columns(spai_handle* h, const ColArgs& a, hipStream_t s) {
+    if (a.ncols <= 0) return SPAI_OK;
+    return a.qr_update ? launch_columns_v<C, true>(h, a, s) : launch_columns_v<C, false>(h, a, s);
 }
 
 // configurations: lanes per problem G (|J| <= G-1), shadow rows, gathered entries,
@@ -932,6 +1057,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     SPAI_ARG(h && A && p && P_out, "NULL handle, matrix, parameters or output");
     *P_out = nullptr;
     SPAI_ARG(p->side == SPAI_LEFT || p->side == SPAI_RIGHT, "side must be SPAI_LEFT or SPAI_RIGHT");
+    SPAI_ARG(p->qr_update == 0 || p->qr_update == 1, "qr_update must be 0 or 1");
     const int n = A->n;
     SPAI_ARG(n > 0, "n must be positive");
     SPAI_ARG(A->nnz >= n && A->rowptr && A->col && A->val, "matrix arrays missing or nnz < n");
@@ -1042,6 +1168,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     a.pat_ptr = J ? J->ptr : nullptr;
     a.pat_idx = J ? J->idx : nullptr;
     a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.maxfill = p->maxfill;
+    a.qr_update = p->qr_update;
     a.cols = nullptr; a.ncols = n; a.stride = stride;
     a.len = P->len; a.jout = P->j_ins; a.mout = P->m_ins; a.steps = P->steps; a.res = P->res;
     a.flags = P->flags; a.nI = nI; a.defer_list = dl; a.defer_count = dc;

@@ -615,3 +615,35 @@ def test_batch4096_full_size(S, h):
         pp, pc, pv = ref.P_csr(w.n)
         o = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, w.ir.tau, w.ir.imax, w.ir.maxit, w.ir.tol_ir)
         assert st[q]["its"] == o.its, f"system {q}"
+
+
+@pytest.mark.parametrize("uf", ["fp32", "fp16", "fp64"])
+def test_qr_update_gives_the_same_bits(S, h, uf):
+    """Updating each column's QR across augmentation steps (qr_update) gives the
+    bits of the factorisation from scratch: insertion-ordered shadows make the
+    two the same sequence of operations on the same values."""
+    for w in (W.convdiff_adaptive(96, u_f=uf), W.random_system(4000, 3)):
+        s = w.spai
+        A = S.DeviceCSR.from_host(w.A)
+        P0, _, st0 = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+        P1, _, st1 = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, uf, qr_update=True)
+        c0, c1 = P0.columns(), P1.columns()
+        for key in ("J", "m", "steps", "res", "flags", "len"):
+            assert torch.equal(c0[key], c1[key]), (w.name, key)
+        assert st0 == st1
+
+
+def test_full_size_build_with_qr_update_matches_oracle_digests(S, h):
+    import hashlib
+
+    w = W.convdiff_adaptive(512)
+    s = w.spai
+    A = S.DeviceCSR.from_host(w.A)
+    P, _, stats = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f, qr_update=True)
+    g = _golden512()
+    cols = P.columns()
+    dig = lambda t: hashlib.sha256(np.ascontiguousarray(t.cpu().numpy()).tobytes()).hexdigest()
+    assert dig(cols["J"]) == g["sha256_J_insertion_order"]
+    assert dig(cols["steps"]) == g["sha256_steps"]
+    assert dig(cols["m"]) == g["sha256_m_insertion_order"]
+    assert stats["nnz"] == g["nnz_P"]

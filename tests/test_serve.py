@@ -159,3 +159,24 @@ def test_bad_requests_are_rejected(S, systems):
     with pytest.raises(S.SpaiError):
         srv.submit(*_args(big))
     srv.close()
+
+
+def test_device_lane_serves_smallest_first(S):
+    """With an age limit the device lane takes the smallest waiting system first:
+    submitted behind a running solve, a small system overtakes a larger one that
+    arrived before it; in arrival order it does not."""
+    import time
+
+    ws = [W.serving_request(W.Arrival(0.0, "convdiff", side, "fp32", 200 + q)) for q, side in
+          enumerate((400, 300, 100))]
+    for age, expect_small_first in ((60000, True), (0, False)):
+        srv = S.Server(batch_lanes=1, batch_max_n=1000, hbm_budget=16 << 30, lane_workspace=256 << 20,
+                       sjf_age_ms=age)
+        ids = [srv.submit(*_args(ws[0]))]
+        time.sleep(0.02)                      # the first one is on the device lane by now
+        ids += [srv.submit(*_args(w)) for w in ws[1:]]
+        recs = [srv.wait(i)[2] for i in ids]
+        srv.close()
+        assert all(r["lane"] == -1 for r in recs)
+        assert recs[0]["t_admit"] <= min(recs[1]["t_admit"], recs[2]["t_admit"])
+        assert (recs[2]["t_admit"] < recs[1]["t_admit"]) == expect_small_first, (age, recs)

@@ -42,14 +42,18 @@ struct SolveState {
 
 // w = A v and y = M^T (D w) (row k of P holds m_k, values in VP, FP64
 // arithmetic; for a right preconditioner row i holds the m_k[i] and y = D (M w))
-// with G lanes per row (G a power of two <= 16): the lanes load the
+// with G lanes per row (G a power of two <= 16).  The product may scale its
+// output, w_i = d_i (A v)_i, so that the left application that follows gathers
+// only w (the product d_k w_k is the one it would form itself: the same bits,
+// one gather per entry instead of two).  The lanes load the
 // row's entries with unit stride, keep lane-strided partial sums and add them
 // by a fixed xor tree, so every call gives the same bits.  Many more waves than
 // one thread per row, and coalesced loads.
 template <int G, int R>
 __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ av, const double* __restrict__ x,
-                                                double* __restrict__ y, const SolveState* __restrict__ st) {
+                                                double* __restrict__ y, const double* __restrict__ dout,
+                                                const SolveState* __restrict__ st) {
     if (st && st->done) return;
     // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
     constexpr int GPB = 256 / G;
@@ -76,11 +80,12 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
         double s = acc[r];
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
-        if (sub == 0 && row0 + r * GPB < n) y[row0 + r * GPB] = s;
+        if (sub == 0 && row0 + r * GPB < n) y[row0 + r * GPB] = dout ? dout[row0 + r * GPB] * s : s;
     }
 }
 
-template <int VP, int G, int R, bool RIGHT>
+// SCALED (left only): w already holds D w, the gather of d is skipped
+template <int VP, int G, int R, bool RIGHT, bool SCALED = false>
 __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                                                    const typename ValType<VP>::T* __restrict__ pv,
                                                    const double* __restrict__ d, const double* __restrict__ w,
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict_
         double s = 0.0;
         for (int q = q0[r]; q < q1[r]; q += G) {
             const int j = pc[q];
-            if constexpr (RIGHT) s = __builtin_fma(to_f64(pv[q]), w[j], s);
+            if constexpr (RIGHT || SCALED) s = __builtin_fma(to_f64(pv[q]), w[j], s);
             else s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
         }
         acc[r] = s;
@@ -1419,7 +1424,7 @@ static int reduce_blocks(int n) {
 constexpr int SPMV_R = 2;
 constexpr int APPLY_R = 4;
 
-template <int VP, bool RIGHT>
+template <int VP, bool RIGHT, bool SCALED = false>
 static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
                       const SolveState* st) {
     using T = typename ValType<VP>::T;
@@ -1427,7 +1432,7 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
     const long long groups = ((long long)n + APPLY_R - 1) / APPLY_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
 #define SPAI_AP(G)                                                                                       \
-    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
+    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT, SCALED>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
                        P->col, pv, P->d, w, y, st)
     switch (g) {
     case 1: SPAI_AP(1); break;
@@ -1439,42 +1444,39 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
 #undef SPAI_AP
 }
 
+// scaled: (left preconditioner) w already holds D w, as written by a product
+// with output scaling d
 static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
-                          const SolveState* st = nullptr) {
+                          const SolveState* st = nullptr, bool scaled = false) {
     const int n = P->n, g = lanes_per_row(P->nnz, n);
     long tk = timer_begin(h, SPAI_KT_APPLY_P);
-    const bool right = P->side == SPAI_RIGHT;
+    const int mode = P->side == SPAI_RIGHT ? 2 : scaled ? 1 : 0;
+#define SPAI_AP_MODE(VP)                                     \
+    if (mode == 2) apply_P_g<VP, true>(g, n, P, w, y, s, st);          \
+    else if (mode == 1) apply_P_g<VP, false, true>(g, n, P, w, y, s, st); \
+    else apply_P_g<VP, false>(g, n, P, w, y, s, st);
     switch (P->val_prec) {
-    case SPAI_FP64:
-        if (right) apply_P_g<SPAI_FP64, true>(g, n, P, w, y, s, st);
-        else apply_P_g<SPAI_FP64, false>(g, n, P, w, y, s, st);
-        break;
-    case SPAI_FP32:
-        if (right) apply_P_g<SPAI_FP32, true>(g, n, P, w, y, s, st);
-        else apply_P_g<SPAI_FP32, false>(g, n, P, w, y, s, st);
-        break;
-    case SPAI_FP16:
-        if (right) apply_P_g<SPAI_FP16, true>(g, n, P, w, y, s, st);
-        else apply_P_g<SPAI_FP16, false>(g, n, P, w, y, s, st);
-        break;
-    default:
-        if (right) apply_P_g<SPAI_BF16, true>(g, n, P, w, y, s, st);
-        else apply_P_g<SPAI_BF16, false>(g, n, P, w, y, s, st);
-        break;
+    case SPAI_FP64: SPAI_AP_MODE(SPAI_FP64); break;
+    case SPAI_FP32: SPAI_AP_MODE(SPAI_FP32); break;
+    case SPAI_FP16: SPAI_AP_MODE(SPAI_FP16); break;
+    default: SPAI_AP_MODE(SPAI_BF16); break;
     }
+#undef SPAI_AP_MODE
     timer_end(h, SPAI_KT_APPLY_P, tk);
     SPAI_HIP(hipGetLastError());
     return SPAI_OK;
 }
 
+// dout (may be NULL): output scaling, y_i = dout_i (A x)_i
 static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
-                       const SolveState* st = nullptr) {
+                       const SolveState* st = nullptr, const double* dout = nullptr) {
     const int n = A->n, g = lanes_per_row(A->nnz, n);
     const long long groups = ((long long)n + SPMV_R - 1) / SPMV_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
     long tk = timer_begin(h, SPAI_KT_SPMV_A);
 #define SPAI_SP(G)                                                                                              \
-    hipLaunchKernelGGL((k_spmv_g<G, SPMV_R>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, st)
+    hipLaunchKernelGGL((k_spmv_g<G, SPMV_R>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, \
+                       dout, st)
     switch (g) {
     case 1: SPAI_SP(1); break;
     case 2: SPAI_SP(2); break;
@@ -1780,9 +1782,9 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
                 if (right) {                                               // y = A P v_j
                     if ((rc = launch_apply_P(h, P, vj, w, s, sst))) return rc;
                     if ((rc = launch_spmv(h, A, w, y, s, sst))) return rc;
-                } else {                                                   // y = P A v_j
-                    if ((rc = launch_spmv(h, A, vj, w, s, sst))) return rc;
-                    if ((rc = launch_apply_P(h, P, w, y, s, sst))) return rc;
+                } else {                                                   // y = M^T (D (A v_j))
+                    if ((rc = launch_spmv(h, A, vj, w, s, sst, P->d))) return rc;
+                    if ((rc = launch_apply_P(h, P, w, y, s, sst, true))) return rc;
                 }
                 if (cfg.nb) {
                     ArnoldiArgs aa{};

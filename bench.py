@@ -103,13 +103,29 @@ def profiled_traffic(kernel_file, sources):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho="dcgs2"):
+def tuned_choice(S, h, w, A, u_f, enabled):
+    """Column-kernel configuration for this build from the autotuner (measured
+    here, outside the timed region; no cache on disk), or the library's rule."""
+    if not enabled:
+        return {"kernel_cfg": 0, "qr_update": 0}
+    from paper_2202_10204_amd import autotune as T
+
+    s = w.spai
+    c = T.tune(h, A, None, w.A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f, cache=None)
+    log(f"autotune {c['bin']}: kernel_cfg={c['kernel_cfg']} qr_update={c['qr_update']} "
+        f"{c['ns_per_col']:.1f} ns/col; candidates {c['candidates']}")
+    return c
+
+
+def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho="dcgs2", tune=True):
     """Build + solve `steps` times after `warmup` untimed steps; per-step times in ms."""
     import torch
 
     s, ir = w.spai, w.ir
+    choice = tuned_choice(S, h, w, A, u_f, tune)
+    cfg = {"qr_update": bool(choice["qr_update"]), "kernel_cfg": int(choice["kernel_cfg"])}
     for _ in range(warmup):
-        P, _, _ = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f)
+        P, _, _ = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f, **cfg)
         h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
         del P
     for kc, every in timed_kernels:
@@ -123,7 +139,7 @@ def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho=
         e1 = torch.cuda.Event(enable_timing=True)
         e2 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        P, warn, bst = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f)
+        P, warn, bst = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f, **cfg)
         e1.record(stream)
         st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
         e2.record(stream)
@@ -135,7 +151,7 @@ def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho=
     timings = {kc: h.timing_read(kc) for kc, _ in timed_kernels}
     for kc, _ in timed_kernels:
         h.timing_enable(kc, 0)
-    return rec, wall, timings
+    return rec, wall, timings, choice
 
 
 def cpu_baseline(w, its_oracle, threads):
@@ -190,13 +206,15 @@ def run_batch(S, W, args):
     A = S.DeviceCSR.from_host(B.A)
     b = torch.as_tensor(B.b, device="cuda")
     s, ir = B.spai, B.ir
+    choice = tuned_choice(S, h, B, A, s.u_f, not args.no_tune)
+    cfg = {"qr_update": bool(choice["qr_update"]), "kernel_cfg": int(choice["kernel_cfg"])}
     stream = torch.cuda.current_stream()
     rec = []
     for k in range(args.warmup + args.steps):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         x = torch.zeros_like(b)
         e0.record(stream)
-        P, warn, bst = h.spai_build_batched(A, B.sys_ptr, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+        P, warn, bst = h.spai_build_batched(A, B.sys_ptr, None, s.eps, s.alpha, s.beta, s.maxfill, s.u_f, **cfg)
         e1.record(stream)
         rc, st = h.gmres_ir_batched(A, P, B.sys_ptr, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir)
         e2.record(stream)
@@ -224,6 +242,8 @@ def run_batch(S, W, args):
         "p50_ms": percentile(step_ms, 50), "p99_ms": percentile(step_ms, 99),
         "its_mean": float(its.mean()), "its_max": int(its.max()), "max_ferr": ferr, "failed_systems": fails,
         "nnz_P": int(bst["nnz"]),
+        "spai_kernel": {k: choice[k] for k in ("kernel_cfg", "qr_update", "ns_per_col", "candidates", "bin")
+                        if k in choice},
     }
     print(json.dumps(out), flush=True)
 
@@ -401,6 +421,8 @@ def main():
                          "longer than this (0: arrival order)")
     ap.add_argument("--ortho", default="dcgs2", choices=["mgs", "cgs2", "dcgs2"],
                     help="Arnoldi orthogonalisation (all three give the oracle's iteration tuple)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="build with the library's configuration rule instead of the autotuner's choice")
     ap.add_argument("--profile-run", action="store_true",
                     help="one untimed build + solve of the mixed form and a 256 MiB device copy "
                          "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE); for profiler runs")
@@ -450,7 +472,8 @@ def main():
     # kernels, every 8th Arnoldi launch and every 16th sparse product (a pair
     # of events around a launch costs a few microseconds of device time)
     kernels = [("columns", 1), ("mgs", 8), ("spmv_a", 16), ("apply_p", 16), ("residual", 1), ("update", 1)]
-    rec, wall, timings = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels, args.ortho)
+    rec, wall, timings, choice = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels,
+                                          args.ortho, not args.no_tune)
     log(f"mixed form: {[(round(a, 1), round(c, 1)) for a, c, *_ in rec]} ms (build, solve)")
     step_ms = [a + c for a, c, *_ in rec]
     build_ms = [a for a, *_ in rec]
@@ -472,7 +495,8 @@ def main():
         if args.fp64_steps <= 0:
             break
         x64 = torch.zeros_like(b)
-        r64, wall64, _ = run_form(S, h, w, A, b, x64, uf, ur, args.fp64_steps, 0, (), args.ortho)
+        r64, wall64, _, _ = run_form(S, h, w, A, b, x64, uf, ur, args.fp64_steps, 0, (), args.ortho,
+                                     not args.no_tune)
         ms64 = float(np.mean([a + c for a, c, *_ in r64]))
         xe = x64.cpu().numpy()
         forms[name] = {
@@ -543,6 +567,8 @@ def main():
         "ferr": ferr,
         "nbe": nbe,
         "nnz_P": int(bst["nnz"]),
+        "spai_kernel": {k: choice[k] for k in ("kernel_cfg", "qr_update", "ns_per_col", "candidates", "bin")
+                        if k in choice},
         "fp64_forms": forms,
         "kernels": per_class,
         "roofline": roof,

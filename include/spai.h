@@ -100,7 +100,44 @@ typedef struct {
                           operations, less LDS left for other columns.  Both give the same
                           bits (the shadow rows are kept in insertion order, so the columns
                           factored earlier are zero in the rows an augmentation adds). */
+    int32_t kernel_cfg; /* column-kernel configuration: 0 (default) = the library's rule
+                           (the smallest configuration holding max(maxfill, longest initial
+                           column), with a sampled choice between the two 20-index shapes);
+                           1..SPAI_KCFG_COUNT = that configuration (spai_column_config), which
+                           must hold max(maxfill, longest initial column) indices, else
+                           SPAI_E_ARG.  Every configuration gives the same bits: a column that
+                           outgrows a configuration's shadow, gather or candidate space is
+                           recomputed from scratch by the largest one.  The choice is a
+                           performance choice, made by spai_tune_build's measurements. */
 } spai_build_params;
+
+/* Column-kernel configurations of Algorithm 1's per-column solver: `lanes` lanes
+ * of a wavefront per column problem (64 / lanes problems per wavefront), at most
+ * `maxp` = lanes - 1 indices in J_k, `maxm` shadow rows I_k, `emax` gathered
+ * entries of B(:, J_k) and `cmax` raw augmentation candidates staged in LDS. */
+enum { SPAI_KCFG_COUNT = 6 };
+typedef struct {
+    int32_t lanes, maxp, maxm, emax, cmax, problems_per_wave;
+    int32_t lds_bytes_per_problem; /* for u_f = FP32 with qr_update = 0 */
+} spai_column_config;
+/* Description of configuration id (1..SPAI_KCFG_COUNT); SPAI_E_ARG otherwise. */
+int spai_column_config_get(int32_t id, spai_column_config* out);
+
+/*
+ * Autotuning measurement for spai_build: runs the build's preprocessing for
+ * (A, J, p) and then, for every configuration id able to hold the pattern
+ * (maxp >= max(maxfill, longest initial column)) and for qr_update 0 and 1, the
+ * column phase over a strided sample of min(sample, n) columns (the columns
+ * sample_k = k * floor(n / count)), including the recomputation of the columns
+ * it defers, `reps` times after one untimed run; writes the fastest time per
+ * sampled column in nanoseconds to ns_per_col[2 * (id - 1) + qr_update] (host
+ * array of 2 * SPAI_KCFG_COUNT doubles; -1 for a configuration that cannot
+ * hold the pattern).  p->kernel_cfg and p->qr_update are ignored.  No
+ * preconditioner is produced.  Errors as spai_build, plus SPAI_E_ARG for
+ * sample < 1, reps < 1 or a NULL ns_per_col.
+ */
+int spai_tune_build(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+                    int32_t sample, int32_t reps, double* ns_per_col);
 
 typedef struct {
     int64_t nnz;            /* stored entries of P (pattern entries, exact zeros included) */
@@ -199,8 +236,9 @@ const char* spai_last_error(void);
  * On success *P receives a new preconditioner owned by the caller (free with
  * spai_precond_destroy) and *st (optional) the statistics.
  * Errors: SPAI_E_ARG for n <= 0, NULL arrays, eps <= 0, beta < 0, alpha < 0,
- * maxfill < 1, maxfill > 63, an unknown u_f, a pattern with a column longer than
- * 63 or a malformed A/pattern (checked on the device); SPAI_E_OOM; SPAI_E_HIP.
+ * maxfill < 1, maxfill > 63, an unknown u_f, a kernel_cfg outside 0..SPAI_KCFG_COUNT
+ * or too small for the pattern, a pattern with a column longer than 63 or a
+ * malformed A/pattern (checked on the device); SPAI_E_OOM; SPAI_E_HIP.
  */
 int spai_build(spai_handle* h, const spai_csr* A, const spai_pattern* J,
                const spai_build_params* p, spai_precond** P, spai_build_stats* st);

@@ -42,7 +42,15 @@ class _Pattern(ctypes.Structure):
 
 class _BuildParams(ctypes.Structure):
     _fields_ = [("eps", _c_f64), ("alpha", _c_i32), ("beta", _c_i32), ("maxfill", _c_i32),
-                ("u_f", ctypes.c_int), ("side", _c_i32), ("qr_update", _c_i32)]
+                ("u_f", ctypes.c_int), ("side", _c_i32), ("qr_update", _c_i32), ("kernel_cfg", _c_i32)]
+
+
+class _ColumnConfig(ctypes.Structure):
+    _fields_ = [("lanes", _c_i32), ("maxp", _c_i32), ("maxm", _c_i32), ("emax", _c_i32), ("cmax", _c_i32),
+                ("problems_per_wave", _c_i32), ("lds_bytes_per_problem", _c_i32)]
+
+
+KCFG_COUNT = 6
 
 
 SIDE = {"left": 0, "right": 1}
@@ -111,6 +119,8 @@ def lib():
         L.spai_destroy.argtypes = [_p]
         L.spai_set_stream.argtypes = [_p, _p]
         L.spai_build.argtypes = [_p, P(_Csr), P(_Pattern), P(_BuildParams), P(_p), P(_BuildStats)]
+        L.spai_tune_build.argtypes = [_p, P(_Csr), P(_Pattern), P(_BuildParams), _c_i32, _c_i32, P(_c_f64)]
+        L.spai_column_config_get.argtypes = [_c_i32, P(_ColumnConfig)]
         L.spai_precond_import.argtypes = [_p, _c_i32, _c_i64, _p, _p, _p, ctypes.c_int, _p, P(_p)]
         L.spai_precond_view_get.argtypes = [_p, P(_View)]
         L.spai_precond_destroy.argtypes = [_p]
@@ -312,12 +322,15 @@ class Handle:
 
     # -- Algorithm 1 ---------------------------------------------------------
     def spai_build(self, A: DeviceCSR, pattern: Optional[DevicePattern], eps: float, alpha: int, beta: int,
-                   maxfill: int, u_f: str = "fp32", side: str = "left", qr_update: bool = False):
+                   maxfill: int, u_f: str = "fp32", side: str = "left", qr_update: bool = False,
+                   kernel_cfg: int = 0):
         """Returns (Precond, warnings, stats dict).  side = "left" (P = M^T D, Algorithm 3)
         or "right" (P = D M with A P ~ I; the solve then preconditions on the right);
-        qr_update: update each column's QR across augmentation steps (same results)."""
+        qr_update: update each column's QR across augmentation steps (same results);
+        kernel_cfg: column-kernel configuration 1..KCFG_COUNT, 0 = the library's rule
+        (same results)."""
         prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], SIDE[side],
-                           int(bool(qr_update)))
+                           int(bool(qr_update)), int(kernel_cfg))
         st = _BuildStats()
         out = ctypes.c_void_p()
         csr = A.c()
@@ -326,6 +339,19 @@ class Handle:
                                      ctypes.byref(prm), ctypes.byref(out), ctypes.byref(st)), "spai_build")
         stats = {f: getattr(st, f) for f, _ in _BuildStats._fields_}
         return Precond(self, out.value, stats), rc, stats
+
+    def tune_build(self, A: DeviceCSR, pattern: Optional[DevicePattern], eps: float, alpha: int, beta: int,
+                   maxfill: int, u_f: str = "fp32", side: str = "left", sample: int = 65536, reps: int = 3):
+        """Time every column-kernel configuration that holds the pattern, with and
+        without the QR update, on a strided sample of columns (spai_tune_build).
+        Returns {(kernel_cfg, qr_update): ns per column}."""
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], SIDE[side], 0, 0)
+        out = (_c_f64 * (2 * KCFG_COUNT))()
+        csr = A.c()
+        pat = pattern.c() if pattern is not None else None
+        _check(lib().spai_tune_build(self._raw, ctypes.byref(csr), ctypes.byref(pat) if pat else None,
+                                     ctypes.byref(prm), int(sample), int(reps), out), "spai_tune_build")
+        return {(1 + q // 2, q % 2): out[q] for q in range(2 * KCFG_COUNT) if out[q] >= 0.0}
 
     def precond_import(self, n: int, rowptr: torch.Tensor, col: torch.Tensor, val_f64: torch.Tensor,
                        val_prec: str, d: torch.Tensor) -> Precond:
@@ -349,10 +375,12 @@ class Handle:
 
     # -- batches of independent systems (block-diagonal A, host sys_ptr) ------
     def spai_build_batched(self, A: DeviceCSR, sys_ptr, pattern: Optional[DevicePattern], eps: float, alpha: int,
-                           beta: int, maxfill: int, u_f: str = "fp32", qr_update: bool = False):
+                           beta: int, maxfill: int, u_f: str = "fp32", qr_update: bool = False,
+                           kernel_cfg: int = 0):
         """Returns (Precond of the whole batch, warnings, stats dict)."""
         sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
-        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], 0, int(bool(qr_update)))
+        prm = _BuildParams(float(eps), int(alpha), int(beta), int(maxfill), PREC[u_f], 0, int(bool(qr_update)),
+                           int(kernel_cfg))
         st = _BuildStats()
         out = ctypes.c_void_p()
         csr = A.c()
@@ -426,13 +454,21 @@ def _serve_request(A, b, pattern, build: dict, ir: dict):
         ji = np.ascontiguousarray(pattern.idx, dtype=np.int32)
         keep += [jp, ji]
     bp = _BuildParams(float(build["eps"]), int(build["alpha"]), int(build["beta"]), int(build["maxfill"]),
-                      PREC[build["u_f"]], SIDE[build.get("side", "left")])
+                      PREC[build["u_f"]], SIDE[build.get("side", "left")], int(bool(build.get("qr_update", 0))),
+                      int(build.get("kernel_cfg", 0)))
     ip = _IrParams(PREC[ir.get("u_r", "dd")], float(ir["tau"]), int(ir["imax"]), int(ir["maxit"]),
                    float(ir["tol_ir"]), ORTHO[ir.get("ortho", "mgs")], PREC[ir.get("u", "fp64")])
     r = _ServeRequest(int(A.n), int(ci.size), rp.ctypes.data, ci.ctypes.data, av.ctypes.data, bb.ctypes.data,
                       int(ji.size) if ji is not None else 0, jp.ctypes.data if jp is not None else None,
                       ji.ctypes.data if ji is not None else None, bp, ip)
     return r, keep
+
+
+def column_config(cfg: int) -> dict:
+    """Shape of column-kernel configuration cfg (1..KCFG_COUNT); host only."""
+    c = _ColumnConfig()
+    _check(lib().spai_column_config_get(int(cfg), ctypes.byref(c)), "spai_column_config_get")
+    return {f: getattr(c, f) for f, _ in _ColumnConfig._fields_}
 
 
 def serve_footprint(A, b, pattern, build: dict, ir: dict) -> int:

@@ -41,7 +41,7 @@ struct Request {
 // the same kind of initial pattern.
 bool same_key(const Request& a, const Request& b) {
     return a.bp.eps == b.bp.eps && a.bp.alpha == b.bp.alpha && a.bp.beta == b.bp.beta && a.bp.side == b.bp.side &&
-           a.bp.qr_update == b.bp.qr_update &&
+           a.bp.qr_update == b.bp.qr_update && a.bp.kernel_cfg == b.bp.kernel_cfg &&
            a.bp.maxfill == b.bp.maxfill && a.bp.u_f == b.bp.u_f && a.ip.u_r == b.ip.u_r && a.ip.tau == b.ip.tau &&
            a.ip.imax == b.ip.imax && a.ip.maxit == b.ip.maxit && a.ip.tol_ir == b.ip.tol_ir && a.ip.u == b.ip.u &&
            a.jptr.empty() == b.jptr.empty();
@@ -95,6 +95,7 @@ int check_request(const spai_serve_request* r) {
     SPAI_ARG(p.u_f == SPAI_FP64 || p.u_f == SPAI_FP32 || p.u_f == SPAI_FP16 || p.u_f == SPAI_BF16, "bad u_f");
     SPAI_ARG(p.side == SPAI_LEFT || p.side == SPAI_RIGHT, "bad side");
     SPAI_ARG(p.qr_update == 0 || p.qr_update == 1, "bad qr_update");
+    SPAI_ARG(p.kernel_cfg >= 0 && p.kernel_cfg <= SPAI_KCFG_COUNT, "bad kernel_cfg");
     const spai_ir_params& q = r->ir;
     SPAI_ARG(q.imax >= 1 && q.imax <= 32 && q.maxit >= 1 && q.tau >= 0, "bad solve parameters");
     SPAI_ARG(q.u_r == SPAI_DD || q.u_r == SPAI_FP64, "bad u_r");

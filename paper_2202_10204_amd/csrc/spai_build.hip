@@ -22,6 +22,7 @@
 #include <climits>
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -841,6 +842,44 @@ template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256>;
 template <int UF> using CfgL = Cfg<UF, 32, 64, 256, 512>;
 template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 2048>;
 
+// configuration ids of the C ABI (spai_column_config_get, spai_build_params.kernel_cfg)
+enum { KC_S = 1, KC_M = 2, KC_M21S = 3, KC_M21 = 4, KC_L = 5, KC_X = 6 };
+static_assert(KC_X == SPAI_KCFG_COUNT, "configuration table and the C ABI disagree");
+
+static int cfg_maxp(int id) {
+    switch (id) {
+    case KC_S: return CfgS<SPAI_FP32>::MAXP;
+    case KC_M: return CfgM<SPAI_FP32>::MAXP;
+    case KC_M21S: return CfgM21s<SPAI_FP32>::MAXP;
+    case KC_M21: return CfgM21<SPAI_FP32>::MAXP;
+    case KC_L: return CfgL<SPAI_FP32>::MAXP;
+    default: return CfgX<SPAI_FP32>::MAXP;
+    }
+}
+
+template <class C>
+static void cfg_describe(spai_column_config* o) {
+    o->lanes = C::G;
+    o->maxp = C::MAXP;
+    o->maxm = C::MAXM;
+    o->emax = C::EMAX;
+    o->cmax = C::CMAX;
+    o->problems_per_wave = C::PPW;
+    o->lds_bytes_per_problem = (int32_t)sizeof(Smem<C, false>);
+}
+
+template <int UF>
+static int launch_cfg(spai_handle* h, int id, const ColArgs& a, hipStream_t s) {
+    switch (id) {
+    case KC_S: return launch_columns<CfgS<UF>>(h, a, s);
+    case KC_M: return launch_columns<CfgM<UF>>(h, a, s);
+    case KC_M21S: return launch_columns<CfgM21s<UF>>(h, a, s);
+    case KC_M21: return launch_columns<CfgM21<UF>>(h, a, s);
+    case KC_L: return launch_columns<CfgL<UF>>(h, a, s);
+    default: return launch_columns<CfgX<UF>>(h, a, s);
+    }
+}
+
 __global__ void k_strided_list(int count, int stride, int* out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) out[i] = i * stride;
@@ -871,33 +910,30 @@ static int launch_columns_m21(spai_handle* h, const ColArgs& a, hipStream_t s, i
     return small ? launch_columns<CfgM21s<UF>>(h, a, s) : launch_columns<CfgM21<UF>>(h, a, s);
 }
 
+// The column phase: the configuration kcfg (0 = the rule below), then the
+// columns it deferred on the largest configuration.
 template <int UF>
-static int run_columns(spai_handle* h, int pmax, ColArgs a, hipStream_t s, int* defer_list2, int* defer_count_dev,
-                       int* defer_count_host, int* cols_deferred) {
+static int run_columns(spai_handle* h, int pmax, int kcfg, ColArgs a, hipStream_t s, int* defer_list2,
+                       int* defer_count_dev, int* defer_count_host, int* cols_deferred) {
     int rc;
     int* dc = a.defer_count;
-    if (pmax <= CfgS<UF>::MAXP) rc = launch_columns<CfgS<UF>>(h, a, s);
-    else if (pmax <= CfgM<UF>::MAXP) rc = launch_columns<CfgM<UF>>(h, a, s);
-    else if (pmax <= CfgM21<UF>::MAXP) rc = launch_columns_m21<UF>(h, a, s, defer_list2, defer_count_host);
-    else if (pmax <= CfgL<UF>::MAXP) rc = launch_columns<CfgL<UF>>(h, a, s);
-    else {
-        // everything goes straight to the large kernel
-        rc = launch_columns<CfgX<UF>>(h, a, s);
-        if (rc) return rc;
-        SPAI_HIP(hipMemcpyAsync(defer_count_host, dc, sizeof(int), hipMemcpyDeviceToHost, s));
-        SPAI_HIP(hipStreamSynchronize(s));
-        *cols_deferred = 0;
-        if (*defer_count_host > 0) {
-            set_error("a column problem exceeds the largest kernel configuration");
-            return SPAI_E_ARG;
-        }
-        return SPAI_OK;
+    int id = kcfg;
+    if (id == 0) {
+        // the smallest configuration holding pmax indices
+        id = pmax <= cfg_maxp(KC_S) ? KC_S : pmax <= cfg_maxp(KC_M) ? KC_M : pmax <= cfg_maxp(KC_M21) ? KC_M21
+           : pmax <= cfg_maxp(KC_L) ? KC_L : KC_X;
     }
+    if (kcfg == 0 && id == KC_M21) rc = launch_columns_m21<UF>(h, a, s, defer_list2, defer_count_host);
+    else rc = launch_cfg<UF>(h, id, a, s);
     if (rc) return rc;
     SPAI_HIP(hipMemcpyAsync(defer_count_host, dc, sizeof(int), hipMemcpyDeviceToHost, s));
     SPAI_HIP(hipStreamSynchronize(s));
     int nd = *defer_count_host;
-    *cols_deferred = nd;
+    *cols_deferred = id == KC_X ? 0 : nd;
+    if (nd > 0 && id == KC_X) {
+        set_error("a column problem exceeds the largest kernel configuration");
+        return SPAI_E_ARG;
+    }
     if (nd > 0) {
         ColArgs b = a;
         b.cols = a.defer_list;
@@ -915,6 +951,56 @@ static int run_columns(spai_handle* h, int pmax, ColArgs a, hipStream_t s, int* 
         }
     }
     return SPAI_OK;
+}
+
+// Autotuning measurement: every configuration that holds pmax, with and
+// without the QR update, over the columns in `sample` (ns of them), deferred
+// columns included; the fastest of `reps` timed runs after an untimed one.
+template <int UF>
+static int tune_columns(spai_handle* h, int pmax, const ColArgs& a, hipStream_t s, int* sample, int ns,
+                        int* defer_list2, int* defer_count_dev, int* defer_count_host, int reps, double* out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SPAI_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error("hipEventCreate failed");
+        return SPAI_E_HIP;
+    }
+    int rc = SPAI_OK;
+    for (int id = 1; id <= SPAI_KCFG_COUNT && rc == SPAI_OK; ++id) {
+        for (int inc = 0; inc < 2 && rc == SPAI_OK; ++inc) {
+            out[2 * (id - 1) + inc] = -1.0;
+            if (cfg_maxp(id) < pmax) continue;
+            ColArgs b = a;
+            b.cols = sample;
+            b.ncols = ns;
+            b.qr_update = inc;
+            float best = -1.0f;
+            for (int r = 0; r <= reps && rc == SPAI_OK; ++r) {
+                int nd = 0;
+                if (hipMemsetAsync(a.defer_count, 0, sizeof(int), s) != hipSuccess ||
+                    hipEventRecord(e0, s) != hipSuccess) {
+                    rc = SPAI_E_HIP;
+                    break;
+                }
+                if ((rc = run_columns<UF>(h, pmax, id, b, s, defer_list2, defer_count_dev, defer_count_host,
+                                          &nd)))
+                    break;
+                float ms = 0.0f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = SPAI_E_HIP;
+                    break;
+                }
+                if (r > 0 && (best < 0.0f || ms < best)) best = ms;
+            }
+            if (rc == SPAI_OK) out[2 * (id - 1) + inc] = (double)best * 1e6 / ns;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SPAI_E_HIP) set_error("a HIP call failed while timing the column configurations");
+    return rc;
 }
 
 static int scan_ints(int n, const int* in, int* out, int* tmp_blocks, int* total, hipStream_t s) {
@@ -1049,15 +1135,23 @@ static int csr_transpose(spai_handle* h, int n, int nnz, const int* rp, const in
     return done(SPAI_OK);
 }
 
-static int build_right(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
-                       spai_precond** P_out, spai_build_stats* st);
+// a tuning run of the build (spai_tune_build): measure, produce no preconditioner
+struct TuneReq {
+    int sample, reps;
+    double* ns_per_col;
+};
 
-int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
-               spai_precond** P_out, spai_build_stats* st) {
+static int build_right(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+                       spai_precond** P_out, spai_build_stats* st, const TuneReq* tq);
+
+static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+                      spai_precond** P_out, spai_build_stats* st, const TuneReq* tq) {
     SPAI_ARG(h && A && p && P_out, "NULL handle, matrix, parameters or output");
     *P_out = nullptr;
     SPAI_ARG(p->side == SPAI_LEFT || p->side == SPAI_RIGHT, "side must be SPAI_LEFT or SPAI_RIGHT");
-    SPAI_ARG(p->qr_update == 0 || p->qr_update == 1, "qr_update must be 0 or 1");
+    SPAI_ARG(tq || p->qr_update == 0 || p->qr_update == 1, "qr_update must be 0 or 1");
+    SPAI_ARG(tq || (p->kernel_cfg >= 0 && p->kernel_cfg <= SPAI_KCFG_COUNT),
+             "kernel_cfg must lie in 0..SPAI_KCFG_COUNT");
     const int n = A->n;
     SPAI_ARG(n > 0, "n must be positive");
     SPAI_ARG(A->nnz >= n && A->rowptr && A->col && A->val, "matrix arrays missing or nnz < n");
@@ -1069,7 +1163,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     if (J) {
         SPAI_ARG(J->n == n && J->ptr && J->idx && J->nnz >= n, "pattern does not match the matrix");
     }
-    if (p->side == SPAI_RIGHT) return build_right(h, A, J, p, P_out, st);
+    if (p->side == SPAI_RIGHT) return build_right(h, A, J, p, P_out, st, tq);
     hipStream_t s = h->stream;
     SPAI_HIP(hipSetDevice(h->device));
     const int nnz = A->nnz;
@@ -1083,7 +1177,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
            o_cur = take(4 * (size_t)n), o_ri = take(4 * (size_t)nnz), o_blk = take(4 * (size_t)nb),
            o_tot = take(16), o_dl = take(4 * (size_t)n), o_dl2 = take(4 * (size_t)n),
            o_dc = take(16), o_prep = take(sizeof(PrepOut)), o_bst = take(sizeof(BuildStatsDev)),
-           o_nI = take(4 * (size_t)n);
+           o_nI = take(4 * (size_t)n), o_sl = take(tq ? 4 * (size_t)n : 0);
     int rc = buffer_reserve(h, h->ws[WS_BUILD0], off);
     if (rc) return rc;
     char* base = (char*)h->ws[WS_BUILD0].ptr;
@@ -1100,6 +1194,7 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     PrepOut* prep = (PrepOut*)(base + o_prep);
     BuildStatsDev* bst = (BuildStatsDev*)(base + o_bst);
     int* nI = (int*)(base + o_nI);
+    int* sl = (int*)(base + o_sl);
     char* hp = (char*)h->host_pinned.ptr;
 
     spai_precond* P = precond_new(h);
@@ -1139,6 +1234,12 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
         return fail(SPAI_E_ARG);
     }
     const int pmax = std::max(p->maxfill, pinit);
+    if (!tq && p->kernel_cfg > 0 && cfg_maxp(p->kernel_cfg) < pmax) {
+        set_error("invalid argument: kernel_cfg " + std::to_string(p->kernel_cfg) + " holds at most " +
+                  std::to_string(cfg_maxp(p->kernel_cfg)) + " indices per column, the build needs " +
+                  std::to_string(pmax));
+        return fail(SPAI_E_ARG);
+    }
     const int stride = pmax;
     P->stride = stride;
 
@@ -1174,11 +1275,28 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     a.flags = P->flags; a.nI = nI; a.defer_list = dl; a.defer_count = dc;
     int cols_deferred = 0;
     int* hcount = (int*)(hp + 256);
+    if (tq) {
+        // strided sample k * floor(n / ns), k < ns
+        const int ns = std::min(tq->sample, n);
+        hipLaunchKernelGGL(k_strided_list, dim3((ns + 255) / 256), dim3(256), 0, s, ns, n / ns, sl);
+        SPAI_HIP(hipGetLastError());
+#define SPAI_TUNE(UF) tune_columns<UF>(h, pmax, a, s, sl, ns, dl2, dc + 1, hcount, tq->reps, tq->ns_per_col)
+        switch (p->u_f) {
+        case SPAI_FP64: rc = SPAI_TUNE(SPAI_FP64); break;
+        case SPAI_FP32: rc = SPAI_TUNE(SPAI_FP32); break;
+        case SPAI_FP16: rc = SPAI_TUNE(SPAI_FP16); break;
+        default: rc = SPAI_TUNE(SPAI_BF16); break;
+        }
+#undef SPAI_TUNE
+        SPAI_HIP(hipStreamSynchronize(s));
+        return fail(rc);
+    }
+    const int kc = p->kernel_cfg;
     switch (p->u_f) {
-    case SPAI_FP64: rc = run_columns<SPAI_FP64>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
-    case SPAI_FP32: rc = run_columns<SPAI_FP32>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
-    case SPAI_FP16: rc = run_columns<SPAI_FP16>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
-    default: rc = run_columns<SPAI_BF16>(h, pmax, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    case SPAI_FP64: rc = run_columns<SPAI_FP64>(h, pmax, kc, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    case SPAI_FP32: rc = run_columns<SPAI_FP32>(h, pmax, kc, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    case SPAI_FP16: rc = run_columns<SPAI_FP16>(h, pmax, kc, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
+    default: rc = run_columns<SPAI_BF16>(h, pmax, kc, a, s, dl2, dc + 1, hcount, &cols_deferred); break;
     }
     if (rc) return fail(rc);
 
@@ -1231,11 +1349,16 @@ int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const s
     return warn;
 }
 
+int build_impl(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+               spai_precond** P_out, spai_build_stats* st) {
+    return build_core(h, A, J, p, P_out, st, nullptr);
+}
+
 // The right preconditioner: the left build of A^T gives rows m_k with
 // A D m_k ~ e_k (D from the rows of A^T, i.e. the columns of A); P = D M is the
 // transpose of that CSR with D applied to the output.
 static int build_right(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
-                       spai_precond** P_out, spai_build_stats* st) {
+                       spai_precond** P_out, spai_build_stats* st, const TuneReq* tq) {
     const int n = A->n, nnz = A->nnz;
     SPAI_ARG(n > 0 && nnz >= n && A->rowptr && A->col && A->val, "matrix arrays missing or nnz < n");
     SPAI_HIP(hipSetDevice(h->device));
@@ -1261,9 +1384,9 @@ static int build_right(spai_handle* h, const spai_csr* A, const spai_pattern* J,
     spai_build_params pl = *p;
     pl.side = SPAI_LEFT;
     spai_precond* P = nullptr;
-    const int warn = build_impl(h, &At, J, &pl, &P, st);
+    const int warn = build_core(h, &At, J, &pl, &P, st, tq);
     free_t();
-    if (warn < 0) return warn;
+    if (warn < 0 || tq) return warn;
     // transpose the rows m_k into rows i of P = D M
     int *prp = nullptr, *pci = nullptr;
     void* pv = nullptr;
@@ -1361,6 +1484,33 @@ int spai::precond_import_impl(spai_handle* h, int32_t n, int64_t nnz, const int3
 extern "C" int spai_build(spai_handle* h, const spai_csr* A, const spai_pattern* J,
                           const spai_build_params* p, spai_precond** P, spai_build_stats* st) {
     return spai::build_impl(h, A, J, p, P, st);
+}
+
+extern "C" int spai_tune_build(spai_handle* h, const spai_csr* A, const spai_pattern* J, const spai_build_params* p,
+                               int32_t sample, int32_t reps, double* ns_per_col) {
+    if (sample < 1 || reps < 1 || !ns_per_col) {
+        spai::set_error("invalid argument: sample and reps must be positive and ns_per_col non-NULL");
+        return SPAI_E_ARG;
+    }
+    spai::TuneReq tq{sample, reps, ns_per_col};
+    spai_precond* P = nullptr;
+    return spai::build_core(h, A, J, p, &P, nullptr, &tq);
+}
+
+extern "C" int spai_column_config_get(int32_t id, spai_column_config* out) {
+    if (!out || id < 1 || id > SPAI_KCFG_COUNT) {
+        spai::set_error("invalid argument: configuration id outside 1..SPAI_KCFG_COUNT or NULL output");
+        return SPAI_E_ARG;
+    }
+    switch (id) {
+    case spai::KC_S: spai::cfg_describe<spai::CfgS<SPAI_FP32>>(out); break;
+    case spai::KC_M: spai::cfg_describe<spai::CfgM<SPAI_FP32>>(out); break;
+    case spai::KC_M21S: spai::cfg_describe<spai::CfgM21s<SPAI_FP32>>(out); break;
+    case spai::KC_M21: spai::cfg_describe<spai::CfgM21<SPAI_FP32>>(out); break;
+    case spai::KC_L: spai::cfg_describe<spai::CfgL<SPAI_FP32>>(out); break;
+    default: spai::cfg_describe<spai::CfgX<SPAI_FP32>>(out); break;
+    }
+    return SPAI_OK;
 }
 
 extern "C" int spai_precond_import(spai_handle* h, int32_t n, int64_t nnz, const int32_t* rowptr,

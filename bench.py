@@ -117,7 +117,7 @@ def tuned_choice(S, h, w, A, u_f, enabled):
     return c
 
 
-def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho="dcgs2", tune=True):
+def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho="dcgs2", tune=True, graph=False):
     """Build + solve `steps` times after `warmup` untimed steps; per-step times in ms."""
     import torch
 
@@ -126,7 +126,7 @@ def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho=
     cfg = {"qr_update": bool(choice["qr_update"]), "kernel_cfg": int(choice["kernel_cfg"])}
     for _ in range(warmup):
         P, _, _ = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f, **cfg)
-        h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
+        h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho, graph=graph)
         del P
     for kc, every in timed_kernels:
         h.timing_enable(kc, every)
@@ -141,7 +141,7 @@ def run_form(S, h, w, A, b, x, u_f, u_r, steps, warmup, timed_kernels=(), ortho=
         e0.record(stream)
         P, warn, bst = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, u_f, **cfg)
         e1.record(stream)
-        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho)
+        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, u_r, ortho, graph=graph)
         e2.record(stream)
         e2.synchronize()
         rec.append((e0.elapsed_time(e1), e1.elapsed_time(e2), st, bst, warn))
@@ -421,6 +421,8 @@ def main():
                          "longer than this (0: arrival order)")
     ap.add_argument("--ortho", default="dcgs2", choices=["mgs", "cgs2", "dcgs2"],
                     help="Arnoldi orthogonalisation (all three give the oracle's iteration tuple)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the DCGS2 Arnoldi chunks as HIP graphs (no per-launch timing inside them)")
     ap.add_argument("--no-tune", action="store_true",
                     help="build with the library's configuration rule instead of the autotuner's choice")
     ap.add_argument("--profile-run", action="store_true",
@@ -473,7 +475,7 @@ def main():
     # of events around a launch costs a few microseconds of device time)
     kernels = [("columns", 1), ("mgs", 8), ("spmv_a", 16), ("apply_p", 16), ("residual", 1), ("update", 1)]
     rec, wall, timings, choice = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels,
-                                          args.ortho, not args.no_tune)
+                                          args.ortho, not args.no_tune, args.graph)
     log(f"mixed form: {[(round(a, 1), round(c, 1)) for a, c, *_ in rec]} ms (build, solve)")
     step_ms = [a + c for a, c, *_ in rec]
     build_ms = [a for a, *_ in rec]

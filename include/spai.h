@@ -206,6 +206,11 @@ typedef struct {
     double tol_ir;  /* refinement stops when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf */
     int32_t ortho;  /* SPAI_ORTHO_MGS (0, default), SPAI_ORTHO_CGS2 or SPAI_ORTHO_DCGS2 */
     spai_prec u;    /* working precision: SPAI_FP64 (0, default) or SPAI_FP32 */
+    int32_t graph;  /* DCGS2 only: 1 = each chunk of 8 Arnoldi steps (the operator's two
+                       sparse products and the orthogonalisation launch, per step) is one
+                       HIP graph, built once per call and replayed; the kernels take the
+                       step index from the device solver state.  Same results as 0
+                       (stream launches, default); other orthogonalisations ignore it. */
 } spai_ir_params;
 
 typedef struct {

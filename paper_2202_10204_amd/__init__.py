@@ -70,7 +70,7 @@ class _View(ctypes.Structure):
 
 class _IrParams(ctypes.Structure):
     _fields_ = [("u_r", ctypes.c_int), ("tau", _c_f64), ("imax", _c_i32), ("maxit", _c_i32),
-                ("tol_ir", _c_f64), ("ortho", _c_i32), ("u", ctypes.c_int)]
+                ("tol_ir", _c_f64), ("ortho", _c_i32), ("u", ctypes.c_int), ("graph", _c_i32)]
 
 
 ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
@@ -363,8 +363,11 @@ class Handle:
 
     # -- Algorithm 3 ---------------------------------------------------------
     def gmres_ir(self, A: DeviceCSR, P: Precond, b: torch.Tensor, x: torch.Tensor, tau: float, imax: int,
-                 maxit: int, tol_ir: float, u_r: str = "dd", ortho: str = "mgs", u: str = "fp64"):
-        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO[ortho], PREC[u])
+                 maxit: int, tol_ir: float, u_r: str = "dd", ortho: str = "mgs", u: str = "fp64",
+                 graph: bool = False):
+        """graph: replay each chunk of DCGS2 Arnoldi steps as one HIP graph (same results)."""
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO[ortho], PREC[u],
+                        int(bool(graph)))
         st = _IrStats()
         csr = A.c()
         rc = _check(lib().spai_gmres_ir(self._raw, ctypes.byref(csr), P.raw, _ptr(b), _ptr(x),
@@ -457,7 +460,8 @@ def _serve_request(A, b, pattern, build: dict, ir: dict):
                       PREC[build["u_f"]], SIDE[build.get("side", "left")], int(bool(build.get("qr_update", 0))),
                       int(build.get("kernel_cfg", 0)))
     ip = _IrParams(PREC[ir.get("u_r", "dd")], float(ir["tau"]), int(ir["imax"]), int(ir["maxit"]),
-                   float(ir["tol_ir"]), ORTHO[ir.get("ortho", "mgs")], PREC[ir.get("u", "fp64")])
+                   float(ir["tol_ir"]), ORTHO[ir.get("ortho", "mgs")], PREC[ir.get("u", "fp64")],
+                   int(bool(ir.get("graph", 0))))
     r = _ServeRequest(int(A.n), int(ci.size), rp.ctypes.data, ci.ctypes.data, av.ctypes.data, bb.ctypes.data,
                       int(ji.size) if ji is not None else 0, jp.ctypes.data if jp is not None else None,
                       ji.ctypes.data if ji is not None else None, bp, ip)

@@ -32,7 +32,7 @@ struct SolveState {
     int done;       // 0 running, 1 converged, 2 maxit reached, 3 device error
     int its;        // GMRES iterations of the step once done
     int err;        // 1: a grid-wide sum timed out
-    int pad;
+    int jcur;       // graph replay: index of the next Arnoldi step (advanced by its launch)
 };
 
 // ---------------------------------------------------------------------------
@@ -53,8 +53,9 @@ template <int G, int R>
 __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ av, const double* __restrict__ x,
                                                 double* __restrict__ y, const double* __restrict__ dout,
-                                                const SolveState* __restrict__ st) {
+                                                const SolveState* __restrict__ st, int by_step) {
     if (st && st->done) return;
+    if (by_step) x += (size_t)st->jcur * n;  // graph replay: x is column jcur of the basis
     // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
     constexpr int GPB = 256 / G;
     const int sub = threadIdx.x & (G - 1);
@@ -89,8 +90,10 @@ template <int VP, int G, int R, bool RIGHT, bool SCALED = false>
 __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                                                    const typename ValType<VP>::T* __restrict__ pv,
                                                    const double* __restrict__ d, const double* __restrict__ w,
-                                                   double* __restrict__ y, const SolveState* __restrict__ st) {
+                                                   double* __restrict__ y, const SolveState* __restrict__ st,
+                                                   int by_step) {
     if (st && st->done) return;
+    if (by_step) w += (size_t)st->jcur * n;  // graph replay: w is column jcur of the basis
     // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
     constexpr int GPB = 256 / G;
     const int sub = threadIdx.x & (G - 1);
@@ -246,6 +249,7 @@ struct ArnoldiArgs {
     SolveState* st;
     double* HRp;         // DCGS2: first projections, column-major ld x maxit
     double* HRf;         // DCGS2: completed Hessenberg columns before rotation, row-major (maxit+1) x maxit
+    int by_step;         // DCGS2 graph replay: j = st->jcur (parity j & 1), advanced by block 0
 };
 
 // Grid-wide sum of one double per block, in two hops that keep every polled
@@ -1057,6 +1061,10 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
     __shared__ double wsum2[2 * (AT_DATA / 64)];
     __shared__ int abort_flag;
     if (a.st->done) return;                  // uniform: written by an earlier launch
+    if (a.by_step) {                         // graph replay: the step comes from the solver state
+        a.j = a.st->jcur;
+        a.parity = a.j & 1;
+    }
     const int b = blockIdx.x, t = threadIdx.x, nb = a.nb, lane = t & 63, wave = t >> 6;
     const bool data = t < AT_DATA;
     const int gstride = nb * AT_DATA;
@@ -1146,6 +1154,9 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
         __builtin_amdgcn_s_setprio(3);
         dcgs2_rows(a, hv, nu, gj);
         if (b == 0 && j >= 1) dcgs2_givens(a, hv, nu, hh, csL, snL);
+        // every block read the step index before publishing its partial sums,
+        // which this block has received: the next launch's index can be set
+        if (a.by_step && b == 0 && lane == 0) a.st->jcur = j + 1;
         __builtin_amdgcn_s_setprio(0);
     }
 }
@@ -1404,6 +1415,7 @@ __global__ void k_init_state(double* g, int len, const double* beta0, SolveState
         st->done = 0;
         st->its = 0;
         st->err = 0;
+        st->jcur = 0;
         st->gabs = *beta0;
     }
 }
@@ -1426,14 +1438,14 @@ constexpr int APPLY_R = 4;
 
 template <int VP, bool RIGHT, bool SCALED = false>
 static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
-                      const SolveState* st) {
+                      const SolveState* st, int by_step) {
     using T = typename ValType<VP>::T;
     const T* pv = (const T*)P->val;
     const long long groups = ((long long)n + APPLY_R - 1) / APPLY_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
 #define SPAI_AP(G)                                                                                       \
     hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT, SCALED>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
-                       P->col, pv, P->d, w, y, st)
+                       P->col, pv, P->d, w, y, st, by_step)
     switch (g) {
     case 1: SPAI_AP(1); break;
     case 2: SPAI_AP(2); break;
@@ -1446,15 +1458,16 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
 
 // scaled: (left preconditioner) w already holds D w, as written by a product
 // with output scaling d
+// by_step (graph replay, st set): the input is column st->jcur of the basis starting at w
 static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
-                          const SolveState* st = nullptr, bool scaled = false) {
+                          const SolveState* st = nullptr, bool scaled = false, int by_step = 0) {
     const int n = P->n, g = lanes_per_row(P->nnz, n);
     long tk = timer_begin(h, SPAI_KT_APPLY_P);
     const int mode = P->side == SPAI_RIGHT ? 2 : scaled ? 1 : 0;
 #define SPAI_AP_MODE(VP)                                     \
-    if (mode == 2) apply_P_g<VP, true>(g, n, P, w, y, s, st);          \
-    else if (mode == 1) apply_P_g<VP, false, true>(g, n, P, w, y, s, st); \
-    else apply_P_g<VP, false>(g, n, P, w, y, s, st);
+    if (mode == 2) apply_P_g<VP, true>(g, n, P, w, y, s, st, by_step);          \
+    else if (mode == 1) apply_P_g<VP, false, true>(g, n, P, w, y, s, st, by_step); \
+    else apply_P_g<VP, false>(g, n, P, w, y, s, st, by_step);
     switch (P->val_prec) {
     case SPAI_FP64: SPAI_AP_MODE(SPAI_FP64); break;
     case SPAI_FP32: SPAI_AP_MODE(SPAI_FP32); break;
@@ -1467,16 +1480,16 @@ static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w
     return SPAI_OK;
 }
 
-// dout (may be NULL): output scaling, y_i = dout_i (A x)_i
+// dout (may be NULL): output scaling, y_i = dout_i (A x)_i; by_step as launch_apply_P
 static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
-                       const SolveState* st = nullptr, const double* dout = nullptr) {
+                       const SolveState* st = nullptr, const double* dout = nullptr, int by_step = 0) {
     const int n = A->n, g = lanes_per_row(A->nnz, n);
     const long long groups = ((long long)n + SPMV_R - 1) / SPMV_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
     long tk = timer_begin(h, SPAI_KT_SPMV_A);
 #define SPAI_SP(G)                                                                                              \
     hipLaunchKernelGGL((k_spmv_g<G, SPMV_R>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, \
-                       dout, st)
+                       dout, st, by_step)
     switch (g) {
     case 1: SPAI_SP(1); break;
     case 2: SPAI_SP(2); break;
@@ -1661,6 +1674,61 @@ struct EventPair {
     }
 };
 
+// A chunk of DCGS2 Arnoldi steps as one HIP graph (graph and executable,
+// destroyed with the scope).
+struct ChunkGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~ChunkGraph() {
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+// Captures `steps` Arnoldi steps (operator products, then the DCGS2 launch) on a
+// private stream into cg: every kernel takes the step index from st->jcur and
+// the DCGS2 launch advances it, so one executable serves every chunk of every
+// refinement step of this call.  No timing events are recorded inside.
+static int capture_chunk(spai_handle* h, const spai_csr* A, const spai_precond* P, const ArnoldiCfg& cfg,
+                         ArnoldiArgs aa, double* V, double* w, double* y, SolveState* sst, int steps,
+                         ChunkGraph& cg) {
+    hipStream_t cs = nullptr;
+    SPAI_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    int saved[SPAI_KT_COUNT];
+    for (int k = 0; k < SPAI_KT_COUNT; ++k) {
+        saved[k] = h->timers[k].every;
+        h->timers[k].every = 0;
+    }
+    const bool right = P->side == SPAI_RIGHT;
+    aa.by_step = 1;
+    aa.j = 0;
+    aa.parity = 0;
+    int rc = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess ? SPAI_OK : SPAI_E_HIP;
+    const bool capturing = rc == SPAI_OK;
+    for (int q = 0; q < steps && rc == SPAI_OK; ++q) {
+        if (right) {                                               // y = A P v_j
+            rc = launch_apply_P(h, P, V, w, cs, sst, false, 1);
+            if (!rc) rc = launch_spmv(h, A, w, y, cs, sst);
+        } else {                                                   // y = M^T (D (A v_j))
+            rc = launch_spmv(h, A, V, w, cs, sst, P->d, 1);
+            if (!rc) rc = launch_apply_P(h, P, w, y, cs, sst, true);
+        }
+        if (!rc) rc = launch_arnoldi(h, cfg, aa, cs);
+    }
+    hipGraph_t g = nullptr;
+    if (capturing && hipStreamEndCapture(cs, &g) != hipSuccess && rc == SPAI_OK) rc = SPAI_E_HIP;
+    for (int k = 0; k < SPAI_KT_COUNT; ++k) h->timers[k].every = saved[k];
+    if (rc == SPAI_OK && g) {
+        cg.g = g;
+        if (hipGraphInstantiate(&cg.x, g, nullptr, nullptr, 0) != hipSuccess) rc = SPAI_E_HIP;
+    } else if (g) {
+        (void)hipGraphDestroy(g);
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc == SPAI_E_HIP) set_error("capturing the Arnoldi chunk into a HIP graph failed");
+    return rc;
+}
+
 int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b, double* x,
                   const spai_ir_params* prm, spai_ir_stats* st) {
     SPAI_ARG(h && prm, "NULL handle or parameters");
@@ -1734,6 +1802,17 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     EventPair ev;          // completion of the flag copies of the last two chunks
     if ((rc = ev.create())) return rc;
 
+    // graph replay of the Arnoldi chunks (DCGS2 with ordinary launches only)
+    ChunkGraph cgraph;
+    const bool use_graph = prm->graph && dcgs2 && cfg.nb && !use_cooperative_launch();
+    if (use_graph) {
+        ArnoldiArgs aa{};
+        aa.n = n; aa.ld = ld; aa.maxit = maxit; aa.maxlinks = maxlinks; aa.nb = cfg.nb;
+        aa.y = y; aa.V = V; aa.H = H; aa.cs = cs; aa.sn = sn; aa.g = g; aa.tau = prm->tau;
+        aa.slots = slots; aa.st = sst; aa.HRp = HRp; aa.HRf = HRf;
+        if ((rc = capture_chunk(h, A, P, cfg, aa, V, w, y, sst, chunk, cgraph))) return rc;
+    }
+
     int status = 0;
     spai_ir_stats loc{};
     if ((rc = launch_x0(P, b, x, s))) return rc;   // x0 = P b in u_f
@@ -1777,6 +1856,12 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
         int cidx = 0;
         for (int j0 = 0; j0 < jend; j0 += chunk, ++cidx) {
             int j1 = std::min(j0 + chunk, jend);
+            if (use_graph) {
+                // steps j0 .. j0 + chunk - 1; those at or past jend return at once
+                // (the stop flag is set by launch maxit at the latest)
+                SPAI_HIP(hipGraphLaunch(cgraph.x, s));
+                j1 = j0;
+            }
             for (int j = j0; j < j1; ++j) {
                 double* vj = V + (size_t)j * n;
                 if (right) {                                               // y = A P v_j

@@ -202,6 +202,24 @@ def test_closed_forms_on_device(S, h):
     assert st["max_steps"] == 1
 
 
+@pytest.mark.parametrize("uf", ["fp32", "fp16"])
+def test_power_of_two_row_scaling_on_device(S, h, uf):
+    """Rows of A scaled by 2^k_i: the scaling D absorbs them exactly, so the device
+    build returns the same M bit for bit and d scaled by 2^-k_i."""
+    w = W.random_system(3000, 7)
+    k = np.random.default_rng(31).integers(-10, 11, w.n)
+    scale = np.repeat(np.ldexp(1.0, k), np.diff(w.A.rowptr))
+    As = W.CSR(w.n, w.A.rowptr, w.A.col, w.A.val * scale)
+    s = w.spai
+    P1, _, st1 = h.spai_build(S.DeviceCSR.from_host(w.A), None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    P2, _, st2 = h.spai_build(S.DeviceCSR.from_host(As), None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    a, b = [t.cpu().numpy() for t in P1.csr()], [t.cpu().numpy() for t in P2.csr()]
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(b[3], np.ldexp(a[3], -k))
+    assert st1["max_steps"] >= 1
+
+
 def test_build_is_deterministic(S, h):
     w = W.convdiff_adaptive(40)
     _, P1, _, _ = _build(S, h, w)

@@ -205,6 +205,44 @@ def test_full_pattern_reproduces_dense_inverse(uf, tol):
 # fixed-pattern columns vs the least-squares definition
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("uf", ["fp64", "fp32", "fp16"])
+def test_power_of_two_row_scaling_leaves_M_unchanged(uf):
+    """Section 4's scaling D = diag(1 / max_j |a_ij|) absorbs any row scaling of A
+    by powers of two exactly: B = (S A)^T D' = A^T D with D' = D S^-1, so Algorithm 1
+    sees the same B and returns the same M bit for bit (adaptive pattern included),
+    while d scales by 2^-k_i.  A scaling taken from the columns, or applied on the
+    other side of A, breaks this; scaling the columns instead does change M."""
+    rng = np.random.default_rng(21)
+    n = 48
+    Ad = _random_dd(n, rng, density=0.12)
+    k = rng.integers(-8, 9, n)
+    R = O.spai(_csr(Ad), None, 0.2, 4, 3, 12, uf)
+    R2 = O.spai(_csr(Ad * np.ldexp(1.0, k)[:, None]), None, 0.2, 4, 3, 12, uf)
+    assert R.steps.max() >= 1                      # the adaptive path ran
+    assert np.array_equal(R.length, R2.length) and np.array_equal(R.J, R2.J)
+    assert np.array_equal(R.m, R2.m) and np.array_equal(R.res, R2.res)
+    assert np.array_equal(R2.d, np.ldexp(R.d, -k))
+    R3 = O.spai(_csr(Ad * np.ldexp(1.0, k)[None, :]), None, 0.2, 4, 3, 12, uf)
+    assert not np.array_equal(R3.m, R.m)
+
+
+def test_power_of_two_column_scaling_leaves_the_right_M_unchanged():
+    """The right form scales the columns of A to unit maximum, so A S with
+    S = diag(2^k_j) gives the same M (rows of P = D M scaled by 2^-k_i through d
+    only) and the same A P."""
+    rng = np.random.default_rng(22)
+    n = 40
+    Ad = _random_dd(n, rng, density=0.15)
+    k = rng.integers(-8, 9, n)
+    R, pp, pc, pv, d = O.spai_right(_csr(Ad), None, 0.25, 3, 4, 10, "fp32")
+    R2, pp2, pc2, pv2, d2 = O.spai_right(_csr(Ad * np.ldexp(1.0, k)[None, :]), None, 0.25, 3, 4, 10, "fp32")
+    assert np.array_equal(pp, pp2) and np.array_equal(pc, pc2) and np.array_equal(pv, pv2)
+    assert np.array_equal(d2, np.ldexp(d, -k))
+    P = np.diag(d) @ sp.csr_matrix((pv, pc, pp), shape=(n, n)).toarray()
+    P2 = np.diag(d2) @ sp.csr_matrix((pv2, pc2, pp2), shape=(n, n)).toarray()
+    assert np.array_equal(Ad @ P, (Ad * np.ldexp(1.0, k)[None, :]) @ P2)
+
+
 @pytest.mark.parametrize("make", [lambda: W.convdiff_small(16), lambda: W.aniso_fixed(6)])
 def test_fixed_pattern_fp64_matches_lstsq(make):
     w = make()

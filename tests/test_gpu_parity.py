@@ -416,6 +416,44 @@ def test_gmres_ir_other_orthogonalisations_match_oracle(S, h, make, ortho):
     assert np.abs(x - oref.x).max() <= 1e-12 * np.abs(w.x_true).max()
 
 
+def _tiny_system(n, seed):
+    """Dense-ish nonsymmetric system with entries on a 1/8 grid and x on a 1/1024
+    grid: b = A x is exact in binary64."""
+    rng = np.random.default_rng(seed)
+    M = rng.integers(-8, 9, (n, n)) * (rng.random((n, n)) < 0.5) / 8.0
+    np.fill_diagonal(M, 0.0)
+    np.fill_diagonal(M, np.abs(M).sum(1) + rng.integers(1, 9, n) / 8.0)
+    import scipy.sparse as sp
+
+    C = sp.csr_matrix(M)
+    C.sort_indices()
+    A = W.CSR(n, C.indptr.astype(np.int32), C.indices.astype(np.int32), C.data.astype(np.float64))
+    x = rng.integers(-1024, 1025, n) / 1024.0
+    return A, M @ x, x
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 37, 65])
+@pytest.mark.parametrize("ortho", ["mgs", "cgs2", "dcgs2"])
+def test_tiny_systems_match_oracle(S, h, n, ortho):
+    """Degenerate sizes (one unknown, fewer unknowns than a wave, than a block):
+    the build is bit-exact and the solve gives the oracle's tuple and x."""
+    A, b, xt = _tiny_system(n, 40 + n)
+    eps, alpha, beta, maxfill = 0.3, 4, 2, 6
+    P, warn, st = h.spai_build(S.DeviceCSR.from_host(A), None, eps, alpha, beta, maxfill, "fp32")
+    ref = O.spai(A, None, eps, alpha, beta, maxfill, "fp32")
+    pp, pc, pv = ref.P_csr(n)
+    rp, col, val, d = (t.cpu().numpy() for t in P.csr())
+    assert np.array_equal(rp, pp) and np.array_equal(col, pc) and np.array_equal(val.astype(np.float64), pv)
+    bd = _dev(b)
+    x = torch.zeros_like(bd)
+    r = h.gmres_ir(S.DeviceCSR.from_host(A), P, bd, x, 1e-8, 10, 50, 2.0 ** -45, "dd", ortho)
+    oref = O.gmres_ir(A, pp, pc, pv, ref.d, "fp32", b, 1e-8, 10, min(50, n), 2.0 ** -45, ortho)
+    assert r["its"] == list(oref.its), (r["its"], oref.its)
+    xg = x.cpu().numpy()
+    assert np.abs(xg - oref.x).max() <= 1e-12 * np.abs(xt).max()
+    assert O.ferr(xg, xt) <= 1e-12
+
+
 @pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
 def test_full_size_solve_other_orthogonalisations_match_oracle_tuple(S, h, full, ortho):
     """CGS2 / delayed CGS2 at full size: the oracle's tuple for the same

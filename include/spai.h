@@ -438,11 +438,13 @@ int spai_serve_submit(spai_server* S, const spai_serve_request* r, int64_t* id);
 /* Block until request `id` is done, copy its solution into x (host, n values;
  * may be NULL) and its record into *res (may be NULL), and forget it.  Returns
  * the request's outcome (res->rc; spai_last_error() describes a negative one),
- * or SPAI_E_ARG for an unknown id. */
+ * or SPAI_E_ARG for an unknown id or one another caller is already waiting for.
+ * Waits for different ids may run concurrently from several threads. */
 int spai_serve_wait(spai_server* S, int64_t id, double* x, spai_serve_result* res);
 
 /* Finish every queued request, stop the lanes and free the server.  Results not
- * yet collected are dropped. */
+ * yet collected are dropped.  No other thread may be inside a spai_serve_* call on
+ * this server meanwhile. */
 int spai_serve_destroy(spai_server* S);
 
 #ifdef __cplusplus

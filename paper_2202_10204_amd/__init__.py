@@ -508,7 +508,9 @@ class Server:
 
     def wait(self, rid: int):
         """Block until request ``rid`` is done; returns (rc, x or None, record dict)."""
-        n = self._n.pop(rid)
+        n = self._n.pop(rid, None)
+        if n is None:
+            raise SpaiError(f"spai_serve_wait: unknown or already collected request {rid}")
         x = np.empty(n, np.float64)
         res = _ServeResult()
         rc = lib().spai_serve_wait(self._raw, int(rid), x.ctypes.data, ctypes.byref(res))

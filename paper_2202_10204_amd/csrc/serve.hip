@@ -35,6 +35,7 @@ struct Request {
     spai_serve_result res{};
     std::string err;
     bool done = false;
+    bool claimed = false;   // a caller is waiting for it
 };
 
 // Requests that can share one batch: the same build and solve parameters and
@@ -643,6 +644,8 @@ extern "C" int spai_serve_wait(spai_server* S, int64_t id, double* x, spai_serve
         auto it = S->reqs.find(id);
         SPAI_ARG(it != S->reqs.end(), "unknown request id");
         Request* r = it->second.get();
+        SPAI_ARG(!r->claimed, "another caller is already waiting for this request");
+        r->claimed = true;
         S->cv.wait(l, [&] { return r->done; });
         q = std::move(it->second);
         S->reqs.erase(it);

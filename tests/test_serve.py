@@ -180,3 +180,25 @@ def test_device_lane_serves_smallest_first(S):
         assert all(r["lane"] == -1 for r in recs)
         assert recs[0]["t_admit"] <= min(recs[1]["t_admit"], recs[2]["t_admit"])
         assert (recs[2]["t_admit"] < recs[1]["t_admit"]) == expect_small_first, (age, recs)
+
+
+def test_second_waiter_for_one_request_is_rejected(S):
+    """A request is waited for once: a second concurrent wait (or one after the
+    first collected it) fails cleanly instead of racing for the result."""
+    import threading
+    import time
+
+    w = W.serving_request(W.Arrival(0.0, "convdiff", 300, "fp32", 300))
+    srv = S.Server(batch_lanes=1, batch_max_n=1000, hbm_budget=8 << 30, lane_workspace=256 << 20)
+    rid = srv.submit(*_args(w))
+    got = {}
+    t = threading.Thread(target=lambda: got.update(r=srv.wait(rid)))
+    t.start()
+    time.sleep(0.05)
+    assert S.lib().spai_serve_wait(srv._raw, int(rid), None, None) == S.E_ARG
+    t.join()
+    with pytest.raises(S.SpaiError):
+        srv.wait(rid)
+    srv.close()
+    rc, x, rec = got["r"]
+    assert rc >= 0 and O.ferr(x, w.x_true) <= 1e-12

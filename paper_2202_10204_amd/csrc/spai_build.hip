@@ -41,37 +41,69 @@ struct PrepOut {
     int max_pat;    // longest initial pattern column
 };
 
-__global__ void k_validate_scale(int n, int nnz, const int* __restrict__ rp, const int* __restrict__ ci,
+// Reductions of one value per lane over the 64 lanes of a wave (every lane takes
+// part).  Atomics on one address serialise at the memory side (one per wave
+// already, the compiler combining a wave's lanes), so the counters and maxima of
+// the build are reduced over a whole block of a grid-stride launch first.
+constexpr int RED_BLOCK = 256;   // threads of the grid-stride reduction kernels
+
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(RED_BLOCK) void k_validate_scale(int n, int nnz, const int* __restrict__ rp,
+                                                               const int* __restrict__ ci,
                                  const double* __restrict__ av, double* __restrict__ d,
                                  int* __restrict__ colcount, PrepOut* out) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    int s = rp[j], e = rp[j + 1];
-    int err = 0;
-    if (j == 0 && s != 0) err |= 1;
-    if (j == n - 1 && e != nnz) err |= 1;
-    if (e < s || s < 0 || e > nnz) {
-        atomicOr(&out->err, err | 1);
-        d[j] = 1.0;
-        return;
+    __shared__ int sh[RED_BLOCK / 64];
+    int len = 0;
+    for (int j = blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += gridDim.x * RED_BLOCK) {
+        int s = rp[j], e = rp[j + 1];
+        int err = 0;
+        if (j == 0 && s != 0) err |= 1;
+        if (j == n - 1 && e != nnz) err |= 1;
+        if (e < s || s < 0 || e > nnz) {
+            atomicOr(&out->err, err | 1);
+            d[j] = 1.0;
+        } else {
+            double mx = 0.0;
+            int prev = -1;
+            for (int q = s; q < e; ++q) {
+                int c = ci[q];
+                double v = av[q];
+                if (c < 0 || c >= n || c <= prev) err |= 2;
+                prev = c;
+                if (!isfinite(v)) err |= 4;
+                double a = fabs(v);
+                if (a > mx) mx = a;
+                if (c >= 0 && c < n) atomicAdd(&colcount[c], 1);
+            }
+            if (!(mx > 0.0)) err |= 8;
+            // Section 4: scale so that the largest entry of every column of A^T D is 1
+            d[j] = mx > 0.0 ? 1.0 / mx : 1.0;
+            if (err) atomicOr(&out->err, err);
+            len = max(len, e - s);
+        }
     }
-    double mx = 0.0;
-    int prev = -1;
-    for (int q = s; q < e; ++q) {
-        int c = ci[q];
-        double v = av[q];
-        if (c < 0 || c >= n || c <= prev) err |= 2;
-        prev = c;
-        if (!isfinite(v)) err |= 4;
-        double a = fabs(v);
-        if (a > mx) mx = a;
-        if (c >= 0 && c < n) atomicAdd(&colcount[c], 1);
+    len = wave_max_i(len);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = len;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < RED_BLOCK / 64; ++w) len = max(len, sh[w]);
+        atomicMax(&out->max_row, len);
     }
-    if (!(mx > 0.0)) err |= 8;
-    // Section 4: scale so that the largest entry of every column of A^T D is 1
-    d[j] = mx > 0.0 ? 1.0 / mx : 1.0;
-    if (err) atomicOr(&out->err, err);
-    atomicMax(&out->max_row, e - s);
 }
 
 // ||B(:,j)||^2 = sum over row j of A (CSR order) of (u_f(d_j a_jl))^2, in F
@@ -90,9 +122,17 @@ __global__ void k_colnorm(int n, const int* __restrict__ rp, const double* __res
     bn[j] = s;
 }
 
-__global__ void k_max_count(int n, const int* __restrict__ cnt, PrepOut* out) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) atomicMax(&out->max_col, cnt[j]);
+__global__ __launch_bounds__(RED_BLOCK) void k_max_count(int n, const int* __restrict__ cnt, PrepOut* out) {
+    __shared__ int sh[RED_BLOCK / 64];
+    int v = 0;
+    for (int j = blockIdx.x * RED_BLOCK + threadIdx.x; j < n; j += gridDim.x * RED_BLOCK) v = max(v, cnt[j]);
+    v = wave_max_i(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < RED_BLOCK / 64; ++w) v = max(v, sh[w]);
+        atomicMax(&out->max_col, v);
+    }
 }
 
 __global__ void k_fill_csc(int n, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -145,15 +185,31 @@ __global__ void k_scan_block(int n, const int* __restrict__ in, int* __restrict_
     if (threadIdx.x == SCAN_BLOCK - 1) block_sums[blockIdx.x] = sh[threadIdx.x];
 }
 
-__global__ void k_scan_sums(int nb, int* __restrict__ block_sums, int* __restrict__ total) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// exclusive scan of the block sums by one block of SCAN_BLOCK threads: each
+// thread scans a contiguous run of them, the runs' totals are scanned in LDS
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int nb, int* __restrict__ block_sums,
+                                                          int* __restrict__ total) {
+    __shared__ int sh[SCAN_BLOCK];
+    const int t = threadIdx.x;
+    const int per = (nb + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const int lo = min(nb, t * per), hi = min(nb, lo + per);
     int run = 0;
-    for (int b = 0; b < nb; ++b) {
-        int v = block_sums[b];
-        block_sums[b] = run;
-        run += v;
+    for (int b = lo; b < hi; ++b) run += block_sums[b];
+    sh[t] = run;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {
+        const int v = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
     }
-    *total = run;
+    int base = sh[t] - run;
+    for (int b = lo; b < hi; ++b) {
+        const int v = block_sums[b];
+        block_sums[b] = base;
+        base += v;
+    }
+    if (t == SCAN_BLOCK - 1) *total = sh[t];
 }
 
 __global__ void k_scan_add(int n, int* __restrict__ out, const int* __restrict__ block_sums,
@@ -789,20 +845,63 @@ struct BuildStatsDev {
     unsigned long long max_res_bits;
 };
 
-__global__ void k_build_stats(int n, const int* __restrict__ len, const int* __restrict__ steps,
+__global__ __launch_bounds__(RED_BLOCK) void k_build_stats(int n, const int* __restrict__ len, const int* __restrict__ steps,
                               const double* __restrict__ res, const int* __restrict__ flags,
                               const int* __restrict__ nI, BuildStatsDev* st) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int f = flags[k];
-    if (f & CF_EPS) atomicAdd(&st->over_eps, 1);
-    if (f & CF_RANKDEF) atomicAdd(&st->rankdef, 1);
-    if (f & CF_NONFINITE) atomicAdd(&st->nonfinite, 1);
-    atomicMax(&st->max_len, len[k]);
-    atomicMax(&st->max_steps, steps[k]);
-    atomicMax(&st->max_shadow, nI[k]);
-    double r = res[k];
-    if (r >= 0.0) atomicMax(&st->max_res_bits, (unsigned long long)__double_as_longlong(r));
+    __shared__ int shi[6][RED_BLOCK / 64];
+    __shared__ unsigned long long shr[RED_BLOCK / 64];
+    int c_eps = 0, c_rd = 0, c_nf = 0, l = 0, sp = 0, sh = 0;
+    unsigned long long rb = 0ull;   // non-negative doubles order as their bit patterns
+    for (int k = blockIdx.x * RED_BLOCK + threadIdx.x; k < n; k += gridDim.x * RED_BLOCK) {
+        const int f = flags[k];
+        c_eps += (f & CF_EPS) ? 1 : 0;
+        c_rd += (f & CF_RANKDEF) ? 1 : 0;
+        c_nf += (f & CF_NONFINITE) ? 1 : 0;
+        l = max(l, len[k]);
+        sp = max(sp, steps[k]);
+        sh = max(sh, nI[k]);
+        const double r = res[k];
+        if (r >= 0.0) {
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(r);
+            rb = bits > rb ? bits : rb;
+        }
+    }
+    c_eps = wave_sum_i(c_eps);
+    c_rd = wave_sum_i(c_rd);
+    c_nf = wave_sum_i(c_nf);
+    l = wave_max_i(l);
+    sp = wave_max_i(sp);
+    sh = wave_max_i(sh);
+    rb = wave_max_u64(rb);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        shi[0][w] = c_eps;
+        shi[1][w] = c_rd;
+        shi[2][w] = c_nf;
+        shi[3][w] = l;
+        shi[4][w] = sp;
+        shi[5][w] = sh;
+        shr[w] = rb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < RED_BLOCK / 64; ++v) {
+            c_eps += shi[0][v];
+            c_rd += shi[1][v];
+            c_nf += shi[2][v];
+            l = max(l, shi[3][v]);
+            sp = max(sp, shi[4][v]);
+            sh = max(sh, shi[5][v]);
+            rb = shr[v] > rb ? shr[v] : rb;
+        }
+        if (c_eps) atomicAdd(&st->over_eps, c_eps);
+        if (c_rd) atomicAdd(&st->rankdef, c_rd);
+        if (c_nf) atomicAdd(&st->nonfinite, c_nf);
+        atomicMax(&st->max_len, l);
+        atomicMax(&st->max_steps, sp);
+        atomicMax(&st->max_shadow, sh);
+        if (rb) atomicMax(&st->max_res_bits, rb);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1003,11 +1102,13 @@ static int tune_columns(spai_handle* h, int pmax, const ColArgs& a, hipStream_t 
     return rc;
 }
 
+static int blocks_red(int n) { return std::max(1, (n + RED_BLOCK - 1) / RED_BLOCK); }
+
 static int scan_ints(int n, const int* in, int* out, int* tmp_blocks, int* total, hipStream_t s) {
     int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(SCAN_BLOCK), 0, s, n, in, out, tmp_blocks);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1), 0, s, nb, tmp_blocks, total);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, nb, tmp_blocks, total);
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, s, n, out, tmp_blocks, total);
     SPAI_HIP(hipGetLastError());
     return SPAI_OK;
@@ -1208,9 +1309,10 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     SPAI_HIP(hipMemsetAsync(bst, 0, sizeof(BuildStatsDev), s));
     if ((rc = dev_alloc(h, &P->d, n))) return fail(rc);
     const int tb = 256, gb = (n + tb - 1) / tb;
-    hipLaunchKernelGGL(k_validate_scale, dim3(gb), dim3(tb), 0, s, n, nnz, A->rowptr, A->col, A->val,
+    const int rgb = std::min(blocks_red(n), 4 * std::max(h->num_cu, 1));
+    hipLaunchKernelGGL(k_validate_scale, dim3(rgb), dim3(RED_BLOCK), 0, s, n, nnz, A->rowptr, A->col, A->val,
                        P->d, cnt, prep);
-    hipLaunchKernelGGL(k_max_count, dim3(gb), dim3(tb), 0, s, n, cnt, prep);
+    hipLaunchKernelGGL(k_max_count, dim3(rgb), dim3(RED_BLOCK), 0, s, n, cnt, prep);
     if (J)
         hipLaunchKernelGGL(k_validate_pattern, dim3(gb), dim3(tb), 0, s, n, J->nnz, J->ptr, J->idx, prep);
     SPAI_HIP(hipGetLastError());
@@ -1303,7 +1405,8 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     // compaction into CSR(P)
     if ((rc = dev_alloc(h, &P->rowptr, (size_t)n + 1))) return fail(rc);
     if ((rc = scan_ints(n, P->len, P->rowptr, blk, tot, s))) return fail(rc);
-    hipLaunchKernelGGL(k_build_stats, dim3(gb), dim3(tb), 0, s, n, P->len, P->steps, P->res, P->flags, nI, bst);
+    hipLaunchKernelGGL(k_build_stats, dim3(rgb), dim3(RED_BLOCK), 0, s, n, P->len, P->steps, P->res, P->flags, nI,
+                       bst);
     SPAI_HIP(hipMemcpyAsync(hp, tot, sizeof(int), hipMemcpyDeviceToHost, s));
     SPAI_HIP(hipMemcpyAsync(hp + 64, bst, sizeof(BuildStatsDev), hipMemcpyDeviceToHost, s));
     SPAI_HIP(hipStreamSynchronize(s));

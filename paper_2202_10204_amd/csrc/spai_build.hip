@@ -23,6 +23,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -260,6 +261,14 @@ struct Cfg {
     static constexpr int MAXM = MAXM_;     // rows of A-bar
     static constexpr int LD = MAXM_ + 1;   // odd leading dimension
     static constexpr int EMAX = EMAX_;     // gathered entries of B(:, J) (power of two)
+    // Sort keys of the gathered entries, (row, slot): 32 bits (row relative to the
+    // smallest gathered row, then log2(EMAX) slot bits) when EMAX <= 256, so a
+    // column whose rows span 2^(32 - log2 EMAX) or more is deferred; the largest
+    // configuration keeps (row << 32 | slot).
+    static constexpr bool KEY32 = EMAX_ <= 256;
+    using Key = std::conditional_t<KEY32, uint32_t, uint64_t>;
+    static constexpr int SB = EMAX_ <= 64 ? 6 : EMAX_ <= 128 ? 7 : EMAX_ <= 256 ? 8 : 32;
+    using Seg = std::conditional_t<(EMAX_ <= 255), uint8_t, uint16_t>;   // holds 0 .. EMAX
     static constexpr int CMAX = CMAX_;     // raw candidate entries (power of two)
     static constexpr int PPW = 64 / G_;    // problems per wavefront
 };
@@ -295,7 +304,7 @@ template <class C> struct QrCand<C, true> {
 template <class C, bool INC>
 struct alignas(16) Smem {
     using F = typename C::F;
-    uint64_t gkey[C::EMAX];  // (row i << 32) | slot, sorted by row then slot
+    typename C::Key gkey[C::EMAX];  // (row, slot), sorted by row then slot
     QrCand<C, INC> u;
 
     F gval[C::EMAX];         // u_f(d_j a_ji) by slot
@@ -303,14 +312,11 @@ struct alignas(16) Smem {
     uint8_t gpos[C::EMAX];   // row position in I of sorted entry e
     int I[C::MAXM];          // shadow in insertion order: earlier solves' rows, then new rows ascending
     uint8_t dpos[C::MAXM];   // position in I of the d-th row in ascending order
-    int seg[C::MAXM + 1];    // first sorted entry of the d-th row in ascending order
+    typename C::Seg seg[C::MAXM + 1];   // first sorted entry of the d-th row in ascending order
     F s[C::MAXM];            // residual s-bar (rows in insertion order)
     int J[C::MAXP + 1];
     F mb[C::MAXP + 1];
     F Rd[C::MAXP + 1];
-    F rf[C::G];              // group scratch
-    int ri[C::G];
-    int rj[C::G];
     F fs[4];
     int is[4];
 };
@@ -352,13 +358,33 @@ __device__ __forceinline__ int bsearch_sorted(const int* v, int len, int key) {
     return -1;
 }
 
+// rows and slots of the sort keys (rbase: the smallest gathered row of the
+// column, for the 32-bit keys); key_rel orders keys by row alone
+template <class C>
+__device__ __forceinline__ uint32_t key_rel(typename C::Key k) {
+    if constexpr (C::KEY32) return k >> C::SB;
+    else return (uint32_t)(k >> 32);
+}
+template <class C>
+__device__ __forceinline__ int key_row(typename C::Key k, int rbase) {
+    if constexpr (C::KEY32) return (int)(k >> C::SB) + rbase;
+    else return (int)(uint32_t)(k >> 32);
+}
+template <class C>
+__device__ __forceinline__ int key_slot(typename C::Key k) {
+    if constexpr (C::KEY32) return (int)(k & ((1u << C::SB) - 1u));
+    else return (int)(uint32_t)(k & 0xffffffffu);
+}
+
 // index d of row i among the shadow rows in ascending order (the row of the d-th
-// segment is the high word of its first sorted entry), or -1
-__device__ __forceinline__ int bsearch_rows(const uint64_t* gkey, const int* seg, int m, int i) {
+// segment is the row of its first sorted entry), or -1
+template <class C>
+__device__ __forceinline__ int bsearch_rows(const typename C::Key* gkey, const typename C::Seg* seg, int m, int i,
+                                            int rbase) {
     int lo = 0, hi = m - 1;
     while (lo <= hi) {
         int mid = (lo + hi) >> 1;
-        int x = (int)(uint32_t)(gkey[seg[mid]] >> 32);
+        int x = key_row<C>(gkey[seg[mid]], rbase);
         if (x == i) return mid;
         if (x < i) lo = mid + 1;
         else hi = mid - 1;
@@ -374,6 +400,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
     const int wl = threadIdx.x;
     const int g = wl / G;
     const int lane = wl - g * G;
+    const int gl0 = wl - lane;                // first lane of the group (lane permutes stay inside it)
     if (g >= C::PPW) return;
     const int prob = blockIdx.x * C::PPW + g;
     if (prob >= a.ncols) return;
@@ -408,6 +435,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
     wave_sync();
     const int cap = a.maxfill > p ? a.maxfill : p;
     int flags = 0, step = 0, m = 0, kpos = -1, p_prev = 0;
+    int rbase = 0;                            // smallest gathered row (32-bit keys)
     F res = F(0);
     if (p == 0 && !defer) flags |= CF_EPS;
 
@@ -424,28 +452,44 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             mys = a.rp[myj];
             myn = a.rp[myj + 1] - mys;
         }
-        S.ri[lane] = myn;
-        wave_sync();
         int off = 0, E = 0;
         for (int t = 0; t < G; ++t) {
-            int v = S.ri[t];
+            const int v = __shfl(myn, gl0 + t, 64);
             off += (t < lane) ? v : 0;
             E += v;
         }
-        wave_sync();
         if (E > C::EMAX) { defer = true; break; }
+        int rlo = INT_MAX, rhi = -1;
         if (lane < p) {
             double dj = a.d[myj];
             for (int q = 0; q < myn; ++q) {
                 int slot = off + q;
                 int i = a.ci[mys + q];
-                S.gkey[slot] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)slot;
+                if constexpr (C::KEY32) {
+                    S.gkey[slot] = (uint32_t)i;        // the row; made a key below
+                    rlo = min(rlo, i);
+                    rhi = max(rhi, i);
+                } else {
+                    S.gkey[slot] = ((uint64_t)(uint32_t)i << 32) | (uint32_t)slot;
+                }
                 S.gval[slot] = scaled_entry<C::UF>(dj, a.av[mys + q]);
                 S.gcol[slot] = (uint8_t)lane;
             }
         }
+        if constexpr (C::KEY32) {
+            // rows relative to the smallest one, with the slot in the low bits
+            const int mylo = rlo, myhi = rhi;
+            for (int t = 0; t < G; ++t) {
+                rlo = min(rlo, __shfl(mylo, gl0 + t, 64));
+                rhi = max(rhi, __shfl(myhi, gl0 + t, 64));
+            }
+            wave_sync();                          // the raw rows are in gkey
+            rbase = rlo;
+            if (E > 0 && (unsigned)(rhi - rlo) >= (1u << (32 - C::SB)) - 1u) { defer = true; break; }
+            for (int e = lane; e < E; e += G) S.gkey[e] = ((S.gkey[e] - (uint32_t)rlo) << C::SB) | (uint32_t)e;
+        }
         const int E2 = next_pow2(E > 0 ? E : 1);
-        for (int e = E + lane; e < E2; e += G) S.gkey[e] = ~0ull;
+        for (int e = E + lane; e < E2; e += G) S.gkey[e] = ~typename C::Key(0);
         wave_sync();
         group_sort<G>(S.gkey, E2, lane);
         // count distinct rows
@@ -454,8 +498,8 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             int e = base + lane;
             bool head = false;
             if (e < E) {
-                uint32_t i = (uint32_t)(S.gkey[e] >> 32);
-                head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
+                const uint32_t i = key_rel<C>(S.gkey[e]);
+                head = (e == 0) || (key_rel<C>(S.gkey[e - 1]) != i);
             }
             m += __popcll(ballot(head) & gmask);
         }
@@ -473,9 +517,9 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                 int e = base + lane;
                 bool head = false, old = false;
                 if (e < E) {
-                    uint32_t i = (uint32_t)(S.gkey[e] >> 32);
-                    head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
-                    old = head && S.gcol[(uint32_t)(S.gkey[e] & 0xffffffffu)] < p_prev;
+                    const uint32_t i = key_rel<C>(S.gkey[e]);
+                    head = (e == 0) || (key_rel<C>(S.gkey[e - 1]) != i);
+                    old = head && S.gcol[key_slot<C>(S.gkey[e])] < p_prev;
                 }
                 const bool fresh = head && !old;
                 uint64_t bal = ballot(head) & gmask, obal = ballot(old) & gmask, nbal = ballot(fresh) & gmask;
@@ -497,27 +541,27 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                 bool head = false;
                 uint32_t i = 0;
                 if (e < E) {
-                    i = (uint32_t)(S.gkey[e] >> 32);
-                    head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != i);
+                    i = key_rel<C>(S.gkey[e]);
+                    head = (e == 0) || (key_rel<C>(S.gkey[e - 1]) != i);
                 }
                 uint64_t bal = ballot(head) & gmask;
                 if (head) {
                     const int d = run + __popcll(bal & below);
                     const int pos = S.gpos[e];
-                    S.seg[d] = e;
+                    S.seg[d] = (typename C::Seg)e;
                     S.dpos[d] = (uint8_t)pos;
-                    if (pos >= m_prev) S.I[pos] = (int)i;
+                    if (pos >= m_prev) S.I[pos] = key_row<C>(S.gkey[e], rbase);
                 }
                 run += __popcll(bal);
             }
             if (lane == 0) {
-                S.seg[m] = E;
+                S.seg[m] = (typename C::Seg)E;
                 S.is[0] = -1;
             }
         }
         wave_sync();
         for (int e = lane; e < E; e += G) {
-            const bool head = (e == 0) || ((uint32_t)(S.gkey[e - 1] >> 32) != (uint32_t)(S.gkey[e] >> 32));
+            const bool head = (e == 0) || (key_rel<C>(S.gkey[e - 1]) != key_rel<C>(S.gkey[e]));
             if (!head) S.gpos[e] = S.dpos[S.gpos[e]];
         }
         // With the update (INC), columns 0 .. p_old-1 and e-bar (in column p_old)
@@ -544,7 +588,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         }
         wave_sync();
         for (int e = lane; e < E; e += G) {
-            int slot = (int)(uint32_t)(S.gkey[e] & 0xffffffffu);
+            int slot = key_slot<C>(S.gkey[e]);
             int pos = S.gpos[e];
             if (S.gcol[slot] >= p_old) S.u.A[S.gcol[slot] * C::LD + pos] = S.gval[slot];
             if (S.I[pos] == k) S.is[0] = pos;
@@ -644,7 +688,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         for (int d = lane; d < m; d += G) {
             F acc = F(0);
             for (int e = S.seg[d]; e < S.seg[d + 1]; ++e) {
-                int slot = (int)(uint32_t)(S.gkey[e] & 0xffffffffu);
+                int slot = key_slot<C>(S.gkey[e]);
                 acc = ffma(S.gval[slot], S.mb[S.gcol[slot]], acc);
             }
             const int pos = S.dpos[d];
@@ -672,15 +716,12 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             cnt += a.cp[l + 1] - a.cp[l];
         }
         if (lane == 0 && kpos < 0) cnt += a.cp[k + 1] - a.cp[k];
-        S.ri[lane] = cnt;
-        wave_sync();
         int coff = 0, Ec = 0;
         for (int t = 0; t < G; ++t) {
-            int v = S.ri[t];
+            const int v = __shfl(cnt, gl0 + t, 64);
             coff += (t < lane) ? v : 0;
             Ec += v;
         }
-        wave_sync();
         if (Ec > C::CMAX) { defer = true; break; }
         for (int pos = lane; pos < m; pos += G) {
             int l = S.I[pos];
@@ -720,7 +761,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             for (int q = a.rp[j]; q < a.rp[j + 1]; ++q) {
                 int i = a.ci[q];
                 F r;
-                int d = bsearch_rows(S.gkey, S.seg, m, i);
+                int d = bsearch_rows<C>(S.gkey, S.seg, m, i, rbase);
                 if (d >= 0) r = S.s[S.dpos[d]];
                 else if (i == k) r = F(-1);
                 else continue;
@@ -762,26 +803,25 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                     bc = c;
                 }
             }
-            S.rf[lane] = br;
-            S.rj[lane] = bj;
-            S.ri[lane] = bc;
-            wave_sync();
-            if (lane == 0) {
+            // the group's lanes in order, read by lane permutes
+            {
                 F r0 = F(0);
                 int j0 = INT_MAX, c0 = -1;
                 for (int t = 0; t < G; ++t) {
-                    int ct = S.ri[t];
+                    const int ct = __shfl(bc, gl0 + t, 64);
+                    const F rt = __shfl(br, gl0 + t, 64);
+                    const int jt = __shfl(bj, gl0 + t, 64);
                     if (ct < 0) continue;
-                    F rt = S.rf[t];
-                    int jt = S.rj[t];
                     if (c0 < 0 || rt < r0 || (rt == r0 && jt < j0)) {
                         r0 = rt;
                         j0 = jt;
                         c0 = ct;
                     }
                 }
-                S.J[p + sel] = j0;
-                S.u.c.cj[c0] = -1;   // taken
+                if (lane == 0) {
+                    S.J[p + sel] = j0;
+                    S.u.c.cj[c0] = -1;   // taken
+                }
             }
             wave_sync();
         }

@@ -228,18 +228,33 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, sp
             }
             __syncthreads();
             for (int i = t; i < n; i += BT) y[r0 + i] = p_row<VP, TW>(a, r0 + i, w);
-            // modified Gram-Schmidt: h_lj = <y, v_l>, y -= h_lj v_l, l = 0 .. jj
+            // modified Gram-Schmidt: h_lj = <y, v_l>, y -= h_lj v_l, l = 0 .. jj, then
+            // ||y||.  The update by v_l and the partial inner product with v_{l+1}
+            // (with y itself after the last projection) share one pass over the
+            // rows: the same operations in the same order as separate passes.
             TW* Hc = H + (size_t)jj * ld;
+            TW p = 0;
+            for (int i = t; i < n; i += BT) p = tw_fma(y[r0 + i], V[i], p);
             for (int l = 0; l <= jj; ++l) {
                 const TW* vl = V + (size_t)l * n;
-                TW p = 0;
-                for (int i = t; i < n; i += BT) p = tw_fma(y[r0 + i], vl[i], p);
                 const TW hl = wg_sum(p, sh);
-                for (int i = t; i < n; i += BT) y[r0 + i] = tw_fma(-hl, vl[i], y[r0 + i]);
                 if (t == 0) Hc[l] = hl;
+                p = 0;
+                if (l < jj) {
+                    const TW* vn = vl + n;
+                    for (int i = t; i < n; i += BT) {
+                        const TW yi = tw_fma(-hl, vl[i], y[r0 + i]);
+                        y[r0 + i] = yi;
+                        p = tw_fma(yi, vn[i], p);
+                    }
+                } else {
+                    for (int i = t; i < n; i += BT) {
+                        const TW yi = tw_fma(-hl, vl[i], y[r0 + i]);
+                        y[r0 + i] = yi;
+                        p = tw_fma(yi, yi, p);
+                    }
+                }
             }
-            TW p = 0;
-            for (int i = t; i < n; i += BT) p = tw_fma(y[r0 + i], y[r0 + i], p);
             const TW hn = tw_sqrt(wg_sum(p, sh));
             TW* vn = V + (size_t)(jj + 1) * n;
             for (int i = t; i < n; i += BT) vn[i] = y[r0 + i] / hn;

@@ -202,3 +202,37 @@ def test_second_waiter_for_one_request_is_rejected(S):
     srv.close()
     rc, x, rec = got["r"]
     assert rc >= 0 and O.ferr(x, w.x_true) <= 1e-12
+
+
+def test_right_preconditioned_and_single_precision_requests(S):
+    """Requests with a right preconditioner (device lane, right-preconditioned
+    GMRES) and with working precision single (batch lane, binary32 solver) give
+    the direct library calls' results bit for bit."""
+    h = S.Handle()
+    w = W.serving_request(W.Arrival(0.0, "random", 1500, "fp32", 400))
+    s, ir = w.spai, w.ir
+    A_h, b_h = w.A, w.b
+    build = {"eps": s.eps, "alpha": s.alpha, "beta": s.beta, "maxfill": s.maxfill, "u_f": "fp32"}
+    srv = S.Server(batch_lanes=2, batch_max_n=BATCH_MAX_N, hbm_budget=8 << 30, lane_workspace=512 << 20)
+    cases = {
+        "right": (dict(build, side="right"), {"tau": ir.tau, "imax": ir.imax, "maxit": ir.maxit, "tol_ir": ir.tol_ir,
+                                               "u_r": "dd", "ortho": "dcgs2"}),
+        "single": (dict(build, u_f="fp16"), {"tau": 1e-4, "imax": ir.imax, "maxit": ir.maxit, "tol_ir": W.TOL_IR32,
+                                              "u_r": "fp64", "u": "fp32"}),
+    }
+    ids = {k: srv.submit(A_h, b_h, None, bp, irp) for k, (bp, irp) in cases.items()}
+    got = {k: srv.wait(i) for k, i in ids.items()}
+    srv.close()
+    A = S.DeviceCSR.from_host(A_h)
+    b = torch.as_tensor(b_h, device="cuda")
+    for k, (bp, irp) in cases.items():
+        rc, x, rec = got[k]
+        assert rc >= 0, rec["error"]
+        assert (rec["lane"] == -1) == (k == "right")
+        P, _, _ = h.spai_build(A, None, bp["eps"], bp["alpha"], bp["beta"], bp["maxfill"], bp["u_f"],
+                               bp.get("side", "left"))
+        xd = torch.zeros_like(b)
+        r = h.gmres_ir(A, P, b, xd, irp["tau"], irp["imax"], irp["maxit"], irp["tol_ir"], irp["u_r"],
+                       irp.get("ortho", "mgs"), irp.get("u", "fp64"))
+        assert rec["its"] == r["its"], (k, rec["its"], r["its"])
+        assert np.array_equal(x, xd.cpu().numpy()), k

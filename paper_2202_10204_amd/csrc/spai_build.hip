@@ -346,18 +346,6 @@ __device__ void group_sort(K* keys, int N, int lane) {
     }
 }
 
-__device__ __forceinline__ int bsearch_sorted(const int* v, int len, int key) {
-    int lo = 0, hi = len - 1;
-    while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
-        int x = v[mid];
-        if (x == key) return mid;
-        if (x < key) lo = mid + 1;
-        else hi = mid - 1;
-    }
-    return -1;
-}
-
 // rows and slots of the sort keys (rbase: the smallest gathered row of the
 // column, for the 32-bit keys); key_rel orders keys by row alone
 template <class C>

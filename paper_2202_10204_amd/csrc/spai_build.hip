@@ -252,7 +252,11 @@ struct ColArgs {
     int qr_update;      // keep each column's QR across augmentation steps (same results)
 };
 
-template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_>
+// AMAX_: capacity of A-bar in elements when the QR is recomputed per solve: A-bar
+// is stored with the odd leading dimension m | 1 of the solve at hand, and a
+// column whose (|J| + 1) (m | 1) exceeds it is deferred (the default holds the
+// largest problem of the shape)
+template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_, int AMAX_ = G_ * (MAXM_ + 1)>
 struct Cfg {
     static constexpr int UF = UF_;
     using F = typename UfTraits<UF_>::F;
@@ -270,6 +274,7 @@ struct Cfg {
     static constexpr int SB = EMAX_ <= 64 ? 6 : EMAX_ <= 128 ? 7 : EMAX_ <= 256 ? 8 : 32;
     using Seg = std::conditional_t<(EMAX_ <= 255), uint8_t, uint16_t>;   // holds 0 .. EMAX
     static constexpr int CMAX = CMAX_;     // raw candidate entries (power of two)
+    static constexpr int AMAX = AMAX_;     // A-bar elements (recomputed QR)
     static constexpr int PPW = 64 / G_;    // problems per wavefront
 };
 
@@ -278,23 +283,24 @@ struct Cfg {
 // augmentation steps (INC) the factorisation must survive the candidate phase, so
 // the two get their own space; otherwise they share it.
 template <class C, bool INC> struct QrCand;
+// The raw candidate keys are sorted in key[] and the unique candidates are
+// compacted into its front in place (each is written at or before the position
+// it is read from).
 template <class C> struct QrCand<C, false> {
     using F = typename C::F;
     union {
-        F A[(C::MAXP + 1) * C::LD];
+        F A[C::AMAX];                 // leading dimension m | 1
         struct {
-            int key[C::CMAX];         // raw candidates, sorted
-            int cj[C::CMAX];          // unique candidates (ascending j)
+            int key[C::CMAX];         // raw candidates, sorted; then the unique ones (ascending j)
             F rho[C::CMAX];
         } c;
     };
 };
 template <class C> struct QrCand<C, true> {
     using F = typename C::F;
-    F A[(C::MAXP + 1) * C::LD];
+    F A[(C::MAXP + 1) * C::LD];       // leading dimension LD (kept across solves)
     struct {
         int key[C::CMAX];
-        int cj[C::CMAX];
         F rho[C::CMAX];
     } c;
     F tau[C::MAXP + 1];      // tau_t of each reflector
@@ -492,6 +498,8 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             m += __popcll(ballot(head) & gmask);
         }
         if (m > C::MAXM) { defer = true; break; }
+        const int ld = INC ? C::LD : (m | 1);   // leading dimension of A-bar
+        if (!INC && (p + 1) * ld > C::AMAX) { defer = true; break; }
         // sorted rows, their segments, and their positions in I.  A row is old
         // (in the previous shadow) iff the first entry of its segment comes from a
         // column of the previous solve (slots follow the column order); old rows
@@ -561,30 +569,30 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         const int p_old = (INC && step > 0) ? p_prev : 0;
         if (p_old > 0 && lane == p) {
             // e-bar after the previous reflectors moves from column p_old to column p
-            const F* src = &S.u.A[p_old * C::LD];
-            F* dst = &S.u.A[p * C::LD];
+            const F* src = &S.u.A[p_old * ld];
+            F* dst = &S.u.A[p * ld];
             for (int i = 0; i < m_prev; ++i) dst[i] = src[i];
             for (int i = m_prev; i < m; ++i) dst[i] = F(0);
         }
         wave_sync();
         if (lane < p_old) {
-            F* col = &S.u.A[lane * C::LD];
+            F* col = &S.u.A[lane * ld];
             for (int i = m_prev; i < m; ++i) col[i] = F(0);
         } else if (lane < p || (p_old == 0 && lane == p)) {
-            F* col = &S.u.A[lane * C::LD];
+            F* col = &S.u.A[lane * ld];
             for (int i = 0; i < m; ++i) col[i] = F(0);
         }
         wave_sync();
         for (int e = lane; e < E; e += G) {
             int slot = key_slot<C>(S.gkey[e]);
             int pos = S.gpos[e];
-            if (S.gcol[slot] >= p_old) S.u.A[S.gcol[slot] * C::LD + pos] = S.gval[slot];
+            if (S.gcol[slot] >= p_old) S.u.A[S.gcol[slot] * ld + pos] = S.gval[slot];
             if (S.I[pos] == k) S.is[0] = pos;
         }
         wave_sync();
         kpos = S.is[0];
         // e-bar = e_k(I): the 1 is placed by a full build, or by the update when k is a new row
-        if (lane == 0 && kpos >= 0 && (p_old == 0 || kpos >= m_prev)) S.u.A[p * C::LD + kpos] = F(1);
+        if (lane == 0 && kpos >= 0 && (p_old == 0 || kpos >= m_prev)) S.u.A[p * ld + kpos] = F(1);
         wave_sync();
 
         // ---- Householder QR of A-bar, applied to e-bar as well ----
@@ -602,10 +610,10 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             for (int t = 0; t < qold; ++t) rankdef |= S.u.rz[t] != 0;
         if constexpr (INC) if (lane >= p_old && lane < p) {
             // the previous reflectors on a new column, one after the other
-            F* col = &S.u.A[lane * C::LD];
+            F* col = &S.u.A[lane * ld];
             for (int t = 0; t < qold; ++t) {
                 if (S.u.rz[t]) continue;
-                const F* v = &S.u.A[t * C::LD];
+                const F* v = &S.u.A[t * ld];
                 F dot = F(0);
                 for (int i = t; i < m; ++i) dot = ffma(v[i], col[i], dot);
                 F f = dot / S.u.tau[t];
@@ -615,7 +623,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         wave_sync();
         for (int t = qold; t < qsteps; ++t) {
             if (lane == t) {
-                F* x = &S.u.A[t * C::LD];
+                F* x = &S.u.A[t * ld];
                 F sig2 = F(0);
                 for (int i = t; i < m; ++i) sig2 = ffma(x[i], x[i], sig2);
                 F sigma = fsqrt(sig2);
@@ -643,8 +651,8 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             }
             const F tau = S.fs[0];
             if (lane > t && lane <= p) {
-                const F* v = &S.u.A[t * C::LD];
-                F* col = &S.u.A[lane * C::LD];
+                const F* v = &S.u.A[t * ld];
+                F* col = &S.u.A[lane * ld];
                 F dot = F(0);
                 for (int i = t; i < m; ++i) dot = ffma(v[i], col[i], dot);
                 F f = dot / tau;
@@ -662,8 +670,8 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                     rd = 1;
                     continue;
                 }
-                F s = S.u.A[p * C::LD + c];
-                for (int c2 = c + 1; c2 < p; ++c2) s = ffma(-S.u.A[c2 * C::LD + c], S.mb[c2], s);
+                F s = S.u.A[p * ld + c];
+                for (int c2 = c + 1; c2 < p; ++c2) s = ffma(-S.u.A[c2 * ld + c], S.mb[c2], s);
                 S.mb[c] = store<C::UF>(s / S.Rd[c]);
             }
             S.is[2] = rd;
@@ -734,7 +742,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                         if (S.J[c] == j) head = false;
             }
             uint64_t bal = ballot(head) & gmask;
-            if (head) S.u.c.cj[nc + __popcll(bal & below)] = j;
+            if (head) S.u.c.key[nc + __popcll(bal & below)] = j;
             nc += __popcll(bal);
         }
         wave_sync();
@@ -743,7 +751,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         // runs over the rows of B(:, j) (= columns of row j of A) ascending, r being
         // the residual on L (s-bar on I, -1 at k when k is outside I)
         for (int c = lane; c < nc; c += G) {
-            int j = S.u.c.cj[c];
+            int j = S.u.c.key[c];
             double dj = a.d[j];
             F tj = F(0);
             for (int q = a.rp[j]; q < a.rp[j + 1]; ++q) {
@@ -783,7 +791,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             F br = F(0);
             int bj = INT_MAX, bc = -1;
             for (int c = lane; c < nc; c += G) {
-                int j = S.u.c.cj[c];
+                int j = S.u.c.key[c];
                 F r = S.u.c.rho[c];
                 if (j >= 0 && r <= rbar && (bc < 0 || r < br || (r == br && j < bj))) {
                     br = r;
@@ -808,7 +816,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                 }
                 if (lane == 0) {
                     S.J[p + sel] = j0;
-                    S.u.c.cj[c0] = -1;   // taken
+                    S.u.c.key[c0] = -1;   // taken
                 }
             }
             wave_sync();
@@ -964,8 +972,10 @@ static int launch_columns(spai_handle* h, const ColArgs& a, hipStream_t s) {
 // raw candidates; the last one is the large-problem kernel for deferred columns
 template <int UF> using CfgS = Cfg<UF, 8, 32, 64, 256>;
 template <int UF> using CfgM = Cfg<UF, 16, 64, 128, 256>;
-template <int UF> using CfgM21s = Cfg<UF, 21, 40, 128, 256>;   // small shadows: more problems per CU
-template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256>;
+// (the two 21-lane ones store A-bar packed: 640 and 1024 elements hold all but a
+// fraction of a percent of the columns of their workloads)
+template <int UF> using CfgM21s = Cfg<UF, 21, 40, 128, 256, 640>;   // small shadows: more problems per CU
+template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256, 1024>;
 template <int UF> using CfgL = Cfg<UF, 32, 64, 256, 512>;
 template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 2048>;
 

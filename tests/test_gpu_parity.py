@@ -686,6 +686,9 @@ def test_qr_update_gives_the_same_bits(S, h, uf):
         c0, c1 = P0.columns(), P1.columns()
         for key in ("J", "m", "steps", "res", "flags", "len"):
             assert torch.equal(c0[key], c1[key]), (w.name, key)
+        # the recompute stores A-bar packed and may defer a column the update
+        # holds: a scheduling count, not part of the result
+        st0.pop("cols_deferred"), st1.pop("cols_deferred")
         assert st0 == st1
 
 

@@ -972,10 +972,11 @@ static int launch_columns(spai_handle* h, const ColArgs& a, hipStream_t s) {
 // raw candidates; the last one is the large-problem kernel for deferred columns
 template <int UF> using CfgS = Cfg<UF, 8, 32, 64, 256>;
 template <int UF> using CfgM = Cfg<UF, 16, 64, 128, 256>;
-// (the two 21-lane ones store A-bar packed: 640 and 1024 elements hold all but a
-// fraction of a percent of the columns of their workloads)
+// (the two 21-lane ones store A-bar packed: 640 and 896 elements hold all but a
+// fraction of a percent of the columns of their workloads, and bring the
+// workgroups per CU from 10 to 12 and from 7 to 9)
 template <int UF> using CfgM21s = Cfg<UF, 21, 40, 128, 256, 640>;   // small shadows: more problems per CU
-template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256, 1024>;
+template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256, 896>;
 template <int UF> using CfgL = Cfg<UF, 32, 64, 256, 512>;
 template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 2048>;
 

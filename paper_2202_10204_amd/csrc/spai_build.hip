@@ -979,6 +979,10 @@ template <int UF> using CfgM21s = Cfg<UF, 21, 40, 128, 256, 640>;   // small sha
 template <int UF> using CfgM21 = Cfg<UF, 21, 64, 128, 256, 896>;
 template <int UF> using CfgL = Cfg<UF, 32, 64, 256, 512>;
 template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 2048>;
+// intermediate stage for the columns a configuration of at most 21 lanes defers
+// (shadows of up to 96 rows, twice the gathered entries and candidates): they
+// run 12 to a CU instead of the large-problem kernel's one
+template <int UF> using CfgW = Cfg<UF, 21, 96, 256, 512>;
 
 // configuration ids of the C ABI (spai_column_config_get, spai_build_params.kernel_cfg)
 enum { KC_S = 1, KC_M = 2, KC_M21S = 3, KC_M21 = 4, KC_L = 5, KC_X = 6 };
@@ -1049,7 +1053,8 @@ static int launch_columns_m21(spai_handle* h, const ColArgs& a, hipStream_t s, i
 }
 
 // The column phase: the configuration kcfg (0 = the rule below), then the
-// columns it deferred on the largest configuration.
+// columns it deferred: through the intermediate 21-lane stage when the
+// configuration has at most 21 lanes, and what is left on the largest one.
 template <int UF>
 static int run_columns(spai_handle* h, int pmax, int kcfg, ColArgs a, hipStream_t s, int* defer_list2,
                        int* defer_count_dev, int* defer_count_host, int* cols_deferred) {
@@ -1072,7 +1077,36 @@ static int run_columns(spai_handle* h, int pmax, int kcfg, ColArgs a, hipStream_
         set_error("a column problem exceeds the largest kernel configuration");
         return SPAI_E_ARG;
     }
-    if (nd > 0) {
+    if (nd > 0 && cfg_maxp(id) <= CfgW<UF>::MAXP) {
+        // the intermediate stage: reads the first list, defers into the second
+        ColArgs b = a;
+        b.cols = a.defer_list;
+        b.ncols = nd;
+        b.defer_list = defer_list2;
+        b.defer_count = defer_count_dev;
+        SPAI_HIP(hipMemsetAsync(defer_count_dev, 0, sizeof(int), s));
+        rc = launch_columns<CfgW<UF>>(h, b, s);
+        if (rc) return rc;
+        SPAI_HIP(hipMemcpyAsync(defer_count_host, defer_count_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPAI_HIP(hipStreamSynchronize(s));
+        nd = *defer_count_host;
+        if (nd > 0) {
+            // the large-problem kernel on the second list (the first one is read by now)
+            b.cols = defer_list2;
+            b.ncols = nd;
+            b.defer_list = a.defer_list;
+            b.defer_count = dc;
+            SPAI_HIP(hipMemsetAsync(dc, 0, sizeof(int), s));
+            rc = launch_columns<CfgX<UF>>(h, b, s);
+            if (rc) return rc;
+            SPAI_HIP(hipMemcpyAsync(defer_count_host, dc, sizeof(int), hipMemcpyDeviceToHost, s));
+            SPAI_HIP(hipStreamSynchronize(s));
+            if (*defer_count_host > 0) {
+                set_error("a column problem exceeds the largest kernel configuration");
+                return SPAI_E_ARG;
+            }
+        }
+    } else if (nd > 0) {
         ColArgs b = a;
         b.cols = a.defer_list;
         b.ncols = nd;

@@ -181,6 +181,22 @@ def test_adaptive_random_banded_and_deferred_columns(S, h):
     _compare_columns(P, ref, "random banded n=3000 adaptive fp32")
 
 
+@pytest.mark.parametrize("kcfg,inc", [(0, False), (3, False), (4, True)])
+def test_columns_deferred_through_both_stages(S, h, kcfg, inc):
+    """Wider rows (10-20 entries within a band of 96): by the oracle's shadows,
+    1128 of the 3000 columns outgrow 64 rows, 535 gather more than 128 entries
+    and 48 outgrow 96 rows, so the 21-lane configurations defer columns to the
+    intermediate stage and that stage defers some on to the large kernel; every
+    column must still agree with the oracle bit for bit."""
+    A = W.random_banded(3000, np.random.default_rng(11), kmin=10, kmax=20, half_band=48)
+    ref = O.spai(A, None, 0.3, 375, 8, 20, "fp32", nthreads=8)
+    assert (ref.nI > 96).sum() > 0 and (ref.nI > 64).sum() > 100
+    P, warn, st = h.spai_build(S.DeviceCSR.from_host(A), None, 0.3, 375, 8, 20, "fp32", qr_update=inc,
+                               kernel_cfg=kcfg)
+    assert st["cols_deferred"] >= int((ref.nI > 64).sum())
+    _compare_columns(P, ref, f"random banded 10-20 per row, cfg {kcfg}, qr_update {inc}")
+
+
 def test_closed_forms_on_device(S, h):
     """Diagonal matrix -> P = diag(fl(1/a_kk)); permutation -> P A = I."""
     rng = np.random.default_rng(5)

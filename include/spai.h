@@ -107,7 +107,9 @@ typedef struct {
                            must hold max(maxfill, longest initial column) indices, else
                            SPAI_E_ARG.  Every configuration gives the same bits: a column that
                            outgrows a configuration's shadow, gather or candidate space is
-                           recomputed from scratch by the largest one.  The choice is a
+                           recomputed from scratch by a larger one (after a configuration of
+                           at most 21 lanes, an internal 21-lane stage with 96 shadow rows,
+                           then the largest configuration).  The choice is a
                            performance choice, made by spai_tune_build's measurements. */
 } spai_build_params;
 
@@ -147,7 +149,7 @@ typedef struct {
     int32_t cols_over_eps;  /* columns ending above eps */
     int32_t cols_rankdef;   /* columns with a rank-deficient reduced problem */
     int32_t cols_nonfinite; /* columns with a non-finite value */
-    int32_t cols_deferred;  /* columns recomputed by the large-problem kernel */
+    int32_t cols_deferred;  /* columns the first configuration deferred to a larger one */
     double max_res;         /* largest final column residual */
 } spai_build_stats;
 

@@ -3,7 +3,7 @@
 The library carries several column-kernel configurations (lanes of a wavefront
 per column problem, shadow rows, gathered entries and augmentation candidates
 staged in LDS; `column_config`).  Every configuration gives the same bits: a
-column that outgrows one is recomputed from scratch by the largest, with the
+column that outgrows one is recomputed from scratch by a larger one, with the
 same arithmetic.  So the choice, and the choice of updating each column's QR
 across augmentation steps or refactoring it, are questions of speed only, and
 their answer depends on the GPU and on the problem's shape (fill cap, adaptive

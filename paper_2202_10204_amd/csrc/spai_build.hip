@@ -16,8 +16,8 @@
 // Index work (shadows, candidate sets) uses per-group bitonic sorts in LDS.
 //
 // Problems that exceed a kernel's LDS capacity (rows of the shadow, gathered
-// entries, raw candidates) are deferred to a second launch of a larger
-// configuration over the deferred list.
+// entries, raw candidates) are deferred to a launch of a larger configuration
+// over the deferred list (and what that one defers to the largest).
 #include <algorithm>
 #include <climits>
 #include <cstring>

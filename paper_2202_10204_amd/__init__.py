@@ -341,7 +341,7 @@ class Handle:
         return Precond(self, out.value, stats), rc, stats
 
     def tune_build(self, A: DeviceCSR, pattern: Optional[DevicePattern], eps: float, alpha: int, beta: int,
-                   maxfill: int, u_f: str = "fp32", side: str = "left", sample: int = 65536, reps: int = 3):
+                   maxfill: int, u_f: str = "fp32", side: str = "left", sample: int = 262144, reps: int = 3):
         """Time every column-kernel configuration that holds the pattern, with and
         without the QR update, on a strided sample of columns (spai_tune_build).
         Returns {(kernel_cfg, qr_update): ns per column}."""

@@ -81,7 +81,7 @@ def pick(times: dict) -> tuple:
 
 
 def tune(h, A_dev, pattern_dev, A, pattern, eps: float, alpha: int, beta: int, maxfill: int, u_f: str = "fp32",
-         side: str = "left", cache: Optional[str] = DEFAULT_CACHE, sample: int = 65536, reps: int = 3,
+         side: str = "left", cache: Optional[str] = DEFAULT_CACHE, sample: int = 262144, reps: int = 3,
          retune: bool = False) -> dict:
     """The cached choice for this problem's bin, measured on a miss (or when
     retune).  Returns {"kernel_cfg", "qr_update", "ns_per_col", "candidates",

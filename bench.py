@@ -193,6 +193,64 @@ def cpu_baseline(w, its_oracle, threads):
     }
 
 
+def run_aniso3d(S, W, args):
+    """The 3D anisotropic workload at N^3 (n = 2,097,152 at N = 128): the fixed
+    pattern(A^2) SPAI build in FP16, BF16 and FP32, and the rates of the two
+    sparse products of the Arnoldi step on it, timed with HIP events over
+    repeated launches: SpMV(A) moves 12 nnz(A) + 4(n+1) + 16n bytes, the
+    application of P = M^T D moves (4 + s_f) nnz(P) + 4(n+1) + 24n (x, D and
+    the result in FP64)."""
+    import torch
+
+    N = args.grid3d
+    w = W.aniso_fixed(N, "fp16")
+    n, s = w.n, w.spai
+    log(f"workload {w.name} n={n} nnz={w.A.nnz} pattern nnz={w.pattern.idx.size}")
+    h = S.Handle()
+    A = S.DeviceCSR.from_host(w.A)
+    pat = S.DevicePattern.from_host(w.pattern)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"metric": "SPAI cols/s and sparse-product GB/s", "workload": w.name, "n": n, "nnz_A": int(w.A.nnz),
+           "pattern_nnz": int(w.pattern.idx.size), "peak_GBs": 8000.0, "builds": {}, "products": {}}
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    xv = torch.rand(n, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+    yv = torch.empty_like(xv)
+    nnz_a = int(w.A.nnz)
+    byt = 12 * nnz_a + 4 * (n + 1) + 16 * n
+    us = timed(lambda: h.spmv(A, xv, yv), args.steps * 20) * 1e3
+    out["products"]["spmv_A"] = {"us": us, "bytes": byt, "GBs": byt / us * 1e-3, "frac": byt / us * 1e-3 / 8000.0}
+    for uf in ("fp16", "bf16", "fp32"):
+        holder = {}
+
+        def build():
+            holder.pop("P", None)
+            holder["P"] = h.spai_build(A, pat, s.eps, s.alpha, s.beta, s.maxfill, uf)
+
+        ms = timed(build, args.steps)
+        P, warn, bst = holder["P"]
+        out["builds"][uf] = {"ms": ms, "cols_per_s": n / ms * 1e3, "nnz_P": bst["nnz"]}
+        sf = 4 if uf == "fp32" else 2
+        byt = (4 + sf) * bst["nnz"] + 4 * (n + 1) + 24 * n
+        us = timed(lambda: h.precond_apply(P, xv, yv), args.steps * 20) * 1e3
+        out["products"][f"apply_P_{uf}"] = {"us": us, "bytes": byt, "GBs": byt / us * 1e-3,
+                                            "frac": byt / us * 1e-3 / 8000.0}
+        holder.clear()
+        del P
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(S, W, args):
     """4096 independent systems (sizes log-uniform in [200, 20000]): the batched
     SPAI build and the batched GMRES-IR (one persistent launch), timed with HIP
@@ -405,7 +463,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, default=512, help="grid side (512 is the benchmark workload)")
-    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "batch", "serve", "tables"],
+    ap.add_argument("--grid3d", type=int, default=128, help="aniso3d: cells per side")
+    ap.add_argument("--workload", default="convdiff", choices=["convdiff", "batch", "serve", "tables", "aniso3d"],
                     help="convdiff: the benchmark line (default); batch: 4096 independent random banded systems "
                          "(a separate measurement of the batched entry points, printed as its own JSON line); "
                          "serve: the serving stream through the library's request loop (its own JSON line); "
@@ -449,6 +508,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         run_batch(S, W, args)
+        return
+    if args.workload == "aniso3d":
+        run_aniso3d(S, W, args)
         return
     w = W.convdiff_adaptive(args.grid)
     n = w.n

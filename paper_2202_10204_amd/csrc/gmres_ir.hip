@@ -49,7 +49,10 @@ struct SolveState {
 // row's entries with unit stride, keep lane-strided partial sums and add them
 // by a fixed xor tree, so every call gives the same bits.  Many more waves than
 // one thread per row, and coalesced loads.
-template <int G, int R>
+
+// IT: entries per lane of a row whose loads are issued together (1 or 2: the
+// lanes per row are chosen so that an average row takes at most 1.5 rounds)
+template <int G, int R, int IT>
 __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ av, const double* __restrict__ x,
                                                 double* __restrict__ y, const double* __restrict__ dout,
@@ -69,16 +72,45 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
         q0[r] = rp[row] + sub;
         q1[r] = row0 + r * GPB < n ? rp[row + 1] : 0;
     }
+    // the first IT entries of every row's lane are loaded before any is used
+    // (the index loads, then the value loads and gathers; a position past the
+    // row's end loads entry 0, which exists since nnz >= 1, and is not added),
+    // the rest of a longer row follows in a loop; each lane sums its entries in
+    // ascending order
     double acc[R];
+    {
+        int qx[R][IT], jx[R][IT];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        double s = 0.0;
-        for (int q = q0[r]; q < q1[r]; q += G) s = __builtin_fma(av[q], x[ci[q]], s);
-        acc[r] = s;
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int q = q0[r] + it * G;
+                qx[r][it] = q < q1[r] ? q : 0;
+                jx[r][it] = ci[qx[r][it]];
+            }
+        double va[R][IT], vx[R][IT];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                va[r][it] = av[qx[r][it]];
+                vx[r][it] = x[jx[r][it]];
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const double f = __builtin_fma(va[r][it], vx[r][it], s);
+                s = q0[r] + it * G < q1[r] ? f : s;
+            }
+            acc[r] = s;
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         double s = acc[r];
+        for (int q = q0[r] + IT * G; q < q1[r]; q += G) s = __builtin_fma(av[q], x[ci[q]], s);
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
         if (sub == 0 && row0 + r * GPB < n) y[row0 + r * GPB] = dout ? dout[row0 + r * GPB] * s : s;
@@ -86,7 +118,7 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
 }
 
 // SCALED (left only): w already holds D w, the gather of d is skipped
-template <int VP, int G, int R, bool RIGHT, bool SCALED = false>
+template <int VP, int G, int R, bool RIGHT, bool SCALED, int IT>
 __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                                                    const typename ValType<VP>::T* __restrict__ pv,
                                                    const double* __restrict__ d, const double* __restrict__ w,
@@ -106,20 +138,49 @@ __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict_
         q0[r] = pp[row] + sub;
         q1[r] = row0 + r * GPB < n ? pp[row + 1] : 0;
     }
+    // as in k_spmv_g: the first IT entries of every row's lane in flight
+    // together (entry 0 standing in past the row's end, not added), the rest in
+    // a loop, each lane's sum in ascending order
     double acc[R];
+    {
+        int qx[R][IT], jx[R][IT];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        double s = 0.0;
-        for (int q = q0[r]; q < q1[r]; q += G) {
-            const int j = pc[q];
-            if constexpr (RIGHT || SCALED) s = __builtin_fma(to_f64(pv[q]), w[j], s);
-            else s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int q = q0[r] + it * G;
+                qx[r][it] = q < q1[r] ? q : 0;
+                jx[r][it] = pc[qx[r][it]];
+            }
+        double vp[R][IT], vw[R][IT];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int j = jx[r][it];
+                vp[r][it] = to_f64(pv[qx[r][it]]);
+                if constexpr (RIGHT || SCALED) vw[r][it] = w[j];
+                else vw[r][it] = d[j] * w[j];
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const double f = __builtin_fma(vp[r][it], vw[r][it], s);
+                s = q0[r] + it * G < q1[r] ? f : s;
+            }
+            acc[r] = s;
         }
-        acc[r] = s;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         double s = acc[r];
+        for (int q = q0[r] + IT * G; q < q1[r]; q += G) {
+            const int j = pc[q];
+            if constexpr (RIGHT || SCALED) s = __builtin_fma(to_f64(pv[q]), w[j], s);
+            else s = __builtin_fma(to_f64(pv[q]), d[j] * w[j], s);
+        }
 #pragma unroll
         for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
         if (sub == 0 && row0 + r * GPB < n) {
@@ -1436,6 +1497,10 @@ static int reduce_blocks(int n) {
 constexpr int SPMV_R = 2;
 constexpr int APPLY_R = 4;
 
+// entries per lane whose loads go out together: 2 when an average row is
+// longer than the lanes per row, else 1
+static inline int row_it(long long nnz, int n, int g) { return (double)nnz > (double)g * n ? 2 : 1; }
+
 template <int VP, bool RIGHT, bool SCALED = false>
 static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
                       const SolveState* st, int by_step) {
@@ -1443,16 +1508,19 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
     const T* pv = (const T*)P->val;
     const long long groups = ((long long)n + APPLY_R - 1) / APPLY_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
-#define SPAI_AP(G)                                                                                       \
-    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT, SCALED>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
+    const int it = row_it(P->nnz, n, g);
+#define SPAI_AP(G, IT)                                                                                       \
+    hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT, SCALED, IT>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
                        P->col, pv, P->d, w, y, st, by_step)
+#define SPAI_AP2(G) if (it == 2) SPAI_AP(G, 2); else SPAI_AP(G, 1)
     switch (g) {
-    case 1: SPAI_AP(1); break;
-    case 2: SPAI_AP(2); break;
-    case 4: SPAI_AP(4); break;
-    case 8: SPAI_AP(8); break;
-    default: SPAI_AP(16); break;
+    case 1: SPAI_AP2(1); break;
+    case 2: SPAI_AP2(2); break;
+    case 4: SPAI_AP2(4); break;
+    case 8: SPAI_AP2(8); break;
+    default: SPAI_AP2(16); break;
     }
+#undef SPAI_AP2
 #undef SPAI_AP
 }
 
@@ -1462,6 +1530,7 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
 static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
                           const SolveState* st = nullptr, bool scaled = false, int by_step = 0) {
     const int n = P->n, g = lanes_per_row(P->nnz, n);
+    SPAI_ARG(P->nnz >= 1, "the preconditioner has no entries");   // the kernel reads entry 0 past row ends
     long tk = timer_begin(h, SPAI_KT_APPLY_P);
     const int mode = P->side == SPAI_RIGHT ? 2 : scaled ? 1 : 0;
 #define SPAI_AP_MODE(VP)                                     \
@@ -1484,19 +1553,23 @@ static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w
 static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
                        const SolveState* st = nullptr, const double* dout = nullptr, int by_step = 0) {
     const int n = A->n, g = lanes_per_row(A->nnz, n);
+    SPAI_ARG(A->nnz >= 1, "the matrix has no entries");   // the kernel reads entry 0 past row ends
     const long long groups = ((long long)n + SPMV_R - 1) / SPMV_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
     long tk = timer_begin(h, SPAI_KT_SPMV_A);
-#define SPAI_SP(G)                                                                                              \
-    hipLaunchKernelGGL((k_spmv_g<G, SPMV_R>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, \
+    const int it = row_it(A->nnz, n, g);
+#define SPAI_SP(G, IT)                                                                                              \
+    hipLaunchKernelGGL((k_spmv_g<G, SPMV_R, IT>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, \
                        dout, st, by_step)
+#define SPAI_SP2(G) if (it == 2) SPAI_SP(G, 2); else SPAI_SP(G, 1)
     switch (g) {
-    case 1: SPAI_SP(1); break;
-    case 2: SPAI_SP(2); break;
-    case 4: SPAI_SP(4); break;
-    case 8: SPAI_SP(8); break;
-    default: SPAI_SP(16); break;
+    case 1: SPAI_SP2(1); break;
+    case 2: SPAI_SP2(2); break;
+    case 4: SPAI_SP2(4); break;
+    case 8: SPAI_SP2(8); break;
+    default: SPAI_SP2(16); break;
     }
+#undef SPAI_SP2
 #undef SPAI_SP
     timer_end(h, SPAI_KT_SPMV_A, tk);
     SPAI_HIP(hipGetLastError());

@@ -9,6 +9,8 @@ for exact equality.  The solve is compared by its GMRES iteration tuple
 (exact), its forward error against the exactly known solution (<= 1e-12) and
 its distance to the oracle's solution.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -106,6 +108,44 @@ def test_spmv(S, h):
     h.spmv(S.DeviceCSR.from_host(w.A), _dev(x), y)
     ref = w.A.to_scipy() @ x
     assert np.allclose(y.cpu().numpy(), ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("avg", [1, 3, 6, 20])
+def test_spmv_ragged_rows(S, h, avg):
+    """Row lengths uniform in 0 .. 2 avg (empty rows included): the lanes per
+    row, the one or two entries per lane loaded together and the loop over the
+    rest of a longer row all meet rows shorter and longer than they cover.
+    Agreement with the row sums to within their rounding, and the same bits on
+    a second call."""
+    rng = np.random.default_rng(100 + avg)
+    n = 3000
+    lens = rng.integers(0, 2 * avg + 1, size=n)
+    rowptr = np.zeros(n + 1, np.int32)
+    rowptr[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, int(k), replace=False)) for k in lens]).astype(np.int32)
+    val = rng.standard_normal(int(rowptr[-1]))
+    A = W.CSR(n, rowptr, col, val)
+    x = rng.standard_normal(n)
+    y1 = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    y2 = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    dA = S.DeviceCSR.from_host(A)
+    h.spmv(dA, _dev(x), y1)
+    h.spmv(dA, _dev(x), y2)
+    y = y1.cpu().numpy()
+    assert np.array_equal(y, y2.cpu().numpy())
+    prod = val * x[col]
+    ref = np.array([math.fsum(prod[rowptr[i]:rowptr[i + 1]]) for i in range(n)])
+    bound = np.add.reduceat(np.abs(prod), rowptr[:-1]) * np.where(lens > 0, 1, 0)
+    assert np.all(np.abs(y - ref) <= 2 * lens * 2.0 ** -53 * bound)
+    assert np.all(y[lens == 0] == 0.0)
+
+
+def test_spmv_rejects_a_matrix_without_entries(S, h):
+    n = 10
+    A = W.CSR(n, np.zeros(n + 1, np.int32), np.zeros(1, np.int32)[:0], np.zeros(1)[:0])
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(S.SpaiError):
+        h.spmv(S.DeviceCSR.from_host(A), _dev(np.ones(n)), y)
 
 
 # ---------------------------------------------------------------------------

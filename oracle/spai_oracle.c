@@ -601,44 +601,68 @@ void oracle_scaling(int n, const int* rp, const double* av, double* d) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* exact summation, correctly rounded (Shewchuk's nonoverlapping partials     */
-/* with the round-half-even correction of the final sum).                     */
+/* exact summation, correctly rounded.  Every finite binary64 value is an      */
+/* integer multiple of 2^-1074, so a sum of them is too: the values are added  */
+/* as integers into a fixed-point accumulator of 32-bit digits (no rounding at */
+/* all), and the exact total is rounded once to binary64 at the end (round to  */
+/* nearest, ties to even).                                                     */
 /* ------------------------------------------------------------------------- */
 
+#define XDIGITS 72 /* 72 x 32 bits: weights 2^-1074 .. 2^1229, room for 2^200 terms */
+
 double oracle_exact_sum(const double* xs, int len, double* scratch) {
-    double* part = scratch; /* capacity len */
-    int np = 0;
+    (void)scratch;
+    int64_t acc[XDIGITS];
+    memset(acc, 0, sizeof acc);
     for (int t = 0; t < len; ++t) {
         double x = xs[t];
-        int i = 0;
-        for (int q = 0; q < np; ++q) {
-            double y = part[q];
-            if (fabs(x) < fabs(y)) { double tmp = x; x = y; y = tmp; }
-            double hi = x + y;
-            double lo = y - (hi - x);
-            if (lo != 0.0) part[i++] = lo;
-            x = hi;
+        if (x == 0.0) continue;
+        int e;
+        double f = frexp(fabs(x), &e);              /* |x| = f 2^e, 1/2 <= f < 1 */
+        uint64_t m = (uint64_t)ldexp(f, 53);        /* |x| = m 2^(e-53), m < 2^53, exact */
+        int sh = e - 53 + 1074;                     /* |x| = m 2^(sh-1074) */
+        if (sh < 0) { m >>= -sh; sh = 0; }          /* subnormal: the dropped bits are zero */
+        unsigned __int128 v = (unsigned __int128)m << (sh % 32);
+        int q = sh / 32;
+        int64_t s = x < 0.0 ? -1 : 1;
+        acc[q] += s * (int64_t)(uint32_t)v;
+        acc[q + 1] += s * (int64_t)(uint32_t)(v >> 32);
+        acc[q + 2] += s * (int64_t)(uint32_t)(v >> 64);
+    }
+    /* carries: every digit into [0, 2^32), the sign ends in the top digit */
+    for (int q = 0; q + 1 < XDIGITS; ++q) {
+        int64_t c = acc[q] >> 32;                   /* floor division by 2^32 */
+        acc[q] -= c * ((int64_t)1 << 32);
+        acc[q + 1] += c;
+    }
+    double sign = 1.0;
+    if (acc[XDIGITS - 1] < 0) {                     /* negative: take the two's complement */
+        sign = -1.0;
+        int64_t borrow = 0;
+        for (int q = 0; q < XDIGITS; ++q) {
+            int64_t v = -acc[q] - borrow;
+            borrow = 0;
+            if (v < 0 && q + 1 < XDIGITS) { v += (int64_t)1 << 32; borrow = 1; }
+            acc[q] = v;
         }
-        part[i] = x;
-        np = i + 1;
     }
-    if (np == 0) return 0.0;
-    int q = np - 1;
-    double hi = part[q], lo = 0.0;
-    while (q > 0) {
-        double x = hi, y = part[--q];
-        hi = x + y;
-        double yr = hi - x;
-        lo = y - yr;
-        if (lo != 0.0) break;
+    int top = -1;                                   /* index of the highest set bit */
+    for (int q = XDIGITS - 1; q >= 0 && top < 0; --q)
+        if (acc[q]) for (int b = 31; b >= 0; --b) if ((acc[q] >> b) & 1) { top = 32 * q + b; break; }
+    if (top < 0) return 0.0;
+#define XBIT(i) ((i) >= 0 ? (int)((acc[(i) / 32] >> ((i) % 32)) & 1) : 0)
+    if (top < 53) {                                 /* below 2^-1021: exact as it stands */
+        uint64_t m = 0;
+        for (int i = top; i >= 0; --i) m = 2 * m + (uint64_t)XBIT(i);
+        return sign * ldexp((double)m, -1074);
     }
-    if (q > 0 && ((lo < 0.0 && part[q - 1] < 0.0) || (lo > 0.0 && part[q - 1] > 0.0))) {
-        double y = lo * 2.0;
-        double x = hi + y;
-        double yr = x - hi;
-        if (y == yr) hi = x;
-    }
-    return hi;
+    uint64_t m = 0;                                 /* the 53 leading bits */
+    for (int i = top; i > top - 53; --i) m = 2 * m + (uint64_t)XBIT(i);
+    int rbit = XBIT(top - 53), sticky = 0;
+    for (int i = top - 54; i >= 0 && !sticky; --i) sticky = XBIT(i);
+    if (rbit && (sticky || (m & 1))) ++m;           /* nearest, ties to even (m may reach 2^53: exact) */
+#undef XBIT
+    return sign * ldexp((double)m, top - 52 - 1074);
 }
 
 /* r = fl(b - A x), each component computed exactly and rounded once to FP64

@@ -104,6 +104,16 @@ def test_exact_sum_vs_fsum_and_fractions():
         rng.shuffle(xs)
         exact = float(sum(Fraction(x) for x in xs))         # Fraction -> float rounds correctly
         assert O.exact_sum(xs) == exact == math.fsum(xs)
+    for _ in range(300):                                    # subnormals, extreme exponents, ties
+        k = rng.randint(1, 12)
+        xs = [rng.choice([1, -1]) * rng.randint(1, 2 ** 53 - 1) * 2.0 ** rng.randint(-1126, 960)
+              for _ in range(k)]
+        xs += [rng.choice([1, -1]) * 2.0 ** -1074 * rng.randint(1, 9)]
+        if rng.random() < 0.5:                              # a halfway case: 1 + 2^-53 (+ tiny)
+            xs += [1.0, 2.0 ** -53] + ([2.0 ** -1000] if rng.random() < 0.5 else [])
+        rng.shuffle(xs)
+        exact = float(sum(Fraction(x) for x in xs))
+        assert O.exact_sum(xs) == exact, xs
 
 
 def test_residual_is_exactly_rounded():
@@ -607,3 +617,232 @@ def test_right_exact_preconditioner_takes_one_iteration_per_step():
                      side="right")
     assert all(k == 1 for k in res.its)
     assert O.ferr(res.x, w.x_true) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# applying P = M^T D and the initial solve with a non-diagonal P and a
+# non-constant scaling (where D applied on the wrong side of M^T would show)
+# ---------------------------------------------------------------------------
+
+_U = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "fp32": 2.0 ** -24, "fp64": 2.0 ** -53}
+
+
+def _nondiagonal_spai(uf):
+    """A fixed-pattern SPAI of the 12x12 convection-diffusion matrix on pattern(A):
+    rows of 3-5 entries, values rounded to u_f by the build."""
+    w = W.convdiff_adaptive(12)
+    R = O.spai(w.A, W.pattern_of(w.A), 0.3, 0, 8, 20, uf)
+    pp, pc, pv = R.P_csr(w.n)
+    assert np.diff(pp).max() >= 4
+    return w, pp, pc, pv
+
+
+def _wide_vector(rng, n):
+    return rng.standard_normal(n) * 10.0 ** rng.uniform(-3, 3, n)
+
+
+def test_apply_P_is_Mt_times_D_for_a_nondiagonal_P():
+    """Section 4 / Algorithm 3: P = M^T D, so y = P w = M^T (D w); checked against
+    scipy's (M^T diag(d)) w with d non-constant, within the FP64 rounding of the
+    row sums (D (M^T w) differs at the O(1) level)."""
+    w, pp, pc, pv = _nondiagonal_spai("fp64")
+    rng = np.random.default_rng(41)
+    n = w.n
+    d = rng.uniform(0.25, 4.0, n)
+    MT = sp.csr_matrix((pv, pc, pp), shape=(n, n))
+    q = np.diff(pp)
+    for _ in range(5):
+        v = _wide_vector(rng, n)
+        y = O.apply_P(pp, pc, pv, d, v)
+        ref = (MT @ sp.diags(d)) @ v
+        scale = abs(MT) @ np.abs(d * v)
+        assert np.all(np.abs(y - ref) <= (q + 2) * _U["fp64"] * scale)
+        wrong = d * (MT @ v)
+        assert np.abs(wrong - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("uf", ["fp64", "fp32", "fp16", "bf16"])
+def test_x0_is_Mt_D_b_in_uf_for_a_nondiagonal_P(uf):
+    """Algorithm 3, initial solve: x0 = P b in u_f = M^T (D b) with D b rounded to
+    u_f and the row sums in the arithmetic precision of u_f (binary32 for
+    FP16/BF16).  Upper bound: the u_f rounding of D b plus the sum's rounding;
+    lower bound (16-bit formats): the largest error reaches the order of u_f,
+    so the storage rounding of D b is really there."""
+    w, pp, pc, pv = _nondiagonal_spai(uf)
+    rng = np.random.default_rng(42)
+    n = w.n
+    d = rng.uniform(0.25, 4.0, n)
+    MT = sp.csr_matrix((pv, pc, pp), shape=(n, n))
+    q = np.diff(pp)
+    arith = _U["fp64"] if uf == "fp64" else _U["fp32"]
+    store = 0.0 if uf in ("fp64", "fp32") else _U[uf]
+    worst = 0.0
+    for _ in range(8):
+        b = _wide_vector(rng, n)
+        x0 = O.x0(pp, pc, pv, d, b, uf)
+        ref = MT @ (d * b)
+        scale = abs(MT) @ np.abs(d * b)
+        err = np.abs(x0 - ref) / scale
+        assert np.all(err <= 1.01 * (store + (q + 3) * arith)), (uf, err.max())
+        worst = max(worst, err.max())
+        wrong = d * (MT @ b)
+        assert np.abs(wrong - ref).max() > 1e-3 * np.abs(ref).max()
+    if store:
+        assert worst >= 0.25 * store, (uf, worst)
+
+
+def test_gmres_step_minimiser_with_a_nondiagonal_P():
+    """The Krylov least-squares pin of GMRES with P = M^T D from a pattern(A)
+    SPAI of a random 8x8 matrix (non-diagonal P, non-constant d): z = P r0 and
+    the operator P A use D on the right of M^T."""
+    rng = np.random.default_rng(43)
+    n = 8
+    Ad = _random_dd(n, rng, density=0.6, dom=0.4)
+    A = _csr(Ad)
+    b = rng.standard_normal(n)
+    R = O.spai(A, W.pattern_of(A), 0.6, 0, 8, 8, "fp64")
+    assert not np.allclose(R.d, R.d[0])
+    pp, pc, pv = R.P_csr(n)
+    assert pp[-1] > n                                   # not diagonal
+    P = (sp.csr_matrix((pv, pc, pp), shape=(n, n)) @ sp.diags(R.d)).toarray()
+    for ortho in ("mgs", "cgs2", "dcgs2"):
+        for k in range(1, 6):
+            res = O.gmres_ir(A, pp, pc, pv, R.d, "fp64", b, 0.0, 1, k, 0.0, ortho)
+            assert res.its == [k]
+            x0 = P @ b
+            r0 = b - Ad @ x0
+            z = P @ r0
+            PA = P @ Ad
+            K = np.column_stack([np.linalg.matrix_power(PA, i) @ z for i in range(k)])
+            Q, _ = np.linalg.qr(K)
+            y, *_ = np.linalg.lstsq(PA @ Q, z, rcond=None)
+            dexp = Q @ y
+            assert np.abs((res.x - x0) - dexp).max() <= 1e-9 * np.abs(dexp).max(), (ortho, k)
+
+
+def _to_uf(x, uf):
+    """Round binary64 values to u_f through binary32 (numpy / torch conversions)."""
+    x32 = np.asarray(x, np.float64).astype(np.float32)
+    if uf == "fp16":
+        return x32.astype(np.float16).astype(np.float64)
+    if uf == "bf16":
+        torch = pytest.importorskip("torch")
+        return torch.tensor(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    return x32.astype(np.float64) if uf == "fp32" else np.asarray(x, np.float64)
+
+
+@pytest.mark.parametrize("uf", ["fp64", "fp32", "fp16", "bf16"])
+def test_x0_right_is_D_M_fl_b(uf):
+    """Right preconditioning: x0 = P b in u_f with P = D M, i.e. row i of M applied
+    to b rounded to u_f, times d_i rounded to u_f.  The two storage points are
+    checked apart: with d on the u_f grid only b's rounding shows (it reaches the
+    order of u_f for the 16-bit formats), with b on the grid only d's rounding
+    (x0 then equals fl(d) (M b) up to the binary32 sum)."""
+    w = W.convdiff_adaptive(12)
+    n = w.n
+    _, pp, pc, pv, d = O.spai_right(w.A, W.pattern_of(w.A), 0.3, 0, 8, 20, uf)
+    assert np.diff(pp).max() >= 4 and not np.allclose(d, d[0])
+    M = sp.csr_matrix((pv, pc, pp), shape=(n, n))
+    q = np.diff(pp)
+    arith = _U["fp64"] if uf == "fp64" else _U["fp32"]
+    store = 0.0 if uf in ("fp64", "fp32") else _U[uf]
+    rng = np.random.default_rng(44)
+    worst_b = worst_d = 0.0
+    for _ in range(8):
+        b = _wide_vector(rng, n)
+        dg = _to_uf(rng.uniform(0.25, 4.0, n), uf)          # d on the u_f grid
+        x0 = O.x0_right(pp, pc, pv, dg, b, uf)
+        ref = dg * (M @ b)
+        scale = dg * (abs(M) @ np.abs(b))
+        err = np.abs(x0 - ref) / scale
+        assert np.all(err <= 1.01 * (store + (q + 4) * arith)), (uf, err.max())
+        worst_b = max(worst_b, err.max())
+        wrong = M @ (dg * b)
+        assert np.abs(wrong - ref).max() > 1e-3 * np.abs(ref).max()
+
+        bg = _to_uf(_wide_vector(rng, n), uf)               # b on the u_f grid
+        x0 = O.x0_right(pp, pc, pv, d, bg, uf)
+        scale = np.abs(d) * (abs(M) @ np.abs(bg))
+        assert np.all(np.abs(x0 - _to_uf(d, uf) * (M @ bg)) <= 1.01 * (q + 4) * arith * scale)
+        worst_d = max(worst_d, (np.abs(x0 - d * (M @ bg)) / scale).max())
+    if store:
+        assert worst_b >= 0.25 * store and worst_d >= 0.25 * store, (uf, worst_b, worst_d)
+
+
+def _reduced_matrix(A, d, J):
+    I = sorted({int(i) for j in J for i in A.col[A.rowptr[j]:A.rowptr[j + 1]]})
+    pos = {i: t for t, i in enumerate(I)}
+    Ab = np.zeros((len(I), len(J)))
+    for c, j in enumerate(J):
+        for t in range(A.rowptr[j], A.rowptr[j + 1]):
+            Ab[pos[int(A.col[t])], c] = d[j] * A.val[t]
+    return Ab, pos
+
+
+@pytest.mark.parametrize("uf", ["fp32", "fp16", "bf16"])
+def test_low_precision_columns_within_the_ls_perturbation_bound(uf):
+    """Fixed pattern(A^2) columns of the 6^3 anisotropic system in u_f against the
+    FP64 least-squares definition (eq. redprob): the relative difference stays
+    within max(tol, 4 x Higham's LS perturbation bound kappa u_f +
+    kappa^2 u_f ||s|| / (||A-bar|| ||m||)), tol = 1e-5 (FP32) or 2e-2 (16-bit);
+    and the largest difference reaches the order of u_f, so the storage
+    roundings of the QR are really there."""
+    w = W.aniso_fixed(6, uf)
+    s = w.spai
+    R = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    u = _U[uf]
+    tol = 1e-5 if uf == "fp32" else 2e-2
+    worst = 0.0
+    for k in range(w.n):
+        L = R.length[k]
+        J = R.J[k, :L]
+        mls, _ = O.ls_column(w.A, R.d, k, J)
+        Ab, pos = _reduced_matrix(w.A, R.d, J)
+        e = np.zeros(Ab.shape[0])
+        e[pos[k]] = 1.0
+        kap = np.linalg.cond(Ab)
+        sres = np.linalg.norm(Ab @ mls - e)
+        bound = kap * u + kap ** 2 * u * sres / (np.linalg.norm(Ab, 2) * np.linalg.norm(mls))
+        rel = np.linalg.norm(R.m[k, :L] - mls) / np.linalg.norm(mls)
+        assert rel <= max(tol, 4 * bound), (uf, k, rel, bound)
+        worst = max(worst, rel)
+    assert worst >= 0.5 * u, (uf, worst)
+
+
+def _grid_matrix(n, rng, bits=8):
+    """Random sparse diagonally dominant matrix whose entries have at most `bits`
+    significant bits (inside the FP16 normal range) and whose diagonal is a power
+    of two and the largest entry of its row: the scaling d_i is then a power of
+    two and every entry of B = A^T D is a binary16 and a bfloat16 value."""
+    M = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.25)
+    np.fill_diagonal(M, 0.0)
+    M = np.where(M != 0, np.sign(M) * np.maximum(np.abs(M), 2.0 ** -6), 0.0)
+    e = np.floor(np.log2(np.abs(np.where(M != 0, M, 1.0))))
+    M = np.where(M != 0, np.round(M * 2.0 ** (bits - 1 - e)) * 2.0 ** (e - bits + 1), 0.0)
+    np.fill_diagonal(M, 2.0 ** np.ceil(np.log2(1.5 * np.abs(M).sum(1) + 1.0)))
+    return M
+
+
+@pytest.mark.parametrize("uf", ["fp16", "bf16"])
+def test_gathered_entries_are_rounded_to_uf(uf):
+    """Storage point 'A-bar rounded to u_f' (Section 3.1's u_f build): a matrix
+    whose scaled entries are u_f values and the same matrix with every
+    off-diagonal entry moved by a relative 2^-14 (well inside half a u_f ulp)
+    gather the same u_f A-bar, so Algorithm 1 gives bit-identical columns, fixed
+    and adaptive; without that rounding they differ."""
+    rng = np.random.default_rng(45)
+    n = 40
+    Ad = _grid_matrix(n, rng)
+    off = ~np.eye(n, dtype=bool) & (Ad != 0)
+    Ap = Ad.copy()
+    Ap[off] *= 1.0 + np.where(rng.random(off.sum()) < 0.5, -1.0, 1.0) * 2.0 ** -14
+    A, A2 = _csr(Ad), _csr(Ap)
+    for pattern, alpha in ((W.pattern_of(A), 0), (None, 5)):
+        R1 = O.spai(A, pattern, 0.2, alpha, 8, 20, uf)
+        R2 = O.spai(A2, pattern, 0.2, alpha, 8, 20, uf)
+        assert np.array_equal(R1.d, R2.d)
+        assert np.array_equal(R1.J, R2.J) and np.array_equal(R1.m, R2.m)
+        assert np.array_equal(_to_uf(R1.m, uf), R1.m)        # m-bar is stored in u_f
+    R64 = O.spai(A, None, 0.2, 5, 8, 20, "fp64")
+    R64p = O.spai(A2, None, 0.2, 5, 8, 20, "fp64")
+    assert not np.array_equal(R64.m, R64p.m)                  # the perturbation is seen in FP64

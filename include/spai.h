@@ -51,7 +51,7 @@ enum {
     SPAI_E_INTERNAL = -4, /* a device-side consistency check failed */
     SPAI_W_EPS = 1,       /* some columns end with ||e_k - B m_k|| > eps (alpha or fill cap hit) */
     SPAI_W_RANKDEF = 2,   /* a reduced problem was rank deficient (zero Householder norm) */
-    SPAI_W_NONFINITE = 4, /* a column produced a non-finite value in u_f */
+    SPAI_W_NONFINITE = 4, /* a column is non-finite even after its FP32 recomputation (see spai_build) */
     SPAI_W_MAXIT = 8,     /* some GMRES solve hit maxit */
     SPAI_W_NOCONV = 16    /* refinement stopped at imax or on stagnation */
 };
@@ -151,6 +151,10 @@ typedef struct {
     int32_t cols_nonfinite; /* columns with a non-finite value */
     int32_t cols_deferred;  /* columns the first configuration deferred to a larger one */
     double max_res;         /* largest final column residual */
+    int64_t nnz_numeric;    /* stored entries of P whose value is not zero (what the paper's tables
+                               count as nnz of the preconditioner, Section 4) */
+    int32_t cols_fallback;  /* FP16/BF16 columns recomputed in FP32 after a non-finite value */
+    int32_t pad;
 } spai_build_stats;
 
 /* Read-only view of a preconditioner P = M^T D (device pointers owned by P).
@@ -177,6 +181,9 @@ typedef struct {
     const int32_t* flags;
     int32_t side;          /* SPAI_LEFT: row k holds m_k, P w = M^T (D w); SPAI_RIGHT: row i holds the
                               entries m_k[i] (columns k ascending), P w = D (M w) */
+    spai_prec u_f;         /* the precision the build ran in; x0 = P b rounds D b (left) or b
+                              (right) to it.  Equal to val_prec, except for an FP16/BF16 build with
+                              recomputed columns, whose values are stored in FP32 */
 } spai_precond_view;
 
 /* Orthogonalisation of the Arnoldi vectors.  Algorithm 3 asks for GMRES; the
@@ -213,6 +220,12 @@ typedef struct {
                        HIP graph, built once per call and replayed; the kernels take the
                        step index from the device solver state.  Same results as 0
                        (stream launches, default); other orthogonalisations ignore it. */
+    int32_t x_given;        /* 0 (default): start from x0 = P b in u_f (Algorithm 3).  1: x holds
+                               the first iterate on entry (a warm start; with working precision
+                               FP32 it is used as rounded to binary32) and refinement step 0 starts
+                               from it */
+    const double* x_true;   /* optional device array of n values: the exact solution, for the
+                               forward error in the statistics (NULL: ferr is reported as -1) */
 } spai_ir_params;
 
 typedef struct {
@@ -222,6 +235,10 @@ typedef struct {
     int32_t status;     /* SPAI_W_MAXIT | SPAI_W_NOCONV bits */
     double gest[32];    /* |g_{k+1}| / ||P r_i|| at the end of each step */
     double dnorm[32];   /* ||d_i||_inf of each step */
+    double nbe;         /* normwise backward error of the returned x (Theorem 2):
+                           ||b - A x||_inf / (||A||_inf ||x||_inf + ||b||_inf), residual in u_r */
+    double ferr;        /* forward error ||x - x_true||_inf / ||x_true||_inf (Theorem 1), or -1
+                           when x_true is NULL */
 } spai_ir_stats;
 
 /* Handle: binds the current HIP device, a stream (default: the null stream) and a
@@ -234,6 +251,30 @@ int spai_set_stream(spai_handle* h, hipStream_t stream);
 const char* spai_last_error(void);
 
 /*
+ * Device memory.  By default the library takes device memory with hipMalloc
+ * and returns it with hipFree.  spai_set_allocator routes every later device
+ * allocation of the library through the caller's functions instead (for
+ * example a framework's caching allocator, so that one owner holds all device
+ * memory):
+ *   alloc(bytes, device, stream, ctx) returns device memory of at least
+ *       `bytes` bytes on `device`, usable by work enqueued on `stream` (the
+ *       stream the library will use it on), or NULL when none is available
+ *       (the library call then fails with SPAI_E_OOM);
+ *   free_(ptr, device, stream, ctx) takes back a block alloc returned, with
+ *       the device and stream it was allocated for; work the library enqueued
+ *       on that stream before the call may still be using it, so the block may
+ *       only be reused for work ordered after that stream's pending work.
+ * Every block is freed by the pair that allocated it, also after a later call
+ * changed the allocator.  alloc = free_ = NULL restores hipMalloc/hipFree.
+ * Process-wide; not to be called while another thread is inside a library
+ * call.  Request servers take their arena (one block) through the same path.
+ * Returns SPAI_E_ARG when exactly one of the two functions is NULL.
+ */
+typedef void* (*spai_alloc_fn)(size_t bytes, int device, hipStream_t stream, void* ctx);
+typedef void (*spai_free_fn)(void* ptr, int device, hipStream_t stream, void* ctx);
+int spai_set_allocator(spai_alloc_fn alloc, spai_free_fn free_, void* ctx);
+
+/*
  * Build the left preconditioner P = M^T D (Algorithm 3, first line, with the
  * scaling of Section 4): D = diag(1 / max_j |a_ij|), Algorithm 1 runs on
  * B = A^T D from the initial pattern J (NULL = identity), and every column solves
@@ -242,6 +283,14 @@ const char* spai_last_error(void);
  * residual is <= eps, alpha steps were taken or |J_k| reached maxfill.
  * On success *P receives a new preconditioner owned by the caller (free with
  * spai_precond_destroy) and *st (optional) the statistics.
+ * Overflow (Section 4 scales A so that the low precision computations do not
+ * overflow; it can still happen when a reduced problem is ill conditioned): an
+ * FP16 or BF16 column whose computation gives a non-finite value is recomputed
+ * from its initial pattern in FP32 (gather, QR, scores and selection, as with
+ * u_f = FP32) and counted in cols_fallback; P's values are then all stored in
+ * FP32 (the other columns keep their FP16/BF16 values exactly), while x0 = P b
+ * still rounds D b to the build's u_f (spai_precond_view.u_f).  A column that
+ * is still non-finite in FP32 keeps its values and sets SPAI_W_NONFINITE.
  * Errors: SPAI_E_ARG for n <= 0, NULL arrays, eps <= 0, beta < 0, alpha < 0,
  * maxfill < 1, maxfill > 63, an unknown u_f, a kernel_cfg outside 0..SPAI_KCFG_COUNT
  * or too small for the pattern, a pattern with a column longer than 63 or a
@@ -393,7 +442,8 @@ typedef struct {
 
 /* One system: host CSR A (validated on the device like spai_build's input),
  * host right-hand side b, optional host initial pattern (jptr: n+1, jidx: jnnz;
- * NULL jptr = identity), and the parameters of the build and of the solve. */
+ * NULL jptr = identity), and the parameters of the build and of the solve
+ * (ir.x_given and ir.x_true are ignored: a request starts from x0 = P b). */
 typedef struct {
     int32_t n;
     int32_t nnz;

@@ -36,7 +36,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 UF = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 
-FLAG_RANKDEF, FLAG_EPS, FLAG_NONFINITE = 1, 2, 4
+FLAG_RANKDEF, FLAG_EPS, FLAG_NONFINITE, FLAG_FALLBACK = 1, 2, 4, 8
 IR_MAXIT, IR_NOCONV, IR_STAGNATED = 1, 2, 4
 
 
@@ -72,7 +72,8 @@ def _lib():
         L.oracle_x0_right.restype = None
         L.oracle_x0_right.argtypes = [i32, P, P, P, P, P, i32, P]
         L.oracle_gmres_ir_fp32.restype = i32
-        L.oracle_gmres_ir_fp32.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64, P, P, P, P]
+        L.oracle_gmres_ir_fp32.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64, P, P, P, P,
+                                           P, P, P]
         L.oracle_residual.restype = None
         L.oracle_residual.argtypes = [i32, P, P, P, P, P, P]
         L.oracle_exact_sum.restype = f64
@@ -173,7 +174,12 @@ def spai(A, pattern, eps: float, alpha: int, beta: int, maxfill: int, uf: str,
     step and ``maxfill`` the cap on |J_k|.  ``spai_oracle.c`` states how it
     reads the points the printed algorithm leaves open (residual on the full
     column, candidates outside J, at most beta best acceptable indices with
-    ties to the smaller index, augmentation only while step < alpha).
+    ties to the smaller index, augmentation only while step < alpha).  With
+    u_f = FP16/BF16 a column whose computation gives a non-finite value is
+    computed again from its initial pattern with u_f = FP32 (FLAG_FALLBACK):
+    the overflow policy of the library (Section 4 scales A so that the low
+    precision build does not overflow; an ill-conditioned reduced problem can
+    still exceed the half range).
     """
     n = A.n
     if cols is None:
@@ -275,6 +281,8 @@ class IrResult:
     status: int           # IR_* bits
     gest: np.ndarray      # |g_{k+1}| / beta0 per step
     dnorm: np.ndarray     # ||d_i||_inf per step
+    xhist: Optional[np.ndarray] = None   # u = fp32: x_0 .. x_s (the iterate each step starts from, then the last)
+    gprev: Optional[np.ndarray] = None   # u = fp32: |g_k| / beta0, the estimate one iteration before the stop
 
     @property
     def total(self) -> int:
@@ -288,7 +296,8 @@ ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 
 def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, maxit: int,
-             tol_ir: float, ortho: str = "mgs", u: str = "fp64", side: str = "left") -> IrResult:
+             tol_ir: float, ortho: str = "mgs", u: str = "fp64", side: str = "left",
+             x_init: Optional[np.ndarray] = None) -> IrResult:
     """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D.
 
     ``ortho`` = "mgs" (modified Gram-Schmidt, the variant analysed in Section
@@ -302,7 +311,11 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
 
     ``side`` = "left" (Algorithm 3: P = M^T D from ``spai``) or "right" (P = D M
     from ``spai_right``, GMRES on A P y = r_i with d_i = P y; working precision
-    double only)."""
+    double only).
+
+    ``x_init`` (u = "fp32" only): start the refinement from this iterate (used
+    as rounded to binary32) instead of x0 = P b; the result then also holds the
+    iterates each step started from (``xhist``) and the stopping margins."""
     n = A.n
     x = np.zeros(n)
     its = np.zeros(imax, np.int32)
@@ -314,12 +327,18 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     dd, bb = _f64(d), _f64(b)
     if side not in ("left", "right") or (side == "right" and u != "fp64"):
         raise ValueError("side must be left or right (right with u = fp64)")
+    xhist = gprev = None
+    if x_init is not None and u != "fp32":
+        raise ValueError("x_init is supported with u = fp32")
     if u == "fp32":
         if ortho != "mgs":
             raise ValueError("the single working precision variant uses MGS")
+        xhist = np.zeros((imax + 1, n))
+        gprev = np.zeros(imax)
+        xi = None if x_init is None else _f64(x_init)
         st = _lib().oracle_gmres_ir_fp32(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
                                          _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
-                                         _p(its), _p(nsteps), _p(gest), _p(dn))
+                                         _p(its), _p(nsteps), _p(gest), _p(dn), _p(xi), _p(xhist), _p(gprev))
     elif u == "fp64":
         st = _lib().oracle_gmres_ir(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
                                     _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
@@ -329,7 +348,8 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
     if st < 0:
         raise ValueError("oracle_gmres_ir: bad argument")
     s = int(nsteps[0])
-    return IrResult(x, [int(v) for v in its[:s]], st, gest[:s].copy(), dn[:s].copy())
+    return IrResult(x, [int(v) for v in its[:s]], st, gest[:s].copy(), dn[:s].copy(),
+                    None if xhist is None else xhist[:s + 1].copy(), None if gprev is None else gprev[:s].copy())
 
 
 def x0(P_rowptr, P_col, P_val, d, b, uf: str) -> np.ndarray:

@@ -225,7 +225,8 @@ typedef struct {
     int len;           /* |J_k| */
     int steps;         /* number of augmentation steps taken */
     int nI;            /* |I_k| at the last solve */
-    int flags;         /* bit0 rank-deficient, bit1 residual above eps, bit2 non-finite */
+    int flags;         /* bit0 rank-deficient, bit1 residual above eps, bit2 non-finite,
+                          bit3 recomputed in FP32 after a non-finite 16-bit result */
     double res;        /* ||e_k - B m_k||_2 at the last solve (as tested) */
     double margin;     /* smallest relative decision margin seen */
 } colinfo_t;
@@ -233,6 +234,7 @@ typedef struct {
 #define FLAG_RANKDEF 1
 #define FLAG_EPS 2
 #define FLAG_NONFINITE 4
+#define FLAG_FALLBACK 8
 
 static double dmin(double a, double b) { return a < b ? a : b; }
 
@@ -495,6 +497,7 @@ int oracle_spai_probe(int n, const int* rp, const int* ci, const double* av, int
 
 typedef struct {
     const prep_t* P;
+    const prep_t* P32;    /* FP32 preprocessing for the recomputation of overflowing 16-bit columns */
     const int* pat_ptr;
     const int* pat_idx;
     const int* cols;
@@ -530,6 +533,14 @@ static void* run_job(void* arg) {
         if (hist) for (int h = 0; h <= jb->stride; ++h) hist[h] = NAN;
         spai_column(jb->P, k, J0, len0, jb->eps, jb->alpha, jb->beta, jb->maxfill, jb->uf, &W,
                     Jtmp, mtmp, &info, hist, jb->stride + 1);
+        if ((info.flags & FLAG_NONFINITE) && jb->P32) {
+            /* overflow policy of the 16-bit formats: the whole column again, from its
+             * initial pattern, with u_f = FP32 (storage points and arithmetic) */
+            if (hist) for (int h = 0; h <= jb->stride; ++h) hist[h] = NAN;
+            spai_column(jb->P32, k, J0, len0, jb->eps, jb->alpha, jb->beta, jb->maxfill, OR_FP32, &W,
+                        Jtmp, mtmp, &info, hist, jb->stride + 1);
+            info.flags |= FLAG_FALLBACK;
+        }
         size_t o = (size_t)t * (size_t)jb->stride;
         jb->out_len[t] = info.len;
         for (int c = 0; c < info.len; ++c) { jb->out_J[o + c] = Jtmp[c]; jb->out_m[o + c] = mtmp[c]; }
@@ -563,15 +574,17 @@ int oracle_spai(int n, const int* rp, const int* ci, const double* av, const int
                 double* out_margin, double* out_d, double* out_hist) {
     if (n <= 0 || uf < 0 || uf > 3 || ncols < 0 || stride <= 0) return -1;
     if (nthreads < 1) nthreads = 1;
-    prep_t P;
+    prep_t P, P32;
     prep_build(&P, n, rp, ci, av, uf);
+    const int low = uf == OR_FP16 || uf == OR_BF16;
+    if (low) prep_build(&P32, n, rp, ci, av, OR_FP32);
     if (out_d) memcpy(out_d, P.d, sizeof(double) * (size_t)n);
     if (nthreads > ncols) nthreads = ncols > 0 ? ncols : 1;
     pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
     job_t* jobs = (job_t*)malloc(sizeof(job_t) * (size_t)nthreads);
     for (int t = 0; t < nthreads; ++t) {
         job_t* jb = &jobs[t];
-        jb->P = &P; jb->pat_ptr = pat_ptr; jb->pat_idx = pat_idx; jb->cols = cols;
+        jb->P = &P; jb->P32 = low ? &P32 : NULL; jb->pat_ptr = pat_ptr; jb->pat_idx = pat_idx; jb->cols = cols;
         jb->c0 = (int)((long long)ncols * t / nthreads);
         jb->c1 = (int)((long long)ncols * (t + 1) / nthreads);
         jb->eps = eps; jb->alpha = alpha; jb->beta = beta; jb->maxfill = maxfill; jb->uf = uf;
@@ -587,6 +600,7 @@ int oracle_spai(int n, const int* rp, const int* ci, const double* av, const int
     free(th);
     free(jobs);
     prep_free(&P);
+    if (low) prep_free(&P32);
     return 0;
 }
 
@@ -1078,7 +1092,7 @@ static void spmv32(int n, const int* rp, const int* ci, const float* av, const f
 int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, const int* pp,
                          const int* pc, const double* pv, const double* d, int uf, const double* b,
                          double* x, double tau, int imax, int maxit, double tol_ir, int* its, int* nsteps,
-                         double* gest, double* dnorm) {
+                         double* gest, double* dnorm, const double* x_init, double* xhist, double* gprev) {
     if (n <= 0 || imax < 1 || maxit < 1 || uf == OR_FP64) return -1;
     const int nnz = rp[n], pnz = pp[n];
     float* af = (float*)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
@@ -1105,9 +1119,14 @@ int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, 
         df[i] = (float)d[i];
         bf[i] = (float)b[i];
     }
-    /* x0 = P b in u_f (as in the double-precision variant), stored in u */
-    oracle_x0(n, pp, pc, pv, d, b, uf, x0);
-    for (int i = 0; i < n; ++i) xf[i] = (float)x0[i];
+    /* x0 = P b in u_f (as in the double-precision variant), stored in u; or the
+     * given first iterate, as rounded to u */
+    if (x_init) for (int i = 0; i < n; ++i) xf[i] = (float)x_init[i];
+    else {
+        oracle_x0(n, pp, pc, pv, d, b, uf, x0);
+        for (int i = 0; i < n; ++i) xf[i] = (float)x0[i];
+    }
+    if (xhist) for (int i = 0; i < n; ++i) xhist[i] = (double)xf[i];
     int status = 0;
     float dprev = INFINITY;
     *nsteps = 0;
@@ -1128,6 +1147,7 @@ int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, 
         for (int i = 0; i <= maxit; ++i) g[i] = 0.0f;
         g[0] = beta0;
         int k = 0;
+        float glast = beta0, gcur = beta0;   /* |g_{j+1}| of the previous and the current iteration */
         for (int j = 0; j < maxit; ++j) {
             float* vj = V + (size_t)j * n;
             spmv32(n, rp, ci, af, vj, w);
@@ -1153,6 +1173,8 @@ int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, 
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             k = j + 1;
+            glast = gcur;
+            gcur = fabsf(g[j + 1]);
             if (fabsf(g[j + 1]) <= (float)tau * beta0 || hn == 0.0f) break;
             if (j + 1 == maxit) { status |= IR_MAXIT; break; }
             float* vn = V + (size_t)(j + 1) * n;
@@ -1160,6 +1182,9 @@ int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, 
         }
         its[step] = k;
         if (gest) gest[step] = (double)(fabsf(g[k]) / beta0);
+        /* the estimate one iteration earlier, which did not stop (beta0 for k = 1):
+         * with gest it tells how close the stopping test came to another count */
+        if (gprev) gprev[step] = (double)(glast / beta0);
         for (int c = k - 1; c >= 0; --c) {
             float s = g[c];
             for (int c2 = c + 1; c2 < k; ++c2) s = fmaf(-HH(c, c2), yk[c2], s);
@@ -1174,6 +1199,7 @@ int oracle_gmres_ir_fp32(int n, const int* rp, const int* ci, const double* av, 
             if (fabsf(xf[i]) > xn) xn = fabsf(xf[i]);
         }
         if (dnorm) dnorm[step] = (double)dn;
+        if (xhist) for (int i = 0; i < n; ++i) xhist[(size_t)(step + 1) * (size_t)n + i] = (double)xf[i];
         if ((double)dn <= tol_ir * (double)xn) break;
         if (step >= 2 && dn > 0.5f * dprev) { status |= IR_STAGNATED; break; }
         dprev = dn;

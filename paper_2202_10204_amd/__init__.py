@@ -59,18 +59,21 @@ SIDE = {"left": 0, "right": 1}
 class _BuildStats(ctypes.Structure):
     _fields_ = [("nnz", _c_i64), ("max_len", _c_i32), ("max_steps", _c_i32), ("max_shadow", _c_i32),
                 ("cols_over_eps", _c_i32), ("cols_rankdef", _c_i32), ("cols_nonfinite", _c_i32),
-                ("cols_deferred", _c_i32), ("max_res", _c_f64)]
+                ("cols_deferred", _c_i32), ("max_res", _c_f64), ("nnz_numeric", _c_i64),
+                ("cols_fallback", _c_i32), ("pad", _c_i32)]
 
 
 class _View(ctypes.Structure):
     _fields_ = [("n", _c_i32), ("nnz", _c_i64), ("rowptr", _p), ("col", _p), ("val", _p),
                 ("val_prec", ctypes.c_int), ("d", _p), ("stride", _c_i32), ("j_ins", _p),
-                ("m_ins", _p), ("len", _p), ("steps", _p), ("res", _p), ("flags", _p), ("side", _c_i32)]
+                ("m_ins", _p), ("len", _p), ("steps", _p), ("res", _p), ("flags", _p), ("side", _c_i32),
+                ("u_f", ctypes.c_int)]
 
 
 class _IrParams(ctypes.Structure):
     _fields_ = [("u_r", ctypes.c_int), ("tau", _c_f64), ("imax", _c_i32), ("maxit", _c_i32),
-                ("tol_ir", _c_f64), ("ortho", _c_i32), ("u", ctypes.c_int), ("graph", _c_i32)]
+                ("tol_ir", _c_f64), ("ortho", _c_i32), ("u", ctypes.c_int), ("graph", _c_i32),
+                ("x_given", _c_i32), ("x_true", _p)]
 
 
 ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
@@ -78,7 +81,14 @@ ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 class _IrStats(ctypes.Structure):
     _fields_ = [("steps", _c_i32), ("its", _c_i32 * 32), ("total_its", _c_i32), ("status", _c_i32),
-                ("gest", _c_f64 * 32), ("dnorm", _c_f64 * 32)]
+                ("gest", _c_f64 * 32), ("dnorm", _c_f64 * 32), ("nbe", _c_f64), ("ferr", _c_f64)]
+
+
+def _ir_dict(st, status) -> dict:
+    k = st.steps
+    return {"steps": k, "its": list(st.its[:k]), "total_its": st.total_its, "status": status,
+            "gest": list(st.gest[:k]), "dnorm": list(st.dnorm[:k]), "nbe": st.nbe,
+            "ferr": None if st.ferr < 0 else st.ferr}
 
 
 class _ServeParams(ctypes.Structure):
@@ -102,6 +112,43 @@ class SpaiError(RuntimeError):
 
 
 _lib = None
+
+# Device memory of the library comes from torch's caching allocator
+# (spai_set_allocator): one owner for all device memory of the process.
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(nbytes, device, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0))
+    except Exception:          # out of memory: the library reports SPAI_E_OOM
+        return None
+
+
+def _torch_free(ptr, device, stream, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:          # interpreter shutdown
+        pass
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+allocator = "hip"              # "torch" once use_torch_allocator() is in force
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through torch's caching allocator
+    (enable) or back to hipMalloc/hipFree.  Installed when the library loads."""
+    global allocator
+    L = lib()
+    if enable:
+        _check(L.spai_set_allocator(_TORCH_ALLOC, _TORCH_FREE, None), "spai_set_allocator")
+        allocator = "torch"
+    else:
+        _check(L.spai_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "spai_set_allocator")   # NULL pair
+        allocator = "hip"
 
 
 def lib():
@@ -137,15 +184,17 @@ def lib():
         L.spai_serve_submit.argtypes = [_p, P(_ServeRequest), P(_c_i64)]
         L.spai_serve_wait.argtypes = [_p, _c_i64, _p, P(_ServeResult)]
         L.spai_serve_destroy.argtypes = [_p]
+        L.spai_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, _p]
         L.spai_timing_enable.argtypes = [_p, ctypes.c_int, ctypes.c_int]
         L.spai_timing_read.argtypes = [_p, ctypes.c_int, P(_c_i64), P(_c_f64)]
         for name in ("spai_timing_enable", "spai_timing_read", "spai_create", "spai_destroy", "spai_set_stream", "spai_build", "spai_precond_import",
                      "spai_precond_view_get", "spai_precond_destroy", "spai_gmres_ir", "spai_residual",
                      "spai_precond_apply", "spai_precond_apply_uf", "spai_spmv", "spai_build_batched",
                      "spai_gmres_ir_batched", "spai_serve_footprint", "spai_serve_create", "spai_serve_submit",
-                     "spai_serve_wait", "spai_serve_destroy"):
+                     "spai_serve_wait", "spai_serve_destroy", "spai_set_allocator"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
+        use_torch_allocator(True)
     return _lib
 
 
@@ -167,6 +216,20 @@ def _ptr(t: Optional[torch.Tensor]):
 # device-resident inputs
 # ---------------------------------------------------------------------------
 
+def _check_structure(n: int, ptr, idx, what: str):
+    """Host check of a compressed structure before it is copied to the device:
+    ptr runs from 0 to len(idx) without decreasing, every index in [0, n)."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    if n <= 0 or ptr.shape != (n + 1,) or ptr[0] != 0 or ptr[-1] != idx.size:
+        raise SpaiError(f"{what} pointers must hold n + 1 = {n + 1} values from 0 to {idx.size}")
+    if np.any(np.diff(ptr) < 0):
+        raise SpaiError(f"{what} pointers decrease")
+    if idx.size and (idx.min() < 0 or idx.max() >= n):
+        raise SpaiError(f"{what} index outside [0, n)")
+    return ptr, idx
+
+
 @dataclasses.dataclass
 class DeviceCSR:
     """CSR matrix on the device (int32 indices, FP64 values)."""
@@ -178,8 +241,8 @@ class DeviceCSR:
 
     @classmethod
     def from_host(cls, A, device="cuda") -> "DeviceCSR":
-        return cls(int(A.n), torch.as_tensor(np.asarray(A.rowptr, np.int32), device=device),
-                   torch.as_tensor(np.asarray(A.col, np.int32), device=device),
+        rp, ci = _check_structure(int(A.n), A.rowptr, A.col, "matrix row")
+        return cls(int(A.n), torch.as_tensor(rp, device=device), torch.as_tensor(ci, device=device),
                    torch.as_tensor(np.asarray(A.val, np.float64), device=device))
 
     @property
@@ -198,8 +261,8 @@ class DevicePattern:
 
     @classmethod
     def from_host(cls, pat, device="cuda") -> "DevicePattern":
-        return cls(int(pat.n), torch.as_tensor(np.asarray(pat.ptr, np.int32), device=device),
-                   torch.as_tensor(np.asarray(pat.idx, np.int32), device=device))
+        pp, pi = _check_structure(int(pat.n), pat.ptr, pat.idx, "pattern column")
+        return cls(int(pat.n), torch.as_tensor(pp, device=device), torch.as_tensor(pi, device=device))
 
     def c(self) -> _Pattern:
         return _Pattern(self.n, int(self.idx.numel()), self.ptr.data_ptr(), self.idx.data_ptr())
@@ -364,17 +427,17 @@ class Handle:
     # -- Algorithm 3 ---------------------------------------------------------
     def gmres_ir(self, A: DeviceCSR, P: Precond, b: torch.Tensor, x: torch.Tensor, tau: float, imax: int,
                  maxit: int, tol_ir: float, u_r: str = "dd", ortho: str = "mgs", u: str = "fp64",
-                 graph: bool = False):
-        """graph: replay each chunk of DCGS2 Arnoldi steps as one HIP graph (same results)."""
+                 graph: bool = False, x_given: bool = False, x_true: Optional[torch.Tensor] = None):
+        """graph: replay each chunk of DCGS2 Arnoldi steps as one HIP graph (same results);
+        x_given: x holds the first iterate (warm start instead of x0 = P b);
+        x_true: exact solution on the device, for the forward error in the result."""
         prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO[ortho], PREC[u],
-                        int(bool(graph)))
+                        int(bool(graph)), int(bool(x_given)), _ptr(x_true))
         st = _IrStats()
         csr = A.c()
         rc = _check(lib().spai_gmres_ir(self._raw, ctypes.byref(csr), P.raw, _ptr(b), _ptr(x),
                                         ctypes.byref(prm), ctypes.byref(st)), "spai_gmres_ir")
-        s = st.steps
-        return {"steps": s, "its": list(st.its[:s]), "total_its": st.total_its, "status": rc,
-                "gest": list(st.gest[:s]), "dnorm": list(st.dnorm[:s])}
+        return _ir_dict(st, rc)
 
     # -- batches of independent systems (block-diagonal A, host sys_ptr) ------
     def spai_build_batched(self, A: DeviceCSR, sys_ptr, pattern: Optional[DevicePattern], eps: float, alpha: int,
@@ -395,21 +458,18 @@ class Handle:
         return Precond(self, out.value, stats), rc, stats
 
     def gmres_ir_batched(self, A: DeviceCSR, P: Precond, sys_ptr, b: torch.Tensor, x: torch.Tensor, tau: float,
-                         imax: int, maxit: int, tol_ir: float, u_r: str = "dd", u: str = "fp64"):
+                         imax: int, maxit: int, tol_ir: float, u_r: str = "dd", u: str = "fp64",
+                         x_given: bool = False, x_true: Optional[torch.Tensor] = None):
         """Returns (warning bits of all systems, list of per-system stats dicts)."""
         nsys = len(sys_ptr) - 1
         sp = (_c_i32 * len(sys_ptr))(*[int(v) for v in sys_ptr])
-        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO["mgs"], PREC[u])
+        prm = _IrParams(PREC[u_r], float(tau), int(imax), int(maxit), float(tol_ir), ORTHO["mgs"], PREC[u], 0,
+                        int(bool(x_given)), _ptr(x_true))
         st = (_IrStats * nsys)()
         csr = A.c()
         rc = _check(lib().spai_gmres_ir_batched(self._raw, ctypes.byref(csr), P.raw, nsys, sp, _ptr(b), _ptr(x),
                                                 ctypes.byref(prm), st), "spai_gmres_ir_batched")
-        out = []
-        for q in range(nsys):
-            k = st[q].steps
-            out.append({"steps": k, "its": list(st[q].its[:k]), "total_its": st[q].total_its,
-                        "status": st[q].status, "gest": list(st[q].gest[:k]), "dnorm": list(st[q].dnorm[:k])})
-        return rc, out
+        return rc, [_ir_dict(st[q], st[q].status) for q in range(nsys)]
 
     # -- measurement ---------------------------------------------------------
     def timing_enable(self, kernel: str, sample_every: int = 1):
@@ -518,7 +578,7 @@ class Server:
         rec = {"rc": res.rc, "lane": res.lane, "batch_size": res.batch_size, "footprint": res.footprint,
                "nnz_p": res.nnz_p, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
                "steps": k, "its": list(res.ir.its[:k]), "total_its": res.ir.total_its, "status": res.ir.status,
-               "error": last_error() if rc < 0 else ""}
+               "nbe": res.ir.nbe, "error": last_error() if rc < 0 else ""}
         return rc, (x if rc >= 0 else None), rec
 
     def close(self):

@@ -1,6 +1,8 @@
 // Handle, error reporting and workspace management of libspai.
 #include <cstdlib>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 
 #include "common.hpp"
 
@@ -10,17 +12,41 @@ static thread_local std::string g_last_error = "no error";
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-int dev_malloc(spai_handle* h, void** p, size_t bytes) {
+// The allocator in force (spai_set_allocator; empty: hipMalloc / hipFree) and,
+// for every block a caller's allocator returned, the pair that frees it with
+// the device and stream it was allocated for.
+struct HookAlloc {
+    spai_alloc_fn alloc = nullptr;
+    spai_free_fn free_ = nullptr;
+    void* ctx = nullptr;
+};
+struct HookBlock {
+    HookAlloc by;
+    int device;
+    hipStream_t stream;
+};
+static std::mutex g_alloc_mu;
+static HookAlloc g_alloc;
+static std::unordered_map<void*, HookBlock> g_blocks;
+
+int raw_malloc(void** p, size_t bytes, int device, hipStream_t stream) {
     *p = nullptr;
     if (bytes == 0) bytes = 1;
-    Arena& a = h->arena;
-    if (a.base) {
-        const size_t off = (a.used + 255) & ~(size_t)255;
-        if (off <= a.size && bytes <= a.size - off) {
-            *p = a.base + off;
-            a.used = off + bytes;
-            return SPAI_OK;
+    HookAlloc by;
+    {
+        std::lock_guard<std::mutex> l(g_alloc_mu);
+        by = g_alloc;
+    }
+    if (by.alloc) {
+        void* q = by.alloc(bytes, device, stream, by.ctx);
+        if (!q) {
+            set_error("device allocation of " + std::to_string(bytes) + " bytes failed (caller's allocator)");
+            return SPAI_E_OOM;
         }
+        std::lock_guard<std::mutex> l(g_alloc_mu);
+        g_blocks[q] = HookBlock{by, device, stream};
+        *p = q;
+        return SPAI_OK;
     }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
@@ -33,9 +59,47 @@ int dev_malloc(spai_handle* h, void** p, size_t bytes) {
     return SPAI_OK;
 }
 
+void raw_free(void* p) {
+    if (!p) return;
+    HookBlock b{};
+    bool hooked = false;
+    {
+        std::lock_guard<std::mutex> l(g_alloc_mu);
+        auto it = g_blocks.find(p);
+        if (it != g_blocks.end()) {
+            b = it->second;
+            hooked = true;
+            g_blocks.erase(it);
+        }
+    }
+    if (hooked) b.by.free_(p, b.device, b.stream, b.by.ctx);
+    else (void)hipFree(p);
+}
+
+int dev_malloc(spai_handle* h, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    Arena& a = h->arena;
+    if (a.base) {
+        // a unit of a request server: its memory is the region it was admitted
+        // with, never more (admission by footprint is a hard bound)
+        const size_t off = (a.used + 255) & ~(size_t)255;
+        if (off <= a.size && bytes <= a.size - off) {
+            *p = a.base + off;
+            a.used = off + bytes;
+            return SPAI_OK;
+        }
+        set_error("device allocation of " + std::to_string(bytes) + " bytes exceeds the " +
+                  std::to_string(a.size) + "-byte region the request was admitted with (" +
+                  std::to_string(a.used) + " bytes in use)");
+        return SPAI_E_OOM;
+    }
+    return raw_malloc(p, bytes, h->device, h->stream);
+}
+
 void dev_free(void* p, const Arena& from) {
     if (!p || from.owns(p)) return;
-    (void)hipFree(p);
+    raw_free(p);
 }
 
 int buffer_reserve(spai_handle* h, Buffer& b, size_t bytes) {
@@ -78,6 +142,16 @@ static int pinned_reserve(spai::Buffer& b, size_t bytes) {
 }
 
 extern "C" const char* spai_last_error(void) { return spai::g_last_error.c_str(); }
+
+extern "C" int spai_set_allocator(spai_alloc_fn alloc, spai_free_fn free_, void* ctx) {
+    if ((alloc == nullptr) != (free_ == nullptr)) {
+        spai::set_error("invalid argument: give both allocator functions or neither");
+        return SPAI_E_ARG;
+    }
+    std::lock_guard<std::mutex> l(spai::g_alloc_mu);
+    spai::g_alloc = spai::HookAlloc{alloc, free_, alloc ? ctx : nullptr};
+    return SPAI_OK;
+}
 
 extern "C" int spai_create(spai_handle** h) {
     if (!h) {

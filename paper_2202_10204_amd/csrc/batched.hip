@@ -59,6 +59,8 @@ struct BatchArgs {
     const double* d;
     const double* b;
     double* x;
+    const double* x_true;  // exact solution for the forward error (NULL: none)
+    int x_given;           // x holds the first iterate (no x0 = P b)
     double tau;
     double tol_ir;
     int imax;
@@ -122,11 +124,48 @@ __device__ __forceinline__ TW p_row(const BatchArgs& a, int gi, const TW* w) {
     return s;
 }
 
+// r_i = b_i - (A x)_i of global row gi in u_r, before its rounding to the
+// working precision: double-double rounded to FP64 (dd), else FP64 fused
+// multiply-adds in CSR order (with u = FP32: A and b as rounded to binary32).
+template <bool U32>
+__device__ __forceinline__ double resid_row(const BatchArgs& a, int gi, const double* x) {
+    if (a.dd) {
+        double shi = a.b[gi], slo = 0.0;
+        for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
+            const double av = a.av[q], xv = x[a.ci[q]];
+            const double ph = av * xv;
+            const double pl = __builtin_fma(av, xv, -ph);
+            dd_add(shi, slo, -ph, -pl, shi, slo);
+        }
+        return shi + slo;
+    }
+    double acc = U32 ? (double)(float)a.b[gi] : a.b[gi];
+    for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
+        const double av = U32 ? (double)(float)a.av[q] : a.av[q];
+        acc = __builtin_fma(-av, x[a.ci[q]], acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double wg_max_d(double v, double* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < BW; ++w) t = fmax(t, sh[w]);
+    __syncthreads();
+    return t;
+}
+
 // One system's whole refinement loop in working precision TW (double: u = FP64;
 // float: u = FP32, where A, b, the scaling, r, the basis, H, the rotations, d
-// and x are binary32 values and the residual is evaluated in binary64).
-template <int VP, typename TW>
-__device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, spai_ir_stats& st) {
+// and x are binary32 values and the residual is evaluated in binary64).  VP is
+// the storage format of P's values, UF the precision of its build (x0 rounds
+// D b to it).
+template <int VP, typename TW, int UF>
+__device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, double* shd, spai_ir_stats& st) {
     using T = typename ValType<VP>::T;
     constexpr bool U32 = sizeof(TW) == 4;
     const int t = threadIdx.x;
@@ -155,10 +194,13 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, sp
             st.dnorm[q] = 0.0;
         }
     }
-    // x0 = P b in u_f (products and sums in the arithmetic precision of u_f, column order), stored in u
+    // x0 = P b in u_f (products and sums in the arithmetic precision of u_f, column order), stored in u;
+    // or the given first iterate (as rounded to u)
     for (int i = t; i < n; i += BT) {
         const int gi = r0 + i;
-        if constexpr (VP == SPAI_FP64) {
+        if (a.x_given) {
+            if constexpr (U32) x[gi] = (double)(float)x[gi];
+        } else if constexpr (VP == SPAI_FP64) {
             double acc = 0.0;
             for (int q = a.pp[gi]; q < a.pp[gi + 1]; ++q) {
                 const int j = a.pc[q];
@@ -170,7 +212,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, sp
             float acc = 0.0f;
             for (int q = a.pp[gi]; q < a.pp[gi + 1]; ++q) {
                 const int j = a.pc[q];
-                const float z = store<VP, float>((float)(a.d[j] * a.b[j]));
+                const float z = store<UF, float>((float)(a.d[j] * a.b[j]));
                 acc = __builtin_fmaf(to_f32(pv[q]), z, acc);
             }
             x[gi] = (double)acc;
@@ -181,26 +223,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, sp
     int status = 0;
     for (int step = 0; step < a.imax; ++step) {
         // r = b - A x in u_r, stored in u (A and b as stored in u)
-        for (int i = t; i < n; i += BT) {
-            const int gi = r0 + i;
-            if (a.dd) {
-                double shi = a.b[gi], slo = 0.0;
-                for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
-                    const double av = a.av[q], xv = x[a.ci[q]];
-                    const double ph = av * xv;
-                    const double pl = __builtin_fma(av, xv, -ph);
-                    dd_add(shi, slo, -ph, -pl, shi, slo);
-                }
-                r[gi] = (TW)(shi + slo);
-            } else {
-                double acc = U32 ? (double)(float)a.b[gi] : a.b[gi];
-                for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
-                    const double av = U32 ? (double)(float)a.av[q] : a.av[q];
-                    acc = __builtin_fma(-av, x[a.ci[q]], acc);
-                }
-                r[gi] = (TW)acc;
-            }
-        }
+        for (int i = t; i < n; i += BT) r[r0 + i] = (TW)resid_row<U32>(a, r0 + i, x);
         __syncthreads();
         // z = P r into V(:, 0); beta0 = ||z||
         TW part = 0;
@@ -325,6 +348,34 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, sp
         dprev = dn;
         if (step == a.imax - 1) status |= SPAI_W_NOCONV;
     }
+    // errors of the returned x (Theorems 1 and 2): residual in u_r, norms in FP64
+    {
+        double rm = 0.0, am = 0.0, xm = 0.0, bm = 0.0, em = 0.0, tm = 0.0;
+        for (int i = t; i < n; i += BT) {
+            const int gi = r0 + i;
+            rm = fmax(rm, fabs(resid_row<U32>(a, gi, x)));
+            double rs = 0.0;
+            for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) rs += fabs(U32 ? (double)(float)a.av[q] : a.av[q]);
+            am = fmax(am, rs);
+            xm = fmax(xm, fabs(x[gi]));
+            bm = fmax(bm, fabs(U32 ? (double)(float)a.b[gi] : a.b[gi]));
+            if (a.x_true) {
+                em = fmax(em, fabs(x[gi] - a.x_true[gi]));
+                tm = fmax(tm, fabs(a.x_true[gi]));
+            }
+        }
+        rm = wg_max_d(rm, shd);
+        am = wg_max_d(am, shd);
+        xm = wg_max_d(xm, shd);
+        bm = wg_max_d(bm, shd);
+        em = wg_max_d(em, shd);
+        tm = wg_max_d(tm, shd);
+        if (t == 0) {
+            const double den = am * xm + bm;
+            st.nbe = den > 0.0 ? rm / den : 0.0;
+            st.ferr = a.x_true ? (tm > 0.0 ? em / tm : em) : -1.0;
+        }
+    }
     if (t == 0) {
         st.status = status;
         a.stats[s] = st;
@@ -332,9 +383,10 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, sp
     __syncthreads();
 }
 
-template <int VP, typename TW>
+template <int VP, typename TW, int UF = VP>
 __global__ __launch_bounds__(BT) void k_gmres_ir_batched(BatchArgs a) {
     __shared__ TW sh[BW + 2];
+    __shared__ double shd[BW];
     __shared__ int sys;
     __shared__ spai_ir_stats st;
     double* ws = a.ws + (size_t)blockIdx.x * a.slot;
@@ -344,7 +396,7 @@ __global__ __launch_bounds__(BT) void k_gmres_ir_batched(BatchArgs a) {
         const int q = sys;
         __syncthreads();
         if (q >= a.nsys) break;
-        solve_system<VP, TW>(a, a.order[q], ws, sh, st);
+        solve_system<VP, TW, UF>(a, a.order[q], ws, sh, shd, st);
     }
 }
 
@@ -413,7 +465,7 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     SPAI_ARG(prm->u == SPAI_FP64 || prm->u == SPAI_FP32, "the working precision u must be FP64 or FP32");
     if (prm->u == SPAI_FP32) {
         SPAI_ARG(prm->u_r == SPAI_FP64, "with working precision FP32 the residual precision must be FP64");
-        SPAI_ARG(P->val_prec != SPAI_FP64, "u_f must not be finer than the working precision");
+        SPAI_ARG(P->u_f != SPAI_FP64, "u_f must not be finer than the working precision");
     }
     SPAI_HIP(hipSetDevice(h->device));
     hipStream_t s = h->stream;
@@ -476,6 +528,8 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     a.d = P->d;
     a.b = b;
     a.x = x;
+    a.x_true = prm->x_true;
+    a.x_given = prm->x_given ? 1 : 0;
     a.tau = prm->tau;
     a.tol_ir = prm->tol_ir;
     a.imax = prm->imax;
@@ -489,18 +543,26 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
     a.stats = dst;
     long tk = timer_begin(h, SPAI_KT_MGS);
     const dim3 grid((unsigned)g), blk(BT);
+    // P's storage format and the precision of its build (FP32 values of a
+    // 16-bit build whose overflowing columns were recomputed in FP32)
+    const int vf = P->val_prec == SPAI_FP32 && (P->u_f == SPAI_FP16 || P->u_f == SPAI_BF16) ? 10 + P->u_f
+                 : P->val_prec;
     if (prm->u == SPAI_FP32) {
-        switch (P->val_prec) {
+        switch (vf) {
         case SPAI_FP32: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, float>), grid, blk, 0, s, a); break;
         case SPAI_FP16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP16, float>), grid, blk, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_BF16, float>), grid, blk, 0, s, a); break;
+        case SPAI_BF16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_BF16, float>), grid, blk, 0, s, a); break;
+        case 10 + SPAI_FP16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, float, SPAI_FP16>), grid, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, float, SPAI_BF16>), grid, blk, 0, s, a); break;
         }
     } else {
-        switch (P->val_prec) {
+        switch (vf) {
         case SPAI_FP64: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP64, double>), grid, blk, 0, s, a); break;
         case SPAI_FP32: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, double>), grid, blk, 0, s, a); break;
         case SPAI_FP16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP16, double>), grid, blk, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_BF16, double>), grid, blk, 0, s, a); break;
+        case SPAI_BF16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_BF16, double>), grid, blk, 0, s, a); break;
+        case 10 + SPAI_FP16: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, double, SPAI_FP16>), grid, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_gmres_ir_batched<SPAI_FP32, double, SPAI_BF16>), grid, blk, 0, s, a); break;
         }
     }
     timer_end(h, SPAI_KT_MGS, tk);

@@ -64,9 +64,13 @@ struct Buffer {
 };
 
 // Device memory of a handle: from the handle's arena when it has one (a free
-// is then a no-op and never waits, where hipFree waits for the whole device),
-// else, or when the arena is exhausted, hipMalloc / hipFree.
+// is then a no-op and never waits, where hipFree waits for the whole device;
+// an allocation beyond the arena fails with SPAI_E_OOM), else from the
+// allocator in force (spai_set_allocator, default hipMalloc / hipFree).
 int dev_malloc(spai_handle* h, void** p, size_t bytes);
+// the allocator in force, for memory no handle owns (a request server's arena)
+int raw_malloc(void** p, size_t bytes, int device, hipStream_t stream);
+void raw_free(void* p);
 void dev_free(void* p, const Arena& from);
 int buffer_reserve(spai_handle* h, Buffer& b, size_t bytes);
 void buffer_free(Buffer& b);
@@ -99,14 +103,15 @@ struct spai_handle {
     spai::Buffer red;              // reduction partials + ticket counters
     spai::Buffer host_pinned;      // pinned host staging
     int num_cu = 256;
-    spai::Arena arena;             // device memory lent by a request server (empty: hipMalloc)
+    spai::Arena arena;             // device memory lent by a request server (empty: the allocator in force)
     size_t ws_cap = 0;             // cap on the batched solver's workspace in bytes (0: a quarter of free memory)
 };
 
 struct spai_precond {
     int32_t n = 0;
     int64_t nnz = 0;
-    spai_prec val_prec = SPAI_FP32;
+    spai_prec val_prec = SPAI_FP32;  // storage format of the values
+    spai_prec u_f = SPAI_FP32;       // precision of the build (x0 = P b rounds its input to it)
     int32_t stride = 0;
     int32_t* rowptr = nullptr;  // n+1
     int32_t* col = nullptr;     // nnz
@@ -133,6 +138,7 @@ constexpr int CF_EPS = 1 << 0;
 constexpr int CF_RANKDEF = 1 << 1;
 constexpr int CF_NONFINITE = 1 << 2;
 constexpr int CF_DEFERRED = 1 << 3;  // problem exceeded the kernel's capacity: redo in the large kernel
+constexpr int CF_FALLBACK = 1 << 4;  // a 16-bit column recomputed in FP32 after a non-finite value
 
 // ---------------------------------------------------------------------------
 // device arithmetic.  The build computes in F = float (u_f = FP32/FP16/BF16)

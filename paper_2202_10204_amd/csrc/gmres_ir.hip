@@ -198,8 +198,11 @@ static inline int lanes_per_row(long long nnz, int n) {
     return g;
 }
 
-// x0 = P b in u_f: z_j = u_f(d_j b_j), products and sums in F, ascending column
-template <int VP, bool RIGHT>
+// x0 = P b in u_f: z_j = u_f(d_j b_j), products and sums in F, ascending column.
+// VP is the storage format of P's values, UF the precision of the build (the
+// two differ for a 16-bit build whose overflowing columns were recomputed in
+// FP32: the values are then FP32, the rounding of the input stays 16-bit).
+template <int VP, int UF, bool RIGHT>
 __global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ pc,
                      const typename ValType<VP>::T* __restrict__ pv, const double* __restrict__ d,
                      const double* __restrict__ b, double* __restrict__ x0) {
@@ -214,8 +217,8 @@ __global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ 
         } else {
             float s = 0.0f;
             for (int q = pp[k]; q < pp[k + 1]; ++q)
-                s = __builtin_fmaf(to_f32(pv[q]), store<VP, float>((float)b[pc[q]]), s);
-            x0[k] = (double)(store<VP, float>((float)d[k]) * s);
+                s = __builtin_fmaf(to_f32(pv[q]), store<UF, float>((float)b[pc[q]]), s);
+            x0[k] = (double)(store<UF, float>((float)d[k]) * s);
         }
     } else if constexpr (VP == SPAI_FP64) {
         double s = 0.0;
@@ -228,10 +231,40 @@ __global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ 
         float s = 0.0f;
         for (int q = pp[k]; q < pp[k + 1]; ++q) {
             int j = pc[q];
-            float z = store<VP, float>((float)(d[j] * b[j]));
+            float z = store<UF, float>((float)(d[j] * b[j]));
             s = __builtin_fmaf(to_f32(pv[q]), z, s);
         }
         x0[k] = (double)s;
+    }
+}
+
+// Maxima behind the error measures of Theorems 1 and 2 for the returned x:
+// out[0..5] = max |r_i|, max_i sum_j |a_ij|, max |x_i|, max |b_i|,
+// max |x_i - xt_i|, max |xt_i| (xt may be NULL).  Non-negative doubles order
+// as their bit patterns, so the maxima are taken on the bits (any order, same
+// result); out must be zero on entry.
+__global__ void k_err_norms(int n, const int* __restrict__ rp, const double* __restrict__ av,
+                            const double* __restrict__ r, const double* __restrict__ x,
+                            const double* __restrict__ b, const double* __restrict__ xt,
+                            unsigned long long* __restrict__ out) {
+    double m[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        m[0] = fmax(m[0], fabs(r[i]));
+        double rs = 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) rs += fabs(av[q]);
+        m[1] = fmax(m[1], rs);
+        m[2] = fmax(m[2], fabs(x[i]));
+        m[3] = fmax(m[3], fabs(b[i]));
+        if (xt) {
+            m[4] = fmax(m[4], fabs(x[i] - xt[i]));
+            m[5] = fmax(m[5], fabs(xt[i]));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double v = m[q];
+        for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+        if ((threadIdx.x & 63) == 0 && v > 0.0) atomicMax(out + q, (unsigned long long)__double_as_longlong(v));
     }
 }
 
@@ -1578,20 +1611,26 @@ static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, doubl
 
 static int launch_x0(const spai_precond* P, const double* b, double* x0, hipStream_t s) {
     int n = P->n, g = blocks_for(n, 256);
-#define SPAI_X0(VP, T, R) hipLaunchKernelGGL((k_x0<VP, R>), dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const T*)P->val, P->d, b, x0)
+#define SPAI_X0(VP, UF, T, R) hipLaunchKernelGGL((k_x0<VP, UF, R>), dim3(g), dim3(256), 0, s, n, P->rowptr, P->col, (const T*)P->val, P->d, b, x0)
     const bool right = P->side == SPAI_RIGHT;
     switch (P->val_prec) {
     case SPAI_FP64:
-        if (right) { SPAI_X0(SPAI_FP64, double, true); } else { SPAI_X0(SPAI_FP64, double, false); }
+        if (right) { SPAI_X0(SPAI_FP64, SPAI_FP64, double, true); } else { SPAI_X0(SPAI_FP64, SPAI_FP64, double, false); }
         break;
     case SPAI_FP32:
-        if (right) { SPAI_X0(SPAI_FP32, float, true); } else { SPAI_X0(SPAI_FP32, float, false); }
+        if (P->u_f == SPAI_FP16) {
+            if (right) { SPAI_X0(SPAI_FP32, SPAI_FP16, float, true); } else { SPAI_X0(SPAI_FP32, SPAI_FP16, float, false); }
+        } else if (P->u_f == SPAI_BF16) {
+            if (right) { SPAI_X0(SPAI_FP32, SPAI_BF16, float, true); } else { SPAI_X0(SPAI_FP32, SPAI_BF16, float, false); }
+        } else {
+            if (right) { SPAI_X0(SPAI_FP32, SPAI_FP32, float, true); } else { SPAI_X0(SPAI_FP32, SPAI_FP32, float, false); }
+        }
         break;
     case SPAI_FP16:
-        if (right) { SPAI_X0(SPAI_FP16, __half, true); } else { SPAI_X0(SPAI_FP16, __half, false); }
+        if (right) { SPAI_X0(SPAI_FP16, SPAI_FP16, __half, true); } else { SPAI_X0(SPAI_FP16, SPAI_FP16, __half, false); }
         break;
     default:
-        if (right) { SPAI_X0(SPAI_BF16, __hip_bfloat16, true); } else { SPAI_X0(SPAI_BF16, __hip_bfloat16, false); }
+        if (right) { SPAI_X0(SPAI_BF16, SPAI_BF16, __hip_bfloat16, true); } else { SPAI_X0(SPAI_BF16, SPAI_BF16, __hip_bfloat16, false); }
         break;
     }
 #undef SPAI_X0
@@ -1888,7 +1927,7 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
 
     int status = 0;
     spai_ir_stats loc{};
-    if ((rc = launch_x0(P, b, x, s))) return rc;   // x0 = P b in u_f
+    if (!prm->x_given && (rc = launch_x0(P, b, x, s))) return rc;   // x0 = P b in u_f
     double dprev = INFINITY;
     for (int step = 0; step < prm->imax; ++step) {
         if ((rc = launch_residual(h, A, b, x, r, prm->u_r, s))) return rc;
@@ -2033,6 +2072,19 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
         if (step == prm->imax - 1) status |= SPAI_W_NOCONV;
     }
     loc.status = status;
+    // backward and forward error of the returned x (residual in u_r)
+    if ((rc = launch_residual(h, A, b, x, r, prm->u_r, s))) return rc;
+    SPAI_HIP(hipMemsetAsync(maxbits + 2, 0, 6 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_err_norms, dim3(std::min(gb, 4 * std::max(h->num_cu, 1))), dim3(tb), 0, s, n, A->rowptr,
+                       A->val, (const double*)r, (const double*)x, b, prm->x_true, maxbits + 2);
+    SPAI_HIP(hipGetLastError());
+    SPAI_HIP(hipMemcpyAsync(hp, maxbits + 2, 6 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SPAI_HIP(hipStreamSynchronize(s));
+    double nm[6];
+    std::memcpy(nm, hp, sizeof(nm));
+    const double den = nm[1] * nm[2] + nm[3];
+    loc.nbe = den > 0.0 ? nm[0] / den : 0.0;
+    loc.ferr = prm->x_true ? (nm[5] > 0.0 ? nm[4] / nm[5] : nm[4]) : -1.0;
     if (st) *st = loc;
     return status;
 }

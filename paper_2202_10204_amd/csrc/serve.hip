@@ -81,14 +81,40 @@ struct Gate {
 
 size_t val_bytes(spai_prec p) { return p == SPAI_FP64 ? 8 : p == SPAI_FP32 ? 4 : 2; }
 
+// Structure of a host CSR-like array pair: ptr runs from 0 to nnz without
+// decreasing and every index lies in [0, n).  Checked on the host before
+// anything is copied, so a malformed request never reaches a kernel that other
+// requests share.
+int check_structure(int32_t n, int32_t nnz, const int32_t* ptr, const int32_t* idx, const char* what) {
+    if (ptr[0] != 0 || ptr[n] != nnz) {
+        set_error(std::string("invalid argument: ") + what + " pointers must run from 0 to the entry count");
+        return SPAI_E_ARG;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        if (ptr[i + 1] < ptr[i]) {
+            set_error(std::string("invalid argument: ") + what + " pointers decrease at row " + std::to_string(i));
+            return SPAI_E_ARG;
+        }
+    }
+    for (int32_t q = 0; q < nnz; ++q) {
+        if (idx[q] < 0 || idx[q] >= n) {
+            set_error(std::string("invalid argument: ") + what + " index " + std::to_string(idx[q]) +
+                      " at entry " + std::to_string(q) + " outside [0, n)");
+            return SPAI_E_ARG;
+        }
+    }
+    return SPAI_OK;
+}
+
 int check_request(const spai_serve_request* r) {
     SPAI_ARG(r, "NULL request");
     SPAI_ARG(r->n > 0 && r->nnz >= 0, "n <= 0 or nnz < 0");
     SPAI_ARG(r->rowptr && r->b && (r->nnz == 0 || (r->col && r->val)), "NULL array in the request");
-    SPAI_ARG(r->rowptr[0] == 0 && r->rowptr[r->n] == r->nnz, "rowptr must run from 0 to nnz");
+    int rc = check_structure(r->n, r->nnz, r->rowptr, r->col, "matrix row");
+    if (rc) return rc;
     if (r->jptr) {
         SPAI_ARG(r->jnnz >= 0 && (r->jnnz == 0 || r->jidx), "pattern without indices");
-        SPAI_ARG(r->jptr[0] == 0 && r->jptr[r->n] == r->jnnz, "pattern pointer must run from 0 to jnnz");
+        if ((rc = check_structure(r->n, r->jnnz, r->jptr, r->jidx, "pattern column"))) return rc;
     }
     const spai_build_params& p = r->build;
     SPAI_ARG(p.eps > 0 && p.alpha >= 0 && p.beta >= 0 && p.maxfill >= 1 && p.maxfill <= 63,
@@ -241,9 +267,8 @@ int pinned(LaneCtx& L, size_t bytes, char** out) {
     return SPAI_OK;
 }
 
-// Forget the handle's workspaces (they live in the unit's region; anything
-// that overflowed into hipMalloc is freed) so that the next unit allocates in
-// its own region.
+// Forget the handle's workspaces (they live in the unit's region) so that the
+// next unit allocates in its own region.
 void lane_trim(LaneCtx& L) {
     for (auto& b : L.h->ws) buffer_free(b);
 }
@@ -573,11 +598,9 @@ extern "C" int spai_serve_create(const spai_serve_params* p, spai_server** out) 
     int dev = 0;
     SPAI_HIP(hipGetDevice(&dev));
     void* arena = nullptr;
-    hipError_t e = hipMalloc(&arena, (size_t)prm.hbm_budget);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
+    if (spai::raw_malloc(&arena, (size_t)prm.hbm_budget, dev, nullptr) != SPAI_OK) {
         spai::set_error(std::string("device allocation of the server's ") + std::to_string(prm.hbm_budget) +
-                        " bytes failed: " + hipGetErrorString(e));
+                        " bytes failed");
         return SPAI_E_OOM;
     }
     spai_server* S = new spai_server();
@@ -620,6 +643,8 @@ extern "C" int spai_serve_submit(spai_server* S, const spai_serve_request* r, in
     }
     q->bp = r->build;
     q->ip = r->ir;
+    q->ip.x_given = 0;        // a request starts from x0 = P b
+    q->ip.x_true = nullptr;   // requests are host data; no device pointer is kept
     q->small = small;
     q->res.footprint = fp;
     {
@@ -647,8 +672,11 @@ extern "C" int spai_serve_wait(spai_server* S, int64_t id, double* x, spai_serve
         SPAI_ARG(!r->claimed, "another caller is already waiting for this request");
         r->claimed = true;
         S->cv.wait(l, [&] { return r->done; });
-        q = std::move(it->second);
-        S->reqs.erase(it);
+        // the wait dropped the lock: submissions may have rehashed the map, so
+        // the entry is looked up again (the request object itself has not moved)
+        auto again = S->reqs.find(id);
+        q = std::move(again->second);
+        S->reqs.erase(again);
     }
     if (x && !q->x.empty()) std::memcpy(x, q->x.data(), 8 * q->x.size());
     if (res) *res = q->res;
@@ -664,7 +692,8 @@ extern "C" int spai_serve_destroy(spai_server* S) {
     }
     S->cv.notify_all();
     for (auto& t : S->threads) t.join();
-    (void)hipFree(S->arena);
+    (void)hipDeviceSynchronize();
+    spai::raw_free(S->arena);
     delete S;
     return SPAI_OK;
 }

@@ -879,20 +879,27 @@ __global__ void k_compact(int n, int stride, const int* __restrict__ len, const 
 struct BuildStatsDev {
     int over_eps, rankdef, nonfinite, max_len, max_steps, max_shadow;
     unsigned long long max_res_bits;
+    unsigned long long nnz_numeric;   // entries of P whose value is not zero
+    int fallback, pad;
 };
 
-__global__ __launch_bounds__(RED_BLOCK) void k_build_stats(int n, const int* __restrict__ len, const int* __restrict__ steps,
-                              const double* __restrict__ res, const int* __restrict__ flags,
-                              const int* __restrict__ nI, BuildStatsDev* st) {
-    __shared__ int shi[6][RED_BLOCK / 64];
-    __shared__ unsigned long long shr[RED_BLOCK / 64];
-    int c_eps = 0, c_rd = 0, c_nf = 0, l = 0, sp = 0, sh = 0;
+__global__ __launch_bounds__(RED_BLOCK) void k_build_stats(int n, int stride, const int* __restrict__ len,
+                              const int* __restrict__ steps, const double* __restrict__ res,
+                              const int* __restrict__ flags, const int* __restrict__ nI,
+                              const double* __restrict__ mval, BuildStatsDev* st) {
+    __shared__ int shi[7][RED_BLOCK / 64];
+    __shared__ unsigned long long shr[2][RED_BLOCK / 64];
+    int c_eps = 0, c_rd = 0, c_nf = 0, c_fb = 0, l = 0, sp = 0, sh = 0;
     unsigned long long rb = 0ull;   // non-negative doubles order as their bit patterns
+    unsigned long long nz = 0ull;
     for (int k = blockIdx.x * RED_BLOCK + threadIdx.x; k < n; k += gridDim.x * RED_BLOCK) {
         const int f = flags[k];
         c_eps += (f & CF_EPS) ? 1 : 0;
         c_rd += (f & CF_RANKDEF) ? 1 : 0;
         c_nf += (f & CF_NONFINITE) ? 1 : 0;
+        c_fb += (f & CF_FALLBACK) ? 1 : 0;
+        const int L = len[k];
+        for (int c = 0; c < L; ++c) nz += mval[(size_t)k * stride + c] != 0.0 ? 1ull : 0ull;
         l = max(l, len[k]);
         sp = max(sp, steps[k]);
         sh = max(sh, nI[k]);
@@ -905,10 +912,12 @@ __global__ __launch_bounds__(RED_BLOCK) void k_build_stats(int n, const int* __r
     c_eps = wave_sum_i(c_eps);
     c_rd = wave_sum_i(c_rd);
     c_nf = wave_sum_i(c_nf);
+    c_fb = wave_sum_i(c_fb);
     l = wave_max_i(l);
     sp = wave_max_i(sp);
     sh = wave_max_i(sh);
     rb = wave_max_u64(rb);
+    for (int o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o, 64);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         shi[0][w] = c_eps;
@@ -917,7 +926,9 @@ __global__ __launch_bounds__(RED_BLOCK) void k_build_stats(int n, const int* __r
         shi[3][w] = l;
         shi[4][w] = sp;
         shi[5][w] = sh;
-        shr[w] = rb;
+        shi[6][w] = c_fb;
+        shr[0][w] = rb;
+        shr[1][w] = nz;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -928,11 +939,15 @@ __global__ __launch_bounds__(RED_BLOCK) void k_build_stats(int n, const int* __r
             l = max(l, shi[3][v]);
             sp = max(sp, shi[4][v]);
             sh = max(sh, shi[5][v]);
-            rb = shr[v] > rb ? shr[v] : rb;
+            c_fb += shi[6][v];
+            rb = shr[0][v] > rb ? shr[0][v] : rb;
+            nz += shr[1][v];
         }
         if (c_eps) atomicAdd(&st->over_eps, c_eps);
         if (c_rd) atomicAdd(&st->rankdef, c_rd);
         if (c_nf) atomicAdd(&st->nonfinite, c_nf);
+        if (c_fb) atomicAdd(&st->fallback, c_fb);
+        if (nz) atomicAdd(&st->nnz_numeric, nz);
         atomicMax(&st->max_len, l);
         atomicMax(&st->max_steps, sp);
         atomicMax(&st->max_shadow, sh);
@@ -1020,6 +1035,20 @@ static int launch_cfg(spai_handle* h, int id, const ColArgs& a, hipStream_t s) {
     case KC_L: return launch_columns<CfgL<UF>>(h, a, s);
     default: return launch_columns<CfgX<UF>>(h, a, s);
     }
+}
+
+// columns whose flags hold `mask`, in any order (list may be NULL: count only)
+__global__ void k_flag_list(int n, const int* __restrict__ flags, int mask, int* __restrict__ list,
+                            int* __restrict__ count) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || !(flags[k] & mask)) return;
+    const int at = atomicAdd(count, 1);
+    if (list) list[at] = k;
+}
+
+__global__ void k_mark_list(int count, const int* __restrict__ list, int bit, int* __restrict__ flags) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) flags[list[t]] |= bit;
 }
 
 __global__ void k_strided_list(int count, int stride, int* out) {
@@ -1374,6 +1403,7 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     spai_precond* P = precond_new(h);
     P->n = n;
     P->val_prec = p->u_f;
+    P->u_f = p->u_f;
     auto fail = [&](int code) { precond_free(P); return code; };
 
     SPAI_HIP(hipMemsetAsync(cnt, 0, 4 * (size_t)n + 4, s));
@@ -1475,11 +1505,61 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     }
     if (rc) return fail(rc);
 
+    // Overflow of the 16-bit formats: a column with a non-finite value is
+    // recomputed from its initial pattern in FP32 (norms of B from the FP32
+    // rounding of its entries), marked, and P's values are then stored in FP32.
+    bool promoted = false;
+    if (p->u_f == SPAI_FP16 || p->u_f == SPAI_BF16) {
+        int* fcount = dc + 2;
+        SPAI_HIP(hipMemsetAsync(fcount, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_flag_list, dim3(gb), dim3(tb), 0, s, n, (const int*)P->flags, CF_NONFINITE,
+                           (int*)nullptr, fcount);
+        SPAI_HIP(hipGetLastError());
+        SPAI_HIP(hipMemcpyAsync(hcount, fcount, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPAI_HIP(hipStreamSynchronize(s));
+        const int nf = *hcount;
+        if (nf > 0) {
+            int* flist = nullptr;
+            float* bn32 = nullptr;
+            auto drop = [&]() {
+                (void)hipStreamSynchronize(s);
+                dev_free(flist, h->arena);
+                dev_free(bn32, h->arena);
+            };
+            if ((rc = dev_alloc(h, &flist, nf)) || (rc = dev_alloc(h, &bn32, n))) {
+                drop();
+                return fail(rc);
+            }
+            SPAI_HIP(hipMemsetAsync(fcount, 0, sizeof(int), s));
+            hipLaunchKernelGGL(k_flag_list, dim3(gb), dim3(tb), 0, s, n, (const int*)P->flags, CF_NONFINITE, flist,
+                               fcount);
+            hipLaunchKernelGGL(k_colnorm<SPAI_FP32>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, bn32);
+            SPAI_HIP(hipGetLastError());
+            ColArgs f = a;
+            f.bnrm2 = bn32;
+            f.cols = flist;
+            f.ncols = nf;
+            SPAI_HIP(hipMemsetAsync(dc, 0, 2 * sizeof(int), s));
+            int nd_fb = 0;
+            rc = run_columns<SPAI_FP32>(h, pmax, 0, f, s, dl2, dc + 1, hcount, &nd_fb);
+            if (rc == SPAI_OK) {
+                hipLaunchKernelGGL(k_mark_list, dim3((nf + 255) / 256), dim3(256), 0, s, nf, (const int*)flist,
+                                   CF_FALLBACK, P->flags);
+                if (hipGetLastError() != hipSuccess) rc = SPAI_E_HIP;
+            }
+            drop();
+            if (rc) return fail(rc);
+            promoted = true;
+        }
+    }
+    const spai_prec vstore = promoted ? SPAI_FP32 : p->u_f;
+    P->val_prec = vstore;
+
     // compaction into CSR(P)
     if ((rc = dev_alloc(h, &P->rowptr, (size_t)n + 1))) return fail(rc);
     if ((rc = scan_ints(n, P->len, P->rowptr, blk, tot, s))) return fail(rc);
-    hipLaunchKernelGGL(k_build_stats, dim3(rgb), dim3(RED_BLOCK), 0, s, n, P->len, P->steps, P->res, P->flags, nI,
-                       bst);
+    hipLaunchKernelGGL(k_build_stats, dim3(rgb), dim3(RED_BLOCK), 0, s, n, stride, P->len, P->steps, P->res,
+                       P->flags, nI, (const double*)P->m_ins, bst);
     SPAI_HIP(hipMemcpyAsync(hp, tot, sizeof(int), hipMemcpyDeviceToHost, s));
     SPAI_HIP(hipMemcpyAsync(hp + 64, bst, sizeof(BuildStatsDev), hipMemcpyDeviceToHost, s));
     SPAI_HIP(hipStreamSynchronize(s));
@@ -1490,12 +1570,12 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     if ((rc = dev_alloc(h, &P->col, (size_t)total))) return fail(rc);
     {
         void* v = nullptr;
-        if ((rc = dev_malloc(h, &v, val_size(p->u_f) * (size_t)std::max(total, 1)))) return fail(rc);
+        if ((rc = dev_malloc(h, &v, val_size(vstore) * (size_t)std::max(total, 1)))) return fail(rc);
         P->val = v;
     }
     long long work = (long long)n * stride;
     int cg = (int)((work + 255) / 256);
-    switch (p->u_f) {
+    switch (vstore) {
     case SPAI_FP64: hipLaunchKernelGGL(k_compact<SPAI_FP64>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (double*)P->val); break;
     case SPAI_FP32: hipLaunchKernelGGL(k_compact<SPAI_FP32>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (float*)P->val); break;
     case SPAI_FP16: hipLaunchKernelGGL(k_compact<SPAI_FP16>, dim3(cg), dim3(256), 0, s, n, stride, P->len, P->j_ins, P->m_ins, P->rowptr, P->col, (__half*)P->val); break;
@@ -1520,6 +1600,9 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
         double mr;
         std::memcpy(&mr, &bs.max_res_bits, sizeof(double));
         st->max_res = mr;
+        st->nnz_numeric = (int64_t)bs.nnz_numeric;
+        st->cols_fallback = bs.fallback;
+        st->pad = 0;
     }
     *P_out = P;
     return warn;
@@ -1630,6 +1713,7 @@ int spai::precond_import_impl(spai_handle* h, int32_t n, int64_t nnz, const int3
     P->n = n;
     P->nnz = nnz;
     P->val_prec = vp;
+    P->u_f = vp;
     auto fail = [&](int code) { precond_free(P); return code; };
     int rc;
     if ((rc = dev_alloc(h, &P->rowptr, (size_t)n + 1))) return fail(rc);
@@ -1715,6 +1799,7 @@ extern "C" int spai_precond_view_get(const spai_precond* P, spai_precond_view* v
     v->res = P->res;
     v->flags = P->flags;
     v->side = P->side;
+    v->u_f = P->u_f;
     return SPAI_OK;
 }
 

@@ -125,3 +125,57 @@ def test_serve_footprint_and_arguments_on_the_host(lib):
     assert lib.spai_serve_submit(None, None, None) == S.E_ARG
     assert lib.spai_serve_wait(None, 1, None, None) == S.E_ARG
     assert lib.spai_serve_destroy(None) == 0
+
+
+def test_malformed_structures_are_rejected_on_the_host(lib):
+    """Requests and device uploads check their compressed structure on the host
+    (monotone pointers, indices in [0, n)) before any copy to the device, so a
+    malformed system never reaches kernels that other requests share."""
+    import numpy as np
+
+    import paper_2202_10204_amd as S
+    import workloads as W
+
+    build = {"eps": 0.3, "alpha": 125, "beta": 8, "maxfill": 20, "u_f": "fp32"}
+    ir = {"tau": 1e-8, "imax": 10, "maxit": 500, "tol_ir": 2.0 ** -45}
+    w = W.serving_request(W.Arrival(0.0, "random", 1000, "fp32", 0))
+    A = w.A
+
+    def variant(rowptr=None, col=None):
+        return W.CSR(A.n, A.rowptr.copy() if rowptr is None else rowptr, A.col.copy() if col is None else col,
+                     A.val)
+
+    rp = A.rowptr.copy()
+    rp[5], rp[6] = rp[6], rp[5]                 # pointers decrease
+    c_neg = A.col.copy()
+    c_neg[3] = -1
+    c_big = A.col.copy()
+    c_big[-1] = A.n
+    for bad in (variant(rowptr=rp), variant(col=c_neg), variant(col=c_big)):
+        with pytest.raises(S.SpaiError):
+            S.serve_footprint(bad, w.b, None, build, ir)
+        with pytest.raises(S.SpaiError):
+            S.DeviceCSR.from_host(bad)           # raises before any device copy
+    n = A.n
+    pat_ok = W.Pattern(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32))
+    S.serve_footprint(A, w.b, pat_ok, build, ir)
+    for pat in (W.Pattern(n, pat_ok.ptr, np.where(np.arange(n) == 7, n + 3, pat_ok.idx).astype(np.int32)),
+                W.Pattern(n, np.where(np.arange(n + 1) == 4, 6, pat_ok.ptr).astype(np.int32), pat_ok.idx)):
+        with pytest.raises(S.SpaiError):
+            S.serve_footprint(A, w.b, pat, build, ir)
+        with pytest.raises(S.SpaiError):
+            S.DevicePattern.from_host(pat)
+
+
+def test_allocator_hook_arguments(lib):
+    """spai_set_allocator takes both functions or neither; the binding installs
+    torch's caching allocator when it loads the library."""
+    import paper_2202_10204_amd as S
+
+    assert S.allocator == "torch"
+    assert lib.spai_set_allocator(S._TORCH_ALLOC, S._FREE_FN(), None) == S.E_ARG
+    assert lib.spai_set_allocator(S._ALLOC_FN(), S._TORCH_FREE, None) == S.E_ARG
+    S.use_torch_allocator(False)
+    assert S.allocator == "hip"
+    S.use_torch_allocator(True)
+    assert S.allocator == "torch"

@@ -846,3 +846,65 @@ def test_gathered_entries_are_rounded_to_uf(uf):
     R64 = O.spai(A, None, 0.2, 5, 8, 20, "fp64")
     R64p = O.spai(A2, None, 0.2, 5, 8, 20, "fp64")
     assert not np.array_equal(R64.m, R64p.m)                  # the perturbation is seen in FP64
+
+
+def _overflow_system(n=24):
+    """Upper bidiagonal A = I - 2 N: (A^-1)_kj = 2^(j-k), so the SPAI of B = A^T D on
+    the pattern of A^-1 has entries up to ~2^(n-1), far beyond the FP16 range
+    (65504), although every entry of B (0.5, -1) is exact in FP16."""
+    A = np.eye(n) + np.diag(-2.0 * np.ones(n - 1), 1)
+    Ai = np.linalg.inv(A)
+    ptr, idx = [0], []
+    for k in range(n):
+        idx += list(np.nonzero(Ai[k])[0])
+        ptr.append(len(idx))
+    pat = W.Pattern(n, np.array(ptr, np.int32), np.array(idx, np.int32))
+    return A, _csr(A), pat
+
+
+def test_fp16_overflow_columns_are_recomputed_in_fp32():
+    """Overflow policy of the 16-bit build (Section 4's scaling keeps the half
+    precision computations in range only where the reduced problems allow it):
+    exactly the columns whose values exceed the FP16 range are recomputed, and
+    they then equal the FP32 build of the same column bit for bit; the others
+    keep their FP16 values; the solve with the resulting P converges."""
+    Ad, A, pat = _overflow_system()
+    n = A.n
+    R16 = O.spai(A, pat, 0.5, 0, 8, 63, "fp16")
+    R32 = O.spai(A, pat, 0.5, 0, 8, 63, "fp32")
+    fb = (R16.flags & O.FLAG_FALLBACK) != 0
+    big = np.abs(R32.m).max(axis=1) > 65504.0
+    assert fb.sum() >= 4 and np.array_equal(fb, big)
+    assert not np.any(R16.flags & O.FLAG_NONFINITE)
+    assert np.array_equal(R16.m[fb], R32.m[fb]) and np.array_equal(R16.J[fb], R32.J[fb])
+    assert np.all(np.isfinite(R16.m))
+    assert np.array_equal(_to_uf(R16.m[~fb], "fp16"), R16.m[~fb])       # FP16 values kept
+    R16b = O.spai(A, pat, 0.5, 0, 8, 63, "bf16")                          # BF16 has FP32's range
+    assert not np.any(R16b.flags & O.FLAG_FALLBACK)
+    x_true = np.linspace(-1.0, 1.0, n)
+    b = Ad @ x_true
+    pp, pc, pv = R16.P_csr(n)
+    res = O.gmres_ir(A, pp, pc, pv, R16.d, "fp16", b, 1e-8, 10, n, W.TOL_IR)
+    assert res.status & ~O.IR_STAGNATED == 0 and O.ferr(res.x, x_true) <= 1e-12
+
+
+def test_fp32_refinement_restarted_from_an_iterate_repeats_its_steps():
+    """Refinement is a chain in x: started from the iterate x_i of a run (warm
+    start), one step reproduces that run's step i (its GMRES count and x_{i+1},
+    bit for bit), and started from the exact solution no step is taken (P r = 0,
+    Algorithm 3's residual is exactly zero)."""
+    w = W.s0_matrix(5)
+    n, ir = w.n, w.ir
+    R = O.spai(w.A, None, 0.3, -(-n // 8), 8, 63, "fp16")
+    pp, pc, pv = R.P_csr(n)
+    full = O.gmres_ir(w.A, pp, pc, pv, R.d, "fp16", w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "mgs", "fp32")
+    assert len(full.its) >= 2 and full.xhist.shape == (len(full.its) + 1, n)
+    assert np.array_equal(full.xhist[-1], full.x)
+    assert np.all((full.gest <= ir.tau) & (full.gprev > ir.tau))
+    for i, k in enumerate(full.its):
+        one = O.gmres_ir(w.A, pp, pc, pv, R.d, "fp16", w.b, ir.tau, 1, ir.maxit, ir.tol_ir, "mgs", "fp32",
+                         x_init=full.xhist[i])
+        assert one.its == [k] and np.array_equal(one.x, full.xhist[i + 1]), i
+    exact = O.gmres_ir(w.A, pp, pc, pv, R.d, "fp16", w.b, ir.tau, 3, ir.maxit, ir.tol_ir, "mgs", "fp32",
+                       x_init=w.x_true)
+    assert exact.its == [] and np.array_equal(exact.x, w.x_true)

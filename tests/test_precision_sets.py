@@ -4,9 +4,11 @@ matrices those tables use, with the paper's protocol (identity start, beta 8,
 alpha = ceil(n / beta), tau = 1e-4 for working precision single).
 
 The build is bit-exact against the oracle (nnz(P) compared); the solve in
-working precision single is compared with the oracle's binary32 GMRES-IR by
-its iteration tuple and its forward error, and the single-system entry point
-equals the batched one bit for bit (the former runs as a batch of one)."""
+working precision single is compared with the oracle's binary32 GMRES-IR step
+by step (each refinement step started on the GPU from the oracle's iterate,
+its GMRES count compared exactly outside near ties of the stopping test), and
+the single-system entry point equals the batched one bit for bit (the former
+runs as a batch of one)."""
 import numpy as np
 import pytest
 
@@ -39,21 +41,24 @@ def mats():
     return {k: W.s0_matrix(k) for k in (4, 5, 6, 8)}
 
 
-def _tuple_close(gpu, ref):
-    """Iteration tuples of binary32 GMRES-IR.  The first refinement step starts
-    from bit-identical data on both sides (x0 = P b in u_f and r0 in binary64
-    are exact replicas; only the order of the binary32 reductions inside GMRES
-    differs: a workgroup tree on the GPU, sequential sums in the oracle), so its
-    count agrees within one iteration.  Every later step starts from an x that
-    the previous correction fixed only to about tau relative, stored in binary32:
-    the two sides' residuals then differ in their leading digits, and so may
-    their counts.  Compared: the first step within one, the number of steps
-    within one."""
-    return abs(gpu[0] - ref[0]) <= 1 and abs(len(gpu) - len(ref)) <= 1
+# Near ties of the GMRES stopping test in binary32.  Started from the same
+# iterate x_i, both sides form bit-identical r_i (binary64 evaluation of binary32
+# data, terms in CSR order) and P r_i (row sums in column order); inside GMRES
+# only the order of the binary32 inner-product sums differs (a workgroup tree on
+# the GPU, sequential in the oracle).  The Givens estimates |g_{j+1}| / beta0 of
+# the two sides then differ by a few hundred binary32 roundings at most over the
+# <= 2205 iterations these systems allow, so a count can differ only where the
+# oracle's estimate at the stopping iteration (gest) or at the one before it
+# (gprev) lies within DELTA32 = 2^-10 (~ 16k u) of tau, relative.
+DELTA32 = 2.0 ** -10
 
 
 @pytest.mark.parametrize("k,uf,eps", CASES)
-def test_single_working_precision_matches_the_oracle(S, h, mats, k, uf, eps):
+def test_single_working_precision_step_by_step(S, h, mats, k, uf, eps):
+    """Refinement step i of the GPU's binary32 GMRES-IR, started from the oracle's
+    iterate x_i (warm start), takes the oracle's GMRES count for that step
+    exactly, unless the oracle's stopping test was a near tie (then within
+    one); x0 = P b in u_f equals the oracle's; the GPU's whole solve converges."""
     w = mats[k]
     n, ir = w.n, w.ir
     A = S.DeviceCSR.from_host(w.A)
@@ -62,14 +67,28 @@ def test_single_working_precision_matches_the_oracle(S, h, mats, k, uf, eps):
     pp, pc, pv = R.P_csr(n)
     assert st["nnz"] == int(pp[-1])
     b = torch.as_tensor(w.b, device="cuda")
-    x = torch.zeros_like(b)
-    r = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "fp64", "mgs", "fp32")
     ref = O.gmres_ir(w.A, pp, pc, pv, R.d, uf, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "mgs", "fp32")
+    x0 = torch.zeros_like(b)
+    h.precond_apply_uf(P, b, x0)
+    assert np.array_equal(x0.cpu().numpy().astype(np.float32).astype(np.float64), ref.xhist[0])
+    near, counts = 0, []
+    for i, ki in enumerate(ref.its):
+        xi = torch.as_tensor(ref.xhist[i], device="cuda").clone()
+        r = h.gmres_ir(A, P, b, xi, ir.tau, 1, ir.maxit, ir.tol_ir, "fp64", "mgs", "fp32", x_given=True)
+        margin = min(abs(ref.gest[i] - ir.tau), abs(ref.gprev[i] - ir.tau)) / ir.tau
+        counts.append((r["its"][0], ki, float(margin)))
+        if margin >= DELTA32:
+            assert r["its"] == [ki], (i, r["its"], ki, margin)
+        else:
+            near += 1
+            assert r["steps"] == 1 and abs(r["its"][0] - ki) <= 1, (i, r["its"], ki, margin)
+    print(w.name, uf, eps, "(gpu, oracle, margin) per step:", counts, "near ties:", near)
+    assert near <= 1
+    x = torch.zeros_like(b)
+    full = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "fp64", "mgs", "fp32")
     xg = x.cpu().numpy()
-    print(w.name, uf, eps, "gpu", r["its"], "oracle", ref.its, O.ferr(xg, w.x_true), O.ferr(ref.x, w.x_true))
     assert np.array_equal(xg.astype(np.float32).astype(np.float64), xg)     # x in binary32
-    assert _tuple_close(r["its"], ref.its), (r["its"], ref.its)
-    assert r["status"] & S.W_MAXIT == 0 and ref.status & O.IR_MAXIT == 0
+    assert full["status"] & S.W_MAXIT == 0 and ref.status & O.IR_MAXIT == 0
     assert O.ferr(xg, w.x_true) <= 2.0 ** -20
     assert O.ferr(ref.x, w.x_true) <= 2.0 ** -20
 

@@ -236,3 +236,25 @@ def test_right_preconditioned_and_single_precision_requests(S):
                        irp.get("ortho", "mgs"), irp.get("u", "fp64"))
         assert rec["its"] == r["its"], (k, rec["its"], r["its"])
         assert np.array_equal(x, xd.cpu().numpy()), k
+
+
+def test_wait_while_another_thread_submits(S):
+    """One thread waits for a request while another submits two hundred more
+    (the server's request table grows and rehashes meanwhile): every request
+    completes with a valid result."""
+    import threading
+
+    w = W.serving_request(W.Arrival(0.0, "random", 1000, "fp32", 500))
+    srv = S.Server(batch_lanes=2, batch_max_n=BATCH_MAX_N, hbm_budget=8 << 30, lane_workspace=512 << 20)
+    first = srv.submit(*_args(w))
+    got = {}
+    t = threading.Thread(target=lambda: got.update(r=srv.wait(first)))
+    t.start()
+    ids = [srv.submit(*_args(w)) for _ in range(200)]
+    t.join()
+    rc, x, rec = got["r"]
+    assert rc >= 0 and O.ferr(x, w.x_true) <= 1e-12
+    for rid in ids:
+        rc2, x2, rec2 = srv.wait(rid)
+        assert rc2 >= 0 and rec2["its"] == rec["its"] and np.array_equal(x2, x)
+    srv.close()

@@ -330,6 +330,28 @@ int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
                   double* x, const spai_ir_params* p, spai_ir_stats* st);
 
 /*
+ * spai_gmres_ir without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, semantics and results as
+ * spai_gmres_ir (bit for bit), with these limits:
+ *   - the workspace (the Krylov basis n (min(maxit, n) + 1) doubles, three
+ *     vectors, the Hessenberg matrix and the grid-sum slots of the chosen
+ *     orthogonalisation) must fit the library's fixed 64 MiB device array
+ *     (about n (maxit + 1) <= 7.5 M doubles with DCGS2 at maxit 500); larger
+ *     problems are rejected with SPAI_E_ARG and a message giving the size;
+ *   - working precision FP64 only (p->u = SPAI_FP32 is rejected); p->graph is
+ *     ignored (stream launches); kernel timing (spai_timing_enable) is not
+ *     recorded during the call.
+ * The array is one per device, set up by spai_create and held until the
+ * process ends; every call on a device uses the same array and leaves its
+ * contents behind (each call initialises what it reads), so calls that overlap
+ * on one device -- from several handles or threads -- race and must not be
+ * made.  No hipMalloc, hipFree, event, stream or graph creation happens inside.
+ */
+int spai_gmres_ir_noalloc(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
+                          double* x, const spai_ir_params* p, spai_ir_stats* st);
+
+/*
  * Batches of independent systems (many systems of different sizes in one call).
  * A batch is one block-diagonal matrix A (the caller concatenates the systems):
  * system s owns rows and columns sys_ptr[s] .. sys_ptr[s+1]-1, with sys_ptr a

@@ -172,6 +172,7 @@ def lib():
         L.spai_precond_view_get.argtypes = [_p, P(_View)]
         L.spai_precond_destroy.argtypes = [_p]
         L.spai_gmres_ir.argtypes = [_p, P(_Csr), _p, _p, _p, P(_IrParams), P(_IrStats)]
+        L.spai_gmres_ir_noalloc.argtypes = [_p, P(_Csr), _p, _p, _p, P(_IrParams), P(_IrStats)]
         L.spai_residual.argtypes = [_p, P(_Csr), _p, _p, _p, ctypes.c_int]
         L.spai_precond_apply.argtypes = [_p, _p, _p, _p]
         L.spai_precond_apply_uf.argtypes = [_p, _p, _p, _p]
@@ -191,7 +192,7 @@ def lib():
                      "spai_precond_view_get", "spai_precond_destroy", "spai_gmres_ir", "spai_residual",
                      "spai_precond_apply", "spai_precond_apply_uf", "spai_spmv", "spai_build_batched",
                      "spai_gmres_ir_batched", "spai_serve_footprint", "spai_serve_create", "spai_serve_submit",
-                     "spai_serve_wait", "spai_serve_destroy", "spai_set_allocator"):
+                     "spai_serve_wait", "spai_serve_destroy", "spai_set_allocator", "spai_gmres_ir_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         use_torch_allocator(True)

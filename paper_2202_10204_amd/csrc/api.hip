@@ -167,7 +167,17 @@ extern "C" int spai_create(spai_handle** h) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) H->num_cu = prop.multiProcessorCount;
     int rc = pinned_reserve(H->host_pinned, 4096);
+    if (rc == SPAI_OK) rc = spai::noalloc_scratch_init(dev);
+    for (int q = 0; q < 2 && rc == SPAI_OK; ++q)
+        if (hipEventCreateWithFlags(&H->chunk_ev[q], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            spai::set_error("hipEventCreateWithFlags failed");
+            rc = SPAI_E_HIP;
+        }
     if (rc) {
+        for (hipEvent_t e : H->chunk_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (H->host_pinned.ptr) (void)hipHostFree(H->host_pinned.ptr);
         delete H;
         return rc;
     }
@@ -182,6 +192,8 @@ extern "C" int spai_destroy(spai_handle* h) {
     else (void)hipDeviceSynchronize();
     for (auto& t : h->timers)
         for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : h->chunk_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& b : h->ws) spai::buffer_free(b);
     spai::buffer_free(h->red);
     if (h->host_pinned.ptr) (void)hipHostFree(h->host_pinned.ptr);

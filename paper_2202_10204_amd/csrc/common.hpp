@@ -71,6 +71,9 @@ int dev_malloc(spai_handle* h, void** p, size_t bytes);
 // the allocator in force, for memory no handle owns (a request server's arena)
 int raw_malloc(void** p, size_t bytes, int device, hipStream_t stream);
 void raw_free(void* p);
+// device address of the workspace array of spai_gmres_ir_noalloc on `device`
+// (looked up once per device, with that device current; spai_create does it)
+int noalloc_scratch_init(int device);
 void dev_free(void* p, const Arena& from);
 int buffer_reserve(spai_handle* h, Buffer& b, size_t bytes);
 void buffer_free(Buffer& b);
@@ -105,6 +108,8 @@ struct spai_handle {
     int num_cu = 256;
     spai::Arena arena;             // device memory lent by a request server (empty: the allocator in force)
     size_t ws_cap = 0;             // cap on the batched solver's workspace in bytes (0: a quarter of free memory)
+    hipEvent_t chunk_ev[2] = {nullptr, nullptr};   // completion of the stop-flag copies of two Arnoldi chunks
+    bool no_alloc = false;         // inside spai_gmres_ir_noalloc: no timing events are created
 };
 
 struct spai_precond {
@@ -228,7 +233,7 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 // Returns the index of the event pair to close after the launch, or -1.
 inline long timer_begin(spai_handle* h, int kc) {
     KernelTimer& t = h->timers[kc];
-    if (t.every <= 0) return -1;
+    if (t.every <= 0 || h->no_alloc) return -1;
     if ((t.seen++ % t.every) != 0) return -1;
     if (2 * t.used + 2 > t.ev.size()) {
         for (int q = 0; q < 2; ++q) {

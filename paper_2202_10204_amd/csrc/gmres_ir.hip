@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include <type_traits>
@@ -1773,18 +1774,46 @@ int gmres_ir_batched_impl(spai_handle* h, const spai_csr* A, const spai_precond*
                           spai_ir_stats* st);
 
 // two events without timing, destroyed with the scope
-struct EventPair {
-    hipEvent_t e[2] = {nullptr, nullptr};
-    int create() {
-        for (auto& x : e) SPAI_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
-        return SPAI_OK;
+// ---------------------------------------------------------------------------
+// Workspace of spai_gmres_ir_noalloc: one array in every device's memory, for
+// callers that cannot allocate.  Host code never passes the array's name to a
+// kernel (in host code it is a host-side stand-in); it uses the device address
+// hipGetSymbolAddress gives for the device at hand, looked up once per device.
+// ---------------------------------------------------------------------------
+
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+int noalloc_scratch_init(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+        set_error("device index " + std::to_string(device) + " beyond the library's table");
+        return SPAI_E_ARG;
     }
-    hipEvent_t operator[](int i) const { return e[i]; }
-    ~EventPair() {
-        for (auto x : e)
-            if (x) (void)hipEventDestroy(x);
+    std::lock_guard<std::mutex> l(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SPAI_OK;
+    int cur = -1;
+    SPAI_HIP(hipGetDevice(&cur));
+    if (cur != device) SPAI_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        set_error(std::string("hipGetSymbolAddress of the no-allocation workspace failed: ") + hipGetErrorString(e));
+        return SPAI_E_HIP;
     }
-};
+    g_scratch_ptr[device] = ptr;
+    return SPAI_OK;
+}
+
+static void* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> l(g_scratch_mu);
+    return device >= 0 && device < NOALLOC_MAX_DEVICES ? g_scratch_ptr[device] : nullptr;
+}
 
 // A chunk of DCGS2 Arnoldi steps as one HIP graph (graph and executable,
 // destroyed with the scope).
@@ -1841,8 +1870,12 @@ static int capture_chunk(spai_handle* h, const spai_csr* A, const spai_precond* 
     return rc;
 }
 
+// scratch != NULL: the workspace is carved from that device memory of
+// scratch_bytes bytes (spai_gmres_ir_noalloc), no device memory is allocated and
+// no event, stream or graph is created; working precision FP64 only.
 int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b, double* x,
-                  const spai_ir_params* prm, spai_ir_stats* st) {
+                  const spai_ir_params* prm, spai_ir_stats* st, void* scratch = nullptr,
+                  size_t scratch_bytes = 0) {
     SPAI_ARG(h && prm, "NULL handle or parameters");
     SPAI_ARG(P, "NULL preconditioner");
     SPAI_ARG(b && x, "NULL right-hand side or solution");
@@ -1859,6 +1892,7 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     SPAI_ARG(prm->u == SPAI_FP64 || prm->u == SPAI_FP32, "the working precision u must be FP64 or FP32");
     const bool right = P->side == SPAI_RIGHT;
     SPAI_ARG(!right || prm->u == SPAI_FP64, "right preconditioning runs in working precision FP64");
+    SPAI_ARG(!scratch || prm->u == SPAI_FP64, "the allocation-free solve runs in working precision FP64");
     if (prm->u == SPAI_FP32) {
         // working precision single: the system runs in the batched solver as a batch of one
         SPAI_ARG(prm->ortho == SPAI_ORTHO_MGS, "working precision FP32 orthogonalises with MGS");
@@ -1877,22 +1911,39 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
              "CGS2 and DCGS2 need the cooperative Arnoldi kernel, which cannot hold this problem");
     const int maxlinks = maxit + 2;
 
-    // workspace
-    rc = buffer_reserve(h, h->ws[WS_SOLVE_V], sizeof(double) * (size_t)n * (size_t)(maxit + 1));
-    if (rc) return rc;
-    rc = buffer_reserve(h, h->ws[WS_SOLVE_VEC], sizeof(double) * (size_t)n * 3);
-    if (rc) return rc;
+    // workspace: the basis, three vectors, and H with the rotations, reduction
+    // partials, solver state and grid-sum slots
     size_t slot_count = cfg.slot_words;
     const bool dcgs2 = prm->ortho == SPAI_ORTHO_DCGS2;
     const size_t hr_words = dcgs2 ? 2 * (size_t)ld * maxit : 0;   // HRp, HRf
+    const size_t vbytes = sizeof(double) * (size_t)n * (size_t)(maxit + 1), wbytes = sizeof(double) * (size_t)n * 3;
     size_t hbytes = sizeof(double) * ((size_t)ld * maxit + 4 * (size_t)ld + RBLOCKS + 64 + slot_count + hr_words);
-    rc = buffer_reserve(h, h->ws[WS_SOLVE_H], hbytes);
-    if (rc) return rc;
-    double* V = (double*)h->ws[WS_SOLVE_V].ptr;
-    double* r = (double*)h->ws[WS_SOLVE_VEC].ptr;
+    double *V, *r, *H;
+    if (scratch) {
+        auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+        const size_t need = up(vbytes) + up(wbytes) + up(hbytes);
+        if (need > scratch_bytes) {
+            set_error("invalid argument: the allocation-free solve needs " + std::to_string(need) +
+                      " bytes of workspace for n = " + std::to_string(n) + ", maxit = " + std::to_string(maxit) +
+                      ", more than its " + std::to_string(scratch_bytes) + "-byte array");
+            return SPAI_E_ARG;
+        }
+        V = (double*)scratch;
+        r = (double*)((char*)scratch + up(vbytes));
+        H = (double*)((char*)r + up(wbytes));
+    } else {
+        rc = buffer_reserve(h, h->ws[WS_SOLVE_V], vbytes);
+        if (rc) return rc;
+        rc = buffer_reserve(h, h->ws[WS_SOLVE_VEC], wbytes);
+        if (rc) return rc;
+        rc = buffer_reserve(h, h->ws[WS_SOLVE_H], hbytes);
+        if (rc) return rc;
+        V = (double*)h->ws[WS_SOLVE_V].ptr;
+        r = (double*)h->ws[WS_SOLVE_VEC].ptr;
+        H = (double*)h->ws[WS_SOLVE_H].ptr;
+    }
     double* w = r + n;
     double* y = w + n;
-    double* H = (double*)h->ws[WS_SOLVE_H].ptr;
     double* cs = H + (size_t)ld * maxit;
     double* sn = cs + ld;
     double* g = sn + ld;
@@ -1911,12 +1962,11 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     const int nbr = reduce_blocks(n);
     SPAI_HIP(hipMemsetAsync(ticket, 0, 16, s));
     const int chunk = 8;   // Arnoldi steps enqueued between checks of the stop flag
-    EventPair ev;          // completion of the flag copies of the last two chunks
-    if ((rc = ev.create())) return rc;
+    hipEvent_t* ev = h->chunk_ev;   // completion of the flag copies of the last two chunks
 
     // graph replay of the Arnoldi chunks (DCGS2 with ordinary launches only)
     ChunkGraph cgraph;
-    const bool use_graph = prm->graph && dcgs2 && cfg.nb && !use_cooperative_launch();
+    const bool use_graph = prm->graph && dcgs2 && cfg.nb && !use_cooperative_launch() && !scratch;
     if (use_graph) {
         ArnoldiArgs aa{};
         aa.n = n; aa.ld = ld; aa.maxit = maxit; aa.maxlinks = maxlinks; aa.nb = cfg.nb;
@@ -2098,6 +2148,23 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
 extern "C" int spai_gmres_ir(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
                              double* x, const spai_ir_params* p, spai_ir_stats* st) {
     return spai::gmres_ir_impl(h, A, P, b, x, p, st);
+}
+
+extern "C" int spai_gmres_ir_noalloc(spai_handle* h, const spai_csr* A, const spai_precond* P, const double* b,
+                                     double* x, const spai_ir_params* p, spai_ir_stats* st) {
+    if (!h) {
+        spai::set_error("invalid argument: NULL handle");
+        return SPAI_E_ARG;
+    }
+    void* ws = spai::noalloc_scratch(h->device);
+    if (!ws) {
+        spai::set_error("the no-allocation workspace of this device was not set up");
+        return SPAI_E_INTERNAL;
+    }
+    h->no_alloc = true;
+    const int rc = spai::gmres_ir_impl(h, A, P, b, x, p, st, ws, spai::NOALLOC_BYTES);
+    h->no_alloc = false;
+    return rc;
 }
 
 extern "C" int spai_residual(spai_handle* h, const spai_csr* A, const double* b, const double* x, double* r,

@@ -62,7 +62,7 @@ def _lib():
         i32, f64 = ctypes.c_int, ctypes.c_double
         L.oracle_spai.restype = i32
         L.oracle_spai.argtypes = [i32, P, P, P, P, P, f64, i32, i32, i32, i32, P, i32, i32, i32,
-                                  P, P, P, P, P, P, P, P, P, P]
+                                  P, P, P, P, P, P, P, P, P, P, P]
         L.oracle_spai_probe.restype = i32
         L.oracle_spai_probe.argtypes = [i32, P, P, P, i32, P, i32, P, i32, i32, i32, P, P, P, P, P, P, P,
                                         P, P]
@@ -146,6 +146,7 @@ class SpaiResult:
     margin: np.ndarray    # smallest relative decision margin of the column
     d: np.ndarray         # scaling vector D
     hist: np.ndarray      # [ncols, stride+1] residual norm of every solve (NaN padded)
+    flops: np.ndarray     # algorithmic flops of the column's solves, 2mp^2 - 2p^3/3 + 4mp + p^2 per m x p solve
 
     def P_csr(self, n: int):
         """Row k of P = M^T D holds m_k: CSR (rowptr, col, val) with columns ascending.
@@ -200,17 +201,19 @@ def spai(A, pattern, eps: float, alpha: int, beta: int, maxfill: int, uf: str,
     out_margin = np.zeros(nc, np.float64)
     out_d = np.zeros(n, np.float64)
     out_hist = np.zeros((nc, stride + 1), np.float64)
+    out_flops = np.zeros(nc, np.float64)
     rp, ci, av = _i32(A.rowptr), _i32(A.col), _f64(A.val)
     pp = None if pattern is None else _i32(pattern.ptr)
     pi = None if pattern is None else _i32(pattern.idx)
     rc = _lib().oracle_spai(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pi), float(eps), int(alpha),
                             int(beta), int(maxfill), UF[uf], _p(cols), nc, stride, int(nthreads),
                             _p(out_len), _p(out_J), _p(out_m), _p(out_steps), _p(out_nI),
-                            _p(out_flags), _p(out_res), _p(out_margin), _p(out_d), _p(out_hist))
+                            _p(out_flags), _p(out_res), _p(out_margin), _p(out_d), _p(out_hist),
+                            _p(out_flops))
     if rc != 0:
         raise ValueError("oracle_spai: bad argument")
     return SpaiResult(cols, out_len, out_J, out_m, out_steps, out_nI, out_flags, out_res,
-                      out_margin, out_d, out_hist)
+                      out_margin, out_d, out_hist, out_flops)
 
 
 @dataclasses.dataclass

@@ -229,6 +229,7 @@ typedef struct {
                           bit3 recomputed in FP32 after a non-finite 16-bit result */
     double res;        /* ||e_k - B m_k||_2 at the last solve (as tested) */
     double margin;     /* smallest relative decision margin seen */
+    double flops;      /* algorithmic flops of the column's solves (see spai_column) */
 } colinfo_t;
 
 #define FLAG_RANKDEF 1
@@ -417,10 +418,16 @@ static void spai_column(const prep_t* P, int k, const int* J0, int len0, double 
     info->flags = 0;
     info->margin = INFINITY;
     info->steps = 0;
+    info->flops = 0.0;
     int m = 0;
     for (int step = 0;; ++step) {
         int kin = 0;
         double res2 = column_solve(P, k, J, p, W, uf, m, &m, &kin, &info->flags);
+        /* algorithmic flops of this solve of an m x p problem: Householder QR
+         * 2mp^2 - 2p^3/3, applying the reflectors to e-bar and forming the
+         * residual 4mp, back substitution p^2 (Section 2.2: cubic in the number
+         * of nonzeros per column) */
+        info->flops += 2.0 * m * p * p - 2.0 * p * p * p / 3.0 + 4.0 * m * p + (double)p * p;
         double res = FSQRT(res2);
         if (hist && step < hcap) hist[step] = res;
         info->res = res;
@@ -513,6 +520,7 @@ typedef struct {
     double* out_res;
     double* out_margin;
     double* out_hist;
+    double* out_flops;
 } job_t;
 
 static void* run_job(void* arg) {
@@ -550,6 +558,7 @@ static void* run_job(void* arg) {
         if (jb->out_flags) jb->out_flags[t] = info.flags;
         if (jb->out_res) jb->out_res[t] = info.res;
         if (jb->out_margin) jb->out_margin[t] = info.margin;
+        if (jb->out_flops) jb->out_flops[t] = info.flops;
     }
     free(Jtmp);
     free(mtmp);
@@ -571,7 +580,7 @@ int oracle_spai(int n, const int* rp, const int* ci, const double* av, const int
                 const int* pat_idx, double eps, int alpha, int beta, int maxfill, int uf,
                 const int* cols, int ncols, int stride, int nthreads, int* out_len, int* out_J,
                 double* out_m, int* out_steps, int* out_nI, int* out_flags, double* out_res,
-                double* out_margin, double* out_d, double* out_hist) {
+                double* out_margin, double* out_d, double* out_hist, double* out_flops) {
     if (n <= 0 || uf < 0 || uf > 3 || ncols < 0 || stride <= 0) return -1;
     if (nthreads < 1) nthreads = 1;
     prep_t P, P32;
@@ -590,7 +599,7 @@ int oracle_spai(int n, const int* rp, const int* ci, const double* av, const int
         jb->eps = eps; jb->alpha = alpha; jb->beta = beta; jb->maxfill = maxfill; jb->uf = uf;
         jb->stride = stride; jb->out_len = out_len; jb->out_J = out_J; jb->out_m = out_m;
         jb->out_steps = out_steps; jb->out_nI = out_nI; jb->out_flags = out_flags;
-        jb->out_res = out_res; jb->out_margin = out_margin; jb->out_hist = out_hist;
+        jb->out_res = out_res; jb->out_margin = out_margin; jb->out_hist = out_hist; jb->out_flops = out_flops;
     }
     if (nthreads == 1) run_job(&jobs[0]);
     else {

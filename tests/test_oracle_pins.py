@@ -908,3 +908,23 @@ def test_fp32_refinement_restarted_from_an_iterate_repeats_its_steps():
     exact = O.gmres_ir(w.A, pp, pc, pv, R.d, "fp16", w.b, ir.tau, 3, ir.maxit, ir.tol_ir, "mgs", "fp32",
                        x_init=w.x_true)
     assert exact.its == [] and np.array_equal(exact.x, w.x_true)
+
+
+def test_flop_count_of_a_fixed_pattern_build():
+    """The algorithmic flop count of a fixed-pattern build (one m x p solve per
+    column, Section 2.2's cost cubic in the entries per column) equals the
+    formula evaluated on shadow sizes counted independently: |I_k| = the
+    number of columns of row k of pattern(P) x pattern(A)."""
+    w = W.aniso_fixed(6, "fp32")
+    s = w.spai
+    R = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, "fp32")
+    n = w.n
+    Ap = sp.csr_matrix((np.ones(w.A.nnz), w.A.col, w.A.rowptr), shape=(n, n))
+    Pp = sp.csr_matrix((np.ones(w.pattern.nnz), w.pattern.idx, w.pattern.ptr), shape=(n, n))
+    m = np.diff((Pp @ Ap).indptr).astype(float)
+    p = np.diff(w.pattern.ptr).astype(float)
+    assert np.array_equal(R.nI, m.astype(np.int32)) and np.array_equal(R.length, p.astype(np.int32))
+    assert np.allclose(R.flops, 2 * m * p * p - 2 * p ** 3 / 3 + 4 * m * p + p * p, rtol=1e-15)
+    Ra = O.spai(w.A, None, 0.3, 5, 8, 20, "fp32")              # adaptive: one term per solve
+    assert np.all(Ra.flops >= 2 * Ra.nI * Ra.length ** 2 - 2 * Ra.length ** 3 / 3)
+    assert np.all((Ra.steps > 0) <= (Ra.flops > 2 * Ra.nI * Ra.length ** 2))

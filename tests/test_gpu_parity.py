@@ -566,20 +566,31 @@ def test_aniso128_sampled_columns(S, h, aniso128, uf):
     _compare_columns(P, ref, f"aniso 128^3 pattern(A^2) {uf} (sample)")
 
 
-def test_aniso128_fp32_solve_reaches_1e12(S, h, aniso128):
-    """FP32 SPAI + GMRES-IR (delayed CGS2) on the full 128^3 system: forward
-    error <= 1e-12 against the exact solution, no GMRES step at the cap (the
-    oracle's GMRES-IR at this size takes too long for a test; the property
-    holds at any size)."""
+def test_aniso128_fp32_build_and_solve_match_the_oracle(S, h, aniso128):
+    """FP32 SPAI + GMRES-IR (delayed CGS2) on the full 128^3 system against the
+    oracle's run stored by tests/golden/make_aniso128_golden.py: every column's
+    values equal (digest of the whole build), the iteration tuple equal
+    (1221(269, 395, 375, 182)), and the forward error <= 1e-12 against the
+    exact solution."""
+    import hashlib
+    import json
+    import os
+
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "aniso128_oracle.json")))
     w, A, pat = aniso128
     s, ir = w.spai, w.ir
     P, warn, stats = h.spai_build(A, pat, s.eps, s.alpha, s.beta, s.maxfill, "fp32")
+    assert stats["nnz"] == gold["nnz_P"] and stats["cols_over_eps"] == gold["cols_over_eps"]
+    m = P.columns()["m"].cpu().numpy()
+    assert hashlib.sha256(np.ascontiguousarray(m.astype(np.float64)).tobytes()).hexdigest() == \
+        gold["sha256_m_insertion_order"]
+    del m
     b = _dev(w.b)
     x = torch.zeros_like(b)
-    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd", "dcgs2")
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd", "dcgs2", x_true=_dev(w.x_true))
+    assert st["status"] == 0 and st["its"] == gold["its_dcgs2"] == gold["its"], (st["its"], gold["its_dcgs2"])
     xh = x.cpu().numpy()
-    assert st["status"] == 0 and max(st["its"]) < ir.maxit
-    assert O.ferr(xh, w.x_true) <= 1e-12
+    assert O.ferr(xh, w.x_true) <= 1e-12 and st["ferr"] == O.ferr(xh, w.x_true)
 
 
 @pytest.mark.parametrize("ortho", ["mgs", "dcgs2"])

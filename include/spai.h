@@ -116,8 +116,12 @@ typedef struct {
 /* Column-kernel configurations of Algorithm 1's per-column solver: `lanes` lanes
  * of a wavefront per column problem (64 / lanes problems per wavefront), at most
  * `maxp` = lanes - 1 indices in J_k, `maxm` shadow rows I_k, `emax` gathered
- * entries of B(:, J_k) and `cmax` raw augmentation candidates staged in LDS. */
-enum { SPAI_KCFG_COUNT = 6 };
+ * entries of B(:, J_k) and `cmax` raw augmentation candidates staged in LDS.
+ * Ids 1-6 keep the reduced matrix A-bar in LDS; ids 7-9 keep it in registers
+ * (lane c holds column c) when u_f is FP32, FP16 or BF16 (with u_f = FP64 they
+ * run as the LDS shapes): 7 and 8 have the shapes of 3 and 4, 9 that of 5 with
+ * 256 candidates.  All give the same bits. */
+enum { SPAI_KCFG_COUNT = 9 };
 typedef struct {
     int32_t lanes, maxp, maxm, emax, cmax, problems_per_wave;
     int32_t lds_bytes_per_problem; /* for u_f = FP32 with qr_update = 0 */

@@ -50,7 +50,7 @@ class _ColumnConfig(ctypes.Structure):
                 ("problems_per_wave", _c_i32), ("lds_bytes_per_problem", _c_i32)]
 
 
-KCFG_COUNT = 6
+KCFG_COUNT = 9
 
 
 SIDE = {"left": 0, "right": 1}

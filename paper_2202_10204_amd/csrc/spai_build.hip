@@ -256,9 +256,13 @@ struct ColArgs {
 // is stored with the odd leading dimension m | 1 of the solve at hand, and a
 // column whose (|J| + 1) (m | 1) exceeds it is deferred (the default holds the
 // largest problem of the shape)
-template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_, int AMAX_ = G_ * (MAXM_ + 1)>
+// AREG_: A-bar lives in registers (lane c holds column c, e-bar in lane p) for the
+// QR; only the Householder vector being applied, R and Q^T e-bar pass through LDS.
+// FP32 arithmetic only (u_f = FP32, FP16, BF16).
+template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_, int AMAX_ = G_ * (MAXM_ + 1), bool AREG_ = false>
 struct Cfg {
     static constexpr int UF = UF_;
+    static constexpr bool AREG = AREG_ && UF_ != SPAI_FP64;
     using F = typename UfTraits<UF_>::F;
     static constexpr int G = G_;           // lanes per problem
     static constexpr int MAXP = G_ - 1;    // columns of A-bar; lane MAXP can hold e-bar
@@ -307,11 +311,31 @@ template <class C> struct QrCand<C, true> {
     uint8_t rz[C::MAXP + 1]; // reflector t skipped (zero column norm)
 };
 
+// A-bar in registers: the row position of every gathered slot (read while the
+// columns are loaded into registers), the Householder vector being applied
+// (rows t .. m-1, zero elsewhere), then R (column c: rows 0 .. c, packed) and
+// Q^T e-bar for the back substitution; the candidate arrays share the space.
+template <class C> struct QrCandReg {
+    using F = typename C::F;
+    union {
+        uint8_t spos[C::EMAX];
+        struct {
+            F vb[C::MAXM];
+            F R[C::MAXP * (C::MAXP + 1) / 2];
+            F qe[C::MAXP + 1];
+        } r;
+        struct {
+            int key[C::CMAX];
+            F rho[C::CMAX];
+        } c;
+    };
+};
+
 template <class C, bool INC>
 struct alignas(16) Smem {
     using F = typename C::F;
     typename C::Key gkey[C::EMAX];  // (row, slot), sorted by row then slot
-    QrCand<C, INC> u;
+    std::conditional_t<C::AREG && !INC, QrCandReg<C>, QrCand<C, INC>> u;
 
     F gval[C::EMAX];         // u_f(d_j a_ji) by slot
     uint8_t gcol[C::EMAX];   // position of j in J by slot
@@ -387,7 +411,7 @@ __device__ __forceinline__ int bsearch_rows(const typename C::Key* gkey, const t
 }
 
 template <class C, bool INC>
-__global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::AREG && !INC ? 3 : 1))) void k_spai_columns(ColArgs a) {
     using F = typename C::F;
     constexpr int G = C::G;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -499,7 +523,7 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         }
         if (m > C::MAXM) { defer = true; break; }
         const int ld = INC ? C::LD : (m | 1);   // leading dimension of A-bar
-        if (!INC && (p + 1) * ld > C::AMAX) { defer = true; break; }
+        if (!INC && !C::AREG && (p + 1) * ld > C::AMAX) { defer = true; break; }
         // sorted rows, their segments, and their positions in I.  A row is old
         // (in the previous shadow) iff the first entry of its segment comes from a
         // column of the previous solve (slots follow the column order); old rows
@@ -567,32 +591,62 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         // column p_old.  Without it (p_old = 0) everything is rebuilt: the same
         // operations on the same values, so the same bits.
         const int p_old = (INC && step > 0) ? p_prev : 0;
-        if (p_old > 0 && lane == p) {
-            // e-bar after the previous reflectors moves from column p_old to column p
-            const F* src = &S.u.A[p_old * ld];
-            F* dst = &S.u.A[p * ld];
-            for (int i = 0; i < m_prev; ++i) dst[i] = src[i];
-            for (int i = m_prev; i < m; ++i) dst[i] = F(0);
+        constexpr bool AR = C::AREG && !INC;
+        F colr[AR ? C::MAXM : 1];
+        if constexpr (AR) {
+            // every slot's row position, then each lane takes its column's entries
+            // (lane c: column c of J; lane p: e-bar)
+            for (int e = lane; e < E; e += G) S.u.spos[key_slot<C>(S.gkey[e])] = S.gpos[e];
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < C::MAXM; ++i) colr[i] = F(0);
+            if (lane < p) {
+                for (int q = 0; q < myn; ++q) {
+                    const int pos = S.u.spos[off + q];
+                    const F v = S.gval[off + q];
+#pragma unroll
+                    for (int i = 0; i < C::MAXM; ++i) colr[i] = (i == pos) ? v : colr[i];
+                }
+            }
+            for (int e = lane; e < E; e += G)
+                if (S.I[S.gpos[e]] == k) S.is[0] = S.gpos[e];
+            wave_sync();
+            kpos = S.is[0];
+            if (lane == p && kpos >= 0) {
+#pragma unroll
+                for (int i = 0; i < C::MAXM; ++i) colr[i] = (i == kpos) ? F(1) : colr[i];
+            }
+        }
+        if constexpr (!AR) {
+            if (p_old > 0 && lane == p) {
+                // e-bar after the previous reflectors moves from column p_old to column p
+                const F* src = &S.u.A[p_old * ld];
+                F* dst = &S.u.A[p * ld];
+                for (int i = 0; i < m_prev; ++i) dst[i] = src[i];
+                for (int i = m_prev; i < m; ++i) dst[i] = F(0);
+            }
         }
         wave_sync();
-        if (lane < p_old) {
-            F* col = &S.u.A[lane * ld];
-            for (int i = m_prev; i < m; ++i) col[i] = F(0);
-        } else if (lane < p || (p_old == 0 && lane == p)) {
-            F* col = &S.u.A[lane * ld];
-            for (int i = 0; i < m; ++i) col[i] = F(0);
+        if constexpr (!AR) {
+            if (lane < p_old) {
+                F* col = &S.u.A[lane * ld];
+                for (int i = m_prev; i < m; ++i) col[i] = F(0);
+            } else if (lane < p || (p_old == 0 && lane == p)) {
+                F* col = &S.u.A[lane * ld];
+                for (int i = 0; i < m; ++i) col[i] = F(0);
+            }
+            wave_sync();
+            for (int e = lane; e < E; e += G) {
+                int slot = key_slot<C>(S.gkey[e]);
+                int pos = S.gpos[e];
+                if (S.gcol[slot] >= p_old) S.u.A[S.gcol[slot] * ld + pos] = S.gval[slot];
+                if (S.I[pos] == k) S.is[0] = pos;
+            }
+            wave_sync();
+            kpos = S.is[0];
+            // e-bar = e_k(I): the 1 is placed by a full build, or by the update when k is a new row
+            if (lane == 0 && kpos >= 0 && (p_old == 0 || kpos >= m_prev)) S.u.A[p * ld + kpos] = F(1);
         }
-        wave_sync();
-        for (int e = lane; e < E; e += G) {
-            int slot = key_slot<C>(S.gkey[e]);
-            int pos = S.gpos[e];
-            if (S.gcol[slot] >= p_old) S.u.A[S.gcol[slot] * ld + pos] = S.gval[slot];
-            if (S.I[pos] == k) S.is[0] = pos;
-        }
-        wave_sync();
-        kpos = S.is[0];
-        // e-bar = e_k(I): the 1 is placed by a full build, or by the update when k is a new row
-        if (lane == 0 && kpos >= 0 && (p_old == 0 || kpos >= m_prev)) S.u.A[p * ld + kpos] = F(1);
         wave_sync();
 
         // ---- Householder QR of A-bar, applied to e-bar as well ----
@@ -621,7 +675,123 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
             }
         }
         wave_sync();
-        for (int t = qold; t < qsteps; ++t) {
+        if constexpr (AR) {
+            // The same operations as below on the register columns, rows in chunks
+            // of 8.  The sums run over whole chunks: the rows outside t .. m-1
+            // contribute exact zeros (the Householder vector is zero there, the
+            // rows past m are zero padding), and an ascending sum that starts at
+            // +0 and adds +-0 terms keeps its value, so the bits equal the sums
+            // over t .. m-1; chunks wholly above row t are skipped (t is uniform).
+            // The squared norm of the next pivot column (rows t+1 .. m-1, in
+            // ascending order, of the values just stored) is summed during the
+            // update of reflector t, the same sum the pivot lane would form next.
+            static_assert(C::MAXM % 8 == 0, "chunks of 8 rows");
+            constexpr int NCH = C::MAXM / 8;
+            F sig2n = F(0);
+            bool sig_ok = false;                // sig2n holds rows t .. m-1 of this column
+            for (int t = 0; t < qsteps; ++t) {
+                const int c0 = t >> 3;          // first chunk with rows >= t
+                if (lane == t) {
+                    F sig2 = sig2n;
+                    if (!sig_ok) {
+                        sig2 = F(0);
+#pragma unroll
+                        for (int i = 0; i < C::MAXM; ++i) {
+                            const F xi = i >= t ? colr[i] : F(0);
+                            sig2 = ffma(xi, xi, sig2);
+                        }
+                    }
+                    const F sigma = fsqrt(sig2);
+                    if (sigma == F(0)) {
+                        S.Rd[t] = F(0);
+                        S.is[1] = 1;
+                    } else {
+                        F xt = F(0);
+#pragma unroll
+                        for (int i = 0; i < C::MAXM; ++i) xt = i == t ? colr[i] : xt;
+                        const F alpha = (xt >= F(0)) ? -sigma : sigma;
+                        const F vt = store<C::UF>(xt - alpha);
+                        // R(0 .. t-1, t) is final: staged for the back substitution
+                        F* rc = &S.u.r.R[t * (t + 1) / 2];
+#pragma unroll
+                        for (int i = 0; i < C::MAXP; ++i)
+                            if (i < t) rc[i] = colr[i];
+                        // the Householder vector: rows t .. m-1 (zero above t and past m)
+                        float4* vb4 = reinterpret_cast<float4*>(S.u.r.vb);
+#pragma unroll
+                        for (int q = 0; q < C::MAXM / 4; ++q) {
+                            float4 o;
+                            const int i = 4 * q;
+                            o.x = i + 0 < t ? F(0) : (i + 0 == t ? vt : colr[i + 0]);
+                            o.y = i + 1 < t ? F(0) : (i + 1 == t ? vt : colr[i + 1]);
+                            o.z = i + 2 < t ? F(0) : (i + 2 == t ? vt : colr[i + 2]);
+                            o.w = i + 3 < t ? F(0) : (i + 3 == t ? vt : colr[i + 3]);
+                            vb4[q] = o;
+                        }
+                        S.fs[0] = sigma * (sigma + fabs(xt));
+                        S.Rd[t] = store<C::UF>(alpha);
+                        S.is[1] = 0;
+                    }
+                }
+                wave_sync();
+                if (S.is[1]) {
+                    rankdef = true;
+                    sig_ok = false;             // the columns did not change: norms from scratch
+                    continue;
+                }
+                const F tau = S.fs[0];
+                if (lane > t && lane <= p) {
+                    const float4* vb4 = reinterpret_cast<const float4*>(S.u.r.vb);
+                    F dot = F(0);
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        if (ch < c0) continue;  // rows above t: zero terms
+                        const float4 a0 = vb4[2 * ch], a1 = vb4[2 * ch + 1];
+                        const int i = 8 * ch;
+                        dot = ffma(a0.x, colr[i + 0], dot);
+                        dot = ffma(a0.y, colr[i + 1], dot);
+                        dot = ffma(a0.z, colr[i + 2], dot);
+                        dot = ffma(a0.w, colr[i + 3], dot);
+                        dot = ffma(a1.x, colr[i + 4], dot);
+                        dot = ffma(a1.y, colr[i + 5], dot);
+                        dot = ffma(a1.z, colr[i + 6], dot);
+                        dot = ffma(a1.w, colr[i + 7], dot);
+                    }
+                    const F f = dot / tau;
+                    F sn = F(0);
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        if (ch < c0) continue;
+                        const float4 a0 = vb4[2 * ch], a1 = vb4[2 * ch + 1];
+                        const F vv[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int i = 8 * ch + q;
+                            const F y = store<C::UF>(ffma(-f, vv[q], colr[i]));
+                            colr[i] = i >= t ? y : colr[i];
+                            const F z = i > t ? y : F(0);
+                            sn = ffma(z, z, sn);
+                        }
+                    }
+                    sig2n = sn;
+                    sig_ok = true;
+                }
+                wave_sync();
+            }
+            // columns that never became pivots (p > m) stage R now; Q^T e-bar (rows 0 .. p-1)
+            if (lane >= qsteps && lane < p) {
+                F* rc = &S.u.r.R[lane * (lane + 1) / 2];
+#pragma unroll
+                for (int i = 0; i < C::MAXP; ++i)
+                    if (i <= lane) rc[i] = colr[i];
+            } else if (lane == p) {
+#pragma unroll
+                for (int i = 0; i < C::MAXP; ++i)
+                    if (i < p) S.u.r.qe[i] = colr[i];
+            }
+            wave_sync();
+        }
+        if constexpr (!AR) for (int t = qold; t < qsteps; ++t) {
             if (lane == t) {
                 F* x = &S.u.A[t * ld];
                 F sig2 = F(0);
@@ -662,7 +832,32 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
         }
         if (p > m) rankdef = true;
         // back substitution, c = p-1 down to 0, inner sum over c' ascending
-        if (lane == 0) {
+        if constexpr (AR) {
+            // m-bar in registers, R read at fixed offsets of its packed columns
+            if (lane == 0) {
+                F mbr[C::MAXP];
+                int rd = 0;
+#pragma unroll
+                for (int c = C::MAXP - 1; c >= 0; --c) {
+                    mbr[c] = F(0);
+                    if (c < p) {
+                        if (c >= m || S.Rd[c] == F(0)) {
+                            rd = 1;
+                        } else {
+                            F s = S.u.r.qe[c];
+#pragma unroll
+                            for (int c2 = c + 1; c2 < C::MAXP; ++c2)
+                                s = c2 < p ? ffma(-S.u.r.R[c2 * (c2 + 1) / 2 + c], mbr[c2], s) : s;
+                            mbr[c] = store<C::UF>(s / S.Rd[c]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < C::MAXP; ++c)
+                    if (c < p) S.mb[c] = mbr[c];
+                S.is[2] = rd;
+            }
+        } else if (lane == 0) {
             int rd = 0;
             for (int c = p - 1; c >= 0; --c) {
                 if (c >= m || S.Rd[c] == F(0)) {
@@ -670,9 +865,11 @@ __global__ __launch_bounds__(64) void k_spai_columns(ColArgs a) {
                     rd = 1;
                     continue;
                 }
-                F s = S.u.A[p * ld + c];
-                for (int c2 = c + 1; c2 < p; ++c2) s = ffma(-S.u.A[c2 * ld + c], S.mb[c2], s);
-                S.mb[c] = store<C::UF>(s / S.Rd[c]);
+                if constexpr (!AR) {
+                    F s = S.u.A[p * ld + c];
+                    for (int c2 = c + 1; c2 < p; ++c2) s = ffma(-S.u.A[c2 * ld + c], S.mb[c2], s);
+                    S.mb[c] = store<C::UF>(s / S.Rd[c]);
+                }
             }
             S.is[2] = rd;
         }
@@ -998,10 +1195,16 @@ template <int UF> using CfgX = Cfg<UF, 64, (UF == SPAI_FP64 ? 128 : 256), 1024, 
 // (shadows of up to 96 rows, twice the gathered entries and candidates): they
 // run 12 to a CU instead of the large-problem kernel's one
 template <int UF> using CfgW = Cfg<UF, 21, 96, 256, 512>;
+// A-bar in registers (FP32 arithmetic; with u_f = FP64 these are the LDS shapes):
+// the 21-lane shapes, and a 32-lane one with half the candidate space of CfgL
+// (a fixed pattern needs none; more candidates are deferred)
+template <int UF> using CfgM21sR = Cfg<UF, 21, 40, 128, 256, 21 * 41, true>;
+template <int UF> using CfgM21R = Cfg<UF, 21, 64, 128, 256, 21 * 65, true>;
+template <int UF> using CfgLR = Cfg<UF, 32, 64, 256, 256, 32 * 65, true>;
 
 // configuration ids of the C ABI (spai_column_config_get, spai_build_params.kernel_cfg)
-enum { KC_S = 1, KC_M = 2, KC_M21S = 3, KC_M21 = 4, KC_L = 5, KC_X = 6 };
-static_assert(KC_X == SPAI_KCFG_COUNT, "configuration table and the C ABI disagree");
+enum { KC_S = 1, KC_M = 2, KC_M21S = 3, KC_M21 = 4, KC_L = 5, KC_X = 6, KC_M21SR = 7, KC_M21R = 8, KC_LR = 9 };
+static_assert(KC_LR == SPAI_KCFG_COUNT, "configuration table and the C ABI disagree");
 
 static int cfg_maxp(int id) {
     switch (id) {
@@ -1010,6 +1213,9 @@ static int cfg_maxp(int id) {
     case KC_M21S: return CfgM21s<SPAI_FP32>::MAXP;
     case KC_M21: return CfgM21<SPAI_FP32>::MAXP;
     case KC_L: return CfgL<SPAI_FP32>::MAXP;
+    case KC_M21SR: return CfgM21sR<SPAI_FP32>::MAXP;
+    case KC_M21R: return CfgM21R<SPAI_FP32>::MAXP;
+    case KC_LR: return CfgLR<SPAI_FP32>::MAXP;
     default: return CfgX<SPAI_FP32>::MAXP;
     }
 }
@@ -1033,6 +1239,9 @@ static int launch_cfg(spai_handle* h, int id, const ColArgs& a, hipStream_t s) {
     case KC_M21S: return launch_columns<CfgM21s<UF>>(h, a, s);
     case KC_M21: return launch_columns<CfgM21<UF>>(h, a, s);
     case KC_L: return launch_columns<CfgL<UF>>(h, a, s);
+    case KC_M21SR: return launch_columns<CfgM21sR<UF>>(h, a, s);
+    case KC_M21R: return launch_columns<CfgM21R<UF>>(h, a, s);
+    case KC_LR: return launch_columns<CfgLR<UF>>(h, a, s);
     default: return launch_columns<CfgX<UF>>(h, a, s);
     }
 }
@@ -1768,6 +1977,9 @@ extern "C" int spai_column_config_get(int32_t id, spai_column_config* out) {
     case spai::KC_M21S: spai::cfg_describe<spai::CfgM21s<SPAI_FP32>>(out); break;
     case spai::KC_M21: spai::cfg_describe<spai::CfgM21<SPAI_FP32>>(out); break;
     case spai::KC_L: spai::cfg_describe<spai::CfgL<SPAI_FP32>>(out); break;
+    case spai::KC_M21SR: spai::cfg_describe<spai::CfgM21sR<SPAI_FP32>>(out); break;
+    case spai::KC_M21R: spai::cfg_describe<spai::CfgM21R<SPAI_FP32>>(out); break;
+    case spai::KC_LR: spai::cfg_describe<spai::CfgLR<SPAI_FP32>>(out); break;
     default: spai::cfg_describe<spai::CfgX<SPAI_FP32>>(out); break;
     }
     return SPAI_OK;

@@ -18,13 +18,17 @@ def S():
 
 def test_configuration_table_on_the_host(S):
     cfgs = [S.column_config(c) for c in range(1, S.KCFG_COUNT + 1)]
-    assert [c["maxp"] for c in cfgs] == [7, 15, 20, 20, 31, 63]
+    assert [c["maxp"] for c in cfgs] == [7, 15, 20, 20, 31, 63, 20, 20, 31]
     for c in cfgs:
         assert c["maxp"] == c["lanes"] - 1
         assert c["problems_per_wave"] == 64 // c["lanes"]
         assert c["maxm"] >= c["maxp"] and c["lds_bytes_per_problem"] > 0
-    # the two 20-index shapes differ in shadow rows only
+    # the two 20-index shapes differ in shadow rows only; the register shapes
+    # mirror them and take less LDS (A-bar leaves it)
     assert cfgs[2]["maxm"] < cfgs[3]["maxm"]
+    for r, l in ((6, 2), (7, 3), (8, 4)):
+        assert cfgs[r]["maxm"] == cfgs[l]["maxm"] and cfgs[r]["lanes"] == cfgs[l]["lanes"]
+        assert cfgs[r]["lds_bytes_per_problem"] < cfgs[l]["lds_bytes_per_problem"]
     for bad in (0, S.KCFG_COUNT + 1, -1):
         with pytest.raises(S.SpaiError):
             S.column_config(bad)
@@ -112,6 +116,8 @@ CASES = {
     "convdiff_adaptive_48": (W.convdiff_adaptive(48), "fp32"),
     "random_3000_fp16": (W.random_system(3000, 7), "fp16"),
     "convdiff_fixed_16": (W.convdiff_small(16), "fp32"),
+    "aniso_fixed_12_fp16": (W.aniso_fixed(12, "fp16"), "fp16"),     # pattern(A^2): the 32-lane shapes
+    "aniso_fixed_12_bf16": (W.aniso_fixed(12, "bf16"), "bf16"),
 }
 
 

@@ -102,7 +102,9 @@ typedef struct {
                           factored earlier are zero in the rows an augmentation adds). */
     int32_t kernel_cfg; /* column-kernel configuration: 0 (default) = the library's rule
                            (the smallest configuration holding max(maxfill, longest initial
-                           column), with a sampled choice between the two 20-index shapes);
+                           column), with a sampled choice between the two 20-index shapes;
+                           when u_f is FP32, FP16 or BF16 the small-shadow 20-index shape
+                           and the 31-index shape are the register ones, ids 7 and 9);
                            1..SPAI_KCFG_COUNT = that configuration (spai_column_config), which
                            must hold max(maxfill, longest initial column) indices, else
                            SPAI_E_ARG.  Every configuration gives the same bits: a column that

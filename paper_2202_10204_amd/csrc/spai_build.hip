@@ -136,13 +136,19 @@ __global__ __launch_bounds__(RED_BLOCK) void k_max_count(int n, const int* __res
     }
 }
 
+// CSC(A): rows j of every column l, and b_lj = u_f(d_j a_jl) (the entries of B by
+// row); the order inside a column is irrelevant (the column kernel sorts them)
+template <int UF>
 __global__ void k_fill_csc(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           int* __restrict__ cursor, int* __restrict__ ri) {
+                           const double* __restrict__ av, const double* __restrict__ d, int* __restrict__ cursor,
+                           int* __restrict__ ri, typename UfTraits<UF>::F* __restrict__ bcv) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const double dj = d[j];
     for (int q = rp[j]; q < rp[j + 1]; ++q) {
         int pos = atomicAdd(&cursor[ci[q]], 1);
-        ri[pos] = j;   // order inside a column is irrelevant: only the set N_l is used
+        ri[pos] = j;
+        bcv[pos] = scaled_entry<UF>(dj, av[q]);
     }
 }
 
@@ -233,6 +239,7 @@ struct ColArgs {
     const int* ri;
     const double* d;
     const void* bnrm2;  // F per column of B
+    const void* bcv;    // F per CSC(A) entry (column l, row j): b_lj = u_f(d_j a_jl)
     const int* pat_ptr;  // initial pattern (NULL: identity)
     const int* pat_idx;
     double eps;
@@ -259,6 +266,12 @@ struct ColArgs {
 // AREG_: A-bar lives in registers (lane c holds column c, e-bar in lane p) for the
 // QR; only the Householder vector being applied, R and Q^T e-bar pass through LDS.
 // FP32 arithmetic only (u_f = FP32, FP16, BF16).
+constexpr int clog2(int x) {
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+}
+
 template <int UF_, int G_, int MAXM_, int EMAX_, int CMAX_, int AMAX_ = G_ * (MAXM_ + 1), bool AREG_ = false>
 struct Cfg {
     static constexpr int UF = UF_;
@@ -278,6 +291,18 @@ struct Cfg {
     static constexpr int SB = EMAX_ <= 64 ? 6 : EMAX_ <= 128 ? 7 : EMAX_ <= 256 ? 8 : 32;
     using Seg = std::conditional_t<(EMAX_ <= 255), uint8_t, uint16_t>;   // holds 0 .. EMAX
     static constexpr int CMAX = CMAX_;     // raw candidate entries (power of two)
+    // Candidate keys (j, rank of the row l, slot): 32 bits when j relative to the
+    // smallest candidate fits in the bits left (CJB >= 15; a column whose
+    // candidates span more is deferred), else (j << 32 | rank << 16 | slot).
+    // Ranks run to 2 MAXM; CMARK, above them all, marks the indices of J.
+    static constexpr int CSB = clog2(CMAX_);
+    static constexpr int CRB = clog2(2 * MAXM_ + 2);
+    static constexpr int CJB = 32 - CSB - CRB;
+    static constexpr bool CKEY32 = CJB >= 15;
+    using CKey = std::conditional_t<CKEY32, uint32_t, uint64_t>;
+    static constexpr int CMARK = CKEY32 ? (1 << CRB) - 1 : 0xFFFF;
+    // scores of the unique candidates, in the space of the gathered values
+    static constexpr int RHOCAP = EMAX_ + EMAX_ / (int)sizeof(F);
     static constexpr int AMAX = AMAX_;     // A-bar elements (recomputed QR)
     static constexpr int PPW = 64 / G_;    // problems per wavefront
 };
@@ -295,8 +320,8 @@ template <class C> struct QrCand<C, false> {
     union {
         F A[C::AMAX];                 // leading dimension m | 1
         struct {
-            int key[C::CMAX];         // raw candidates, sorted; then the unique ones (ascending j)
-            F rho[C::CMAX];
+            typename C::CKey key[C::CMAX];   // candidate keys, sorted; then the unique j (ascending)
+            F val[C::CMAX];                  // b_lj by slot
         } c;
     };
 };
@@ -304,8 +329,8 @@ template <class C> struct QrCand<C, true> {
     using F = typename C::F;
     F A[(C::MAXP + 1) * C::LD];       // leading dimension LD (kept across solves)
     struct {
-        int key[C::CMAX];
-        F rho[C::CMAX];
+        typename C::CKey key[C::CMAX];
+        F val[C::CMAX];
     } c;
     F tau[C::MAXP + 1];      // tau_t of each reflector
     uint8_t rz[C::MAXP + 1]; // reflector t skipped (zero column norm)
@@ -325,8 +350,8 @@ template <class C> struct QrCandReg {
             F qe[C::MAXP + 1];
         } r;
         struct {
-            int key[C::CMAX];
-            F rho[C::CMAX];
+            typename C::CKey key[C::CMAX];
+            F val[C::CMAX];
         } c;
     };
 };
@@ -337,8 +362,13 @@ struct alignas(16) Smem {
     typename C::Key gkey[C::EMAX];  // (row, slot), sorted by row then slot
     std::conditional_t<C::AREG && !INC, QrCandReg<C>, QrCand<C, INC>> u;
 
-    F gval[C::EMAX];         // u_f(d_j a_ji) by slot
-    uint8_t gcol[C::EMAX];   // position of j in J by slot
+    union {
+        struct {
+            F gval[C::EMAX];         // u_f(d_j a_ji) by slot
+            uint8_t gcol[C::EMAX];   // position of j in J by slot
+        };
+        F rho[C::RHOCAP];            // candidate scores (the gathered values are dead by then)
+    };
     uint8_t gpos[C::EMAX];   // row position in I of sorted entry e
     int I[C::MAXM];          // shadow in insertion order: earlier solves' rows, then new rows ascending
     uint8_t dpos[C::MAXM];   // position in I of the d-th row in ascending order
@@ -348,7 +378,7 @@ struct alignas(16) Smem {
     F mb[C::MAXP + 1];
     F Rd[C::MAXP + 1];
     F fs[4];
-    int is[4];
+    int is[8];
 };
 
 __device__ __forceinline__ int next_pow2(int x) {
@@ -394,20 +424,20 @@ __device__ __forceinline__ int key_slot(typename C::Key k) {
     else return (int)(uint32_t)(k & 0xffffffffu);
 }
 
-// index d of row i among the shadow rows in ascending order (the row of the d-th
-// segment is the row of its first sorted entry), or -1
 template <class C>
-__device__ __forceinline__ int bsearch_rows(const typename C::Key* gkey, const typename C::Seg* seg, int m, int i,
-                                            int rbase) {
-    int lo = 0, hi = m - 1;
-    while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
-        int x = key_row<C>(gkey[seg[mid]], rbase);
-        if (x == i) return mid;
-        if (x < i) lo = mid + 1;
-        else hi = mid - 1;
-    }
-    return -1;
+__device__ __forceinline__ typename C::CKey ckey_j(typename C::CKey k) {
+    if constexpr (C::CKEY32) return k >> (C::CSB + C::CRB);
+    else return k >> 32;
+}
+template <class C>
+__device__ __forceinline__ int ckey_rank(typename C::CKey k) {
+    if constexpr (C::CKEY32) return (int)((k >> C::CSB) & ((1u << C::CRB) - 1u));
+    else return (int)((k >> 16) & 0xffffu);
+}
+template <class C>
+__device__ __forceinline__ int ckey_slot(typename C::CKey k) {
+    if constexpr (C::CKEY32) return (int)(k & ((1u << C::CSB) - 1u));
+    else return (int)(k & 0xffffu);
 }
 
 template <class C, bool INC>
@@ -426,6 +456,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::AREG && !
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
     const uint64_t below = (wl == 0) ? 0ull : ((~0ull) >> (64 - wl));
     const F* bnrm2 = reinterpret_cast<const F*>(a.bnrm2);
+    const F* bcv = reinterpret_cast<const F*>(a.bcv);
+    using CKey = typename C::CKey;
 
     const int k = a.cols ? a.cols[prob] : prob;
     int p;
@@ -894,6 +926,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::AREG && !
             // row k of the full residual is -1 when k lies outside the shadow
             if (kpos < 0) r2 = r2 + F(1);
             S.fs[1] = r2;
+            S.is[3] = 0;                      // candidate phase: entries, smallest and largest j
+            S.is[4] = INT_MAX;
+            S.is[5] = -1;
         }
         wave_sync();
         const F res2 = S.fs[1];
@@ -903,121 +938,185 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::AREG && !
         if (step >= a.alpha || p >= cap) { flags |= CF_EPS; break; }
 
         // ---- candidates: L = I u {k}, J~ = (union of N_l) \ J ----
-        int cnt = 0;
-        for (int pos = lane; pos < m; pos += G) {
-            int l = S.I[pos];
-            cnt += a.cp[l + 1] - a.cp[l];
+        // One entry per pair (l, j) with l in L and b_lj != 0, read from CSC(B):
+        // its key orders by j, then by the row l (the rank of l among L in
+        // ascending order: 2d + 1 for the d-th row of I, 2 #{rows of I < k} for k
+        // outside I), then the slot holding b_lj; every j of J adds a marker that
+        // sorts after its entries.  After the sort, the entries of candidate j are
+        // contiguous and in ascending row order, which is the order of the sum
+        // r^T B e_j over the rows of B(:, j) that lie in L.
+        constexpr int RPL = (C::MAXM + G - 1) / G;   // shadow rows per lane
+        int rq0[RPL], rcnt[RPL], roff[RPL];
+        int cnt = 0, rk = 0;
+#pragma unroll
+        for (int it = 0; it < RPL; ++it) {
+            const int d = lane + it * G;
+            int l = 0;
+            if (d < m) l = key_row<C>(S.gkey[S.seg[d]], rbase);
+            rq0[it] = d < m ? a.cp[l] : 0;
+            rcnt[it] = d < m ? a.cp[l + 1] - rq0[it] : 0;
+            cnt += rcnt[it];
+            rk += __popcll(ballot(d < m && l < k) & gmask);
         }
-        if (lane == 0 && kpos < 0) cnt += a.cp[k + 1] - a.cp[k];
-        int coff = 0, Ec = 0;
-        for (int t = 0; t < G; ++t) {
-            const int v = __shfl(cnt, gl0 + t, 64);
-            coff += (t < lane) ? v : 0;
-            Ec += v;
-        }
+        const int kq0 = a.cp[k], kcnt = kpos < 0 ? a.cp[k + 1] - kq0 : 0;
+        const int mine = cnt + (lane == 0 ? kcnt : 0) + (lane < p ? 1 : 0);
+        // slots in any order: the keys are distinct without them, so the sorted
+        // order and every sum below do not depend on it
+        int coff = atomicAdd(&S.is[3], mine);
+        wave_sync();
+        const int Ec = S.is[3];
         if (Ec > C::CMAX) { defer = true; break; }
-        for (int pos = lane; pos < m; pos += G) {
-            int l = S.I[pos];
-            for (int q = a.cp[l]; q < a.cp[l + 1]; ++q) S.u.c.key[coff++] = a.ri[q];
+        int jlo = INT_MAX, jhi = -1;
+        auto fill = [&](int q0, int qn) {
+            for (int qb = 0; qb < qn; qb += 8) {
+                int jj[8];
+                F bb[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q0 + min(qb + u, qn - 1);
+                    jj[u] = a.ri[q];
+                    bb[u] = bcv[q];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (qb + u < qn) {
+                        S.u.c.key[coff] = (CKey)jj[u];
+                        S.u.c.val[coff] = bb[u];
+                        ++coff;
+                        jlo = min(jlo, jj[u]);
+                        jhi = max(jhi, jj[u]);
+                    }
+            }
+        };
+#pragma unroll
+        for (int it = 0; it < RPL; ++it) {
+            roff[it] = coff;
+            fill(rq0[it], rcnt[it]);
         }
-        if (lane == 0 && kpos < 0)
-            for (int q = a.cp[k]; q < a.cp[k + 1]; ++q) S.u.c.key[coff++] = a.ri[q];
+        const int koff = coff;
+        if (lane == 0) fill(kq0, kcnt);
+        const int moff = coff;
+        if (lane < p) {
+            const int jm = S.J[lane];
+            S.u.c.key[moff] = (CKey)jm;
+            jlo = min(jlo, jm);
+            jhi = max(jhi, jm);
+        }
+        if (jhi >= 0) {
+            atomicMin(&S.is[4], jlo);
+            atomicMax(&S.is[5], jhi);
+        }
+        wave_sync();
+        const int jbase = S.is[4];
+        if constexpr (C::CKEY32) {
+            if ((unsigned)(S.is[5] - jbase) >= (1u << C::CJB) - 1u) { defer = true; break; }
+        }
+        auto mk = [&](int slot, int rank) {
+            const CKey j = S.u.c.key[slot];
+            if constexpr (C::CKEY32)
+                S.u.c.key[slot] = ((j - (CKey)jbase) << (C::CSB + C::CRB)) | ((CKey)rank << C::CSB) | (CKey)slot;
+            else
+                S.u.c.key[slot] = (j << 32) | ((CKey)rank << 16) | (CKey)slot;
+        };
+#pragma unroll
+        for (int it = 0; it < RPL; ++it)
+            for (int e = 0; e < rcnt[it]; ++e) mk(roff[it] + e, 2 * (lane + it * G) + 1);
+        if (lane == 0)
+            for (int e = 0; e < kcnt; ++e) mk(koff + e, 2 * rk);
+        if (lane < p) mk(moff, C::CMARK);
         const int Ec2 = next_pow2(Ec > 0 ? Ec : 1);
-        for (int e = Ec + lane; e < Ec2; e += G) S.u.c.key[e] = INT_MAX;
+        for (int e = Ec + lane; e < Ec2; e += G) S.u.c.key[e] = ~CKey(0);
         wave_sync();
         group_sort<G>(S.u.c.key, Ec2, lane);
+        // unique candidates outside J, in ascending j: the first entry of each run
+        // of equal j sums its run (a marker at the end of the run: j is in J) and
+        // scores rho_j = sqrt(max(res^2 - (r^T B e_j)^2 / ||B e_j||^2, 0)), r being
+        // the residual on L (s-bar on I, -1 at k when k is outside I).  Candidate c
+        // goes to key[c] (c is at most the position of its first entry, read
+        // before) and rho[c] (the space of the gathered values, unused from here).
         int nc = 0;
+        bool over = false;
+        CKey jprev = 0;                      // j of the last entry of the previous stride
         for (int base = 0; base < Ec; base += G) {
-            int e = base + lane;
+            const int e = base + lane;
             bool head = false;
-            int j = 0;
+            CKey jk = 0;
             if (e < Ec) {
-                j = S.u.c.key[e];
-                head = (e == 0 || S.u.c.key[e - 1] != j);
-                if (head)
-                    for (int c = 0; c < p; ++c)
-                        if (S.J[c] == j) head = false;
+                jk = ckey_j<C>(S.u.c.key[e]);
+                // entry e - 1 of the first lane may already hold a compacted candidate
+                const CKey jp = lane == 0 ? jprev : ckey_j<C>(S.u.c.key[e - 1]);
+                head = (e == 0) || (jp != jk);
             }
-            uint64_t bal = ballot(head) & gmask;
-            if (head) S.u.c.key[nc + __popcll(bal & below)] = j;
+            const int last = min(base + G, Ec) - 1;
+            jprev = ckey_j<C>(S.u.c.key[last]);
+            const int j = (int)jk + (C::CKEY32 ? jbase : 0);
+            F bn = F(1), tj = F(0);
+            bool inJ = false;
+            if (head) {
+                bn = bnrm2[j];
+                for (int e2 = e; e2 < Ec; ++e2) {
+                    const CKey kk = S.u.c.key[e2];
+                    if (ckey_j<C>(kk) != jk) break;
+                    const int rank = ckey_rank<C>(kk);
+                    if (rank == C::CMARK) {
+                        inJ = true;
+                        break;
+                    }
+                    const F r = (rank & 1) ? S.s[S.dpos[rank >> 1]] : F(-1);
+                    tj = ffma(r, S.u.c.val[ckey_slot<C>(kk)], tj);
+                }
+            }
+            const bool valid = head && !inJ;
+            const uint64_t bal = ballot(valid) & gmask;
+            if (nc + __popcll(bal) > C::RHOCAP) {
+                over = true;
+                break;
+            }
+            if (valid) {
+                F r2 = res2 - (tj * tj) / bn;
+                if (r2 <= F(0)) r2 = F(0);
+                const int c = nc + __popcll(bal & below);
+                S.u.c.key[c] = (CKey)j;
+                S.rho[c] = fsqrt(r2);
+            }
             nc += __popcll(bal);
         }
+        if (over) { defer = true; break; }
         wave_sync();
         if (nc == 0) { flags |= CF_EPS; break; }
-        // scores rho_j = sqrt(max(res^2 - (r^T B e_j)^2 / ||B e_j||^2, 0)); the sum
-        // runs over the rows of B(:, j) (= columns of row j of A) ascending, r being
-        // the residual on L (s-bar on I, -1 at k when k is outside I)
-        for (int c = lane; c < nc; c += G) {
-            int j = S.u.c.key[c];
-            double dj = a.d[j];
-            F tj = F(0);
-            for (int q = a.rp[j]; q < a.rp[j + 1]; ++q) {
-                int i = a.ci[q];
-                F r;
-                int d = bsearch_rows<C>(S.gkey, S.seg, m, i, rbase);
-                if (d >= 0) r = S.s[S.dpos[d]];
-                else if (i == k) r = F(-1);
-                else continue;
-                tj = ffma(r, scaled_entry<C::UF>(dj, a.av[q]), tj);
-            }
-            F r2 = res2 - (tj * tj) / bnrm2[j];
-            if (r2 <= F(0)) r2 = F(0);
-            S.u.c.rho[c] = fsqrt(r2);
-        }
-        wave_sync();
         if (lane == 0) {
             F rs = F(0);
-            for (int c = 0; c < nc; ++c) rs = rs + S.u.c.rho[c];   // ascending j
+            for (int c = 0; c < nc; ++c) rs = rs + S.rho[c];   // ascending j
             S.fs[2] = rs / (F)nc;
         }
         wave_sync();
         const F rbar = S.fs[2];
         // acceptable: rho_j <= rho-bar; add the min(beta, #acceptable, cap - |J|)
-        // best, ordered by (rho, j)
+        // best, ordered by (rho, j): candidate c goes to position p + (its rank in
+        // that order) when the rank is below the number taken (every candidate
+        // ordered before an acceptable one is acceptable)
         int na = 0;
         for (int base = 0; base < nc; base += G) {
             int c = base + lane;
-            bool ok = (c < nc) && (S.u.c.rho[c] <= rbar);
+            bool ok = (c < nc) && (S.rho[c] <= rbar);
             na += __popcll(ballot(ok) & gmask);
         }
         int nsel = a.beta;
         if (na < nsel) nsel = na;
         if (cap - p < nsel) nsel = cap - p;
         if (nsel <= 0) { flags |= CF_EPS; break; }
-        for (int sel = 0; sel < nsel; ++sel) {
-            F br = F(0);
-            int bj = INT_MAX, bc = -1;
-            for (int c = lane; c < nc; c += G) {
-                int j = S.u.c.key[c];
-                F r = S.u.c.rho[c];
-                if (j >= 0 && r <= rbar && (bc < 0 || r < br || (r == br && j < bj))) {
-                    br = r;
-                    bj = j;
-                    bc = c;
-                }
+        for (int c = lane; c < nc; c += G) {
+            const F rc = S.rho[c];
+            const int jc = (int)S.u.c.key[c];
+            if (!(rc <= rbar)) continue;
+            int rank = 0;
+            for (int c2 = 0; c2 < nc; ++c2) {
+                const F r2 = S.rho[c2];
+                rank += (r2 < rc || (r2 == rc && (int)S.u.c.key[c2] < jc)) ? 1 : 0;
             }
-            // the group's lanes in order, read by lane permutes
-            {
-                F r0 = F(0);
-                int j0 = INT_MAX, c0 = -1;
-                for (int t = 0; t < G; ++t) {
-                    const int ct = __shfl(bc, gl0 + t, 64);
-                    const F rt = __shfl(br, gl0 + t, 64);
-                    const int jt = __shfl(bj, gl0 + t, 64);
-                    if (ct < 0) continue;
-                    if (c0 < 0 || rt < r0 || (rt == r0 && jt < j0)) {
-                        r0 = rt;
-                        j0 = jt;
-                        c0 = ct;
-                    }
-                }
-                if (lane == 0) {
-                    S.J[p + sel] = j0;
-                    S.u.c.key[c0] = -1;   // taken
-                }
-            }
-            wave_sync();
+            if (rank < nsel) S.J[p + rank] = jc;
         }
+        wave_sync();
         p_prev = p;
         p += nsel;
     }
@@ -1273,6 +1372,8 @@ __global__ void k_strided_list(int count, int stride, int* out) {
 template <int UF>
 static int launch_columns_m21(spai_handle* h, const ColArgs& a, hipStream_t s, int* sample_list,
                               int* count_host) {
+    // the small-shadow shape with A-bar in registers when the arithmetic is FP32
+    using Small = std::conditional_t<UF == SPAI_FP64, CfgM21s<UF>, CfgM21sR<UF>>;
     if (a.cols != nullptr || a.ncols < 4096) return launch_columns<CfgM21<UF>>(h, a, s);
     const int ns = 2048, stride = a.ncols / ns;
     hipLaunchKernelGGL(k_strided_list, dim3((ns + 255) / 256), dim3(256), 0, s, ns, stride, sample_list);
@@ -1281,13 +1382,13 @@ static int launch_columns_m21(spai_handle* h, const ColArgs& a, hipStream_t s, i
     smp.cols = sample_list;
     smp.ncols = ns;
     SPAI_HIP(hipMemsetAsync(a.defer_count, 0, sizeof(int), s));
-    int rc = launch_columns<CfgM21s<UF>>(h, smp, s);
+    int rc = launch_columns<Small>(h, smp, s);
     if (rc) return rc;
     SPAI_HIP(hipMemcpyAsync(count_host, a.defer_count, sizeof(int), hipMemcpyDeviceToHost, s));
     SPAI_HIP(hipStreamSynchronize(s));
     const bool small = *count_host * 50 <= ns;
     SPAI_HIP(hipMemsetAsync(a.defer_count, 0, sizeof(int), s));
-    return small ? launch_columns<CfgM21s<UF>>(h, a, s) : launch_columns<CfgM21<UF>>(h, a, s);
+    return small ? launch_columns<Small>(h, a, s) : launch_columns<CfgM21<UF>>(h, a, s);
 }
 
 // The column phase: the configuration kcfg (0 = the rule below), then the
@@ -1303,6 +1404,10 @@ static int run_columns(spai_handle* h, int pmax, int kcfg, ColArgs a, hipStream_
         // the smallest configuration holding pmax indices
         id = pmax <= cfg_maxp(KC_S) ? KC_S : pmax <= cfg_maxp(KC_M) ? KC_M : pmax <= cfg_maxp(KC_M21) ? KC_M21
            : pmax <= cfg_maxp(KC_L) ? KC_L : KC_X;
+        // with FP32 arithmetic the 32-lane shape keeps A-bar in registers: three
+        // times faster on a fixed 27-point pattern (its smaller candidate space
+        // defers more adaptive columns, which the large-problem kernel takes)
+        if (UF != SPAI_FP64 && id == KC_L) id = KC_LR;
     }
     if (kcfg == 0 && id == KC_M21) rc = launch_columns_m21<UF>(h, a, s, defer_list2, defer_count_host);
     else rc = launch_cfg<UF>(h, id, a, s);
@@ -1581,12 +1686,13 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     const int nnz = A->nnz;
     const size_t fsz = (p->u_f == SPAI_FP64) ? 8 : 4;
 
-    // workspace: d, bnrm2, col counts, cursor, CSC rows, scan blocks, defer lists, stats
+    // workspace: d, bnrm2, col counts, cursor, CSC rows and values, scan blocks, defer lists, stats
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1;
     size_t o_bn = take(fsz * n), o_cnt = take(4 * (size_t)n + 4), o_cp = take(4 * ((size_t)n + 1)),
-           o_cur = take(4 * (size_t)n), o_ri = take(4 * (size_t)nnz), o_blk = take(4 * (size_t)nb),
+           o_cur = take(4 * (size_t)n), o_ri = take(4 * (size_t)nnz), o_bcv = take(fsz * (size_t)nnz),
+           o_blk = take(4 * (size_t)nb),
            o_tot = take(16), o_dl = take(4 * (size_t)n), o_dl2 = take(4 * (size_t)n),
            o_dc = take(16), o_prep = take(sizeof(PrepOut)), o_bst = take(sizeof(BuildStatsDev)),
            o_nI = take(4 * (size_t)n), o_sl = take(tq ? 4 * (size_t)n : 0);
@@ -1598,6 +1704,7 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     int* cp = (int*)(base + o_cp);
     int* cur = (int*)(base + o_cur);
     int* ri = (int*)(base + o_ri);
+    void* bcv = base + o_bcv;
     int* blk = (int*)(base + o_blk);
     int* tot = (int*)(base + o_tot);
     int* dl = (int*)(base + o_dl);
@@ -1660,13 +1767,17 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     // CSC structure of A (rows of B) and ||B(:, j)||^2
     if ((rc = scan_ints(n, cnt, cp, blk, tot, s))) return fail(rc);
     SPAI_HIP(hipMemcpyAsync(cur, cp, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_fill_csc, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->col, cur, ri);
+#define SPAI_PREP(UF, T)                                                                                         \
+    hipLaunchKernelGGL(k_fill_csc<UF>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->col, A->val, P->d, cur, ri,     \
+                       (T*)bcv);                                                                                 \
+    hipLaunchKernelGGL(k_colnorm<UF>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (T*)bn)
     switch (p->u_f) {
-    case SPAI_FP64: hipLaunchKernelGGL(k_colnorm<SPAI_FP64>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (double*)bn); break;
-    case SPAI_FP32: hipLaunchKernelGGL(k_colnorm<SPAI_FP32>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (float*)bn); break;
-    case SPAI_FP16: hipLaunchKernelGGL(k_colnorm<SPAI_FP16>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (float*)bn); break;
-    default: hipLaunchKernelGGL(k_colnorm<SPAI_BF16>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, (float*)bn); break;
+    case SPAI_FP64: SPAI_PREP(SPAI_FP64, double); break;
+    case SPAI_FP32: SPAI_PREP(SPAI_FP32, float); break;
+    case SPAI_FP16: SPAI_PREP(SPAI_FP16, float); break;
+    default: SPAI_PREP(SPAI_BF16, float); break;
     }
+#undef SPAI_PREP
     SPAI_HIP(hipGetLastError());
 
     // per-column outputs
@@ -1680,6 +1791,7 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
     ColArgs a{};
     a.n = n; a.rp = A->rowptr; a.ci = A->col; a.av = A->val; a.cp = cp; a.ri = ri; a.d = P->d;
     a.bnrm2 = bn;
+    a.bcv = bcv;
     a.pat_ptr = J ? J->ptr : nullptr;
     a.pat_idx = J ? J->idx : nullptr;
     a.eps = p->eps; a.alpha = p->alpha; a.beta = p->beta; a.maxfill = p->maxfill;
@@ -1730,12 +1842,19 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
         if (nf > 0) {
             int* flist = nullptr;
             float* bn32 = nullptr;
+            float* bcv32 = nullptr;
+            int *ri32 = nullptr, *cur32 = nullptr;
             auto drop = [&]() {
                 (void)hipStreamSynchronize(s);
                 dev_free(flist, h->arena);
                 dev_free(bn32, h->arena);
+                dev_free(bcv32, h->arena);
+                dev_free(ri32, h->arena);
+                dev_free(cur32, h->arena);
             };
-            if ((rc = dev_alloc(h, &flist, nf)) || (rc = dev_alloc(h, &bn32, n))) {
+            if ((rc = dev_alloc(h, &flist, nf)) || (rc = dev_alloc(h, &bn32, n)) ||
+                (rc = dev_alloc(h, &bcv32, (size_t)nnz)) || (rc = dev_alloc(h, &ri32, (size_t)nnz)) ||
+                (rc = dev_alloc(h, &cur32, (size_t)n))) {
                 drop();
                 return fail(rc);
             }
@@ -1743,9 +1862,14 @@ static int build_core(spai_handle* h, const spai_csr* A, const spai_pattern* J, 
             hipLaunchKernelGGL(k_flag_list, dim3(gb), dim3(tb), 0, s, n, (const int*)P->flags, CF_NONFINITE, flist,
                                fcount);
             hipLaunchKernelGGL(k_colnorm<SPAI_FP32>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->val, P->d, bn32);
+            SPAI_HIP(hipMemcpyAsync(cur32, cp, 4 * (size_t)n, hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_fill_csc<SPAI_FP32>, dim3(gb), dim3(tb), 0, s, n, A->rowptr, A->col, A->val, P->d,
+                               cur32, ri32, bcv32);
             SPAI_HIP(hipGetLastError());
             ColArgs f = a;
             f.bnrm2 = bn32;
+            f.ri = ri32;
+            f.bcv = bcv32;
             f.cols = flist;
             f.ncols = nf;
             SPAI_HIP(hipMemsetAsync(dc, 0, 2 * sizeof(int), s));

@@ -439,10 +439,14 @@ int spai_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y);
  *     batches are still running.
  *   - one device lane runs larger systems one at a time with spai_build and
  *     spai_gmres_ir (the request's ortho), in arrival order or smallest first
- *     (sjf_age_ms).  Its Arnoldi launches synchronise
- *     across the whole grid and need every workgroup resident, so while that
- *     solve runs no batch starts (running batches finish first); builds
- *     overlap freely.
+ *     (sjf_age_ms).  Its Arnoldi launches synchronise across their whole grid
+ *     and need every workgroup resident.  With device_lane_cus = K > 0 the
+ *     device lane's solve runs on a stream masked to K CUs of every XCD, its
+ *     Arnoldi grid sized to them, and the batch lanes' streams are masked to
+ *     the other CUs, so batches start and run beside the solve; a system too
+ *     large for the fused Arnoldi launch on the K CUs (or K = 0) takes the
+ *     whole device for its solve instead, and then no batch starts while it
+ *     runs (running batches finish first).  Builds overlap freely.
  * A system's result does not depend on what else is in flight: a batch gives
  * every system the bits it gets in a batch of its own (every system is solved
  * by one workgroup in a fixed order, and the block-diagonal build equals each
@@ -466,6 +470,10 @@ typedef struct {
     int64_t hbm_budget;        /* device bytes of the server's arena (allocated at creation) */
     int64_t lane_workspace;    /* batched-solver workspace of a batch in bytes (0: min(8 GiB,
                                   hbm_budget / 4 / batch_lanes)) */
+    int32_t device_lane_cus;   /* CUs per XCD reserved for the device lane's solves, 0..31 (gfx950:
+                                  8 XCDs of 32 CUs): batch lanes run on the other CUs, so batches
+                                  keep running beside a device-lane solve; 0 = no reservation */
+    int32_t pad;
 } spai_serve_params;
 
 /* One system: host CSR A (validated on the device like spai_build's input),
@@ -490,11 +498,13 @@ typedef struct {
     int32_t rc;             /* the request's outcome: 0, a SPAI_W_* mask, or a negative SPAI_E_* */
     int32_t lane;           /* batch lane index, or -1 for the device lane */
     int32_t batch_size;     /* systems solved in the same batch (1 on the device lane) */
-    int32_t pad;
+    int32_t cus;            /* CUs the solve could use (the reservation, the batch lanes' share,
+                               or the whole device) */
     int64_t footprint;      /* device bytes reserved at admission (an upper estimate) */
     int64_t nnz_p;          /* stored entries of the system's preconditioner */
     double t_submit;        /* seconds since the server was created */
     double t_admit;
+    double t_solve;         /* the solve (of the batch, or of the system) was started */
     double t_done;          /* result copied back to the host */
     spai_ir_stats ir;
 } spai_serve_result;

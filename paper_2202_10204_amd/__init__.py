@@ -93,7 +93,7 @@ def _ir_dict(st, status) -> dict:
 
 class _ServeParams(ctypes.Structure):
     _fields_ = [("batch_lanes", _c_i32), ("batch_max_n", _c_i32), ("batch_max_systems", _c_i32), ("sjf_age_ms", _c_i32),
-                ("hbm_budget", _c_i64), ("lane_workspace", _c_i64)]
+                ("hbm_budget", _c_i64), ("lane_workspace", _c_i64), ("device_lane_cus", _c_i32), ("pad", _c_i32)]
 
 
 class _ServeRequest(ctypes.Structure):
@@ -102,9 +102,9 @@ class _ServeRequest(ctypes.Structure):
 
 
 class _ServeResult(ctypes.Structure):
-    _fields_ = [("rc", _c_i32), ("lane", _c_i32), ("batch_size", _c_i32), ("pad", _c_i32),
+    _fields_ = [("rc", _c_i32), ("lane", _c_i32), ("batch_size", _c_i32), ("cus", _c_i32),
                 ("footprint", _c_i64), ("nnz_p", _c_i64), ("t_submit", _c_f64), ("t_admit", _c_f64),
-                ("t_done", _c_f64), ("ir", _IrStats)]
+                ("t_solve", _c_f64), ("t_done", _c_f64), ("ir", _IrStats)]
 
 
 class SpaiError(RuntimeError):
@@ -548,11 +548,14 @@ class Server:
     """The library's request loop on the current device (see spai_serve_* in include/spai.h)."""
 
     def __init__(self, batch_lanes: int = 3, batch_max_n: int = 20000, batch_max_systems: int = 1024,
-                 hbm_budget: int = 64 << 30, lane_workspace: int = 0, sjf_age_ms: int = 0):
+                 hbm_budget: int = 64 << 30, lane_workspace: int = 0, sjf_age_ms: int = 0,
+                 device_lane_cus: int = 0):
+        """device_lane_cus: CUs per XCD reserved for the device lane's solves (batches
+        run on the others and keep running beside such a solve); 0 = none."""
         if not torch.cuda.is_available():
             raise SpaiError("no GPU available: libspai runs on the device only")
         prm = _ServeParams(int(batch_lanes), int(batch_max_n), int(batch_max_systems), int(sjf_age_ms),
-                           int(hbm_budget), int(lane_workspace))
+                           int(hbm_budget), int(lane_workspace), int(device_lane_cus), 0)
         raw = ctypes.c_void_p()
         _check(lib().spai_serve_create(ctypes.byref(prm), ctypes.byref(raw)), "spai_serve_create")
         self._raw = raw
@@ -577,7 +580,8 @@ class Server:
         rc = lib().spai_serve_wait(self._raw, int(rid), x.ctypes.data, ctypes.byref(res))
         k = res.ir.steps
         rec = {"rc": res.rc, "lane": res.lane, "batch_size": res.batch_size, "footprint": res.footprint,
-               "nnz_p": res.nnz_p, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
+               "nnz_p": res.nnz_p, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_solve": res.t_solve,
+               "t_done": res.t_done, "cus": res.cus,
                "steps": k, "its": list(res.ir.its[:k]), "total_its": res.ir.total_its, "status": res.ir.status,
                "nbe": res.ir.nbe, "error": last_error() if rc < 0 else ""}
         return rc, (x if rc >= 0 else None), rec

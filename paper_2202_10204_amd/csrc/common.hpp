@@ -74,6 +74,8 @@ void raw_free(void* p);
 // device address of the workspace array of spai_gmres_ir_noalloc on `device`
 // (looked up once per device, with that device current; spai_create does it)
 int noalloc_scratch_init(int device);
+// whether a solve of n unknowns fits the fused Arnoldi launch on h->num_cu CUs
+bool arnoldi_fused_fits(spai_handle* h, int n, int maxit, int ortho);
 void dev_free(void* p, const Arena& from);
 int buffer_reserve(spai_handle* h, Buffer& b, size_t bytes);
 void buffer_free(Buffer& b);

@@ -1742,6 +1742,12 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
     return c;
 }
 
+// Whether a solve of n unknowns runs the fused Arnoldi launch on the CUs the
+// handle counts (h->num_cu) rather than the separate-kernel path.
+bool arnoldi_fused_fits(spai_handle* h, int n, int maxit, int ortho) {
+    return arnoldi_config(h, n, std::min(maxit, n), ortho).nb > 0;
+}
+
 // The blocks of an Arnoldi launch must be resident together (they wait on each
 // other's partial sums).  arnoldi_config admits a configuration only when the
 // occupancy query shows that all nb blocks fit on the device at once, so an

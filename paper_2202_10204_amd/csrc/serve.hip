@@ -233,16 +233,43 @@ struct LaneCtx {
     spai_server* S = nullptr;
     int lane = -1;
     hipStream_t stream = nullptr;
+    hipStream_t solve_stream = nullptr;   // device lane with reserved CUs: the solve's stream
+    int all_cus = 0, solve_cus = 0;
     spai_handle* h = nullptr;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
 };
 
+// CU masks on gfx950: bit i of a stream's mask enables a CU of XCD i mod 8 (the
+// driver deals consecutive bits to the XCDs in turn, and within an XCD to its
+// shader engines in turn), so bits [0, 8K) enable K CUs in every XCD and a grid
+// dealt round-robin to the XCDs finds K CUs in each.
+constexpr int XCDS = 8;
+
+int masked_stream(hipStream_t* s, int num_cu, int lo, int hi) {
+    std::vector<uint32_t> mask((num_cu + 31) / 32, 0u);
+    for (int b = lo; b < hi; ++b) mask[b / 32] |= 1u << (b % 32);
+    SPAI_HIP(hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data()));
+    return SPAI_OK;
+}
+
 int lane_init(LaneCtx& L, size_t ws_cap) {
     SPAI_HIP(hipSetDevice(L.S->device));
-    SPAI_HIP(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
     int rc = spai_create(&L.h);
     if (rc) return rc;
+    const int num_cu = L.h->num_cu, rsv = XCDS * L.S->prm.device_lane_cus;
+    L.all_cus = num_cu;
+    if (rsv > 0 && L.lane >= 0) {
+        // batch lane: the CUs outside the device lane's reservation
+        if ((rc = masked_stream(&L.stream, num_cu, rsv, num_cu))) return rc;
+        L.h->num_cu = num_cu - rsv;
+    } else {
+        SPAI_HIP(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+    }
+    if (rsv > 0 && L.lane < 0) {
+        if ((rc = masked_stream(&L.solve_stream, num_cu, 0, rsv))) return rc;
+        L.solve_cus = rsv;
+    }
     L.h->stream = L.stream;
     L.h->ws_cap = ws_cap;
     return SPAI_OK;
@@ -252,6 +279,7 @@ void lane_fini(LaneCtx& L) {
     if (L.h) (void)spai_destroy(L.h);
     if (L.pinned) (void)hipHostFree(L.pinned);
     if (L.stream) (void)hipStreamDestroy(L.stream);
+    if (L.solve_stream) (void)hipStreamDestroy(L.solve_stream);
 }
 
 int pinned(LaneCtx& L, size_t bytes, char** out) {
@@ -416,6 +444,7 @@ int run_batch(LaneCtx& L, const std::vector<Request*>& rs) {
     ip.ortho = SPAI_ORTHO_MGS;
     S->gate.lock_shared();
     int rb = spai_build_batched(L.h, &A, nsys, g.sys_ptr.data(), g.jptr ? &J : nullptr, &rs[0]->bp, &P, nullptr);
+    const double ts = seconds_since(S->t0);
     int rs_ = rb < 0 ? rb : spai_gmres_ir_batched(L.h, &A, P, nsys, g.sys_ptr.data(), g.b, g.x, &ip, st.data());
     S->gate.unlock_shared();
     if (rb < 0 || rs_ < 0) {
@@ -438,6 +467,8 @@ int run_batch(LaneCtx& L, const std::vector<Request*>& rs) {
         rs[q]->res.ir = st[q];
         rs[q]->res.rc = warn | st[q].status;
         rs[q]->res.batch_size = nsys;
+        rs[q]->res.t_solve = ts;
+        rs[q]->res.cus = L.h->num_cu;
     }
     return SPAI_OK;
 }
@@ -460,9 +491,26 @@ int run_single(LaneCtx& L, Request* r) {
     if (rb < 0) return rb;
     lane_trim(L);   // the build's workspace is not needed by the solve
     spai_ir_stats st{};
-    S->gate.lock();
-    int rs_ = spai_gmres_ir(L.h, &A, P, g.b, g.x, &r->ip, &st);
-    S->gate.unlock();
+    int rs_;
+    // on the reserved CUs when the fused Arnoldi launch fits them (batches go on
+    // beside it), else on the whole device with no batch running
+    L.h->num_cu = L.solve_cus;
+    const bool masked = L.solve_cus > 0 && arnoldi_fused_fits(L.h, g.n, r->ip.maxit, r->ip.ortho);
+    L.h->num_cu = L.all_cus;
+    if (masked) {
+        L.h->num_cu = L.solve_cus;
+        L.h->stream = L.solve_stream;
+        r->res.t_solve = seconds_since(S->t0);
+        rs_ = spai_gmres_ir(L.h, &A, P, g.b, g.x, &r->ip, &st);
+        L.h->stream = L.stream;
+        L.h->num_cu = L.all_cus;
+    } else {
+        S->gate.lock();
+        r->res.t_solve = seconds_since(S->t0);
+        rs_ = spai_gmres_ir(L.h, &A, P, g.b, g.x, &r->ip, &st);
+        S->gate.unlock();
+    }
+    r->res.cus = masked ? L.solve_cus : L.all_cus;
     if (rs_ < 0) {
         spai_precond_destroy(P);
         return rs_;
@@ -590,6 +638,16 @@ extern "C" int spai_serve_create(const spai_serve_params* p, spai_server** out) 
     SPAI_ARG(p->batch_max_n >= 1 && p->batch_max_systems >= 1, "batch_max_n and batch_max_systems must be >= 1");
     SPAI_ARG(p->hbm_budget > 0 && p->lane_workspace >= 0, "bad budget");
     SPAI_ARG(p->sjf_age_ms >= 0, "sjf_age_ms must be non-negative");
+    SPAI_ARG(p->device_lane_cus >= 0, "device_lane_cus must be non-negative");
+    if (p->device_lane_cus > 0) {
+        int dev0 = 0;
+        hipDeviceProp_t prop;
+        SPAI_HIP(hipGetDevice(&dev0));
+        SPAI_HIP(hipGetDeviceProperties(&prop, dev0));
+        SPAI_ARG(prop.multiProcessorCount % spai::XCDS == 0 &&
+                     p->device_lane_cus < prop.multiProcessorCount / spai::XCDS,
+                 "device_lane_cus must leave every XCD a CU for the batch lanes");
+    }
     spai_serve_params prm = *p;
     if (prm.lane_workspace == 0)
         prm.lane_workspace = std::min<int64_t>(8ll << 30, prm.hbm_budget / 4 / prm.batch_lanes);

@@ -154,22 +154,45 @@ __global__ void k_fill_csc(int n, const int* __restrict__ rp, const int* __restr
 
 __global__ void k_validate_pattern(int n, int pnnz, const int* __restrict__ pp, const int* __restrict__ pi,
                                    PrepOut* out) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    int s = pp[k], e = pp[k + 1];
-    if (s < 0 || e < s || e > pnnz || (k == 0 && s != 0) || (k == n - 1 && e != pnnz)) {
-        atomicOr(&out->err, 16);
-        return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    int err = 0, len = 0;
+    if (k < n) {
+        const int s = pp[k], e = pp[k + 1];
+        if (s < 0 || e < s || e > pnnz || (k == 0 && s != 0) || (k == n - 1 && e != pnnz)) {
+            err = 16;
+        } else {
+            if (e == s) err = 16;      // every column needs at least one index
+            len = e - s;
+            if (len <= 32) {
+                // the column in registers, compared pairwise (distinct fillers past its end)
+                int v[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) v[u] = u < len ? pi[s + u] : -1 - u;
+                bool bad = false;
+#pragma unroll
+                for (int u = 0; u < 32; ++u) {
+                    bad |= u < len && (v[u] < 0 || v[u] >= n);
+#pragma unroll
+                    for (int u2 = 0; u2 < u; ++u2) bad |= v[u] == v[u2];
+                }
+                if (bad) err = 16;
+            } else {
+                for (int q = s; q < e; ++q) {
+                    int j = pi[q];
+                    if (j < 0 || j >= n) err = 16;
+                    for (int q2 = s; q2 < q; ++q2)
+                        if (pi[q2] == j) err = 16;
+                }
+            }
+        }
     }
-    int err = (e == s) ? 16 : 0;   // every column needs at least one index
-    for (int q = s; q < e; ++q) {
-        int j = pi[q];
-        if (j < 0 || j >= n) err = 16;
-        for (int q2 = s; q2 < q; ++q2)
-            if (pi[q2] == j) err = 16;
+    // one atomic per wave (a word updated by every thread serialises the launch)
+    len = wave_max_i(len);
+    err = wave_max_i(err);
+    if ((threadIdx.x & 63) == 0) {
+        if (err) atomicOr(&out->err, err);
+        if (len) atomicMax(&out->max_pat, len);
     }
-    if (err) atomicOr(&out->err, err);
-    atomicMax(&out->max_pat, e - s);
 }
 
 // exclusive scan of n ints into out[0..n], out[n] = total (three passes)

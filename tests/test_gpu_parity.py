@@ -297,6 +297,39 @@ def test_malformed_matrix_is_rejected(S, h):
         h.spai_build(S.DeviceCSR.from_host(W.CSR(w.n, w.A.rowptr, w.A.col, val)), None, 0.3, 2, 8, 20, "fp32")
 
 
+def _with_column(pat, k, cols):
+    """pat with column k's indices replaced by cols."""
+    ptr, idx = pat.ptr.astype(np.int64), pat.idx
+    idx2 = np.concatenate([idx[:ptr[k]], np.asarray(cols, np.int64), idx[ptr[k + 1]:]]).astype(np.int32)
+    ptr2 = ptr.copy()
+    ptr2[k + 1:] += len(cols) - (ptr[k + 1] - ptr[k])
+    return W.Pattern(pat.n, ptr2.astype(np.int32), idx2)
+
+
+def test_malformed_pattern_is_rejected_and_the_longest_column_found(S, h):
+    """A duplicate index, an index out of range or an empty column is rejected;
+    the longest initial column (here one column of 12 in the 20th wave of
+    columns) sets the indices a configuration must hold."""
+    w = W.convdiff_adaptive(40)
+    A = S.DeviceCSR.from_host(w.A)
+    pat = W.pattern_of(w.A)
+    k = 1234
+    own = list(pat.idx[pat.ptr[k]:pat.ptr[k + 1]])
+    def dev(P):        # the device's own check (from_host would reject a bad index first)
+        return S.DevicePattern(P.n, torch.as_tensor(P.ptr, device="cuda"), torch.as_tensor(P.idx, device="cuda"))
+
+    for bad in (own + [own[0]], own[:-1] + [w.n], []):
+        with pytest.raises(S.SpaiError, match="pattern malformed"):
+            h.spai_build(A, dev(_with_column(pat, k, bad)), 0.3, 0, 8, 5, "fp32")
+    long12 = sorted(set(own) | {k - 7, k - 5, k - 3, k + 3, k + 5, k + 7, k + 9})
+    assert len(long12) == 12
+    P12 = dev(_with_column(pat, k, long12))
+    with pytest.raises(S.SpaiError, match="holds at most 7 indices per column, the build needs 12"):
+        h.spai_build(A, P12, 0.3, 0, 8, 5, "fp32", kernel_cfg=1)
+    _, _, st = h.spai_build(A, P12, 0.3, 0, 8, 5, "fp32")
+    assert st["max_len"] == 12
+
+
 # ---------------------------------------------------------------------------
 # preconditioner application
 # ---------------------------------------------------------------------------

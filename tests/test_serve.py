@@ -258,3 +258,51 @@ def test_wait_while_another_thread_submits(S):
         rc2, x2, rec2 = srv.wait(rid)
         assert rc2 >= 0 and rec2["its"] == rec["its"] and np.array_equal(x2, x)
     srv.close()
+
+
+def test_reserved_cus_let_batches_run_beside_a_device_lane_solve(S):
+    """With 8 CUs of every XCD reserved for the device lane, a large system's
+    solve runs on those 64 CUs (its Arnoldi grid sized to them) while batches of
+    small systems run on the other 192: batches start and finish inside the
+    large solve.  Every result equals the one the same server gives the request
+    alone, bit for bit, and the large solve reaches ferr <= 1e-12."""
+    import threading
+    import time
+
+    big = W.serving_request(W.Arrival(0.0, "convdiff", 320, "fp32", 700))
+    pool = [W.serving_request(W.Arrival(0.0, "random", 1000 + 37 * i, "fp32", 701 + i)) for i in range(40)]
+
+    def server():
+        return S.Server(batch_lanes=3, batch_max_n=BATCH_MAX_N, batch_max_systems=2, hbm_budget=8 << 30,
+                        lane_workspace=256 << 20, device_lane_cus=8)
+
+    srv = server()
+    got = {}
+    ib = srv.submit(*_args(big, "dcgs2"))
+    t = threading.Thread(target=lambda: got.update(r=srv.wait(ib)))
+    t.start()
+    sent = []
+    while t.is_alive() and len(sent) < 400:
+        w = pool[len(sent) % len(pool)]
+        sent.append((w, srv.submit(*_args(w))))
+        time.sleep(0.002)
+    t.join()
+    mix = [(w, srv.wait(i)) for w, i in sent]
+    srv.close()
+    rc, xb, recb = got["r"]
+    assert rc >= 0 and recb["lane"] == -1 and recb["cus"] == 64, recb
+    assert O.ferr(xb, big.x_true) <= 1e-12
+    inside = [r for _, (_, _, r) in mix if recb["t_solve"] < r["t_solve"] and r["t_done"] < recb["t_done"]]
+    print("large solve", recb["t_solve"], recb["t_done"], "small requests sent", len(sent),
+          "finished inside it", len(inside), flush=True)
+    assert inside and all(r["cus"] == 192 and r["lane"] >= 0 for r in inside)
+    srv = server()
+    rc_a, xb_a, recb_a = srv.wait(srv.submit(*_args(big, "dcgs2")))
+    assert rc_a == rc and recb_a["its"] == recb["its"] and np.array_equal(xb_a, xb)
+    alone = {}
+    for w, (rc_m, x_m, rec_m) in mix:
+        if w.name not in alone:
+            alone[w.name] = srv.wait(srv.submit(*_args(w)))
+        rc_s, x_s, rec_s = alone[w.name]
+        assert rc_m == rc_s and rec_m["its"] == rec_s["its"] and np.array_equal(x_m, x_s), w.name
+    srv.close()

@@ -434,7 +434,8 @@ def run_serve(S, W, args):
 
     def one_pass(u_f_override=None):
         srv = S.Server(batch_lanes=args.lanes, batch_max_n=args.batch_max_n, batch_max_systems=1024,
-                       hbm_budget=args.budget_gib << 30, sjf_age_ms=args.sjf_age_ms)
+                       hbm_budget=args.budget_gib << 30, sjf_age_ms=args.sjf_age_ms,
+                       device_lane_cus=args.device_lane_cus)
         reqs = []
         for w in ws:
             s, ir = w.spai, w.ir
@@ -480,7 +481,13 @@ def run_serve(S, W, args):
             k["p99_ms"] = percentile(k["lat_ms"], 99)
             del k["lat_ms"]
         batches = [rec["batch_size"] for _, _, rec in out if rec["lane"] >= 0]
-        return {"solves_per_s": ok / span, "requests_per_s": len(out) / span, "span_s": span,
+        big = [rec for _, _, rec in out if rec["lane"] < 0]
+        # batches that started and finished inside some device-lane solve
+        inside = sum(1 for _, _, r in out if r["lane"] >= 0 and
+                     any(b["t_solve"] < r["t_solve"] and r["t_done"] < b["t_done"] for b in big))
+        return {"device_lane_requests": len(big), "device_lane_solves_on_reserved_cus":
+                sum(1 for b in big if args.device_lane_cus and b["cus"] == 8 * args.device_lane_cus),
+                "batched_requests_inside_a_device_lane_solve": inside,"solves_per_s": ok / span, "requests_per_s": len(out) / span, "span_s": span,
                 "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "solved": ok, "failed": fails,
                 "by_kind": kinds, "mean_batch": float(np.mean(batches)) if batches else 0.0,
                 "late_submissions": len(late), "max_late_ms": 1e3 * max(late) if late else 0.0}
@@ -496,12 +503,16 @@ def run_serve(S, W, args):
                                f"logU[1e3,2e4] adaptive; u_f FP16/FP32 50/50; u FP64, u_r DD",
                    "requests": len(trace), "batch_lanes": args.lanes, "batch_max_n": args.batch_max_n,
                    "hbm_budget_gib": args.budget_gib, "device_lane_arnoldi": args.ortho,
+                   "device_lane_cus_per_xcd": args.device_lane_cus,
                    "device_lane_order": f"smallest first, age limit {args.sjf_age_ms} ms" if args.sjf_age_ms
                    else "arrival"},
         "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed": mixed,
     }
     if args.serve_fp64:
-        out["fp64_form"] = one_pass("fp64")
+        f = one_pass("fp64")
+        out["fp64_form"] = f
+        out["speedup_of_mixed"] = {"solves_per_s": mixed["solves_per_s"] / f["solves_per_s"] if f["solves_per_s"] else None,
+                                   "p50": f["p50_ms"] / mixed["p50_ms"], "p99": f["p99_ms"] / mixed["p99_ms"]}
     print(json.dumps(out), flush=True)
 
 
@@ -578,6 +589,8 @@ def main():
     ap.add_argument("--batch-max-n", type=int, default=20000, help="serve: largest batched system")
     ap.add_argument("--budget-gib", type=int, default=128, help="serve: device memory budget in GiB")
     ap.add_argument("--serve-fp64", action="store_true", help="serve: run the stream again with u_f = FP64")
+    ap.add_argument("--device-lane-cus", type=int, default=0,
+                    help="serve: CUs per XCD reserved for the device lane's solves (0: none)")
     ap.add_argument("--sjf-age-ms", type=int, default=2000,
                     help="serve: device lane serves the smallest waiting system first unless the oldest waited "
                          "longer than this (0: arrival order)")

@@ -68,7 +68,7 @@ def _lib():
                                         P, P]
         L.oracle_gmres_ir.restype = i32
         L.oracle_gmres_ir.argtypes = [i32, P, P, P, P, P, P, P, i32, P, P, f64, i32, i32, f64,
-                                      i32, i32, P, P, P, P]
+                                      i32, i32, P, P, P, P, P]
         L.oracle_x0_right.restype = None
         L.oracle_x0_right.argtypes = [i32, P, P, P, P, P, i32, P]
         L.oracle_gmres_ir_fp32.restype = i32
@@ -286,6 +286,7 @@ class IrResult:
     dnorm: np.ndarray     # ||d_i||_inf per step
     xhist: Optional[np.ndarray] = None   # u = fp32: x_0 .. x_s (the iterate each step starts from, then the last)
     gprev: Optional[np.ndarray] = None   # u = fp32: |g_k| / beta0, the estimate one iteration before the stop
+    basis0: Optional[np.ndarray] = None  # basis=True: the first step's orthonormal Arnoldi vectors (n x its[0])
 
     @property
     def total(self) -> int:
@@ -300,7 +301,7 @@ ORTHO = {"mgs": 0, "cgs2": 1, "dcgs2": 2}
 
 def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, maxit: int,
              tol_ir: float, ortho: str = "mgs", u: str = "fp64", side: str = "left",
-             x_init: Optional[np.ndarray] = None) -> IrResult:
+             x_init: Optional[np.ndarray] = None, basis: bool = False) -> IrResult:
     """SPAI-GMRES-IR (Algorithm 3) with P = M^T D given as CSR(M^T) + D.
 
     ``ortho`` = "mgs" (modified Gram-Schmidt, the variant analysed in Section
@@ -318,7 +319,10 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
 
     ``x_init`` (u = "fp32" only): start the refinement from this iterate (used
     as rounded to binary32) instead of x0 = P b; the result then also holds the
-    iterates each step started from (``xhist``) and the stopping margins."""
+    iterates each step started from (``xhist``) and the stopping margins.
+
+    ``basis`` (u = "fp64"): also return the first refinement step's Arnoldi
+    vectors v_0 .. v_{k-1} (an inspection output: the arithmetic is unchanged)."""
     n = A.n
     x = np.zeros(n)
     its = np.zeros(imax, np.int32)
@@ -343,16 +347,19 @@ def gmres_ir(A, P_rowptr, P_col, P_val, d, uf: str, b, tau: float, imax: int, ma
                                          _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
                                          _p(its), _p(nsteps), _p(gest), _p(dn), _p(xi), _p(xhist), _p(gprev))
     elif u == "fp64":
+        B0 = np.zeros((maxit, n)) if basis else None
         st = _lib().oracle_gmres_ir(n, _p(rp), _p(ci), _p(av), _p(pp), _p(pc), _p(pv), _p(dd), UF[uf],
                                     _p(bb), _p(x), float(tau), int(imax), int(maxit), float(tol_ir),
-                                    ORTHO[ortho], int(side == "right"), _p(its), _p(nsteps), _p(gest), _p(dn))
+                                    ORTHO[ortho], int(side == "right"), _p(its), _p(nsteps), _p(gest), _p(dn),
+                                    _p(B0))
     else:
         raise ValueError(f"unknown working precision {u}")
     if st < 0:
         raise ValueError("oracle_gmres_ir: bad argument")
     s = int(nsteps[0])
     return IrResult(x, [int(v) for v in its[:s]], st, gest[:s].copy(), dn[:s].copy(),
-                    None if xhist is None else xhist[:s + 1].copy(), None if gprev is None else gprev[:s].copy())
+                    None if xhist is None else xhist[:s + 1].copy(), None if gprev is None else gprev[:s].copy(),
+                    None if u != "fp64" or not basis or s == 0 else B0[:its[0]].T.copy())
 
 
 def x0(P_rowptr, P_col, P_val, d, b, uf: str) -> np.ndarray:

@@ -917,7 +917,8 @@ static int arnoldi_dcgs2(int right, int n, const int* rp, const int* ci, const d
  * 1 = classical Gram-Schmidt applied twice (CGS2), 2 = CGS2 with the second
  * projection delayed by one step (arnoldi_dcgs2).  P = M^T D: CSR rows pp/pc with u_f values pv (held
  * in double) and the FP64 scaling d; uf is the precision of the initial solve.
- * x (out) receives the solution.  its[0..imax) receives GMRES iterations per
+ * x (out) receives the solution; basis0 (optional, n x maxit) receives the first
+ * refinement step's orthonormal Arnoldi vectors v_0 .. v_{k-1}, column by column.  its[0..imax) receives GMRES iterations per
  * refinement step; *nsteps the number of steps.  Left-preconditioned MGS-GMRES
  * with zero initial guess, no restart, stopped when the Givens estimate of the
  * preconditioned residual |g_{j+1}| <= tau * ||P r_i||_2 (or at maxit or on an
@@ -931,7 +932,7 @@ static int arnoldi_dcgs2(int right, int n, const int* rp, const int* ci, const d
 int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const int* pp,
                     const int* pc, const double* pv, const double* d, int uf, const double* b,
                     double* x, double tau, int imax, int maxit, double tol_ir, int ortho, int right, int* its,
-                    int* nsteps, double* gest, double* dnorm) {
+                    int* nsteps, double* gest, double* dnorm, double* basis0) {
     if (n <= 0 || imax < 1 || maxit < 1 || ortho < 0 || ortho > 2) return -1;
     int status = 0;
     double* r = (double*)malloc(sizeof(double) * (size_t)n);
@@ -1021,6 +1022,9 @@ int oracle_gmres_ir(int n, const int* rp, const int* ci, const double* av, const
         }
         its[step] = k;
         if (gest) gest[step] = fabs(g[k]) / beta0;
+        /* inspection: the first step's orthonormal basis v_0 .. v_{k-1} (n x k,
+         * column-major; maxit columns reserved by the caller) */
+        if (basis0 && step == 0) memcpy(basis0, V, sizeof(double) * (size_t)n * (size_t)k);
         /* back substitution H(1:k,1:k) y = g(1:k) */
         for (int c = k - 1; c >= 0; --c) {
             double s = g[c];

@@ -458,6 +458,62 @@ def test_gmres_step_is_the_krylov_least_squares_minimiser(ortho):
             assert np.abs((res.x - x0) - dexp).max() <= 1e-9 * np.abs(dexp).max()
 
 
+def test_long_arnoldi_runs_stay_the_krylov_minimiser():
+    """Over 10, 40 and 120 iterations (tau = 0) of one GMRES step with a
+    non-diagonal SPAI P (n = 400), MGS, CGS2 and delayed CGS2 each return the
+    minimiser of ||z - PA d||_2 over K_k(PA, z), z = P r0, against a basis built
+    here by numpy (each new direction PA q_i projected out twice with matrix
+    products, then normalised): a wrong index or lag in the delayed recurrences
+    shows up after a few steps, which the short runs above cannot see."""
+    w = W.convdiff_adaptive(20)
+    s = w.spai
+    R = O.spai(w.A, None, s.eps, s.alpha, s.beta, s.maxfill, "fp64")
+    pp, pc, pv = R.P_csr(w.n)
+    Ad = _dense(w.A)
+    P = sp.csr_matrix((pv * R.d[pc], pc, pp), shape=(w.n, w.n)).toarray()
+    PA = P @ Ad
+    x0 = P @ w.b
+    z = P @ (w.b - Ad @ x0)
+    Q = np.zeros((w.n, 121))
+    Q[:, 0] = z / np.linalg.norm(z)
+    for i in range(120):
+        v = PA @ Q[:, i]
+        for _ in range(2):
+            v -= Q[:, :i + 1] @ (Q[:, :i + 1].T @ v)
+        Q[:, i + 1] = v / np.linalg.norm(v)
+    for k in (10, 40, 120):
+        y, *_ = np.linalg.lstsq(PA @ Q[:, :k], z, rcond=None)
+        dexp = Q[:, :k] @ y
+        for ortho in ("mgs", "cgs2", "dcgs2"):
+            res = O.gmres_ir(w.A, pp, pc, pv, R.d, "fp64", w.b, 0.0, 1, k, 0.0, ortho)
+            assert res.its == [k]
+            err = np.abs((res.x - x0) - dexp).max() / np.abs(dexp).max()
+            assert err <= 1e-9, (k, ortho, err)
+
+
+def test_twice_projected_bases_stay_orthonormal():
+    """Classical Gram-Schmidt applied twice keeps the Arnoldi basis orthonormal to
+    working precision while the one-pass orthogonalisations lose it in
+    proportion to the conditioning the iteration reaches (Giraud, Langou and
+    Rozloznik, 2005; modified Gram-Schmidt's loss is what Section 3.2's analysis
+    allows for).  On plain GMRES (P = I) over a convection-diffusion matrix,
+    where MGS's basis has lost orthogonality completely by 70 iterations, the
+    CGS2 and delayed-CGS2 bases stay within 1e-14 of orthonormal; the delayed
+    scheme with its second projection removed (CGS1) fails this."""
+    w = W.convdiff_adaptive(24)
+    n = w.n
+    pp, pc, pv, d = np.arange(n + 1), np.arange(n), np.ones(n), np.ones(n)
+    loss = {}
+    for ortho in ("mgs", "cgs2", "dcgs2"):
+        for k in (40, 70, 90):
+            V = O.gmres_ir(w.A, pp, pc, pv, d, "fp64", w.b, 0.0, 1, k, 0.0, ortho, basis=True).basis0
+            assert V.shape == (n, k)
+            loss[ortho, k] = float(np.abs(np.eye(k) - V.T @ V).max())
+    assert loss["mgs", 40] <= 1e-9 and loss["mgs", 90] >= 0.1, loss
+    for k in (40, 70, 90):
+        assert loss["cgs2", k] <= 1e-14 and loss["dcgs2", k] <= 1e-14, loss
+
+
 def test_exact_preconditioner_takes_one_iteration_per_step():
     """Table 5 prints 1(1) for the exact (full LU, u_f = u) preconditioner."""
     its_golden = int(open(f"{GOLDEN}/exact_preconditioner_its.txt").read().split("its_per_step")[1])

@@ -411,43 +411,48 @@ def _serve_gen(a):
     return W.serving_request(a)
 
 
-def run_serve(S, W, args):
+def measure_serve(S, W, rate, duration, lanes, batch_max_n, budget_gib, sjf_age_ms, device_lane_cus, ortho,
+                  fp64, mp_context=None):
     """The serving stream: Poisson arrivals of systems of the three families (2D
     convection-diffusion, 3D anisotropic diffusion, random banded; u_f FP16 or
     FP32), submitted to the library's request loop at their arrival times.
     Latency = completion - submission on the server's clock; a request counts
-    as solved when it reaches a forward error <= 1e-12.  With --serve-fp64 the
-    same stream runs again with u_f = FP64 (the all-FP64 SPAI form)."""
-    import numpy as np
+    as solved when it reaches a forward error <= 1e-12.  With fp64 the same
+    stream runs again with u_f = FP64 (the all-FP64 SPAI form).  The requests
+    are generated on the host in worker processes (mp_context "spawn" once this
+    process has initialised the GPU)."""
+    import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
 
+    import numpy as np
     import torch
 
-    trace = W.serving_trace(args.rate, args.duration)
-    log(f"serving stream: {len(trace)} arrivals over {args.duration} s at {args.rate}/s")
+    trace = W.serving_trace(rate, duration)
+    log(f"serving stream: {len(trace)} arrivals over {duration} s at {rate}/s")
     t = time.time()
-    # host-side generation in worker processes, forked before this process touches the GPU
-    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+    ctx = multiprocessing.get_context(mp_context) if mp_context else None
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1), mp_context=ctx) as ex:
         ws = list(ex.map(_serve_gen, trace, chunksize=1))
     log(f"generated in {time.time() - t:.1f} s; n from {min(w.n for w in ws)} to {max(w.n for w in ws)}")
     torch.cuda.set_device(0)
+    torch.cuda.empty_cache()          # the server allocates its arena once
 
     def one_pass(u_f_override=None):
-        srv = S.Server(batch_lanes=args.lanes, batch_max_n=args.batch_max_n, batch_max_systems=1024,
-                       hbm_budget=args.budget_gib << 30, sjf_age_ms=args.sjf_age_ms,
-                       device_lane_cus=args.device_lane_cus)
+        srv = S.Server(batch_lanes=lanes, batch_max_n=batch_max_n, batch_max_systems=1024,
+                       hbm_budget=budget_gib << 30, sjf_age_ms=sjf_age_ms,
+                       device_lane_cus=device_lane_cus)
         reqs = []
         for w in ws:
             s, ir = w.spai, w.ir
             build = {"eps": s.eps, "alpha": s.alpha, "beta": s.beta, "maxfill": s.maxfill,
                      "u_f": u_f_override or s.u_f}
             irp = {"tau": ir.tau, "imax": ir.imax, "maxit": ir.maxit, "tol_ir": ir.tol_ir, "u_r": "dd",
-                   "ortho": args.ortho}
+                   "ortho": ortho}
             reqs.append((w.A, w.b, w.pattern, build, irp))
         # warm-up: one request of each batch key and one device-lane request, untimed
         seen = set()
         for r, a in zip(reqs, trace):
-            key = (a.kind == "aniso", r[3]["u_f"], r[0].n > args.batch_max_n)
+            key = (a.kind == "aniso", r[3]["u_f"], r[0].n > batch_max_n)
             if key not in seen:
                 seen.add(key)
                 srv.wait(srv.submit(*r))
@@ -486,33 +491,44 @@ def run_serve(S, W, args):
         inside = sum(1 for _, _, r in out if r["lane"] >= 0 and
                      any(b["t_solve"] < r["t_solve"] and r["t_done"] < b["t_done"] for b in big))
         return {"device_lane_requests": len(big), "device_lane_solves_on_reserved_cus":
-                sum(1 for b in big if args.device_lane_cus and b["cus"] == 8 * args.device_lane_cus),
+                sum(1 for b in big if device_lane_cus and b["cus"] == 8 * device_lane_cus),
                 "batched_requests_inside_a_device_lane_solve": inside,"solves_per_s": ok / span, "requests_per_s": len(out) / span, "span_s": span,
                 "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99), "solved": ok, "failed": fails,
                 "by_kind": kinds, "mean_batch": float(np.mean(batches)) if batches else 0.0,
                 "late_submissions": len(late), "max_late_ms": 1e3 * max(late) if late else 0.0}
 
     mixed = one_pass()
-    out = {
-        "metric": "serving: GMRES-IR solves/s at 1e-12 fwd err with p50/p99 latency", "value": mixed["solves_per_s"],
-        "unit": "solves/s", "n_gpus": 1, "steps": len(trace), "warmup": 0, "ms_per_step": 1e3 * mixed["span_s"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16/f32+f64+dd",
-        "data": "synthetic",
-        "config": {"workload": f"serving stream, Poisson {args.rate}/s for {args.duration} s: 2D convdiff side "
-                               f"logU[32,512] adaptive, 3D aniso side logU[10,128] pattern(A^2)<=27, random banded n "
-                               f"logU[1e3,2e4] adaptive; u_f FP16/FP32 50/50; u FP64, u_r DD",
-                   "requests": len(trace), "batch_lanes": args.lanes, "batch_max_n": args.batch_max_n,
-                   "hbm_budget_gib": args.budget_gib, "device_lane_arnoldi": args.ortho,
-                   "device_lane_cus_per_xcd": args.device_lane_cus,
-                   "device_lane_order": f"smallest first, age limit {args.sjf_age_ms} ms" if args.sjf_age_ms
-                   else "arrival"},
-        "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed": mixed,
-    }
-    if args.serve_fp64:
+    out = {"requests": len(trace), "rate_per_s": rate, "duration_s": duration, "solves_per_s": mixed["solves_per_s"],
+           "p50_ms": mixed["p50_ms"], "p99_ms": mixed["p99_ms"], "mixed": mixed,
+           "config": {"workload": f"serving stream, Poisson {rate}/s for {duration} s: 2D convdiff side "
+                                  f"logU[32,512] adaptive, 3D aniso side logU[10,128] pattern(A^2)<=27, random banded "
+                                  f"n logU[1e3,2e4] adaptive; u_f FP16/FP32 50/50; u FP64, u_r DD",
+                      "requests": len(trace), "batch_lanes": lanes, "batch_max_n": batch_max_n,
+                      "hbm_budget_gib": budget_gib, "device_lane_arnoldi": ortho,
+                      "device_lane_cus_per_xcd": device_lane_cus,
+                      "device_lane_order": f"smallest first, age limit {sjf_age_ms} ms" if sjf_age_ms
+                      else "arrival"}}
+    if fp64:
         f = one_pass("fp64")
         out["fp64_form"] = f
-        out["speedup_of_mixed"] = {"solves_per_s": mixed["solves_per_s"] / f["solves_per_s"] if f["solves_per_s"] else None,
-                                   "p50": f["p50_ms"] / mixed["p50_ms"], "p99": f["p99_ms"] / mixed["p99_ms"]}
+        out["speedup_of_mixed"] = {"solves_per_s": mixed["solves_per_s"] / f["solves_per_s"] if f["solves_per_s"]
+                                   else None, "p50": f["p50_ms"] / mixed["p50_ms"], "p99": f["p99_ms"] / mixed["p99_ms"]}
+    return out
+
+
+def run_serve(S, W, args):
+    """The serving stream as its own JSON line (see measure_serve)."""
+    m = measure_serve(S, W, args.rate, args.duration, args.lanes, args.batch_max_n, args.budget_gib, args.sjf_age_ms,
+                      args.device_lane_cus, args.ortho, args.serve_fp64)
+    out = {
+        "metric": "serving: GMRES-IR solves/s at 1e-12 fwd err with p50/p99 latency", "value": m["solves_per_s"],
+        "unit": "solves/s", "n_gpus": 1, "steps": m["requests"], "warmup": 0, "ms_per_step": 1e3 * m["mixed"]["span_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16/f32+f64+dd",
+        "data": "synthetic", "config": m["config"], "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"], "mixed": m["mixed"],
+    }
+    for k in ("fp64_form", "speedup_of_mixed"):
+        if k in m:
+            out[k] = m[k]
     print(json.dumps(out), flush=True)
 
 
@@ -574,8 +590,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="leave out the 3D anisotropic and the batch measurements of the benchmark line")
+                    help="leave out the 3D anisotropic, batch and serving measurements of the benchmark line")
     ap.add_argument("--batch-systems", type=int, default=4096, help="systems of the batch measurement (0: none)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of arrivals of the serving measurement in the benchmark line (0: none)")
+    ap.add_argument("--serve-rate", type=float, default=3.0, help="arrivals per second of that measurement")
     ap.add_argument("--grid", type=int, default=512, help="grid side (512 is the benchmark workload)")
     ap.add_argument("--grid3d", type=int, default=128, help="aniso3d: cells per side (0: no 3D measurement)")
     ap.add_argument("--workload", default="convdiff", choices=["convdiff", "batch", "serve", "tables", "aniso3d"],
@@ -781,6 +800,11 @@ def main():
         if args.batch_systems > 0:
             log(f"batch of {args.batch_systems} systems")
             out["batch"] = measure_batch(S, W, 2, 1, not args.no_tune, args.batch_systems)
+        if args.serve_seconds > 0:
+            # the serving stream at a rate one GPU sustains for this mix, mixed and all-FP64
+            log(f"serving stream, {args.serve_seconds} s at {args.serve_rate}/s")
+            out["serve"] = measure_serve(S, W, args.serve_rate, args.serve_seconds, 3, 20000, 128, 2000, 0,
+                                         args.ortho, True, "spawn")
     if not args.no_cpu_baseline and args.grid == 512:
         threads = min(len(os.sched_getaffinity(0)), 16)
         log(f"cpu baseline on {threads} threads")

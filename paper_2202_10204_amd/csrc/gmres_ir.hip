@@ -1256,6 +1256,461 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pipelined DCGS2 step: the step of k_arnoldi_dcgs2 with its grid-wide sum
+// split by groups of 8 basis vectors, so that pass 2 trails pass 1 by a few
+// groups instead of waiting for the whole of pass 1.  Pass 2 then re-reads
+// basis entries the same thread loaded a few microseconds before (from the
+// L2 or the memory-side cache, not from HBM), and the latency of the sums is
+// hidden behind the streaming.  Every data thread owns EPT rows (as in pass 2
+// of the two-pass launch); group g = vectors 8g .. 8g+7:
+//   pass 1: per vector l, the thread's products with (u_j, y) summed over its
+//           rows (FMA chain), a fixed tree over the wave, then the 8 waves in
+//           order by the last wave to arrive, which publishes the block's
+//           partials of a_l and b_l into the write-once slots;
+//   sums:   the poll wave of block l mod nb owns vector l: it adds the nb
+//           partials (lane-strided in block order, then a fixed tree) and
+//           writes a_l and b_l into every block's mailbox; every poll wave
+//           moves its mailbox into LDS in vector order and raises `ready`;
+//   pass 2: u_j -= a_l v_l and y -= b_l v_l for the vectors of group
+//           g - DCGS2P_LAG, ascending l, once `ready` covers them.
+// omega and c (block partials formed first) are owned by block j mod nb.  The
+// poll wave then forms nu and gj, releases the data waves for the final
+// scaling (v_j, u_{j+1}) and completes its Hessenberg rows and the Givens step
+// as in the two-pass launch.  All sums have a fixed order, so the results do
+// not depend on timing.  Deadlock-free by induction over the groups given
+// co-residency (a thread waits only for sums of groups every block has
+// already published or will publish without waiting); every wait is bounded.
+// ---------------------------------------------------------------------------
+constexpr int DCGS2P_GS = 4;                   // basis vectors per group
+constexpr int DCGS2P_LAG = 5;                  // groups between pass 1 and pass 2
+constexpr int DCGS2P_RING = DCGS2P_LAG + 2;    // wave partials of the groups in flight
+constexpr int DCGS2P_NBUF = DCGS2P_LAG + 2;    // register buffers: groups g - LAG .. g + 1
+static_assert(64 % (2 * DCGS2P_GS) == 0, "a lane set of the poll wave holds one group's values");
+
+__host__ __device__ constexpr size_t dcgs2p_lds_words(int rmax, int maxlinks, int maxit) {
+    return (size_t)rmax + (size_t)maxlinks + 2 * (size_t)maxit + (size_t)DCGS2P_RING * (AT_DATA / 64) * 2 * DCGS2P_GS;
+}
+
+// Ordering of LDS traffic between the waves of a block.  A wave's LDS
+// operations are performed in order, so a flag stored (or an atomic performed)
+// after data stores is seen after them; what must not happen is that the
+// compiler moves the accesses across each other, and a workgroup fence would
+// also wait for the wave's outstanding global loads (the prefetch of the next
+// group).  So: wait for the wave's LDS operations only (s_waitcnt lgkmcnt(0),
+// the other counters at their maximum) and a compiler barrier.
+__device__ __forceinline__ void lds_order() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __asm__ volatile("" ::: "memory");
+}
+
+// A data wave's wait for the poll wave: until *flag >= need, or the poll wave
+// gave up (its own waits are bounded); bounded too, with a bound beyond the poll
+// wave's, so that it only trips if the poll wave stopped without a word.
+__device__ __forceinline__ bool wait_lds_at_least(int* flag, int need, const int* abort_flag) {
+    long long spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+        if (++spins > 16 * SPIN_LIMIT) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    lds_order();
+    return true;
+}
+
+// Wave totals of eight values per lane at once: three halving exchanges (lanes
+// 32, 16, 8 apart: each lane keeps half of its values and adds its partner's
+// half, so that after them lane L holds value L / 8 summed over 8 lanes), then
+// the sum over the 8 lanes of each group (xor 1 and xor 2 by DPP moves, xor 4
+// by a lane permute).  Lane 8v returns the total of value v; a fixed tree.
+__device__ __forceinline__ double wave_sum8(const double (&x)[8], int lane) {
+    double c4[4], c2[2];
+    const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const double send = h32 ? x[m] : x[m + 4];
+        c4[m] = (h32 ? x[m + 4] : x[m]) + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const double send = h16 ? c4[m] : c4[m + 2];
+        c2[m] = (h16 ? c4[m + 2] : c4[m]) + __shfl_xor(send, 16, 64);
+    }
+    const double send = h8 ? c2[0] : c2[1];
+    double w = (h8 ? c2[1] : c2[0]) + dpp_mov<0x128>(send);   // row_ror:8 = lane xor 8 in a row of 16
+    w += dpp_mov<0xB1>(w);                                      // quad_perm xor 1
+    w += dpp_mov<0x4E>(w);                                      // quad_perm xor 2
+    w += __shfl_xor(w, 4, 64);
+    return w;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
+    extern __shared__ __align__(16) double dyn[];
+    __shared__ double nu_s, gj_s;
+    __shared__ double wsum2[2 * (AT_DATA / 64)];
+    __shared__ int abort_flag, ready, fin;
+    __shared__ int arrived[DCGS2P_RING];
+    if (a.st->done) return;                  // uniform: written by an earlier launch
+    if (a.by_step) {                         // graph replay: the step comes from the solver state
+        a.j = a.st->jcur;
+        a.parity = a.j & 1;
+    }
+    const int b = blockIdx.x, t = threadIdx.x, nb = a.nb, lane = t & 63, wave = t >> 6;
+    const int gstride = nb * AT_DATA;
+    const int base = b * AT_DATA + t;
+    const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
+    constexpr int DW = AT_DATA / 64;
+    // LDS (dcgs2p_lds_words): totals hv (a_l = hv[l], omega = hv[j], b_l = hv[j+1+l],
+    // c = hv[2j+1]), the Hessenberg column, cs, sn, the wave partials [RING][DW][2 GS]
+    double* hv = dyn;
+    double* hh = hv + rmax;
+    double* csL = hh + a.maxlinks;
+    double* snL = csL + a.maxit;
+    double* wpart = snL + a.maxit;
+    const size_t pw = dcgs2_parity_words(a.maxlinks, nb);
+    unsigned long long* cur = a.slots + (size_t)a.parity * pw;
+    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * pw;
+    const size_t blk = (size_t)rmax * nb;
+    unsigned long long* slots = cur;         // [rmax][nb]
+    unsigned long long* mbox = cur + blk;    // [nb][rmax]
+    // re-arm this block's words of the other buffer for the next launch (2j + 4 values)
+    for (int r = t; r < min(R + 2, rmax); r += AT) {
+        nxt[(size_t)r * nb + b] = SENTINEL;
+        nxt[blk + (size_t)b * rmax + r] = SENTINEL;
+    }
+    if (t == 0) {
+        abort_flag = 0;
+        ready = 0;
+        fin = 0;
+    }
+    if (t < DCGS2P_RING) arrived[t] = 0;
+    if (b == 0) {
+        for (int l = t; l + 1 < j; l += AT) {
+            csL[l] = a.cs[l];
+            snL[l] = a.sn[l];
+        }
+        if (wave == DW)                       // first projections of column j - 1
+            for (int l = lane; l < j; l += 64) hh[l] = a.HRp[(size_t)(j - 1) * a.ld + l];
+    }
+    constexpr int GS = DCGS2P_GS, GV = 2 * GS;   // vectors and values per group
+    const int G = (j + GS - 1) / GS;
+    double u[EPT], yv[EPT];
+    if (wave < DW) {
+        const double* uj = a.V + (size_t)j * n;
+        double om = 0.0, c = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = base + e * gstride;
+            const bool ok = i < n;
+            u[e] = ld0(uj, i, ok);
+            yv[e] = ld0(a.y, i, ok);
+            om = __builtin_fma(u[e], u[e], om);
+            c = __builtin_fma(u[e], yv[e], c);
+        }
+        om = wave_sum(om);
+        c = wave_sum(c);
+        if (lane == 0) {
+            wsum2[2 * wave] = om;
+            wsum2[2 * wave + 1] = c;
+        }
+    }
+    __syncthreads();
+    if (wave == DW) {
+        // ---- poll wave: block partials of omega and c, the sums, then the bookkeeping ----
+        __builtin_amdgcn_s_setprio(3);
+        if (lane == 0) {
+            double om = 0.0, c = 0.0;
+            for (int w = 0; w < DW; ++w) {
+                om += wsum2[2 * w];
+                c += wsum2[2 * w + 1];
+            }
+            __hip_atomic_store(&slots[(size_t)j * nb + b], (unsigned long long)__double_as_longlong(om),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&slots[(size_t)(2 * j + 1) * nb + b], (unsigned long long)__double_as_longlong(c),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // An event loop, so that no single wait holds up the others: each pass
+        // polls (once, without waiting) the mailbox words of four groups at a time
+        // (lanes 16q .. 16q + 15 take the groups q, q + 4, ... in order, lane 16q + k
+        // the value k of its group: a_l for even k, b_l for odd k) and the slots of
+        // the next column this block owns (columns b, b + nb, ..., then omega and c
+        // as column j); `ready` is raised to the groups complete in every lane set.
+        constexpr int SETS = 64 / GV;
+        const int q4 = lane / GV, k16 = lane % GV;
+        int gq = q4;                          // this lane set's group
+        bool have = false;                    // this lane's value of group gq is in hv
+        int own = b < j ? b : (j % nb == b ? j : -1);   // next owned column (j: omega and c)
+        unsigned long long ov[8];             // owned column: partials of sources lane, lane + 64, ... (a, b)
+        unsigned omask = 0u;
+        bool ready_c = false;                 // omega and c are in hv
+        long long idle = 0;
+        bool to = false;
+        const unsigned omask_all = [&] {
+            unsigned m = 0u;
+            for (int s4 = 0; s4 < 4; ++s4)
+                if (lane + 64 * s4 < nb) m |= 3u << (2 * s4);
+            return m;
+        }();
+        for (;;) {
+            bool progress = false;
+            // mailbox words of the lane sets' groups
+            if (gq < G) {
+                const int l = GS * gq + (k16 >> 1);
+                if (l < j && !have) {
+                    const int r = (k16 & 1) ? j + 1 + l : l;
+                    const unsigned long long v =
+                        __hip_atomic_load(&mbox[(size_t)b * rmax + r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (v != SENTINEL) {
+                        hv[r] = __longlong_as_double((long long)v);
+                        have = true;
+                    }
+                }
+                if (l >= j) have = true;
+            }
+            if (!ready_c && lane < 2) {
+                const int r = lane ? 2 * j + 1 : j;
+                const unsigned long long v =
+                    __hip_atomic_load(&mbox[(size_t)b * rmax + r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v != SENTINEL) hv[r] = __longlong_as_double((long long)v);
+                ready_c = v != SENTINEL;
+            }
+            ready_c = (__builtin_amdgcn_ballot_w64(ready_c) & 3ull) == 3ull;
+            // a lane set whose group is complete moves to its next group
+            const unsigned long long hb = __builtin_amdgcn_ballot_w64(have || gq >= G);
+            constexpr unsigned long long SETMASK = GV == 64 ? ~0ull : ((1ull << GV) - 1ull);
+            const bool set_done = ((hb >> (GV * q4)) & SETMASK) == SETMASK;
+            if (set_done && gq < G) {
+                gq += SETS;
+                have = false;
+                progress = true;
+            }
+            // groups complete in every set: the smallest group a set still waits for
+            int gmin = gq;
+#pragma unroll
+            for (int off = GV; off < 64; off <<= 1) gmin = min(gmin, __shfl_xor(gmin, off, 64));
+            const int rdy = min(GS * min(gmin, G), j);
+            lds_order();
+            if (lane == 0 && rdy > __hip_atomic_load(&ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                __hip_atomic_store(&ready, rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // the owned column: its partials, then the totals into every mailbox
+            if (own >= 0) {
+                const int r1 = own < j ? own : j, r2 = own < j ? j + 1 + own : 2 * j + 1;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const int src = lane + 64 * s4;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const unsigned bit = 1u << (2 * s4 + h);
+                        if (src < nb && !(omask & bit)) {
+                            const unsigned long long v = __hip_atomic_load(
+                                &slots[(size_t)(h ? r2 : r1) * nb + src], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            if (v != SENTINEL) {
+                                ov[2 * s4 + h] = v;
+                                omask |= bit;
+                            }
+                        }
+                    }
+                }
+                if (__builtin_amdgcn_ballot_w64(omask != omask_all) == 0ull) {
+                    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4)
+                        if (lane + 64 * s4 < nb) {
+                            s1 += __longlong_as_double((long long)ov[2 * s4]);
+                            s2 += __longlong_as_double((long long)ov[2 * s4 + 1]);
+                        }
+                    s1 = wave_sum(s1);
+                    s2 = wave_sum(s2);
+                    const unsigned long long w1 = (unsigned long long)__double_as_longlong(s1);
+                    const unsigned long long w2 = (unsigned long long)__double_as_longlong(s2);
+                    for (int q = lane; q < nb; q += 64) {
+                        __hip_atomic_store(&mbox[(size_t)q * rmax + r1], w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&mbox[(size_t)q * rmax + r2], w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    omask = 0u;
+                    own = own == j ? -1 : (own + nb < j ? own + nb : (j % nb == b ? j : -1));
+                    progress = true;
+                }
+            }
+            if (gmin >= G && ready_c && own < 0) break;
+            if (progress) {
+                idle = 0;
+            } else {
+                if (++idle > SPIN_LIMIT) {
+                    to = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (to) {
+            if (lane == 0) {
+                __hip_atomic_store(&abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                a.st->err = 1;
+                a.st->done = 3;
+            }
+            return;
+        }
+        lds_order();
+        double q = 0.0, ab = 0.0;
+        for (int l = lane; l < j; l += 64) {
+            q = __builtin_fma(hv[l], hv[l], q);
+            ab = __builtin_fma(hv[l], hv[j + 1 + l], ab);
+        }
+        q = wave_sum(q);
+        ab = wave_sum(ab);
+        double nu = 1.0;
+        if (j > 0) {
+            double qq = hv[j] - q;
+            nu = qq > 0.0 ? __builtin_sqrt(qq) : 0.0;
+        }
+        const double gj = (hv[2 * j + 1] - ab) / nu;
+        if (lane == 0) {
+            nu_s = nu;
+            gj_s = gj;
+        }
+        lds_order();
+        if (lane == 0) __hip_atomic_store(&fin, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        dcgs2_rows(a, hv, nu, gj);
+        if (b == 0 && j >= 1) dcgs2_givens(a, hv, nu, hh, csL, snL);
+        // every block read the step index before publishing its partial sums,
+        // which this block has received: the next launch's index can be set
+        if (a.by_step && b == 0 && lane == 0) a.st->jcur = j + 1;
+        __builtin_amdgcn_s_setprio(0);
+        return;
+    }
+    // ---- data waves: pass 1 of group g and pass 2 of group g - LAG ----
+    const bool update = j < a.maxit;         // launch maxit only completes column maxit - 1
+    double au[EPT], ay[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        au[e] = u[e];
+        ay[e] = yv[e];
+    }
+    // loads of group gl's vectors at the thread's rows (a vector past j - 1 reads vector 0, unused)
+    auto load_group = [&](int gl, double (&v)[GS][EPT]) {
+#pragma unroll
+        for (int c = 0; c < GS; ++c) {
+            const int l = GS * gl + c;
+            const double* col = a.V + (size_t)(l < j ? l : 0) * n;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int i = base + e * gstride;
+                v[c][e] = col[pf_index(i, i < n)];
+            }
+        }
+    };
+    // one step g: the loads of group g + 1 into vn, pass 1 of group g from vc
+    // (loaded the step before), pass 2 of group g - LAG from vp, the values this
+    // thread loaded for that group's pass 1 (so the basis is read once from
+    // memory); LAG + 2 buffers in turn, one loop trip per LAG + 2 steps
+    bool ok = true;
+    auto step = [&](int g, double (&vc)[GS][EPT], double (&vn)[GS][EPT], double (&vp)[GS][EPT]) {
+        const int g2 = g - DCGS2P_LAG;
+        if (g + 1 < G) load_group(g + 1, vn);
+        if (g < G) {
+            const int ring = g % DCGS2P_RING;
+            double* wp = wpart + ((size_t)ring * DW + wave) * GV;
+            static_assert(GV == 8, "wave_sum8 reduces the 8 values of a group of 4 vectors");
+            double pv[GV];
+#pragma unroll
+            for (int c = 0; c < GS; ++c) {
+                double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    const int i = base + e * gstride;
+                    const double vv = i < n ? vc[c][e] : 0.0;
+                    p1 = __builtin_fma(vv, u[e], p1);
+                    p2 = __builtin_fma(vv, yv[e], p2);
+                }
+                pv[2 * c] = p1;
+                pv[2 * c + 1] = p2;
+            }
+            const double tot = wave_sum8(pv, lane);
+            if ((lane & 7) == 0) wp[lane >> 3] = tot;
+            lds_order();
+            int old = 0;
+            if (lane == 0) old = __hip_atomic_fetch_add(&arrived[ring], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old == DW - 1) {
+                // the last wave of the block to finish the group: the block's partials, waves in order
+                lds_order();
+                if (lane < GV) {
+                    const int c = lane >> 1, l = GS * g + c;
+                    double sum = 0.0;
+                    for (int w = 0; w < DW; ++w) sum += wpart[((size_t)ring * DW + w) * GV + lane];
+                    if (l < j) {
+                        const int r = (lane & 1) ? j + 1 + l : l;
+                        __hip_atomic_store(&slots[(size_t)r * nb + b], (unsigned long long)__double_as_longlong(sum),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                lds_order();
+                if (lane == 0) __hip_atomic_store(&arrived[ring], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        if (g2 >= 0) {
+            // the wait also paces the waves of the block when pass 2 is skipped: no
+            // wave runs more than DCGS2P_LAG + 1 groups ahead of the block's last
+            // published group, so a ring entry is free again before its next use
+            const int l0 = GS * g2;
+            if (!wait_lds_at_least(&ready, min(l0 + GS, j), &abort_flag)) {
+                ok = false;
+                return;
+            }
+            if (update) {
+#pragma unroll
+                for (int c = 0; c < GS; ++c) {
+                    const int l = l0 + c;
+                    if (l < j) {
+                        const double al = hv[l], bl = hv[j + 1 + l];
+#pragma unroll
+                        for (int e = 0; e < EPT; ++e) {
+                            au[e] = __builtin_fma(-al, vp[c][e], au[e]);
+                            ay[e] = __builtin_fma(-bl, vp[c][e], ay[e]);
+                        }
+                    }
+                }
+            }
+        }
+    };
+    constexpr int NBUF = DCGS2P_NBUF;
+    double B[NBUF][GS][EPT];
+    if (G > 0) load_group(0, B[0]);
+    for (int g = 0; g < G + DCGS2P_LAG && ok; g += NBUF) {
+#pragma unroll
+        for (int k = 0; k < NBUF; ++k)
+            if (ok && g + k < G + DCGS2P_LAG)
+                step(g + k, B[k], B[(k + 1) % NBUF], B[(k + NBUF - DCGS2P_LAG) % NBUF]);
+    }
+    if (!ok) {
+        if (lane == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    if (!update) return;
+    if (!wait_lds_at_least(&fin, 1, &abort_flag)) {
+        if (lane == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    const double nu = nu_s, gj = gj_s;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = base + e * gstride;
+        if (i < n) {
+            const double v = j > 0 ? au[e] / nu : au[e];
+            if (j > 0) a.V[(size_t)j * n + i] = v;
+            a.V[(size_t)(j + 1) * n + i] = __builtin_fma(-gj, v, ay[e]) / nu;
+        }
+    }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, size_t len, unsigned long long v) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) p[i] = v;
@@ -1668,11 +2123,25 @@ struct ArnoldiCfg {
     size_t slot_words = 0;   // both parities
 };
 
+// DCGS2 with at most 2 rows per thread runs the pipelined launch unless
+// SPAI_DCGS2=twopass selects the two-pass one (both give the same iterates up to
+// the order of their sums)
+static bool dcgs2_pipelined() {
+    static const bool p = [] {
+        const char* e = getenv("SPAI_DCGS2");
+        return !(e && std::string(e) == "twopass");
+    }();
+    return p;
+}
+
 template <int EPT>
 static const void* arnoldi_fn(int ortho) {
     switch (ortho) {
     case SPAI_ORTHO_CGS2: return (const void*)k_arnoldi_cgs2<EPT>;
-    case SPAI_ORTHO_DCGS2: return (const void*)k_arnoldi_dcgs2<EPT>;
+    case SPAI_ORTHO_DCGS2:
+        if constexpr (EPT <= 2)
+            if (dcgs2_pipelined()) return (const void*)k_arnoldi_dcgs2p<EPT>;
+        return (const void*)k_arnoldi_dcgs2<EPT>;
     default: return (const void*)k_arnoldi<EPT>;
     }
 }
@@ -1718,7 +2187,8 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
         c.shmem = sizeof(double) * ((size_t)(AT_DATA / 64 + 4) * maxlinks + nb + 2 * (size_t)maxit);
         c.slot_words = 2 * cgs2_parity_words(maxlinks, nb);
     } else if (ortho == SPAI_ORTHO_DCGS2) {
-        c.shmem = sizeof(double) * dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit);
+        c.shmem = sizeof(double) * (ept <= 2 && dcgs2_pipelined() ? dcgs2p_lds_words(2 * maxlinks, maxlinks, maxit)
+                                                                  : dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit));
         c.slot_words = 2 * dcgs2_parity_words(maxlinks, nb);
     } else {
         c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);

@@ -554,19 +554,23 @@ def test_full_size_solve_other_orthogonalisations_match_oracle_tuple(S, h, full,
     assert O.ferr(x, w.x_true) <= 1e-12
 
 
-def test_dcgs2_maxit_cap(S, h):
+@pytest.mark.parametrize("maxit,tau", [(12, None), (64, 0.0)])
+def test_dcgs2_maxit_cap(S, h, maxit, tau):
     """Delayed CGS2 when GMRES stops at maxit: the completing launch j = maxit
-    reports SPAI_W_MAXIT and the same iterations as the oracle."""
+    (which skips the update and, in the pipelined launch, still paces its waves
+    group by group: 64 = 8 groups of basis vectors) reports SPAI_W_MAXIT and the
+    same iterations as the oracle."""
     w = W.convdiff_adaptive(40)
     A, P, warn, stats = _build(S, h, w)
     s, ir = w.spai, w.ir
+    tau = ir.tau if tau is None else tau
     ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
     pp, pc, pv = ref.P_csr(w.n)
-    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, 3, 12, ir.tol_ir, "dcgs2")
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, tau, 3, maxit, ir.tol_ir, "dcgs2")
     b = _dev(w.b)
     x = torch.zeros_like(b)
-    st = h.gmres_ir(A, P, b, x, ir.tau, 3, 12, ir.tol_ir, "dd", "dcgs2")
-    assert st["its"] == oref.its == [12] * len(oref.its)
+    st = h.gmres_ir(A, P, b, x, tau, 3, maxit, ir.tol_ir, "dd", "dcgs2")
+    assert st["its"] == oref.its == [maxit] * len(oref.its)
     assert st["status"] & S.W_MAXIT
     assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
 

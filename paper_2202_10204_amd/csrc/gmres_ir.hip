@@ -1258,12 +1258,14 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
 
 // ---------------------------------------------------------------------------
 // Pipelined DCGS2 step: the step of k_arnoldi_dcgs2 with its grid-wide sum
-// split by groups of 8 basis vectors, so that pass 2 trails pass 1 by a few
-// groups instead of waiting for the whole of pass 1.  Pass 2 then re-reads
-// basis entries the same thread loaded a few microseconds before (from the
-// L2 or the memory-side cache, not from HBM), and the latency of the sums is
-// hidden behind the streaming.  Every data thread owns EPT rows (as in pass 2
-// of the two-pass launch); group g = vectors 8g .. 8g+7:
+// split by groups of DCGS2P_GS basis vectors, so that pass 2 trails pass 1 by
+// LAG groups instead of waiting for the whole of pass 1.  A thread keeps the
+// basis entries it loaded for a group's pass 1 (in registers for DCGS2P_LAG
+// groups, then, where the LDS holds them, in its own LDS words for NL more)
+// and runs that group's pass 2 on them, so the basis is read from memory once
+// per step; the latency of the sums is hidden behind the streaming of the
+// next LAG groups.  Every data thread owns EPT rows (as in pass 2 of the
+// two-pass launch); group g = vectors GS g .. GS g + GS - 1:
 //   pass 1: per vector l, the thread's products with (u_j, y) summed over its
 //           rows (FMA chain), a fixed tree over the wave, then the 8 waves in
 //           order by the last wave to arrive, which publishes the block's
@@ -1273,7 +1275,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
 //           writes a_l and b_l into every block's mailbox; every poll wave
 //           moves its mailbox into LDS in vector order and raises `ready`;
 //   pass 2: u_j -= a_l v_l and y -= b_l v_l for the vectors of group
-//           g - DCGS2P_LAG, ascending l, once `ready` covers them.
+//           g - LAG, ascending l, once `ready` covers them.
 // omega and c (block partials formed first) are owned by block j mod nb.  The
 // poll wave then forms nu and gj, releases the data waves for the final
 // scaling (v_j, u_{j+1}) and completes its Hessenberg rows and the Givens step
@@ -1283,13 +1285,19 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
 // already published or will publish without waiting); every wait is bounded.
 // ---------------------------------------------------------------------------
 constexpr int DCGS2P_GS = 4;                   // basis vectors per group
-constexpr int DCGS2P_LAG = 5;                  // groups between pass 1 and pass 2
-constexpr int DCGS2P_RING = DCGS2P_LAG + 2;    // wave partials of the groups in flight
+constexpr int DCGS2P_LAG = 5;                  // groups a thread keeps in registers after their pass 1
 constexpr int DCGS2P_NBUF = DCGS2P_LAG + 2;    // register buffers: groups g - LAG .. g + 1
 static_assert(64 % (2 * DCGS2P_GS) == 0, "a lane set of the poll wave holds one group's values");
+// LDS slots that extend the lag: a thread moves the oldest group of its register
+// ring into LDS instead of running its pass 2 at once, and pass 2 reads it back
+// NL groups later (128 KB of LDS per block at either EPT); NL = 0: no extension
+template <int EPT>
+constexpr int dcgs2p_nl_ext() { return 8 / EPT; }
+__host__ __device__ constexpr int dcgs2p_ring(int nl) { return DCGS2P_LAG + nl + 2; }   // wave partials in flight
 
-__host__ __device__ constexpr size_t dcgs2p_lds_words(int rmax, int maxlinks, int maxit) {
-    return (size_t)rmax + (size_t)maxlinks + 2 * (size_t)maxit + (size_t)DCGS2P_RING * (AT_DATA / 64) * 2 * DCGS2P_GS;
+__host__ __device__ constexpr size_t dcgs2p_lds_words(int rmax, int maxlinks, int maxit, int nl, int ept) {
+    return (size_t)rmax + (size_t)maxlinks + 2 * (size_t)maxit +
+           (size_t)dcgs2p_ring(nl) * (AT_DATA / 64) * 2 * DCGS2P_GS + (size_t)nl * DCGS2P_GS * ept * AT_DATA;
 }
 
 // Ordering of LDS traffic between the waves of a block.  A wave's LDS
@@ -1344,13 +1352,15 @@ __device__ __forceinline__ double wave_sum8(const double (&x)[8], int lane) {
     return w;
 }
 
-template <int EPT>
+template <int EPT, int NL>
 __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
+    constexpr int RING = dcgs2p_ring(NL);
+    constexpr int LAG = DCGS2P_LAG + NL;     // groups between pass 1 and pass 2
     extern __shared__ __align__(16) double dyn[];
     __shared__ double nu_s, gj_s;
     __shared__ double wsum2[2 * (AT_DATA / 64)];
     __shared__ int abort_flag, ready, fin;
-    __shared__ int arrived[DCGS2P_RING];
+    __shared__ int arrived[RING];
     if (a.st->done) return;                  // uniform: written by an earlier launch
     if (a.by_step) {                         // graph replay: the step comes from the solver state
         a.j = a.st->jcur;
@@ -1362,12 +1372,14 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
     constexpr int DW = AT_DATA / 64;
     // LDS (dcgs2p_lds_words): totals hv (a_l = hv[l], omega = hv[j], b_l = hv[j+1+l],
-    // c = hv[2j+1]), the Hessenberg column, cs, sn, the wave partials [RING][DW][2 GS]
+    // c = hv[2j+1]), the Hessenberg column, cs, sn, the wave partials [RING][DW][2 GS],
+    // the lag extension [NL][GS * EPT][AT_DATA] (a thread's own words)
     double* hv = dyn;
     double* hh = hv + rmax;
     double* csL = hh + a.maxlinks;
     double* snL = csL + a.maxit;
     double* wpart = snL + a.maxit;
+    double* ext = wpart + (size_t)RING * (AT_DATA / 64) * 2 * DCGS2P_GS;
     const size_t pw = dcgs2_parity_words(a.maxlinks, nb);
     unsigned long long* cur = a.slots + (size_t)a.parity * pw;
     unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * pw;
@@ -1384,7 +1396,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         ready = 0;
         fin = 0;
     }
-    if (t < DCGS2P_RING) arrived[t] = 0;
+    if (t < RING) arrived[t] = 0;
     if (b == 0) {
         for (int l = t; l + 1 < j; l += AT) {
             csL[l] = a.cs[l];
@@ -1431,8 +1443,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         // An event loop, so that no single wait holds up the others: each pass
-        // polls (once, without waiting) the mailbox words of four groups at a time
-        // (lanes 16q .. 16q + 15 take the groups q, q + 4, ... in order, lane 16q + k
+        // polls (once, without waiting) the mailbox words of eight groups at a time
+        // (lanes 8q .. 8q + 7 take the groups q, q + 8, ... in order, lane 8q + k
         // the value k of its group: a_l for even k, b_l for odd k) and the slots of
         // the next column this block owns (columns b, b + nb, ..., then omega and c
         // as column j); `ready` is raised to the groups complete in every lane set.
@@ -1454,26 +1466,37 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         }();
         for (;;) {
             bool progress = false;
-            // mailbox words of the lane sets' groups
-            if (gq < G) {
-                const int l = GS * gq + (k16 >> 1);
-                if (l < j && !have) {
-                    const int r = (k16 & 1) ? j + 1 + l : l;
-                    const unsigned long long v =
-                        __hip_atomic_load(&mbox[(size_t)b * rmax + r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (v != SENTINEL) {
-                        hv[r] = __longlong_as_double((long long)v);
-                        have = true;
-                    }
+            // every load of the pass is issued before any of them is used, so that
+            // one memory round trip serves the mailbox words of the lane sets'
+            // groups, omega and c, and the partials of the owned column
+            const int l = GS * gq + (k16 >> 1);
+            const bool want_m = gq < G && l < j && !have;
+            const int rm = (k16 & 1) ? j + 1 + l : l;
+            const bool want_c = !ready_c && lane < 2;
+            const int rc = lane ? 2 * j + 1 : j;
+            const int r1 = own < j ? own : j, r2 = own < j ? j + 1 + own : 2 * j + 1;
+            unsigned long long mv = SENTINEL, cv = SENTINEL, nv[8];
+            if (want_m) mv = __hip_atomic_load(&mbox[(size_t)b * rmax + rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (want_c) cv = __hip_atomic_load(&mbox[(size_t)b * rmax + rc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int src = lane + 64 * s4;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    nv[2 * s4 + h] = SENTINEL;
+                    if (own >= 0 && src < nb && !(omask & (1u << (2 * s4 + h))))
+                        nv[2 * s4 + h] = __hip_atomic_load(&slots[(size_t)(h ? r2 : r1) * nb + src], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
                 }
-                if (l >= j) have = true;
             }
-            if (!ready_c && lane < 2) {
-                const int r = lane ? 2 * j + 1 : j;
-                const unsigned long long v =
-                    __hip_atomic_load(&mbox[(size_t)b * rmax + r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (v != SENTINEL) hv[r] = __longlong_as_double((long long)v);
-                ready_c = v != SENTINEL;
+            if (want_m && mv != SENTINEL) {
+                hv[rm] = __longlong_as_double((long long)mv);
+                have = true;
+            }
+            if (gq < G && l >= j) have = true;
+            if (want_c) {
+                if (cv != SENTINEL) hv[rc] = __longlong_as_double((long long)cv);
+                ready_c = cv != SENTINEL;
             }
             ready_c = (__builtin_amdgcn_ballot_w64(ready_c) & 3ull) == 3ull;
             // a lane set whose group is complete moves to its next group
@@ -1495,23 +1518,12 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
                 __hip_atomic_store(&ready, rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             // the owned column: its partials, then the totals into every mailbox
             if (own >= 0) {
-                const int r1 = own < j ? own : j, r2 = own < j ? j + 1 + own : 2 * j + 1;
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    const int src = lane + 64 * s4;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const unsigned bit = 1u << (2 * s4 + h);
-                        if (src < nb && !(omask & bit)) {
-                            const unsigned long long v = __hip_atomic_load(
-                                &slots[(size_t)(h ? r2 : r1) * nb + src], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            if (v != SENTINEL) {
-                                ov[2 * s4 + h] = v;
-                                omask |= bit;
-                            }
-                        }
+                for (int k = 0; k < 8; ++k)
+                    if (nv[k] != SENTINEL) {
+                        ov[k] = nv[k];
+                        omask |= 1u << k;
                     }
-                }
                 if (__builtin_amdgcn_ballot_w64(omask != omask_all) == 0ull) {
                     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -1602,15 +1614,21 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         }
     };
     // one step g: the loads of group g + 1 into vn, pass 1 of group g from vc
-    // (loaded the step before), pass 2 of group g - LAG from vp, the values this
+    // (loaded the step before), pass 2 of group g - LAG from the values this
     // thread loaded for that group's pass 1 (so the basis is read once from
-    // memory); LAG + 2 buffers in turn, one loop trip per LAG + 2 steps
+    // memory): from vp, the register buffer of group g - DCGS2P_LAG, or with the
+    // LDS extension from its LDS slot, into which vp then moves;
+    // DCGS2P_LAG + 2 register buffers in turn, one loop trip per DCGS2P_LAG + 2 steps
     bool ok = true;
+    double* mine = ext + t;                  // this thread's LDS words: [slot][GS * EPT] stride AT_DATA
     auto step = [&](int g, double (&vc)[GS][EPT], double (&vn)[GS][EPT], double (&vp)[GS][EPT]) {
-        const int g2 = g - DCGS2P_LAG;
-        if (g + 1 < G) load_group(g + 1, vn);
+        const int g2 = g - LAG;
+        // unconditional (past the last group the loads fall on vector 0): a load
+        // under a branch makes the compiler's wait counts assume the loads of the
+        // step before are the most recent, so pass 1 would wait for every load
+        load_group(g + 1, vn);
         if (g < G) {
-            const int ring = g % DCGS2P_RING;
+            const int ring = g % RING;
             double* wp = wpart + ((size_t)ring * DW + wave) * GV;
             static_assert(GV == 8, "wave_sum8 reduces the 8 values of a group of 4 vectors");
             double pv[GV];
@@ -1652,14 +1670,18 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         }
         if (g2 >= 0) {
             // the wait also paces the waves of the block when pass 2 is skipped: no
-            // wave runs more than DCGS2P_LAG + 1 groups ahead of the block's last
+            // wave runs more than LAG + 1 groups ahead of the block's last
             // published group, so a ring entry is free again before its next use
             const int l0 = GS * g2;
-            if (!wait_lds_at_least(&ready, min(l0 + GS, j), &abort_flag)) {
-                ok = false;
-                return;
-            }
-            if (update) {
+            if (ok && !wait_lds_at_least(&ready, min(l0 + GS, j), &abort_flag)) ok = false;
+            if (update && ok) {
+                double w[GS][EPT];
+#pragma unroll
+                for (int c = 0; c < GS; ++c)
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e)
+                        w[c][e] = NL > 0 ? mine[((size_t)(g2 % (NL > 0 ? NL : 1)) * GS * EPT + c * EPT + e) * AT_DATA]
+                                         : vp[c][e];
 #pragma unroll
                 for (int c = 0; c < GS; ++c) {
                     const int l = l0 + c;
@@ -1667,22 +1689,33 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
                         const double al = hv[l], bl = hv[j + 1 + l];
 #pragma unroll
                         for (int e = 0; e < EPT; ++e) {
-                            au[e] = __builtin_fma(-al, vp[c][e], au[e]);
-                            ay[e] = __builtin_fma(-bl, vp[c][e], ay[e]);
+                            au[e] = __builtin_fma(-al, w[c][e], au[e]);
+                            ay[e] = __builtin_fma(-bl, w[c][e], ay[e]);
                         }
                     }
                 }
             }
         }
+        if constexpr (NL > 0) {
+            // the oldest register group moves into the slot just read (g2 = gr - NL)
+            const int gr = g - DCGS2P_LAG;
+            if (update && ok && gr >= 0 && gr < G)
+#pragma unroll
+                for (int c = 0; c < GS; ++c)
+#pragma unroll
+                    for (int e = 0; e < EPT; ++e)
+                        mine[((size_t)(gr % NL) * GS * EPT + c * EPT + e) * AT_DATA] = vp[c][e];
+        }
     };
     constexpr int NBUF = DCGS2P_NBUF;
     double B[NBUF][GS][EPT];
-    if (G > 0) load_group(0, B[0]);
-    for (int g = 0; g < G + DCGS2P_LAG && ok; g += NBUF) {
+    load_group(0, B[0]);
+    for (int g = 0; g < G + LAG && ok; g += NBUF) {
+        // whole trips, no step under a branch (see load_group above): a step past
+        // G + LAG - 1 has no pass 1, no pass 2 and nothing to move, and its wait
+        // is for all j sums, which every block receives
 #pragma unroll
-        for (int k = 0; k < NBUF; ++k)
-            if (ok && g + k < G + DCGS2P_LAG)
-                step(g + k, B[k], B[(k + 1) % NBUF], B[(k + NBUF - DCGS2P_LAG) % NBUF]);
+        for (int k = 0; k < NBUF; ++k) step(g + k, B[k], B[(k + 1) % NBUF], B[(k + NBUF - DCGS2P_LAG) % NBUF]);
     }
     if (!ok) {
         if (lane == 0) {
@@ -2119,6 +2152,7 @@ struct ArnoldiCfg {
     int nb = 0;
     int ept = 0;
     int ortho = SPAI_ORTHO_MGS;
+    bool ext = false;        // pipelined DCGS2: the lag extended through LDS
     size_t shmem = 0;
     size_t slot_words = 0;   // both parities
 };
@@ -2134,25 +2168,36 @@ static bool dcgs2_pipelined() {
     return p;
 }
 
+// SPAI_DCGS2_LDS=0 keeps the pipelined launch's lag to its register ring
+static bool dcgs2_lds_ext() {
+    static const bool x = [] {
+        const char* e = getenv("SPAI_DCGS2_LDS");
+        return !(e && std::string(e) == "0");
+    }();
+    return x;
+}
+
 template <int EPT>
-static const void* arnoldi_fn(int ortho) {
+static const void* arnoldi_fn(int ortho, bool ext) {
     switch (ortho) {
     case SPAI_ORTHO_CGS2: return (const void*)k_arnoldi_cgs2<EPT>;
     case SPAI_ORTHO_DCGS2:
         if constexpr (EPT <= 2)
-            if (dcgs2_pipelined()) return (const void*)k_arnoldi_dcgs2p<EPT>;
+            if (dcgs2_pipelined())
+                return ext ? (const void*)k_arnoldi_dcgs2p<EPT, dcgs2p_nl_ext<EPT>()>
+                           : (const void*)k_arnoldi_dcgs2p<EPT, 0>;
         return (const void*)k_arnoldi_dcgs2<EPT>;
     default: return (const void*)k_arnoldi<EPT>;
     }
 }
 
-static const void* arnoldi_fn(int ortho, int ept) {
+static const void* arnoldi_fn(int ortho, int ept, bool ext) {
     switch (ept) {
-    case 1: return arnoldi_fn<1>(ortho);
-    case 2: return arnoldi_fn<2>(ortho);
-    case 4: return arnoldi_fn<4>(ortho);
-    case 8: return arnoldi_fn<8>(ortho);
-    default: return arnoldi_fn<16>(ortho);
+    case 1: return arnoldi_fn<1>(ortho, ext);
+    case 2: return arnoldi_fn<2>(ortho, ext);
+    case 4: return arnoldi_fn<4>(ortho, ext);
+    case 8: return arnoldi_fn<8>(ortho, ext);
+    default: return arnoldi_fn<16>(ortho, ext);
     }
 }
 
@@ -2187,15 +2232,22 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
         c.shmem = sizeof(double) * ((size_t)(AT_DATA / 64 + 4) * maxlinks + nb + 2 * (size_t)maxit);
         c.slot_words = 2 * cgs2_parity_words(maxlinks, nb);
     } else if (ortho == SPAI_ORTHO_DCGS2) {
-        c.shmem = sizeof(double) * (ept <= 2 && dcgs2_pipelined() ? dcgs2p_lds_words(2 * maxlinks, maxlinks, maxit)
-                                                                  : dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit));
+        if (ept <= 2 && dcgs2_pipelined()) {
+            // the LDS extension of the lag where it fits beside the per-step arrays
+            const int nl = ept == 1 ? dcgs2p_nl_ext<1>() : dcgs2p_nl_ext<2>();
+            c.shmem = sizeof(double) * dcgs2p_lds_words(2 * maxlinks, maxlinks, maxit, nl, ept);
+            c.ext = dcgs2_lds_ext() && c.shmem <= 159 * 1024;
+            if (!c.ext) c.shmem = sizeof(double) * dcgs2p_lds_words(2 * maxlinks, maxlinks, maxit, 0, ept);
+        } else {
+            c.shmem = sizeof(double) * dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit);
+        }
         c.slot_words = 2 * dcgs2_parity_words(maxlinks, nb);
     } else {
         c.shmem = sizeof(double) * (size_t)(3 * maxit + 2);
         c.slot_words = (size_t)2 * maxlinks * nb * (1 + MBOX_STRIDE);
     }
     if (c.shmem > 159 * 1024) return ArnoldiCfg{};   // 160 KB of LDS per CU, 1 KB for static arrays
-    const void* fn = arnoldi_fn(ortho, ept);
+    const void* fn = arnoldi_fn(ortho, ept, c.ext);
     if (c.shmem > 48 * 1024 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.shmem) != hipSuccess) {
         (void)hipGetLastError();
@@ -2236,7 +2288,7 @@ static bool use_cooperative_launch() {
 
 static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, hipStream_t s) {
     void* args[] = {&a};
-    const void* fn = arnoldi_fn(c.ortho, c.ept);
+    const void* fn = arnoldi_fn(c.ortho, c.ept, c.ext);
     long tk = timer_begin(h, SPAI_KT_MGS);
     hipError_t e = use_cooperative_launch() ? hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s)
                                             : hipLaunchKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);

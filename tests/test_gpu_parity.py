@@ -575,6 +575,24 @@ def test_dcgs2_maxit_cap(S, h, maxit, tau):
     assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
 
 
+def test_dcgs2_long_restart(S, h):
+    """Delayed CGS2 with room for 640 basis vectors per restart: the per-step
+    arrays then leave no LDS for the lag extension of the pipelined launch,
+    which keeps its register lag; the iterations and the solution are the
+    oracle's (the default maxit runs the extended lag in the other tests)."""
+    w = W.convdiff_adaptive(40)
+    A, P, warn, stats = _build(S, h, w)
+    s, ir = w.spai, w.ir
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, 640, ir.tol_ir, "dcgs2")
+    b = _dev(w.b)
+    x = torch.zeros_like(b)
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, 640, ir.tol_ir, "dd", "dcgs2")
+    assert st["its"] == oref.its
+    assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
+
+
 # ---------------------------------------------------------------------------
 # 3D anisotropic diffusion at full size (128^3, n = 2,097,152, pattern(A^2)
 # capped at 27 entries per column: nnz(P) = 51,742,208)

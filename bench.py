@@ -43,7 +43,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def arnoldi_bytes_per_solve(its, n, ortho):
+def arnoldi_bytes_per_solve(its, n, ortho, pipelined=False):
     """Algorithmic HBM bytes of the Arnoldi iterations of one solve, the bytes the
     chosen kernel streams by design, and the number of launches that do work.
 
@@ -51,9 +51,10 @@ def arnoldi_bytes_per_solve(its, n, ortho):
     basis vectors v_0 .. v_j (8n(j+1)) once each and writes v_{j+1} (8n):
     8n(j+3), whatever the orthogonalisation.  By design, MGS streams exactly
     that; CGS2 reads the basis four times (8n(4(j+1)+2)); delayed CGS2 launch j
-    reads V_{j-1}, u_j and y, then V_{j-1} again, and writes v_j and u_{j+1}
-    (8n(2j+4)), and one more launch per refinement step (pass 1 only) completes
-    the last column."""
+    reads V_{j-1}, u_j and y, then (two-pass launch) V_{j-1} again, and writes
+    v_j and u_{j+1}: 8n(2j+4), or 8n(j+4) for the pipelined launch, which keeps
+    what it read for its second pass (launch 0: 8n 3); one more launch per
+    refinement step (pass 1 only) completes the last column."""
     alg, design, launches = 0, 0, 0
     for k in its:
         for j in range(k):
@@ -62,6 +63,8 @@ def arnoldi_bytes_per_solve(its, n, ortho):
                 design += 8 * n * (j + 3)
             elif ortho == "cgs2":
                 design += 8 * n * (4 * (j + 1) + 2)
+            elif pipelined:
+                design += 8 * n * (3 if j == 0 else j + 4)
             else:
                 design += 8 * n * (2 * j + 4)
             launches += 1
@@ -734,12 +737,17 @@ def main():
         # dispatched per solve gives the Arnoldi time of a solve.  Launches
         # enqueued past convergence (no-ops) count in the time but not in the
         # bytes, so the figure is conservative.
-        tot_bytes, design_bytes, real = arnoldi_bytes_per_solve(st["its"], n, args.ortho)
+        # the delayed-CGS2 launch is the pipelined one up to 2 rows per thread
+        # (512 data threads per block, a block per CU)
+        ncu = min(torch.cuda.get_device_properties(0).multi_processor_count, 256)
+        pipelined = args.ortho == "dcgs2" and os.environ.get("SPAI_DCGS2") != "twopass" and n <= ncu * 1024
+        tot_bytes, design_bytes, real = arnoldi_bytes_per_solve(st["its"], n, args.ortho, pipelined)
         cnt, ms = timings["mgs"]
         dispatched = arnoldi_launches_dispatched(st["its"], min(w.ir.maxit, n), args.ortho)
         secs = ms * 1e-3 / cnt * dispatched
         achieved = tot_bytes / secs / 1e9
-        kname = {"mgs": "k_arnoldi", "cgs2": "k_arnoldi_cgs2", "dcgs2": "k_arnoldi_dcgs2"}[args.ortho]
+        kname = {"mgs": "k_arnoldi", "cgs2": "k_arnoldi_cgs2",
+                 "dcgs2": "k_arnoldi_dcgs2p" if pipelined else "k_arnoldi_dcgs2"}[args.ortho]
         traffic = profiled_traffic(f"{kname}_convdiff512_traffic.txt",
                                    ["paper_2202_10204_amd/csrc/gmres_ir.hip", "paper_2202_10204_amd/csrc/common.hpp"])
         roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

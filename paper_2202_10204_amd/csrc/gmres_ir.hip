@@ -1361,8 +1361,9 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     __shared__ double wsum2[2 * (AT_DATA / 64)];
     __shared__ int abort_flag, ready, fin;
     __shared__ int arrived[RING];
-    if (a.st->done) return;                  // uniform: written by an earlier launch
-    if (a.by_step) {                         // graph replay: the step comes from the solver state
+    const bool by_step = a.by_step;
+    if (by_step) {                           // graph replay: the step comes from the solver state
+        if (a.st->done) return;              // uniform: written by an earlier launch
         a.j = a.st->jcur;
         a.parity = a.j & 1;
     }
@@ -1386,6 +1387,38 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     const size_t blk = (size_t)rmax * nb;
     unsigned long long* slots = cur;         // [rmax][nb]
     unsigned long long* mbox = cur + blk;    // [nb][rmax]
+    constexpr int GS = DCGS2P_GS, GV = 2 * GS;   // vectors and values per group
+    const int G = (j + GS - 1) / GS;
+    // loads of group gl's vectors at the thread's rows (a vector past j - 1 reads vector 0, unused)
+    auto load_group = [&](int gl, double (&v)[GS][EPT]) {
+#pragma unroll
+        for (int c = 0; c < GS; ++c) {
+            const int l = GS * gl + c;
+            const double* col = a.V + (size_t)(l < j ? l : 0) * n;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int i = base + e * gstride;
+                v[c][e] = col[pf_index(i, i < n)];
+            }
+        }
+    };
+    constexpr int NBUF = DCGS2P_NBUF;
+    double B[NBUF][GS][EPT];
+    double u[EPT], yv[EPT];
+    if (wave < DW) {
+        // u_j, y and the first group go out before the launch looks at the stop
+        // flag, so that its latency overlaps theirs (all in bounds: j <= maxit)
+        const double* uj = a.V + (size_t)j * n;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = base + e * gstride;
+            const bool ok = i < n;
+            u[e] = ld0(uj, i, ok);
+            yv[e] = ld0(a.y, i, ok);
+        }
+        load_group(0, B[0]);                  // in flight through the block's first barrier
+    }
+    if (!by_step && a.st->done) return;      // uniform: written by an earlier launch
     // re-arm this block's words of the other buffer for the next launch (2j + 4 values)
     for (int r = t; r < min(R + 2, rmax); r += AT) {
         nxt[(size_t)r * nb + b] = SENTINEL;
@@ -1405,18 +1438,10 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         if (wave == DW)                       // first projections of column j - 1
             for (int l = lane; l < j; l += 64) hh[l] = a.HRp[(size_t)(j - 1) * a.ld + l];
     }
-    constexpr int GS = DCGS2P_GS, GV = 2 * GS;   // vectors and values per group
-    const int G = (j + GS - 1) / GS;
-    double u[EPT], yv[EPT];
     if (wave < DW) {
-        const double* uj = a.V + (size_t)j * n;
         double om = 0.0, c = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = base + e * gstride;
-            const bool ok = i < n;
-            u[e] = ld0(uj, i, ok);
-            yv[e] = ld0(a.y, i, ok);
             om = __builtin_fma(u[e], u[e], om);
             c = __builtin_fma(u[e], yv[e], c);
         }
@@ -1600,19 +1625,6 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         au[e] = u[e];
         ay[e] = yv[e];
     }
-    // loads of group gl's vectors at the thread's rows (a vector past j - 1 reads vector 0, unused)
-    auto load_group = [&](int gl, double (&v)[GS][EPT]) {
-#pragma unroll
-        for (int c = 0; c < GS; ++c) {
-            const int l = GS * gl + c;
-            const double* col = a.V + (size_t)(l < j ? l : 0) * n;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int i = base + e * gstride;
-                v[c][e] = col[pf_index(i, i < n)];
-            }
-        }
-    };
     // one step g: the loads of group g + 1 into vn, pass 1 of group g from vc
     // (loaded the step before), pass 2 of group g - LAG from the values this
     // thread loaded for that group's pass 1 (so the basis is read once from
@@ -1707,9 +1719,6 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
                         mine[((size_t)(gr % NL) * GS * EPT + c * EPT + e) * AT_DATA] = vp[c][e];
         }
     };
-    constexpr int NBUF = DCGS2P_NBUF;
-    double B[NBUF][GS][EPT];
-    load_group(0, B[0]);
     for (int g = 0; g < G + LAG && ok; g += NBUF) {
         // whole trips, no step under a branch (see load_group above): a step past
         // G + LAG - 1 has no pass 1, no pass 2 and nothing to move, and its wait

@@ -38,7 +38,9 @@ struct SolveState {
 
 // ---------------------------------------------------------------------------
 // sparse products (a set `done` flag turns them into no-ops so that steps
-// enqueued past convergence cost only their launch)
+// enqueued past convergence cost only their launch; launched from the stream,
+// they read the flag once their first loads are out, so that its latency
+// overlaps theirs, and then write nothing)
 // ---------------------------------------------------------------------------
 
 // w = A v and y = M^T (D w) (row k of P holds m_k, values in VP, FP64
@@ -58,8 +60,10 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
                                                 const double* __restrict__ av, const double* __restrict__ x,
                                                 double* __restrict__ y, const double* __restrict__ dout,
                                                 const SolveState* __restrict__ st, int by_step) {
-    if (st && st->done) return;
-    if (by_step) x += (size_t)st->jcur * n;  // graph replay: x is column jcur of the basis
+    if (by_step) {                           // graph replay: x is column jcur of the basis
+        if (st->done) return;
+        x += (size_t)st->jcur * n;
+    }
     // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
     constexpr int GPB = 256 / G;
     const int sub = threadIdx.x & (G - 1);
@@ -97,6 +101,8 @@ __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ r
                 va[r][it] = av[qx[r][it]];
                 vx[r][it] = x[jx[r][it]];
             }
+        __asm__ volatile("" ::: "memory");   // the loads above stay ahead of the flag's test
+        if (!by_step && st && st->done) return;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             double s = 0.0;
@@ -125,8 +131,10 @@ __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict_
                                                    const double* __restrict__ d, const double* __restrict__ w,
                                                    double* __restrict__ y, const SolveState* __restrict__ st,
                                                    int by_step) {
-    if (st && st->done) return;
-    if (by_step) w += (size_t)st->jcur * n;  // graph replay: w is column jcur of the basis
+    if (by_step) {                           // graph replay: w is column jcur of the basis
+        if (st->done) return;
+        w += (size_t)st->jcur * n;
+    }
     // a block covers R slabs of 256 / G consecutive rows: each slab is read by the whole block at once
     constexpr int GPB = 256 / G;
     const int sub = threadIdx.x & (G - 1);
@@ -163,6 +171,8 @@ __global__ __launch_bounds__(256) void k_apply_P_g(int n, const int* __restrict_
                 if constexpr (RIGHT || SCALED) vw[r][it] = w[j];
                 else vw[r][it] = d[j] * w[j];
             }
+        __asm__ volatile("" ::: "memory");   // the loads above stay ahead of the flag's test
+        if (!by_step && st && st->done) return;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             double s = 0.0;

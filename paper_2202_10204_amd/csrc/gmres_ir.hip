@@ -1362,6 +1362,180 @@ __device__ __forceinline__ double wave_sum8(const double (&x)[8], int lane) {
     return w;
 }
 
+// The poll wave of a pipelined DCGS2 launch (groups of GS basis vectors): the
+// block partials of omega and c, the event loop of the grid-wide sums (mailbox
+// words of the lane sets' groups, the partials of the owned columns), then nu
+// and gj for the data waves, the block's Hessenberg rows and (block 0) the
+// Givens step.  ready, fin, abort_flag, nu_s and gj_s are the block's LDS words.
+template <int GS>
+__device__ __forceinline__ void dcgs2p_poll(ArnoldiArgs& a, int b, int nb, int lane, int j, int G, int rmax,
+                                            unsigned long long* slots, unsigned long long* mbox, double* hv,
+                                            double* hh, const double* csL, const double* snL, const double* wsum2,
+                                            int& ready, int& fin, int& abort_flag, double& nu_s, double& gj_s) {
+    constexpr int DW = AT_DATA / 64, GV = 2 * GS;
+    // ---- poll wave: block partials of omega and c, the sums, then the bookkeeping ----
+    __builtin_amdgcn_s_setprio(3);
+    if (lane == 0) {
+        double om = 0.0, c = 0.0;
+        for (int w = 0; w < DW; ++w) {
+            om += wsum2[2 * w];
+            c += wsum2[2 * w + 1];
+        }
+        __hip_atomic_store(&slots[(size_t)j * nb + b], (unsigned long long)__double_as_longlong(om),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&slots[(size_t)(2 * j + 1) * nb + b], (unsigned long long)__double_as_longlong(c),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // An event loop, so that no single wait holds up the others: each pass
+    // polls (once, without waiting) the mailbox words of eight groups at a time
+    // (lanes 8q .. 8q + 7 take the groups q, q + 8, ... in order, lane 8q + k
+    // the value k of its group: a_l for even k, b_l for odd k) and the slots of
+    // the next column this block owns (columns b, b + nb, ..., then omega and c
+    // as column j); `ready` is raised to the groups complete in every lane set.
+    constexpr int SETS = 64 / GV;
+    const int q4 = lane / GV, k16 = lane % GV;
+    int gq = q4;                          // this lane set's group
+    bool have = false;                    // this lane's value of group gq is in hv
+    int own = b < j ? b : (j % nb == b ? j : -1);   // next owned column (j: omega and c)
+    unsigned long long ov[8];             // owned column: partials of sources lane, lane + 64, ... (a, b)
+    unsigned omask = 0u;
+    bool ready_c = false;                 // omega and c are in hv
+    long long idle = 0;
+    bool to = false;
+    const unsigned omask_all = [&] {
+        unsigned m = 0u;
+        for (int s4 = 0; s4 < 4; ++s4)
+            if (lane + 64 * s4 < nb) m |= 3u << (2 * s4);
+        return m;
+    }();
+    for (;;) {
+        bool progress = false;
+        // every load of the pass is issued before any of them is used, so that
+        // one memory round trip serves the mailbox words of the lane sets'
+        // groups, omega and c, and the partials of the owned column
+        const int l = GS * gq + (k16 >> 1);
+        const bool want_m = gq < G && l < j && !have;
+        const int rm = (k16 & 1) ? j + 1 + l : l;
+        const bool want_c = !ready_c && lane < 2;
+        const int rc = lane ? 2 * j + 1 : j;
+        const int r1 = own < j ? own : j, r2 = own < j ? j + 1 + own : 2 * j + 1;
+        unsigned long long mv = SENTINEL, cv = SENTINEL, nv[8];
+        if (want_m) mv = __hip_atomic_load(&mbox[(size_t)b * rmax + rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (want_c) cv = __hip_atomic_load(&mbox[(size_t)b * rmax + rc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int src = lane + 64 * s4;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                nv[2 * s4 + h] = SENTINEL;
+                if (own >= 0 && src < nb && !(omask & (1u << (2 * s4 + h))))
+                    nv[2 * s4 + h] = __hip_atomic_load(&slots[(size_t)(h ? r2 : r1) * nb + src], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (want_m && mv != SENTINEL) {
+            hv[rm] = __longlong_as_double((long long)mv);
+            have = true;
+        }
+        if (gq < G && l >= j) have = true;
+        if (want_c) {
+            if (cv != SENTINEL) hv[rc] = __longlong_as_double((long long)cv);
+            ready_c = cv != SENTINEL;
+        }
+        ready_c = (__builtin_amdgcn_ballot_w64(ready_c) & 3ull) == 3ull;
+        // a lane set whose group is complete moves to its next group
+        const unsigned long long hb = __builtin_amdgcn_ballot_w64(have || gq >= G);
+        constexpr unsigned long long SETMASK = GV == 64 ? ~0ull : ((1ull << GV) - 1ull);
+        const bool set_done = ((hb >> (GV * q4)) & SETMASK) == SETMASK;
+        if (set_done && gq < G) {
+            gq += SETS;
+            have = false;
+            progress = true;
+        }
+        // groups complete in every set: the smallest group a set still waits for
+        int gmin = gq;
+#pragma unroll
+        for (int off = GV; off < 64; off <<= 1) gmin = min(gmin, __shfl_xor(gmin, off, 64));
+        const int rdy = min(GS * min(gmin, G), j);
+        lds_order();
+        if (lane == 0 && rdy > __hip_atomic_load(&ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+            __hip_atomic_store(&ready, rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // the owned column: its partials, then the totals into every mailbox
+        if (own >= 0) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (nv[k] != SENTINEL) {
+                    ov[k] = nv[k];
+                    omask |= 1u << k;
+                }
+            if (__builtin_amdgcn_ballot_w64(omask != omask_all) == 0ull) {
+                double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    if (lane + 64 * s4 < nb) {
+                        s1 += __longlong_as_double((long long)ov[2 * s4]);
+                        s2 += __longlong_as_double((long long)ov[2 * s4 + 1]);
+                    }
+                s1 = wave_sum(s1);
+                s2 = wave_sum(s2);
+                const unsigned long long w1 = (unsigned long long)__double_as_longlong(s1);
+                const unsigned long long w2 = (unsigned long long)__double_as_longlong(s2);
+                for (int q = lane; q < nb; q += 64) {
+                    __hip_atomic_store(&mbox[(size_t)q * rmax + r1], w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&mbox[(size_t)q * rmax + r2], w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                omask = 0u;
+                own = own == j ? -1 : (own + nb < j ? own + nb : (j % nb == b ? j : -1));
+                progress = true;
+            }
+        }
+        if (gmin >= G && ready_c && own < 0) break;
+        if (progress) {
+            idle = 0;
+        } else {
+            if (++idle > SPIN_LIMIT) {
+                to = true;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if (to) {
+        if (lane == 0) {
+            __hip_atomic_store(&abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    lds_order();
+    double q = 0.0, ab = 0.0;
+    for (int l = lane; l < j; l += 64) {
+        q = __builtin_fma(hv[l], hv[l], q);
+        ab = __builtin_fma(hv[l], hv[j + 1 + l], ab);
+    }
+    q = wave_sum(q);
+    ab = wave_sum(ab);
+    double nu = 1.0;
+    if (j > 0) {
+        double qq = hv[j] - q;
+        nu = qq > 0.0 ? __builtin_sqrt(qq) : 0.0;
+    }
+    const double gj = (hv[2 * j + 1] - ab) / nu;
+    if (lane == 0) {
+        nu_s = nu;
+        gj_s = gj;
+    }
+    lds_order();
+    if (lane == 0) __hip_atomic_store(&fin, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    dcgs2_rows(a, hv, nu, gj);
+    if (b == 0 && j >= 1) dcgs2_givens(a, hv, nu, hh, csL, snL);
+    // every block read the step index before publishing its partial sums,
+    // which this block has received: the next launch's index can be set
+    if (a.by_step && b == 0 && lane == 0) a.st->jcur = j + 1;
+    __builtin_amdgcn_s_setprio(0);
+}
+
 template <int EPT, int NL>
 __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     constexpr int RING = dcgs2p_ring(NL);
@@ -1464,167 +1638,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     }
     __syncthreads();
     if (wave == DW) {
-        // ---- poll wave: block partials of omega and c, the sums, then the bookkeeping ----
-        __builtin_amdgcn_s_setprio(3);
-        if (lane == 0) {
-            double om = 0.0, c = 0.0;
-            for (int w = 0; w < DW; ++w) {
-                om += wsum2[2 * w];
-                c += wsum2[2 * w + 1];
-            }
-            __hip_atomic_store(&slots[(size_t)j * nb + b], (unsigned long long)__double_as_longlong(om),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&slots[(size_t)(2 * j + 1) * nb + b], (unsigned long long)__double_as_longlong(c),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // An event loop, so that no single wait holds up the others: each pass
-        // polls (once, without waiting) the mailbox words of eight groups at a time
-        // (lanes 8q .. 8q + 7 take the groups q, q + 8, ... in order, lane 8q + k
-        // the value k of its group: a_l for even k, b_l for odd k) and the slots of
-        // the next column this block owns (columns b, b + nb, ..., then omega and c
-        // as column j); `ready` is raised to the groups complete in every lane set.
-        constexpr int SETS = 64 / GV;
-        const int q4 = lane / GV, k16 = lane % GV;
-        int gq = q4;                          // this lane set's group
-        bool have = false;                    // this lane's value of group gq is in hv
-        int own = b < j ? b : (j % nb == b ? j : -1);   // next owned column (j: omega and c)
-        unsigned long long ov[8];             // owned column: partials of sources lane, lane + 64, ... (a, b)
-        unsigned omask = 0u;
-        bool ready_c = false;                 // omega and c are in hv
-        long long idle = 0;
-        bool to = false;
-        const unsigned omask_all = [&] {
-            unsigned m = 0u;
-            for (int s4 = 0; s4 < 4; ++s4)
-                if (lane + 64 * s4 < nb) m |= 3u << (2 * s4);
-            return m;
-        }();
-        for (;;) {
-            bool progress = false;
-            // every load of the pass is issued before any of them is used, so that
-            // one memory round trip serves the mailbox words of the lane sets'
-            // groups, omega and c, and the partials of the owned column
-            const int l = GS * gq + (k16 >> 1);
-            const bool want_m = gq < G && l < j && !have;
-            const int rm = (k16 & 1) ? j + 1 + l : l;
-            const bool want_c = !ready_c && lane < 2;
-            const int rc = lane ? 2 * j + 1 : j;
-            const int r1 = own < j ? own : j, r2 = own < j ? j + 1 + own : 2 * j + 1;
-            unsigned long long mv = SENTINEL, cv = SENTINEL, nv[8];
-            if (want_m) mv = __hip_atomic_load(&mbox[(size_t)b * rmax + rm], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (want_c) cv = __hip_atomic_load(&mbox[(size_t)b * rmax + rc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int src = lane + 64 * s4;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    nv[2 * s4 + h] = SENTINEL;
-                    if (own >= 0 && src < nb && !(omask & (1u << (2 * s4 + h))))
-                        nv[2 * s4 + h] = __hip_atomic_load(&slots[(size_t)(h ? r2 : r1) * nb + src], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-            if (want_m && mv != SENTINEL) {
-                hv[rm] = __longlong_as_double((long long)mv);
-                have = true;
-            }
-            if (gq < G && l >= j) have = true;
-            if (want_c) {
-                if (cv != SENTINEL) hv[rc] = __longlong_as_double((long long)cv);
-                ready_c = cv != SENTINEL;
-            }
-            ready_c = (__builtin_amdgcn_ballot_w64(ready_c) & 3ull) == 3ull;
-            // a lane set whose group is complete moves to its next group
-            const unsigned long long hb = __builtin_amdgcn_ballot_w64(have || gq >= G);
-            constexpr unsigned long long SETMASK = GV == 64 ? ~0ull : ((1ull << GV) - 1ull);
-            const bool set_done = ((hb >> (GV * q4)) & SETMASK) == SETMASK;
-            if (set_done && gq < G) {
-                gq += SETS;
-                have = false;
-                progress = true;
-            }
-            // groups complete in every set: the smallest group a set still waits for
-            int gmin = gq;
-#pragma unroll
-            for (int off = GV; off < 64; off <<= 1) gmin = min(gmin, __shfl_xor(gmin, off, 64));
-            const int rdy = min(GS * min(gmin, G), j);
-            lds_order();
-            if (lane == 0 && rdy > __hip_atomic_load(&ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
-                __hip_atomic_store(&ready, rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            // the owned column: its partials, then the totals into every mailbox
-            if (own >= 0) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (nv[k] != SENTINEL) {
-                        ov[k] = nv[k];
-                        omask |= 1u << k;
-                    }
-                if (__builtin_amdgcn_ballot_w64(omask != omask_all) == 0ull) {
-                    double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4)
-                        if (lane + 64 * s4 < nb) {
-                            s1 += __longlong_as_double((long long)ov[2 * s4]);
-                            s2 += __longlong_as_double((long long)ov[2 * s4 + 1]);
-                        }
-                    s1 = wave_sum(s1);
-                    s2 = wave_sum(s2);
-                    const unsigned long long w1 = (unsigned long long)__double_as_longlong(s1);
-                    const unsigned long long w2 = (unsigned long long)__double_as_longlong(s2);
-                    for (int q = lane; q < nb; q += 64) {
-                        __hip_atomic_store(&mbox[(size_t)q * rmax + r1], w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&mbox[(size_t)q * rmax + r2], w2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    omask = 0u;
-                    own = own == j ? -1 : (own + nb < j ? own + nb : (j % nb == b ? j : -1));
-                    progress = true;
-                }
-            }
-            if (gmin >= G && ready_c && own < 0) break;
-            if (progress) {
-                idle = 0;
-            } else {
-                if (++idle > SPIN_LIMIT) {
-                    to = true;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        if (to) {
-            if (lane == 0) {
-                __hip_atomic_store(&abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                a.st->err = 1;
-                a.st->done = 3;
-            }
-            return;
-        }
-        lds_order();
-        double q = 0.0, ab = 0.0;
-        for (int l = lane; l < j; l += 64) {
-            q = __builtin_fma(hv[l], hv[l], q);
-            ab = __builtin_fma(hv[l], hv[j + 1 + l], ab);
-        }
-        q = wave_sum(q);
-        ab = wave_sum(ab);
-        double nu = 1.0;
-        if (j > 0) {
-            double qq = hv[j] - q;
-            nu = qq > 0.0 ? __builtin_sqrt(qq) : 0.0;
-        }
-        const double gj = (hv[2 * j + 1] - ab) / nu;
-        if (lane == 0) {
-            nu_s = nu;
-            gj_s = gj;
-        }
-        lds_order();
-        if (lane == 0) __hip_atomic_store(&fin, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        dcgs2_rows(a, hv, nu, gj);
-        if (b == 0 && j >= 1) dcgs2_givens(a, hv, nu, hh, csL, snL);
-        // every block read the step index before publishing its partial sums,
-        // which this block has received: the next launch's index can be set
-        if (a.by_step && b == 0 && lane == 0) a.st->jcur = j + 1;
-        __builtin_amdgcn_s_setprio(0);
+        dcgs2p_poll<GS>(a, b, nb, lane, j, G, rmax, slots, mbox, hv, hh, csL, snL, wsum2, ready, fin, abort_flag,
+                        nu_s, gj_s);
         return;
     }
     // ---- data waves: pass 1 of group g and pass 2 of group g - LAG ----
@@ -1735,6 +1750,219 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         // is for all j sums, which every block receives
 #pragma unroll
         for (int k = 0; k < NBUF; ++k) step(g + k, B[k], B[(k + 1) % NBUF], B[(k + NBUF - DCGS2P_LAG) % NBUF]);
+    }
+    if (!ok) {
+        if (lane == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    if (!update) return;
+    if (!wait_lds_at_least(&fin, 1, &abort_flag)) {
+        if (lane == 0) {
+            a.st->err = 1;
+            a.st->done = 3;
+        }
+        return;
+    }
+    const double nu = nu_s, gj = gj_s;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = base + e * gstride;
+        if (i < n) {
+            const double v = j > 0 ? au[e] / nu : au[e];
+            if (j > 0) a.V[(size_t)j * n + i] = v;
+            a.V[(size_t)(j + 1) * n + i] = __builtin_fma(-gj, v, ay[e]) / nu;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined DCGS2 step for more than 2 rows per thread (the registers cannot
+// keep a lag of groups there): groups of one basis vector; u_j and y wait in
+// LDS (the thread's own words), and pass 2 of vector g - LAG reads that vector
+// again, LAG vectors after its pass 1 read it, into the buffer
+// pass 1 of vector g has just released; the memory-side cache (256 MB) still
+// holds those few vectors (the nearer ones the L2), so the basis streams from
+// HBM about once per step.
+// Sums, poll wave and final steps as in k_arnoldi_dcgs2p.
+// ---------------------------------------------------------------------------
+constexpr int DCGS2M_LAG16 = 3, DCGS2M_LAG8 = 6, DCGS2M_LAG4 = 10;
+// vectors between pass 1 and pass 2 by rows per thread: enough to cover the
+// grid-wide sum at the time a vector takes to stream, few enough that pass 2
+// finds the vector in a cache close by (measured at 16 rows per thread: lag 3, 4,
+// 6, 9 gave 283, 284, 290, 315 ms for a fixed 300-step solve at 128^3)
+__host__ __device__ constexpr int dcgs2m_lag(int ept) { return ept >= 16 ? DCGS2M_LAG16 : ept >= 8 ? DCGS2M_LAG8 : DCGS2M_LAG4; }
+__host__ __device__ constexpr int dcgs2m_ring(int ept) { return dcgs2m_lag(ept) + 2; }
+
+__host__ __device__ constexpr size_t dcgs2m_lds_words(int rmax, int maxlinks, int maxit, int ept) {
+    return (size_t)rmax + (size_t)maxlinks + 2 * (size_t)maxit + (size_t)dcgs2m_ring(ept) * (AT_DATA / 64) * 2 +
+           2 * (size_t)ept * AT_DATA;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(AT) void k_arnoldi_dcgs2m(ArnoldiArgs a) {
+    constexpr int LAG = dcgs2m_lag(EPT), RING = dcgs2m_ring(EPT), DW = AT_DATA / 64;
+    extern __shared__ __align__(16) double dyn[];
+    __shared__ double nu_s, gj_s;
+    __shared__ double wsum2[2 * DW];
+    __shared__ int abort_flag, ready, fin;
+    __shared__ int arrived[RING];
+    const bool by_step = a.by_step;
+    if (by_step) {                           // graph replay: the step comes from the solver state
+        if (a.st->done) return;              // uniform: written by an earlier launch
+        a.j = a.st->jcur;
+        a.parity = a.j & 1;
+    }
+    const int b = blockIdx.x, t = threadIdx.x, nb = a.nb, lane = t & 63, wave = t >> 6;
+    const int gstride = nb * AT_DATA;
+    const int base = b * AT_DATA + t;
+    const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
+    // LDS (dcgs2m_lds_words): totals hv, the Hessenberg column, cs, sn, the wave
+    // partials [RING][DW][2], then u_j and y at the thread's rows [2][EPT][AT_DATA]
+    double* hv = dyn;
+    double* hh = hv + rmax;
+    double* csL = hh + a.maxlinks;
+    double* snL = csL + a.maxit;
+    double* wpart = snL + a.maxit;
+    double* uy = wpart + (size_t)RING * DW * 2;
+    const size_t pw = dcgs2_parity_words(a.maxlinks, nb);
+    unsigned long long* cur = a.slots + (size_t)a.parity * pw;
+    unsigned long long* nxt = a.slots + (size_t)(1 - a.parity) * pw;
+    const size_t blk = (size_t)rmax * nb;
+    unsigned long long* slots = cur;         // [rmax][nb]
+    unsigned long long* mbox = cur + blk;    // [nb][rmax]
+    const int G = j;                         // one vector per group
+    // loads of vector l at the thread's rows (l past j - 1 reads vector 0, unused).
+    // A row past n - 1 is not clamped: with EPT >= 2 the rows end below 2n
+    // (EPT is the smallest power of two that covers n), so it reads vector l + 1,
+    // which the basis holds (l + 1 <= j <= maxit); its product is not added.  One
+    // row offset then serves every load of the thread.
+    auto load_vec = [&](int l, double (&v)[EPT]) {
+        const double* col = a.V + (size_t)(l < j ? l : 0) * n + base;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) v[e] = col[(size_t)e * gstride];
+    };
+    double B[2][EPT];
+    double au[EPT], ay[EPT];                 // u_j and y, then their updates by pass 2
+    if (wave < DW) {
+        const double* uj = a.V + (size_t)j * n;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = base + e * gstride;
+            const bool ok = i < n;
+            au[e] = ld0(uj, i, ok);
+            ay[e] = ld0(a.y, i, ok);
+        }
+        load_vec(0, B[0]);
+    }
+    if (!by_step && a.st->done) return;      // uniform: written by an earlier launch
+    // re-arm this block's words of the other buffer for the next launch (2j + 4 values)
+    for (int r = t; r < min(R + 2, rmax); r += AT) {
+        nxt[(size_t)r * nb + b] = SENTINEL;
+        nxt[blk + (size_t)b * rmax + r] = SENTINEL;
+    }
+    if (t == 0) {
+        abort_flag = 0;
+        ready = 0;
+        fin = 0;
+    }
+    if (t < RING) arrived[t] = 0;
+    if (b == 0) {
+        for (int l = t; l + 1 < j; l += AT) {
+            csL[l] = a.cs[l];
+            snL[l] = a.sn[l];
+        }
+        if (wave == DW)                       // first projections of column j - 1
+            for (int l = lane; l < j; l += 64) hh[l] = a.HRp[(size_t)(j - 1) * a.ld + l];
+    }
+    if (wave < DW) {
+        double om = 0.0, c = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            om = __builtin_fma(au[e], au[e], om);
+            c = __builtin_fma(au[e], ay[e], c);
+            uy[(size_t)e * AT_DATA + t] = au[e];
+            uy[(size_t)(EPT + e) * AT_DATA + t] = ay[e];
+        }
+        om = wave_sum(om);
+        c = wave_sum(c);
+        if (lane == 0) {
+            wsum2[2 * wave] = om;
+            wsum2[2 * wave + 1] = c;
+        }
+    }
+    __syncthreads();
+    if (wave == DW) {
+        dcgs2p_poll<1>(a, b, nb, lane, j, G, rmax, slots, mbox, hv, hh, csL, snL, wsum2, ready, fin, abort_flag,
+                       nu_s, gj_s);
+        return;
+    }
+    // ---- data waves: pass 1 of vector g and pass 2 of vector g - LAG ----
+    const bool update = j < a.maxit;         // launch maxit only completes column maxit - 1
+    const double* us = uy + t;
+    const double* ys = uy + (size_t)EPT * AT_DATA + t;
+    bool ok = true;
+    // one step g: the loads of vector g + 1 into vn, pass 1 of vector g from vc
+    // (loaded the step before), then vector g - LAG again into vc for its pass 2;
+    // two buffers in turn, whole trips of two steps (a step past G + LAG - 1 only
+    // waits for all sums; the loads are unconditional, past the end vector 0)
+    auto step = [&](int g, double (&vc)[EPT], double (&vn)[EPT]) {
+        const int g2 = g - LAG;
+        load_vec(g + 1, vn);
+        if (g < G) {
+            const int ring = g % RING;
+            double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int i = base + e * gstride;
+                const double vv = i < n ? vc[e] : 0.0;
+                p1 = __builtin_fma(vv, us[(size_t)e * AT_DATA], p1);
+                p2 = __builtin_fma(vv, ys[(size_t)e * AT_DATA], p2);
+            }
+            p1 = wave_sum(p1);
+            p2 = wave_sum(p2);
+            if (lane == 0) {
+                wpart[((size_t)ring * DW + wave) * 2] = p1;
+                wpart[((size_t)ring * DW + wave) * 2 + 1] = p2;
+            }
+            lds_order();
+            int old = 0;
+            if (lane == 0) old = __hip_atomic_fetch_add(&arrived[ring], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            old = __builtin_amdgcn_readfirstlane(old);
+            if (old == DW - 1) {
+                // the last wave of the block to finish the vector: the block's partials, waves in order
+                lds_order();
+                if (lane < 2) {
+                    double sum = 0.0;
+                    for (int w = 0; w < DW; ++w) sum += wpart[((size_t)ring * DW + w) * 2 + lane];
+                    const int r = lane ? j + 1 + g : g;
+                    __hip_atomic_store(&slots[(size_t)r * nb + b], (unsigned long long)__double_as_longlong(sum),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                lds_order();
+                if (lane == 0) __hip_atomic_store(&arrived[ring], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        if (g2 >= 0) {
+            // the wait also paces the waves of the block when pass 2 is skipped (a
+            // ring entry is free again before its next use)
+            if (ok && !wait_lds_at_least(&ready, min(g2 + 1, j), &abort_flag)) ok = false;
+            if (update && ok && g2 < G) {
+                load_vec(g2, vc);
+                const double al = hv[g2], bl = hv[j + 1 + g2];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    au[e] = __builtin_fma(-al, vc[e], au[e]);
+                    ay[e] = __builtin_fma(-bl, vc[e], ay[e]);
+                }
+            }
+        }
+    };
+    for (int g = 0; g < G + LAG && ok; g += 2) {
+        step(g, B[0], B[1]);
+        step(g + 1, B[1], B[0]);
     }
     if (!ok) {
         if (lane == 0) {
@@ -2172,6 +2400,7 @@ struct ArnoldiCfg {
     int ept = 0;
     int ortho = SPAI_ORTHO_MGS;
     bool ext = false;        // pipelined DCGS2: the lag extended through LDS
+    bool reread = false;     // pipelined DCGS2 with more than 2 rows per thread (pass 2 reads its vector again)
     size_t shmem = 0;
     size_t slot_words = 0;   // both parities
 };
@@ -2187,6 +2416,15 @@ static bool dcgs2_pipelined() {
     return p;
 }
 
+// SPAI_DCGS2_REREAD=0 keeps the two-pass launch for more than 2 rows per thread
+static bool dcgs2_reread() {
+    static const bool x = [] {
+        const char* e = getenv("SPAI_DCGS2_REREAD");
+        return !(e && std::string(e) == "0");
+    }();
+    return x;
+}
+
 // SPAI_DCGS2_LDS=0 keeps the pipelined launch's lag to its register ring
 static bool dcgs2_lds_ext() {
     static const bool x = [] {
@@ -2197,26 +2435,29 @@ static bool dcgs2_lds_ext() {
 }
 
 template <int EPT>
-static const void* arnoldi_fn(int ortho, bool ext) {
+static const void* arnoldi_fn(int ortho, bool ext, bool reread) {
     switch (ortho) {
     case SPAI_ORTHO_CGS2: return (const void*)k_arnoldi_cgs2<EPT>;
     case SPAI_ORTHO_DCGS2:
-        if constexpr (EPT <= 2)
+        if constexpr (EPT <= 2) {
             if (dcgs2_pipelined())
                 return ext ? (const void*)k_arnoldi_dcgs2p<EPT, dcgs2p_nl_ext<EPT>()>
                            : (const void*)k_arnoldi_dcgs2p<EPT, 0>;
+        } else {
+            if (reread) return (const void*)k_arnoldi_dcgs2m<EPT>;
+        }
         return (const void*)k_arnoldi_dcgs2<EPT>;
     default: return (const void*)k_arnoldi<EPT>;
     }
 }
 
-static const void* arnoldi_fn(int ortho, int ept, bool ext) {
+static const void* arnoldi_fn(int ortho, int ept, bool ext, bool reread) {
     switch (ept) {
-    case 1: return arnoldi_fn<1>(ortho, ext);
-    case 2: return arnoldi_fn<2>(ortho, ext);
-    case 4: return arnoldi_fn<4>(ortho, ext);
-    case 8: return arnoldi_fn<8>(ortho, ext);
-    default: return arnoldi_fn<16>(ortho, ext);
+    case 1: return arnoldi_fn<1>(ortho, ext, reread);
+    case 2: return arnoldi_fn<2>(ortho, ext, reread);
+    case 4: return arnoldi_fn<4>(ortho, ext, reread);
+    case 8: return arnoldi_fn<8>(ortho, ext, reread);
+    default: return arnoldi_fn<16>(ortho, ext, reread);
     }
 }
 
@@ -2258,7 +2499,11 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
             c.ext = dcgs2_lds_ext() && c.shmem <= 159 * 1024;
             if (!c.ext) c.shmem = sizeof(double) * dcgs2p_lds_words(2 * maxlinks, maxlinks, maxit, 0, ept);
         } else {
-            c.shmem = sizeof(double) * dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit);
+            // more rows per thread: the pipelined launch that reads each vector again
+            // for pass 2, where u_j and y fit in LDS beside the per-step arrays
+            c.shmem = sizeof(double) * dcgs2m_lds_words(2 * maxlinks, maxlinks, maxit, ept);
+            c.reread = dcgs2_pipelined() && dcgs2_reread() && c.shmem <= 159 * 1024;
+            if (!c.reread) c.shmem = sizeof(double) * dcgs2_lds_words(ept, 2 * maxlinks, nb, maxlinks, maxit);
         }
         c.slot_words = 2 * dcgs2_parity_words(maxlinks, nb);
     } else {
@@ -2266,7 +2511,7 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
         c.slot_words = (size_t)2 * maxlinks * nb * (1 + MBOX_STRIDE);
     }
     if (c.shmem > 159 * 1024) return ArnoldiCfg{};   // 160 KB of LDS per CU, 1 KB for static arrays
-    const void* fn = arnoldi_fn(ortho, ept, c.ext);
+    const void* fn = arnoldi_fn(ortho, ept, c.ext, c.reread);
     if (c.shmem > 48 * 1024 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.shmem) != hipSuccess) {
         (void)hipGetLastError();
@@ -2307,7 +2552,7 @@ static bool use_cooperative_launch() {
 
 static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, hipStream_t s) {
     void* args[] = {&a};
-    const void* fn = arnoldi_fn(c.ortho, c.ept, c.ext);
+    const void* fn = arnoldi_fn(c.ortho, c.ept, c.ext, c.reread);
     long tk = timer_begin(h, SPAI_KT_MGS);
     hipError_t e = use_cooperative_launch() ? hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s)
                                             : hipLaunchKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);

@@ -593,6 +593,27 @@ def test_dcgs2_long_restart(S, h):
     assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
 
 
+@pytest.mark.parametrize("blocks,ept", [(8, 4), (4, 8), (2, 16)])
+def test_dcgs2_reread_rows_per_thread(S, h, blocks, ept, monkeypatch):
+    """The pipelined delayed-CGS2 launch for more than 2 rows per thread (pass 2
+    reads its basis vector again, u_j and y staged in LDS): the 128x128 system
+    with the Arnoldi grid cut to `blocks` blocks, so that every thread holds
+    `ept` rows; iterations and solution are the oracle's."""
+    monkeypatch.setenv("SPAI_ARNOLDI_BLOCKS", str(blocks))
+    w = W.convdiff_adaptive(128)
+    assert blocks * 512 * ept == w.n
+    A, P, warn, stats = _build(S, h, w)
+    s, ir = w.spai, w.ir
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dcgs2")
+    b = _dev(w.b)
+    x = torch.zeros_like(b)
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd", "dcgs2")
+    assert st["status"] == 0 and st["its"] == oref.its
+    assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
+
+
 # ---------------------------------------------------------------------------
 # 3D anisotropic diffusion at full size (128^3, n = 2,097,152, pattern(A^2)
 # capped at 27 entries per column: nnz(P) = 51,742,208)

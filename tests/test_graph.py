@@ -70,6 +70,20 @@ def test_graph_replay_at_full_size(S, h):
     assert O.ferr(x1, w.x_true) <= 1e-12
 
 
+@pytest.mark.parametrize("blocks", [8, 2])
+def test_graph_replay_with_more_rows_per_thread(S, h, blocks, monkeypatch):
+    """The pipelined launch for more than 2 rows per thread (4 and 16 here: the
+    128x128 system on 8 or 2 blocks) replayed from graphs, taking its step from
+    the solver state: same bits as its stream launches."""
+    monkeypatch.setenv("SPAI_ARNOLDI_BLOCKS", str(blocks))
+    w = W.convdiff_adaptive(128)
+    x0, r0 = _solve(S, h, w, "left", False)
+    x1, r1 = _solve(S, h, w, "left", True)
+    assert r1["its"] == r0["its"] and r1["status"] == r0["status"] == 0
+    assert np.array_equal(x1, x0), float(np.abs(x1 - x0).max())
+    assert O.ferr(x1, w.x_true) <= 1e-12
+
+
 def test_graph_option_is_ignored_by_other_orthogonalisations(S, h):
     w = W.convdiff_adaptive(48)
     s, ir = w.spai, w.ir

@@ -1274,8 +1274,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
 // groups, then, where the LDS holds them, in its own LDS words for NL more)
 // and runs that group's pass 2 on them, so the basis is read from memory once
 // per step; the latency of the sums is hidden behind the streaming of the
-// next LAG groups.  Every data thread owns EPT rows (as in pass 2 of the
-// two-pass launch); group g = vectors GS g .. GS g + GS - 1:
+// next LAG groups.  Every data thread owns EPT consecutive rows; group g =
+// vectors GS g .. GS g + GS - 1:
 //   pass 1: per vector l, the thread's products with (u_j, y) summed over its
 //           rows (FMA chain), a fixed tree over the wave, then the 8 waves in
 //           order by the last wave to arrive, which publishes the block's
@@ -1552,8 +1552,9 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         a.parity = a.j & 1;
     }
     const int b = blockIdx.x, t = threadIdx.x, nb = a.nb, lane = t & 63, wave = t >> 6;
-    const int gstride = nb * AT_DATA;
-    const int base = b * AT_DATA + t;
+    // a data thread's rows: EPT consecutive ones from row0 (at EPT = 2 one 16-byte
+    // load per vector)
+    const int row0 = EPT * (b * AT_DATA + t);
     const int n = a.n, j = a.j, rmax = 2 * a.maxlinks, R = 2 * j + 2;
     constexpr int DW = AT_DATA / 64;
     // LDS (dcgs2p_lds_words): totals hv (a_l = hv[l], omega = hv[j], b_l = hv[j+1+l],
@@ -1581,8 +1582,12 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
             const double* col = a.V + (size_t)(l < j ? l : 0) * n;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                const int i = base + e * gstride;
-                v[c][e] = col[pf_index(i, i < n)];
+                const int i = row0 + e;
+                // at EPT = 2 a row past n - 1 is not clamped: the rows end below 2n
+                // (one row per thread did not cover n), so it reads vector l + 1,
+                // which the basis holds (l + 1 <= j <= maxit); its product is not added
+                if constexpr (EPT >= 2) v[c][e] = col[i];
+                else v[c][e] = col[pf_index(i, i < n)];
             }
         }
     };
@@ -1595,7 +1600,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         const double* uj = a.V + (size_t)j * n;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = base + e * gstride;
+            const int i = row0 + e;
             const bool ok = i < n;
             u[e] = ld0(uj, i, ok);
             yv[e] = ld0(a.y, i, ok);
@@ -1674,7 +1679,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
                 double p1 = 0.0, p2 = 0.0;
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
-                    const int i = base + e * gstride;
+                    const int i = row0 + e;
                     const double vv = i < n ? vc[c][e] : 0.0;
                     p1 = __builtin_fma(vv, u[e], p1);
                     p2 = __builtin_fma(vv, yv[e], p2);
@@ -1769,7 +1774,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     const double nu = nu_s, gj = gj_s;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-        const int i = base + e * gstride;
+        const int i = row0 + e;
         if (i < n) {
             const double v = j > 0 ? au[e] / nu : au[e];
             if (j > 0) a.V[(size_t)j * n + i] = v;

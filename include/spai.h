@@ -197,9 +197,11 @@ typedef struct {
  * Gram-Schmidt applied twice) spans the same Krylov space with orthogonality to
  * working precision and needs three global reductions per iteration instead of
  * j+2.  DCGS2 is CGS2 with the second projection and the normalisation of each
- * new vector delayed to the next iteration: one global reduction and two passes
- * over the basis per iteration; the stopping decision for iteration j is taken
- * one iteration later, so one extra product with P A is computed per solve.
+ * new vector delayed to the next iteration: one set of inner products per
+ * iteration, reduced over the grid group by group of basis vectors while the
+ * second pass trails the first, so that the basis streams from memory about
+ * once per iteration; the stopping decision for iteration j is taken one
+ * iteration later, so one extra product with P A is computed per solve.
  * CGS2 and DCGS2 need the cooperative Arnoldi kernel (SPAI_E_ARG otherwise). */
 enum { SPAI_ORTHO_MGS = 0, SPAI_ORTHO_CGS2 = 1, SPAI_ORTHO_DCGS2 = 2 };
 

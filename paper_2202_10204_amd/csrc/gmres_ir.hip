@@ -1274,8 +1274,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
 // Pipelined DCGS2 step: the step of k_arnoldi_dcgs2 with its grid-wide sum
 // split by groups of DCGS2P_GS basis vectors, so that pass 2 trails pass 1 by
 // LAG groups instead of waiting for the whole of pass 1.  A thread keeps the
-// basis entries it loaded for a group's pass 1 (in registers for DCGS2P_LAG
-// groups, then, where the LDS holds them, in its own LDS words for NL more)
+// basis entries it loaded for a group's pass 1 (in registers for LR groups,
+// then, where the LDS holds them, in its own LDS words for NL more)
 // and runs that group's pass 2 on them, so the basis is read from memory once
 // per step; the latency of the sums is hidden behind the streaming of the
 // next LAG groups.  Every data thread owns EPT consecutive rows; group g =
@@ -1299,15 +1299,20 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2(ArnoldiArgs a) {
 // already published or will publish without waiting); every wait is bounded.
 // ---------------------------------------------------------------------------
 constexpr int DCGS2P_GS = 4;                   // basis vectors per group
-constexpr int DCGS2P_LAG = 5;                  // groups a thread keeps in registers after their pass 1
-constexpr int DCGS2P_NBUF = DCGS2P_LAG + 2;    // register buffers: groups g - LAG .. g + 1
 static_assert(64 % (2 * DCGS2P_GS) == 0, "a lane set of the poll wave holds one group's values");
+// Register ring of a thread (7 buffers of a group at 163 VGPRs): LR groups kept
+// after their pass 1 and the loads of PF groups ahead.  With the LDS extension
+// LR = 4, PF = 2 (a fixed 400-step solve at 512^2: 45.7 ms against 46.7 for
+// LR = 5, PF = 1, 46.2 for 3 and 3, 47.1 for 2 and 4); without it the lag has
+// no slack to give up: LR = 5, PF = 1.
+__host__ __device__ constexpr int dcgs2p_lr(int nl) { return nl > 0 ? 4 : 5; }
+__host__ __device__ constexpr int dcgs2p_pf(int nl) { return nl > 0 ? 2 : 1; }
 // LDS slots that extend the lag: a thread moves the oldest group of its register
 // ring into LDS instead of running its pass 2 at once, and pass 2 reads it back
 // NL groups later (128 KB of LDS per block at either EPT); NL = 0: no extension
 template <int EPT>
 constexpr int dcgs2p_nl_ext() { return 8 / EPT; }
-__host__ __device__ constexpr int dcgs2p_ring(int nl) { return DCGS2P_LAG + nl + 2; }   // wave partials in flight
+__host__ __device__ constexpr int dcgs2p_ring(int nl) { return dcgs2p_lr(nl) + nl + 2; }   // wave partials in flight
 
 __host__ __device__ constexpr size_t dcgs2p_lds_words(int rmax, int maxlinks, int maxit, int nl, int ept) {
     return (size_t)rmax + (size_t)maxlinks + 2 * (size_t)maxit +
@@ -1543,7 +1548,8 @@ __device__ __forceinline__ void dcgs2p_poll(ArnoldiArgs& a, int b, int nb, int l
 template <int EPT, int NL>
 __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     constexpr int RING = dcgs2p_ring(NL);
-    constexpr int LAG = DCGS2P_LAG + NL;     // groups between pass 1 and pass 2
+    constexpr int LR = dcgs2p_lr(NL), PF = dcgs2p_pf(NL);
+    constexpr int LAG = LR + NL;             // groups between pass 1 and pass 2
     extern __shared__ __align__(16) double dyn[];
     __shared__ double nu_s, gj_s;
     __shared__ double wsum2[2 * (AT_DATA / 64)];
@@ -1595,7 +1601,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
             }
         }
     };
-    constexpr int NBUF = DCGS2P_NBUF;
+    constexpr int NBUF = LR + 1 + PF;        // register buffers: groups g - LR .. g + PF
     double B[NBUF][GS][EPT];
     double u[EPT], yv[EPT];
     if (wave < DW) {
@@ -1609,7 +1615,8 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
             u[e] = ld0(uj, i, ok);
             yv[e] = ld0(a.y, i, ok);
         }
-        load_group(0, B[0]);                  // in flight through the block's first barrier
+#pragma unroll
+        for (int q = 0; q < PF; ++q) load_group(q, B[q]);   // in flight through the block's first barrier
     }
     if (!by_step && a.st->done) return;      // uniform: written by an earlier launch
     // re-arm this block's words of the other buffer for the next launch (2j + 4 values)
@@ -1659,12 +1666,12 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         au[e] = u[e];
         ay[e] = yv[e];
     }
-    // one step g: the loads of group g + 1 into vn, pass 1 of group g from vc
-    // (loaded the step before), pass 2 of group g - LAG from the values this
+    // one step g: the loads of group g + PF into vn, pass 1 of group g from vc
+    // (loaded PF steps before), pass 2 of group g - LAG from the values this
     // thread loaded for that group's pass 1 (so the basis is read once from
-    // memory): from vp, the register buffer of group g - DCGS2P_LAG, or with the
-    // LDS extension from its LDS slot, into which vp then moves;
-    // DCGS2P_LAG + 2 register buffers in turn, one loop trip per DCGS2P_LAG + 2 steps
+    // memory): from vp, the register buffer of group g - LR, or with the LDS
+    // extension from its LDS slot, into which vp then moves; NBUF register
+    // buffers in turn, one loop trip per NBUF steps
     bool ok = true;
     double* mine = ext + t;                  // this thread's LDS words: [slot][GS * EPT] stride AT_DATA
     auto step = [&](int g, double (&vc)[GS][EPT], double (&vn)[GS][EPT], double (&vp)[GS][EPT]) {
@@ -1672,7 +1679,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         // unconditional (past the last group the loads fall on vector 0): a load
         // under a branch makes the compiler's wait counts assume the loads of the
         // step before are the most recent, so pass 1 would wait for every load
-        load_group(g + 1, vn);
+        load_group(g + PF, vn);
         if (g < G) {
             const int ring = g % RING;
             double* wp = wpart + ((size_t)ring * DW + wave) * GV;
@@ -1744,7 +1751,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         }
         if constexpr (NL > 0) {
             // the oldest register group moves into the slot just read (g2 = gr - NL)
-            const int gr = g - DCGS2P_LAG;
+            const int gr = g - LR;
             if (update && ok && gr >= 0 && gr < G)
 #pragma unroll
                 for (int c = 0; c < GS; ++c)
@@ -1758,7 +1765,7 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
         // G + LAG - 1 has no pass 1, no pass 2 and nothing to move, and its wait
         // is for all j sums, which every block receives
 #pragma unroll
-        for (int k = 0; k < NBUF; ++k) step(g + k, B[k], B[(k + 1) % NBUF], B[(k + NBUF - DCGS2P_LAG) % NBUF]);
+        for (int k = 0; k < NBUF; ++k) step(g + k, B[k], B[(k + PF) % NBUF], B[(k + NBUF - LR) % NBUF]);
     }
     if (!ok) {
         if (lane == 0) {

@@ -74,17 +74,21 @@ struct BatchArgs {
     spai_ir_stats* stats;  // per system
 };
 
-// sum over the workgroup; every thread gets the same bits
+// sum over the workgroup; every thread gets the same bits.  The wave totals go
+// to one of two buffers in turn (par, flipped here), so one barrier suffices:
+// the next sum writes the other buffer, and this one is written again only
+// after every thread has passed the next sum's barrier, past its reads here.
 template <typename TW>
-__device__ __forceinline__ TW wg_sum(TW v, TW* sh) {
+__device__ __forceinline__ TW wg_sum(TW v, TW* sh2, int& par) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    TW* sh = sh2 + par * BW;
+    par ^= 1;
     v = wave_sum(v);
     if (lane == 0) sh[wave] = v;
     __syncthreads();
     TW t = 0;
 #pragma unroll
     for (int w = 0; w < BW; ++w) t += sh[w];
-    __syncthreads();
     return t;
 }
 
@@ -165,7 +169,8 @@ __device__ __forceinline__ double wg_max_d(double v, double* sh) {
 // the storage format of P's values, UF the precision of its build (x0 rounds
 // D b to it).
 template <int VP, typename TW, int UF>
-__device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, double* shd, spai_ir_stats& st) {
+__device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, TW* sh2, double* shd,
+                             spai_ir_stats& st) {
     using T = typename ValType<VP>::T;
     constexpr bool U32 = sizeof(TW) == 4;
     const int t = threadIdx.x;
@@ -221,6 +226,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, do
     __syncthreads();
     TW dprev = INFINITY;
     int status = 0;
+    int par = 0;                              // buffer of the next workgroup sum
     for (int step = 0; step < a.imax; ++step) {
         // r = b - A x in u_r, stored in u (A and b as stored in u)
         for (int i = t; i < n; i += BT) r[r0 + i] = (TW)resid_row<U32>(a, r0 + i, x);
@@ -232,7 +238,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, do
             V[i] = z;
             part = tw_fma(z, z, part);
         }
-        const TW beta0 = tw_sqrt(wg_sum(part, sh));
+        const TW beta0 = tw_sqrt(wg_sum(part, sh2, par));
         if (beta0 == (TW)0) break;           // P r_i = 0: x_i solves the system
         if (t == 0) st.steps = step + 1;
         for (int i = t; i < n; i += BT) V[i] = V[i] / beta0;
@@ -260,7 +266,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, do
             for (int i = t; i < n; i += BT) p = tw_fma(y[r0 + i], V[i], p);
             for (int l = 0; l <= jj; ++l) {
                 const TW* vl = V + (size_t)l * n;
-                const TW hl = wg_sum(p, sh);
+                const TW hl = wg_sum(p, sh2, par);
                 if (t == 0) Hc[l] = hl;
                 p = 0;
                 if (l < jj) {
@@ -278,7 +284,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, do
                     }
                 }
             }
-            const TW hn = tw_sqrt(wg_sum(p, sh));
+            const TW hn = tw_sqrt(wg_sum(p, sh2, par));
             TW* vn = V + (size_t)(jj + 1) * n;
             for (int i = t; i < n; i += BT) vn[i] = y[r0 + i] / hn;
             if (t == 0) {
@@ -386,6 +392,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, do
 template <int VP, typename TW, int UF = VP>
 __global__ __launch_bounds__(BT) void k_gmres_ir_batched(BatchArgs a) {
     __shared__ TW sh[BW + 2];
+    __shared__ TW sh2[2 * BW];               // the workgroup sums' two buffers
     __shared__ double shd[BW];
     __shared__ int sys;
     __shared__ spai_ir_stats st;
@@ -396,7 +403,7 @@ __global__ __launch_bounds__(BT) void k_gmres_ir_batched(BatchArgs a) {
         const int q = sys;
         __syncthreads();
         if (q >= a.nsys) break;
-        solve_system<VP, TW, UF>(a, a.order[q], ws, sh, shd, st);
+        solve_system<VP, TW, UF>(a, a.order[q], ws, sh, sh2, shd, st);
     }
 }
 

@@ -244,6 +244,29 @@ def fixed_pattern_flops(A, pattern):
 ANISO_COND2_AT_128 = 1.0e6
 
 
+def profile_run_aniso3d(S, W):
+    """--profile-run --workload aniso3d: one untimed FP32 SPAI build and delayed-CGS2
+    solve of the 128^3 system, then a 256 MiB device copy (the reference for
+    scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+
+    w = W.aniso_fixed(128, "fp32")
+    s, ir = w.spai, w.ir
+    h = S.Handle()
+    A = S.DeviceCSR.from_host(w.A)
+    pat = S.DevicePattern.from_host(w.pattern)
+    P, _, bst = h.spai_build(A, pat, s.eps, s.alpha, s.beta, s.maxfill, "fp32")
+    b = torch.as_tensor(w.b, device="cuda")
+    x = torch.zeros_like(b)
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd", "dcgs2")
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": w.name, "its": st["its"], "nnz_P": bst["nnz"], "copy_bytes": 256 << 20}),
+          flush=True)
+
+
 def measure_aniso3d(S, W, N, reps, solve_golden=None):
     """The 3D anisotropic workload at N^3 (n = 2,097,152 at N = 128): the fixed
     pattern(A^2) SPAI build in FP16, BF16 and FP32 (time, columns/s, algorithmic
@@ -624,7 +647,8 @@ def main():
                     help="build with the library's configuration rule instead of the autotuner's choice")
     ap.add_argument("--profile-run", action="store_true",
                     help="one untimed build + solve of the mixed form and a 256 MiB device copy "
-                         "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE); for profiler runs")
+                         "(the reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE); for profiler runs; "
+                         "with --workload aniso3d the 128^3 FP32 SPAI build and solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each system is solved on one "
@@ -646,6 +670,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         run_batch(S, W, args)
+        return
+    if args.workload == "aniso3d" and args.profile_run:
+        profile_run_aniso3d(S, W)
         return
     if args.workload == "aniso3d":
         run_aniso3d(S, W, args)

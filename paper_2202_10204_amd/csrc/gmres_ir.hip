@@ -1799,16 +1799,19 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
 // keep a lag of groups there): groups of one basis vector; u_j and y wait in
 // LDS (the thread's own words), and pass 2 of vector g - LAG reads that vector
 // again, LAG vectors after its pass 1 read it, into the buffer
-// pass 1 of vector g has just released; the memory-side cache (256 MB) still
-// holds those few vectors (the nearer ones the L2), so the basis streams from
-// HBM about once per step.
-// Sums, poll wave and final steps as in k_arnoldi_dcgs2p.
+// pass 1 of vector g has just released.  That second read misses the L2 (the
+// lag spans more than an XCD's L2 holds), and the memory-side cache (256 MB)
+// serves what it still holds, so HBM sees between one and two reads of the
+// basis per step; the launch gains over the two-pass one mostly by its
+// pipelining.  Sums, poll wave and final steps as in k_arnoldi_dcgs2p.
 // ---------------------------------------------------------------------------
 constexpr int DCGS2M_LAG16 = 3, DCGS2M_LAG8 = 6, DCGS2M_LAG4 = 10;
 // vectors between pass 1 and pass 2 by rows per thread: enough to cover the
-// grid-wide sum at the time a vector takes to stream, few enough that pass 2
-// finds the vector in a cache close by (measured at 16 rows per thread: lag 3, 4,
-// 6, 9 gave 283, 284, 290, 315 ms for a fixed 300-step solve at 128^3)
+// grid-wide sum at the time a vector takes to stream, few enough that the
+// second read still finds much of its vector in the memory-side cache (swept
+// on fixed-step solves: at 16 rows per thread lags 3, 4, 6, 9 gave 283, 284,
+// 290, 315 ms; at 8 rows lags 3, 6, 10 gave 65.0, 61.3, 61.8 ms; at 4 rows
+// lags 4, 10, 16 gave 38.3, 35.5, 36.2 ms)
 __host__ __device__ constexpr int dcgs2m_lag(int ept) { return ept >= 16 ? DCGS2M_LAG16 : ept >= 8 ? DCGS2M_LAG8 : DCGS2M_LAG4; }
 __host__ __device__ constexpr int dcgs2m_ring(int ept) { return dcgs2m_lag(ept) + 2; }
 

@@ -593,6 +593,28 @@ def test_dcgs2_long_restart(S, h):
     assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
 
 
+@pytest.mark.parametrize("blocks,ept,maxit", [(32, 1, None), (32, 1, 700), (16, 2, None), (16, 2, 700)])
+def test_dcgs2_pipelined_shapes(S, h, blocks, ept, maxit, monkeypatch):
+    """The pipelined delayed-CGS2 launch at 1 and 2 rows per thread (the 128x128
+    system on 32 or 16 blocks), with the lag extended through LDS (default
+    maxit) and, at maxit 700, without it (the per-step arrays leave no room):
+    iterations and solution are the oracle's."""
+    monkeypatch.setenv("SPAI_ARNOLDI_BLOCKS", str(blocks))
+    w = W.convdiff_adaptive(128)
+    assert blocks * 512 * ept == w.n
+    A, P, warn, stats = _build(S, h, w)
+    s, ir = w.spai, w.ir
+    maxit = ir.maxit if maxit is None else maxit
+    ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, s.u_f)
+    pp, pc, pv = ref.P_csr(w.n)
+    oref = O.gmres_ir(w.A, pp, pc, pv, ref.d, s.u_f, w.b, ir.tau, ir.imax, maxit, ir.tol_ir, "dcgs2")
+    b = _dev(w.b)
+    x = torch.zeros_like(b)
+    st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, maxit, ir.tol_ir, "dd", "dcgs2")
+    assert st["status"] == 0 and st["its"] == oref.its
+    assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
+
+
 @pytest.mark.parametrize("blocks,ept", [(8, 4), (4, 8), (2, 16)])
 def test_dcgs2_reread_rows_per_thread(S, h, blocks, ept, monkeypatch):
     """The pipelined delayed-CGS2 launch for more than 2 rows per thread (pass 2

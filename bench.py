@@ -704,9 +704,11 @@ def main():
     xt = torch.as_tensor(w.x_true, device="cuda")
 
     # sampled launch timing inside the timed region: every launch of the rare
-    # kernels, every 8th Arnoldi launch and every 16th sparse product (a pair
-    # of events around a launch costs a few microseconds of device time)
-    kernels = [("columns", 1), ("mgs", 8), ("spmv_a", 16), ("apply_p", 16), ("residual", 1), ("update", 1)]
+    # kernels, every 32nd Arnoldi launch and every 64th sparse product (a pair
+    # of events around a launch costs a few microseconds of device time; a
+    # GMRES run of ~400 launches is not a multiple of the stride, so the
+    # samples spread over the whole range of basis sizes)
+    kernels = [("columns", 1), ("mgs", 32), ("spmv_a", 64), ("apply_p", 64), ("residual", 1), ("update", 1)]
     rec, wall, timings, choice = run_form(S, h, w, A, b, x, "fp32", "dd", args.steps, args.warmup, kernels,
                                           args.ortho, not args.no_tune, args.graph, x_true=xt)
     log(f"mixed form: {[(round(a, 1), round(c, 1)) for a, c, *_ in rec]} ms (build, solve)")
@@ -760,7 +762,7 @@ def main():
     dom = max(per_class, key=lambda k: per_class[k]["est_total_ms_per_step"])
     roof = None
     if dom == "mgs" and per_class["mgs"]["avg_ms"]:
-        # every 8th launch is timed; the mean sampled duration times the launches
+        # every 32nd launch is timed; the mean sampled duration times the launches
         # dispatched per solve gives the Arnoldi time of a solve.  Launches
         # enqueued past convergence (no-ops) count in the time but not in the
         # bytes, so the figure is conservative.

@@ -43,7 +43,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def arnoldi_bytes_per_solve(its, n, ortho, pipelined=False):
+def arnoldi_bytes_per_solve(its, n, ortho, pipelined=False, fused=None):
     """Algorithmic HBM bytes of the Arnoldi iterations of one solve, the bytes the
     chosen kernel streams by design, and the number of launches that do work.
 
@@ -54,22 +54,28 @@ def arnoldi_bytes_per_solve(its, n, ortho, pipelined=False):
     reads V_{j-1}, u_j and y, then (two-pass launch) V_{j-1} again, and writes
     v_j and u_{j+1}: 8n(2j+4), or 8n(j+4) for the pipelined launch, which keeps
     what it read for its second pass (launch 0: 8n 3); one more launch per
-    refinement step (pass 1 only) completes the last column."""
+    refinement step (pass 1 only) completes the last column.
+
+    fused = (nnz, value bytes) of the operator's second factor when the
+    pipelined launch computes y itself: instead of y (8n) every launch then
+    reads that factor in CSR (4(n+1) + nnz(4 + value bytes)) and its input
+    vector (8n)."""
+    extra = 0 if fused is None else 4 * (n + 1) + fused[0] * (4 + fused[1])
     alg, design, launches = 0, 0, 0
     for k in its:
         for j in range(k):
-            alg += 8 * n * (j + 3)
+            alg += 8 * n * (j + 3) + extra
             if ortho == "mgs":
                 design += 8 * n * (j + 3)
             elif ortho == "cgs2":
                 design += 8 * n * (4 * (j + 1) + 2)
             elif pipelined:
-                design += 8 * n * (3 if j == 0 else j + 4)
+                design += 8 * n * (3 if j == 0 else j + 4) + extra
             else:
                 design += 8 * n * (2 * j + 4)
             launches += 1
         if ortho == "dcgs2":
-            design += 8 * n * (k + 2)
+            design += 8 * n * (k + 2) + extra
             launches += 1
     return alg, design, launches
 
@@ -770,7 +776,11 @@ def main():
         # (512 data threads per block, a block per CU)
         ncu = min(torch.cuda.get_device_properties(0).multi_processor_count, 256)
         pipelined = args.ortho == "dcgs2" and os.environ.get("SPAI_DCGS2") != "twopass" and n <= ncu * 1024
-        tot_bytes, design_bytes, real = arnoldi_bytes_per_solve(st["its"], n, args.ortho, pipelined)
+        # the pipelined launch with its LDS extension computes y = P w itself (FP32 values of P)
+        fused = (pipelined and os.environ.get("SPAI_DCGS2_LDS") != "0"
+                 and os.environ.get("SPAI_DCGS2_FUSE") != "0")
+        tot_bytes, design_bytes, real = arnoldi_bytes_per_solve(st["its"], n, args.ortho, pipelined,
+                                                                (int(bst["nnz"]), 4) if fused else None)
         cnt, ms = timings["mgs"]
         dispatched = arnoldi_launches_dispatched(st["its"], min(w.ir.maxit, n), args.ortho)
         secs = ms * 1e-3 / cnt * dispatched
@@ -783,7 +793,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                 "bytes_per_launch": tot_bytes / real, "design_bytes_per_launch": design_bytes / real,
                 "design_rate_GBs": design_bytes / secs / 1e9, "avg_launch_us": ms * 1e3 / cnt,
-                "launches_timed": cnt, "launches_per_step": dispatched, "real_launches_per_step": real}
+                "launches_timed": cnt, "launches_per_step": dispatched, "real_launches_per_step": real,
+                "fused_product": bool(pipelined and fused)}
     elif per_class[dom]["avg_ms"]:
         roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "avg_launch_us": per_class[dom]["avg_ms"] * 1e3}

@@ -202,6 +202,11 @@ typedef struct {
  * second pass trails the first, so that the basis streams from memory about
  * once per iteration; the stopping decision for iteration j is taken one
  * iteration later, so one extra product with P A is computed per solve.
+ * Where at most 2 rows per thread suffice, the DCGS2 launch also forms the
+ * iteration's second sparse product (P for left, A for right preconditioning)
+ * at its own rows, so an iteration is two launches; the environment variable
+ * SPAI_DCGS2_FUSE=0 (read at every solve) keeps that product a launch of its own
+ * (same iterates up to the rounding order of that product's sums).
  * CGS2 and DCGS2 need the cooperative Arnoldi kernel (SPAI_E_ARG otherwise). */
 enum { SPAI_ORTHO_MGS = 0, SPAI_ORTHO_CGS2 = 1, SPAI_ORTHO_DCGS2 = 2 };
 
@@ -223,7 +228,7 @@ typedef struct {
     double tol_ir;  /* refinement stops when ||d_i||_inf <= tol_ir ||x_{i+1}||_inf */
     int32_t ortho;  /* SPAI_ORTHO_MGS (0, default), SPAI_ORTHO_CGS2 or SPAI_ORTHO_DCGS2 */
     spai_prec u;    /* working precision: SPAI_FP64 (0, default) or SPAI_FP32 */
-    int32_t graph;  /* DCGS2 only: 1 = each chunk of 8 Arnoldi steps (the operator's two
+    int32_t graph;  /* DCGS2 only: 1 = each chunk of 8 Arnoldi steps (the operator's
                        sparse products and the orthogonalisation launch, per step) is one
                        HIP graph, built once per call and replayed; the kernels take the
                        step index from the device solver state.  Same results as 0

@@ -359,6 +359,13 @@ struct ArnoldiArgs {
     double* HRp;         // DCGS2: first projections, column-major ld x maxit
     double* HRf;         // DCGS2: completed Hessenberg columns before rotation, row-major (maxit+1) x maxit
     int by_step;         // DCGS2 graph replay: j = st->jcur (parity j & 1), advanced by block 0
+    // pipelined DCGS2 with the step's second operator product fused in: y = M mx
+    // at the launch's rows, M in CSR (mrp, mcol, and mval of the value type the
+    // launch is built for); y above is then neither read nor written
+    const int* mrp;
+    const int* mcol;
+    const void* mval;
+    const double* mx;
 };
 
 // Grid-wide sum of one double per block, in two hops that keep every polled
@@ -1545,8 +1552,60 @@ __device__ __forceinline__ void dcgs2p_poll(ArnoldiArgs& a, int b, int nb, int l
     __builtin_amdgcn_s_setprio(0);
 }
 
-template <int EPT, int NL>
+// The step's second operator product inside the pipelined launch: y = M x at a
+// data thread's EPT consecutive rows.  The 64 EPT rows of a wave own one
+// contiguous run of CSR entries, which the wave reads coalesced in chunks of
+// 64 K entries (entry c0 + 64 k + lane on lane `lane`); each lane multiplies its
+// entries by the gathered x and stages the products in the wave's own columns
+// of the lag extension (word k AT_DATA + lane of `stage`, free until the lag
+// first moves a group there), and each thread then adds its rows' products in
+// ascending entry order.  The sums and their order do not depend on the launch
+// shape beyond EPT.  pr: the row pointers of the thread's rows and the one after
+// (clamped to n, so rows past n - 1 are empty).
+template <int EPT, int K, typename T>
+__device__ __forceinline__ void fused_rows(const int (&pr)[EPT + 1], const int* __restrict__ mcol,
+                                           const T* __restrict__ mval, const double* __restrict__ x,
+                                           double* stage, int lane, double (&y)[EPT]) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) y[e] = 0.0;
+    const int lo = __builtin_amdgcn_readlane(pr[0], 0), hi = __builtin_amdgcn_readlane(pr[EPT], 63);
+    for (int c0 = lo; c0 < hi; c0 += 64 * K) {
+        int cj[K];
+        T cv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int q = c0 + 64 * k + lane;
+            const int qq = q < hi ? q : c0;  // past the run: entry c0 again, not staged
+            cj[k] = mcol[qq];
+            cv[k] = mval[qq];
+        }
+        double xv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) xv[k] = x[cj[k]];
+#pragma unroll
+        for (int k = 0; k < K; ++k) stage[(size_t)k * AT_DATA + lane] = to_f64(cv[k]) * xv[k];
+        lds_order();                         // a wave's LDS operations complete in order
+        const int c1 = min(hi, c0 + 64 * K);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            double s = y[e];
+            for (int q = max(pr[e], c0); q < min(pr[e + 1], c1); ++q) {
+                const int o = q - c0;
+                s += stage[(size_t)(o >> 6) * AT_DATA + (o & 63)];
+            }
+            y[e] = s;
+        }
+        lds_order();                         // read before the next chunk overwrites
+    }
+}
+// entries per lane and chunk of the fused product (the stage holds 32 words per lane)
+constexpr int DCGS2P_FK = 24;
+
+// MV < 0: y is read from a.y; MV = a value precision (SPAI_FP64 ..): y = M mx
+// computed in the launch (fused_rows), M's values of that precision
+template <int EPT, int NL, int MV>
 __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
+    static_assert(MV < 0 || DCGS2P_FK <= NL * DCGS2P_GS * EPT, "the fused product stages in the lag extension");
     constexpr int RING = dcgs2p_ring(NL);
     constexpr int LR = dcgs2p_lr(NL), PF = dcgs2p_pf(NL);
     constexpr int LAG = LR + NL;             // groups between pass 1 and pass 2
@@ -1604,17 +1663,22 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
     constexpr int NBUF = LR + 1 + PF;        // register buffers: groups g - LR .. g + PF
     double B[NBUF][GS][EPT];
     double u[EPT], yv[EPT];
+    int pr[EPT + 1];
     if (wave < DW) {
-        // u_j, y and the first group go out before the launch looks at the stop
-        // flag, so that its latency overlaps theirs (all in bounds: j <= maxit)
+        // u_j, y (or the row pointers of the fused product) and the first group
+        // go out before the launch looks at the stop flag, so that its latency
+        // overlaps theirs (all in bounds: j <= maxit)
         const double* uj = a.V + (size_t)j * n;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = row0 + e;
             const bool ok = i < n;
             u[e] = ld0(uj, i, ok);
-            yv[e] = ld0(a.y, i, ok);
+            if constexpr (MV < 0) yv[e] = ld0(a.y, i, ok);
         }
+        if constexpr (MV >= 0)
+#pragma unroll
+            for (int e = 0; e <= EPT; ++e) pr[e] = a.mrp[min(row0 + e, n)];
 #pragma unroll
         for (int q = 0; q < PF; ++q) load_group(q, B[q]);   // in flight through the block's first barrier
     }
@@ -1639,6 +1703,9 @@ __global__ __launch_bounds__(AT) void k_arnoldi_dcgs2p(ArnoldiArgs a) {
             for (int l = lane; l < j; l += 64) hh[l] = a.HRp[(size_t)(j - 1) * a.ld + l];
     }
     if (wave < DW) {
+        if constexpr (MV >= 0)
+            fused_rows<EPT, DCGS2P_FK>(pr, a.mcol, (const typename ValType<MV < 0 ? 0 : MV>::T*)a.mval, a.mx,
+                                       ext + 64 * wave, lane, yv);
         double om = 0.0, c = 0.0;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -2420,6 +2487,7 @@ struct ArnoldiCfg {
     int ortho = SPAI_ORTHO_MGS;
     bool ext = false;        // pipelined DCGS2: the lag extended through LDS
     bool reread = false;     // pipelined DCGS2 with more than 2 rows per thread (pass 2 reads its vector again)
+    int mv = -1;             // pipelined DCGS2 with the LDS extension: value precision of the fused second product, or -1
     size_t shmem = 0;
     size_t slot_words = 0;   // both parities
 };
@@ -2453,15 +2521,30 @@ static bool dcgs2_lds_ext() {
     return x;
 }
 
+// SPAI_DCGS2_FUSE=0 keeps the step's second operator product a launch of its
+// own (read at every solve, so that one process can compare both)
+static bool dcgs2_fuse() {
+    const char* e = getenv("SPAI_DCGS2_FUSE");
+    return !(e && std::string(e) == "0");
+}
+
 template <int EPT>
-static const void* arnoldi_fn(int ortho, bool ext, bool reread) {
+static const void* arnoldi_fn(int ortho, bool ext, bool reread, int mv) {
     switch (ortho) {
     case SPAI_ORTHO_CGS2: return (const void*)k_arnoldi_cgs2<EPT>;
     case SPAI_ORTHO_DCGS2:
         if constexpr (EPT <= 2) {
-            if (dcgs2_pipelined())
-                return ext ? (const void*)k_arnoldi_dcgs2p<EPT, dcgs2p_nl_ext<EPT>()>
-                           : (const void*)k_arnoldi_dcgs2p<EPT, 0>;
+            constexpr int NE = dcgs2p_nl_ext<EPT>();
+            if (dcgs2_pipelined()) {
+                if (!ext) return (const void*)k_arnoldi_dcgs2p<EPT, 0, -1>;
+                switch (mv) {
+                case SPAI_FP64: return (const void*)k_arnoldi_dcgs2p<EPT, NE, SPAI_FP64>;
+                case SPAI_FP32: return (const void*)k_arnoldi_dcgs2p<EPT, NE, SPAI_FP32>;
+                case SPAI_FP16: return (const void*)k_arnoldi_dcgs2p<EPT, NE, SPAI_FP16>;
+                case SPAI_BF16: return (const void*)k_arnoldi_dcgs2p<EPT, NE, SPAI_BF16>;
+                default: return (const void*)k_arnoldi_dcgs2p<EPT, NE, -1>;
+                }
+            }
         } else {
             if (reread) return (const void*)k_arnoldi_dcgs2m<EPT>;
         }
@@ -2470,17 +2553,19 @@ static const void* arnoldi_fn(int ortho, bool ext, bool reread) {
     }
 }
 
-static const void* arnoldi_fn(int ortho, int ept, bool ext, bool reread) {
+static const void* arnoldi_fn(int ortho, int ept, bool ext, bool reread, int mv) {
     switch (ept) {
-    case 1: return arnoldi_fn<1>(ortho, ext, reread);
-    case 2: return arnoldi_fn<2>(ortho, ext, reread);
-    case 4: return arnoldi_fn<4>(ortho, ext, reread);
-    case 8: return arnoldi_fn<8>(ortho, ext, reread);
-    default: return arnoldi_fn<16>(ortho, ext, reread);
+    case 1: return arnoldi_fn<1>(ortho, ext, reread, mv);
+    case 2: return arnoldi_fn<2>(ortho, ext, reread, mv);
+    case 4: return arnoldi_fn<4>(ortho, ext, reread, mv);
+    case 8: return arnoldi_fn<8>(ortho, ext, reread, mv);
+    default: return arnoldi_fn<16>(ortho, ext, reread, mv);
     }
 }
 
-static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
+// mv: value precision of the step's second operator product (fused into the
+// pipelined DCGS2 launch where that launch has its LDS extension), or -1
+static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho, int mv = -1) {
     ArnoldiCfg c;
     c.ortho = ortho;
     if (ortho == SPAI_ORTHO_MGS)
@@ -2530,18 +2615,22 @@ static ArnoldiCfg arnoldi_config(spai_handle* h, int n, int maxit, int ortho) {
         c.slot_words = (size_t)2 * maxlinks * nb * (1 + MBOX_STRIDE);
     }
     if (c.shmem > 159 * 1024) return ArnoldiCfg{};   // 160 KB of LDS per CU, 1 KB for static arrays
-    const void* fn = arnoldi_fn(ortho, ept, c.ext, c.reread);
-    if (c.shmem > 48 * 1024 &&
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.shmem) != hipSuccess) {
-        (void)hipGetLastError();
-        return ArnoldiCfg{};
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AT, c.shmem) != hipSuccess) {
-        (void)hipGetLastError();
-        return ArnoldiCfg{};
-    }
-    if (per_cu * h->num_cu < nb) return ArnoldiCfg{};
+    // whether every block of a launch of fn can be resident at once
+    auto admits = [&](const void* fn) {
+        if (c.shmem > 48 * 1024 &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.shmem) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, AT, c.shmem) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return per_cu * h->num_cu >= nb;
+    };
+    if (c.ext && mv >= 0 && dcgs2_fuse() && admits(arnoldi_fn(ortho, ept, true, false, mv))) c.mv = mv;
+    if (c.mv < 0 && !admits(arnoldi_fn(ortho, ept, c.ext, c.reread, -1))) return ArnoldiCfg{};
     c.nb = nb;
     c.ept = ept;
     return c;
@@ -2571,7 +2660,7 @@ static bool use_cooperative_launch() {
 
 static int launch_arnoldi(spai_handle* h, const ArnoldiCfg& c, ArnoldiArgs& a, hipStream_t s) {
     void* args[] = {&a};
-    const void* fn = arnoldi_fn(c.ortho, c.ept, c.ext, c.reread);
+    const void* fn = arnoldi_fn(c.ortho, c.ept, c.ext, c.reread, c.mv);
     long tk = timer_begin(h, SPAI_KT_MGS);
     hipError_t e = use_cooperative_launch() ? hipLaunchCooperativeKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s)
                                             : hipLaunchKernel(fn, dim3(c.nb), dim3(AT), args, c.shmem, s);
@@ -2637,6 +2726,23 @@ struct ChunkGraph {
     }
 };
 
+// The operands of the second operator product when it runs inside the pipelined
+// DCGS2 launch: y = A w (right preconditioning) or y = P w with w = D A v_j (left)
+static void fused_operands(const ArnoldiCfg& cfg, const spai_csr* A, const spai_precond* P, const double* w,
+                           ArnoldiArgs& aa) {
+    if (cfg.mv < 0) return;
+    if (P->side == SPAI_RIGHT) {
+        aa.mrp = A->rowptr;
+        aa.mcol = A->col;
+        aa.mval = A->val;
+    } else {
+        aa.mrp = P->rowptr;
+        aa.mcol = P->col;
+        aa.mval = P->val;
+    }
+    aa.mx = w;
+}
+
 // Captures `steps` Arnoldi steps (operator products, then the DCGS2 launch) on a
 // private stream into cg: every kernel takes the step index from st->jcur and
 // the DCGS2 launch advances it, so one executable serves every chunk of every
@@ -2657,13 +2763,14 @@ static int capture_chunk(spai_handle* h, const spai_csr* A, const spai_precond* 
     aa.parity = 0;
     int rc = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess ? SPAI_OK : SPAI_E_HIP;
     const bool capturing = rc == SPAI_OK;
+    const bool fused = cfg.mv >= 0;   // the second product runs inside the Arnoldi launch
     for (int q = 0; q < steps && rc == SPAI_OK; ++q) {
         if (right) {                                               // y = A P v_j
             rc = launch_apply_P(h, P, V, w, cs, sst, false, 1);
-            if (!rc) rc = launch_spmv(h, A, w, y, cs, sst);
+            if (!rc && !fused) rc = launch_spmv(h, A, w, y, cs, sst);
         } else {                                                   // y = M^T (D (A v_j))
             rc = launch_spmv(h, A, V, w, cs, sst, P->d, 1);
-            if (!rc) rc = launch_apply_P(h, P, w, y, cs, sst, true);
+            if (!rc && !fused) rc = launch_apply_P(h, P, w, y, cs, sst, true);
         }
         if (!rc) rc = launch_arnoldi(h, cfg, aa, cs);
     }
@@ -2717,7 +2824,9 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
     hipStream_t s = h->stream;
     const int maxit = std::min(prm->maxit, n);
     const int ld = maxit + 1;
-    const ArnoldiCfg cfg = arnoldi_config(h, n, maxit, prm->ortho);
+    // the step's second operator product (A for right, P for left preconditioning)
+    // can run inside the pipelined DCGS2 launch
+    const ArnoldiCfg cfg = arnoldi_config(h, n, maxit, prm->ortho, P->side == SPAI_RIGHT ? SPAI_FP64 : P->val_prec);
     SPAI_ARG(cfg.nb > 0 || prm->ortho == SPAI_ORTHO_MGS,
              "CGS2 and DCGS2 need the cooperative Arnoldi kernel, which cannot hold this problem");
     const int maxlinks = maxit + 2;
@@ -2783,6 +2892,7 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
         aa.n = n; aa.ld = ld; aa.maxit = maxit; aa.maxlinks = maxlinks; aa.nb = cfg.nb;
         aa.y = y; aa.V = V; aa.H = H; aa.cs = cs; aa.sn = sn; aa.g = g; aa.tau = prm->tau;
         aa.slots = slots; aa.st = sst; aa.HRp = HRp; aa.HRf = HRf;
+        fused_operands(cfg, A, P, w, aa);
         if ((rc = capture_chunk(h, A, P, cfg, aa, V, w, y, sst, chunk, cgraph))) return rc;
     }
 
@@ -2837,12 +2947,13 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
             }
             for (int j = j0; j < j1; ++j) {
                 double* vj = V + (size_t)j * n;
+                const bool fused = cfg.nb && cfg.mv >= 0;   // the second product inside the Arnoldi launch
                 if (right) {                                               // y = A P v_j
                     if ((rc = launch_apply_P(h, P, vj, w, s, sst))) return rc;
-                    if ((rc = launch_spmv(h, A, w, y, s, sst))) return rc;
+                    if (!fused && (rc = launch_spmv(h, A, w, y, s, sst))) return rc;
                 } else {                                                   // y = M^T (D (A v_j))
                     if ((rc = launch_spmv(h, A, vj, w, s, sst, P->d))) return rc;
-                    if ((rc = launch_apply_P(h, P, w, y, s, sst, true))) return rc;
+                    if (!fused && (rc = launch_apply_P(h, P, w, y, s, sst, true))) return rc;
                 }
                 if (cfg.nb) {
                     ArnoldiArgs aa{};
@@ -2850,6 +2961,7 @@ int gmres_ir_impl(spai_handle* h, const spai_csr* A, const spai_precond* P, cons
                     aa.parity = sweep & 1;
                     aa.y = y; aa.V = V; aa.H = H; aa.cs = cs; aa.sn = sn; aa.g = g; aa.tau = prm->tau;
                     aa.slots = slots; aa.st = sst; aa.HRp = HRp; aa.HRf = HRf;
+                    fused_operands(cfg, A, P, w, aa);
                     if ((rc = launch_arnoldi(h, cfg, aa, s))) return rc;
                     ++sweep;
                 } else {

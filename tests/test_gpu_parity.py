@@ -636,6 +636,42 @@ def test_dcgs2_reread_rows_per_thread(S, h, blocks, ept, monkeypatch):
     assert np.abs(x.cpu().numpy() - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
 
 
+@pytest.mark.parametrize("blocks,side,uf", [(32, "left", "fp32"), (16, "left", "fp32"), (16, "left", "fp16"),
+                                             (32, "left", "bf16"), (16, "left", "fp64"), (32, "right", "fp32"),
+                                             (16, "right", "fp32")])
+def test_dcgs2_fused_second_product(S, h, blocks, side, uf, monkeypatch):
+    """The pipelined delayed-CGS2 launch computing the step's second operator
+    product itself (y = P w with w = D A v_j for left, y = A w with w = P v_j for
+    right preconditioning; P's values in every storage precision) and, with
+    SPAI_DCGS2_FUSE=0, that product as a launch of its own: the 128x128 system
+    on 32 blocks (1 row per thread) or 16 (2 rows per thread).  Both give the
+    oracle's iterations, and solutions that agree with the oracle's and with
+    each other."""
+    monkeypatch.setenv("SPAI_ARNOLDI_BLOCKS", str(blocks))
+    w = W.convdiff_adaptive(128)
+    s, ir = w.spai, w.ir
+    A = S.DeviceCSR.from_host(w.A)
+    if side == "left":
+        P, _, _ = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, uf)
+        ref = O.spai(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, uf)
+        pp, pc, pv = ref.P_csr(w.n)
+        d = ref.d
+    else:
+        P, _, _ = h.spai_build(A, None, s.eps, s.alpha, s.beta, s.maxfill, uf, "right")
+        _, pp, pc, pv, d = O.spai_right(w.A, w.pattern, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    oref = O.gmres_ir(w.A, pp, pc, pv, d, uf, w.b, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dcgs2", side=side)
+    b = _dev(w.b)
+    xs = []
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("SPAI_DCGS2_FUSE", fuse)
+        x = torch.zeros_like(b)
+        st = h.gmres_ir(A, P, b, x, ir.tau, ir.imax, ir.maxit, ir.tol_ir, "dd", "dcgs2")
+        assert st["status"] == 0 and st["its"] == oref.its, (fuse, st["its"], oref.its)
+        xs.append(x.cpu().numpy())
+        assert np.abs(xs[-1] - oref.x).max() <= 1e-10 * np.abs(w.x_true).max()
+    assert np.abs(xs[0] - xs[1]).max() <= 1e-10 * np.abs(w.x_true).max()
+
+
 # ---------------------------------------------------------------------------
 # 3D anisotropic diffusion at full size (128^3, n = 2,097,152, pattern(A^2)
 # capped at 27 entries per column: nnz(P) = 51,742,208)

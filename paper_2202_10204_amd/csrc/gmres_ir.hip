@@ -54,7 +54,9 @@ struct SolveState {
 // one thread per row, and coalesced loads.
 
 // IT: entries per lane of a row whose loads are issued together (1 or 2: the
-// lanes per row are chosen so that an average row takes at most 1.5 rounds)
+// lanes per row are chosen so that an average row takes at most 1.5 rounds;
+// for a large matrix with short rows, one lane per row and IT = 4..8, a whole
+// average row in flight: spmv_shape)
 template <int G, int R, int IT>
 __global__ __launch_bounds__(256) void k_spmv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const double* __restrict__ av, const double* __restrict__ x,
@@ -2404,20 +2406,46 @@ static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w
     return SPAI_OK;
 }
 
+// Lanes per row and entries per lane in flight of the operator's product.  A
+// large matrix with short rows (at least 65,536 rows of at most 8 entries on
+// average) takes one lane per row with ceil(average) entries in flight, 4 to 8:
+// measured for 5 entries per row at 512^2 (an Arnoldi solve of 400 fixed steps
+// 43.5 ms against 44.0 with 4 lanes of two entries) and for 7 at 128^3 (a
+// product 46.0 us against 53.5; 46.8 with 8 in flight, 51.8 with 2 lanes of 3).
+// Otherwise lanes_per_row and row_it, as for P (small systems keep that shape).
+struct SpmvShape {
+    int g, it;
+};
+static SpmvShape spmv_shape(long long nnz, int n) {
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    if (n >= (1 << 16) && avg <= 8.0) return {1, std::max(4, (int)std::ceil(avg))};
+    const int g = lanes_per_row(nnz, n);
+    return {g, row_it(nnz, n, g)};
+}
+
 // dout (may be NULL): output scaling, y_i = dout_i (A x)_i; by_step as launch_apply_P
 static int launch_spmv(spai_handle* h, const spai_csr* A, const double* x, double* y, hipStream_t s,
                        const SolveState* st = nullptr, const double* dout = nullptr, int by_step = 0) {
-    const int n = A->n, g = lanes_per_row(A->nnz, n);
+    const int n = A->n;
+    const SpmvShape sh = spmv_shape(A->nnz, n);
+    const int g = sh.g, it = sh.it;
     SPAI_ARG(A->nnz >= 1, "the matrix has no entries");   // the kernel reads entry 0 past row ends
     const long long groups = ((long long)n + SPMV_R - 1) / SPMV_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
     long tk = timer_begin(h, SPAI_KT_SPMV_A);
-    const int it = row_it(A->nnz, n, g);
 #define SPAI_SP(G, IT)                                                                                              \
     hipLaunchKernelGGL((k_spmv_g<G, SPMV_R, IT>), dim3(grid), dim3(256), 0, s, n, A->rowptr, A->col, A->val, x, y, \
                        dout, st, by_step)
 #define SPAI_SP2(G) if (it == 2) SPAI_SP(G, 2); else SPAI_SP(G, 1)
-    switch (g) {
+    if (g == 1 && it >= 4) {
+        switch (it) {
+        case 4: SPAI_SP(1, 4); break;
+        case 5: SPAI_SP(1, 5); break;
+        case 6: SPAI_SP(1, 6); break;
+        case 7: SPAI_SP(1, 7); break;
+        default: SPAI_SP(1, 8); break;
+        }
+    } else switch (g) {
     case 1: SPAI_SP2(1); break;
     case 2: SPAI_SP2(2); break;
     case 4: SPAI_SP2(4); break;

@@ -2358,6 +2358,23 @@ constexpr int APPLY_R = 4;
 // longer than the lanes per row, else 1
 static inline int row_it(long long nnz, int n, int g) { return (double)nnz > (double)g * n ? 2 : 1; }
 
+// Lanes per row and entries per lane in flight of an application of P.  A
+// large preconditioner with 17 to 32 entries per row on average takes 4 lanes
+// per row with ceil(average / 4) entries each in flight: measured at 128^3
+// (25 per row; a fixed 300-step solve 268 ms against 276 with 16 lanes of two,
+// 271 with 8 of four, 270 with 4 of eight, 280 with 2 of fourteen).  Otherwise
+// lanes_per_row and row_it.
+static inline int apply_it(long long nnz, int n, int g) {
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    if (g == 4 && n >= (1 << 16) && avg > 16.0 && avg <= 32.0) return (int)std::ceil(avg / 4.0);
+    return row_it(nnz, n, g);
+}
+static inline int apply_lanes(long long nnz, int n) {
+    const double avg = n > 0 ? (double)nnz / n : 0.0;
+    if (n >= (1 << 16) && avg > 16.0 && avg <= 32.0) return 4;
+    return lanes_per_row(nnz, n);
+}
+
 template <int VP, bool RIGHT, bool SCALED = false>
 static void apply_P_g(int g, int n, const spai_precond* P, const double* w, double* y, hipStream_t s,
                       const SolveState* st, int by_step) {
@@ -2365,12 +2382,19 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
     const T* pv = (const T*)P->val;
     const long long groups = ((long long)n + APPLY_R - 1) / APPLY_R;
     const unsigned grid = (unsigned)((groups * g + 255) / 256);
-    const int it = row_it(P->nnz, n, g);
+    const int it = apply_it(P->nnz, n, g);
 #define SPAI_AP(G, IT)                                                                                       \
     hipLaunchKernelGGL((k_apply_P_g<VP, G, APPLY_R, RIGHT, SCALED, IT>), dim3(grid), dim3(256), 0, s, n, P->rowptr, \
                        P->col, pv, P->d, w, y, st, by_step)
 #define SPAI_AP2(G) if (it == 2) SPAI_AP(G, 2); else SPAI_AP(G, 1)
-    switch (g) {
+    if (g == 4 && it >= 5) {
+        switch (it) {
+        case 5: SPAI_AP(4, 5); break;
+        case 6: SPAI_AP(4, 6); break;
+        case 7: SPAI_AP(4, 7); break;
+        default: SPAI_AP(4, 8); break;
+        }
+    } else switch (g) {
     case 1: SPAI_AP2(1); break;
     case 2: SPAI_AP2(2); break;
     case 4: SPAI_AP2(4); break;
@@ -2386,7 +2410,7 @@ static void apply_P_g(int g, int n, const spai_precond* P, const double* w, doub
 // by_step (graph replay, st set): the input is column st->jcur of the basis starting at w
 static int launch_apply_P(spai_handle* h, const spai_precond* P, const double* w, double* y, hipStream_t s,
                           const SolveState* st = nullptr, bool scaled = false, int by_step = 0) {
-    const int n = P->n, g = lanes_per_row(P->nnz, n);
+    const int n = P->n, g = apply_lanes(P->nnz, n);
     SPAI_ARG(P->nnz >= 1, "the preconditioner has no entries");   // the kernel reads entry 0 past row ends
     long tk = timer_begin(h, SPAI_KT_APPLY_P);
     const int mode = P->side == SPAI_RIGHT ? 2 : scaled ? 1 : 0;

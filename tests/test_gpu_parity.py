@@ -672,6 +672,39 @@ def test_dcgs2_fused_second_product(S, h, blocks, side, uf, monkeypatch):
     assert np.abs(xs[0] - xs[1]).max() <= 1e-10 * np.abs(w.x_true).max()
 
 
+@pytest.mark.parametrize("uf", ["fp32", "fp16", "fp64"])
+def test_product_shapes_of_large_operators(S, h, uf):
+    """The shapes the operator products take for at least 65,536 rows: A with 7
+    entries per row (one lane per row, all 7 in flight) and P with about 25 per
+    row (4 lanes per row, 7 entries each in flight), on the 41^3 anisotropic
+    system (n = 68,921), element by element against the same products formed
+    on the CPU from the matrices' own values (P as stored, in every precision)."""
+    import scipy.sparse as sp
+
+    w = W.aniso_fixed(41, uf)
+    assert w.n >= 65536
+    A = S.DeviceCSR.from_host(w.A)
+    pat = S.DevicePattern.from_host(w.pattern)
+    s = w.spai
+    P, _, _ = h.spai_build(A, pat, s.eps, s.alpha, s.beta, s.maxfill, uf)
+    rp, col, val, d = (t.cpu() for t in P.csr())
+    Ph = sp.csr_matrix((val.double().numpy(), col.numpy(), rp.numpy()), shape=(w.n, w.n))
+    assert 16 < Ph.nnz / w.n <= 32 and w.A.nnz / w.n <= 8
+    Ah = sp.csr_matrix((w.A.val, w.A.col, w.A.rowptr), shape=(w.n, w.n))
+    rng = np.random.default_rng(5)
+    xv = rng.standard_normal(w.n)
+    x = _dev(xv)
+    y = torch.empty_like(x)
+    h.spmv(A, x, y)
+    ref = Ah @ xv
+    scale = (abs(Ah) @ np.abs(xv)).max()
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-14 * scale
+    h.precond_apply(P, x, y)                 # y = M^T (D x), left preconditioner
+    ref = Ph @ (d.numpy() * xv)
+    scale = (abs(Ph) @ np.abs(d.numpy() * xv)).max()
+    assert np.abs(y.cpu().numpy() - ref).max() <= 1e-14 * scale
+
+
 # ---------------------------------------------------------------------------
 # 3D anisotropic diffusion at full size (128^3, n = 2,097,152, pattern(A^2)
 # capped at 27 entries per column: nnz(P) = 51,742,208)

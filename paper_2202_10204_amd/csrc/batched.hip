@@ -114,6 +114,11 @@ template <typename TW, typename T> __device__ __forceinline__ TW to_tw(T v) {
     else return to_f32(v);
 }
 
+// The entry loops of a row are unrolled by 4 so that four entries' index,
+// value and gather loads are in flight together; the sums keep their order (the
+// same bits).  Measured on the 4096-system batch: the solve 133.0 -> 109.8 ms
+// (products and residual; 111.1 with the products alone, 118.1 unrolled by 8).
+
 // y_i = sum_q m_q (d_j w_j) over row i of P in the working precision TW (d
 // rounded to TW; rows r0 + i, columns global)
 template <int VP, typename TW>
@@ -121,6 +126,7 @@ __device__ __forceinline__ TW p_row(const BatchArgs& a, int gi, const TW* w) {
     using T = typename ValType<VP>::T;
     const T* pv = (const T*)a.pv;
     TW s = 0;
+#pragma unroll 4
     for (int q = a.pp[gi]; q < a.pp[gi + 1]; ++q) {
         const int j = a.pc[q];
         s = tw_fma(to_tw<TW>(pv[q]), (TW)a.d[j] * w[j], s);
@@ -135,6 +141,7 @@ template <bool U32>
 __device__ __forceinline__ double resid_row(const BatchArgs& a, int gi, const double* x) {
     if (a.dd) {
         double shi = a.b[gi], slo = 0.0;
+#pragma unroll 4
         for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
             const double av = a.av[q], xv = x[a.ci[q]];
             const double ph = av * xv;
@@ -144,6 +151,7 @@ __device__ __forceinline__ double resid_row(const BatchArgs& a, int gi, const do
         return shi + slo;
     }
     double acc = U32 ? (double)(float)a.b[gi] : a.b[gi];
+#pragma unroll 4
     for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) {
         const double av = U32 ? (double)(float)a.av[q] : a.av[q];
         acc = __builtin_fma(-av, x[a.ci[q]], acc);
@@ -252,6 +260,7 @@ __device__ void solve_system(const BatchArgs& a, int s, double* ws_d, TW* sh, TW
             for (int i = t; i < n; i += BT) {
                 const int gi = r0 + i;
                 TW acc = 0;
+#pragma unroll 4
                 for (int q = a.rp[gi]; q < a.rp[gi + 1]; ++q) acc = tw_fma((TW)a.av[q], vj[a.ci[q] - r0], acc);
                 w[gi] = acc;
             }

@@ -535,6 +535,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(C::AREG && !
         int rlo = INT_MAX, rhi = -1;
         if (lane < p) {
             double dj = a.d[myj];
+            // unrolled by 4: four entries' index and value loads in flight (each
+            // entry has its own slot, so the order does not matter)
+#pragma unroll 4
             for (int q = 0; q < myn; ++q) {
                 int slot = off + q;
                 int i = a.ci[mys + q];

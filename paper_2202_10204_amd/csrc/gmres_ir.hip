@@ -225,20 +225,24 @@ __global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ 
                      const double* __restrict__ b, double* __restrict__ x0) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    // entry loops unrolled by 4 (loads in flight together, the same order)
     if constexpr (RIGHT) {
         // P = D M: b rounded to u_f, the row's sum in the arithmetic of u_f, times d_k rounded to u_f
         if constexpr (VP == SPAI_FP64) {
             double s = 0.0;
+#pragma unroll 4
             for (int q = pp[k]; q < pp[k + 1]; ++q) s = __builtin_fma(pv[q], b[pc[q]], s);
             x0[k] = d[k] * s;
         } else {
             float s = 0.0f;
+#pragma unroll 4
             for (int q = pp[k]; q < pp[k + 1]; ++q)
                 s = __builtin_fmaf(to_f32(pv[q]), store<UF, float>((float)b[pc[q]]), s);
             x0[k] = (double)(store<UF, float>((float)d[k]) * s);
         }
     } else if constexpr (VP == SPAI_FP64) {
         double s = 0.0;
+#pragma unroll 4
         for (int q = pp[k]; q < pp[k + 1]; ++q) {
             int j = pc[q];
             s = __builtin_fma(pv[q], d[j] * b[j], s);
@@ -246,6 +250,7 @@ __global__ void k_x0(int n, const int* __restrict__ pp, const int* __restrict__ 
         x0[k] = s;
     } else {
         float s = 0.0f;
+#pragma unroll 4
         for (int q = pp[k]; q < pp[k + 1]; ++q) {
             int j = pc[q];
             float z = store<UF, float>((float)(d[j] * b[j]));
@@ -293,8 +298,10 @@ __global__ void k_residual(int n, const int* __restrict__ rp, const int* __restr
                            const double* __restrict__ x, double* __restrict__ r) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // entry loops unrolled by 4: four entries' loads in flight, the same order
     if constexpr (DD) {
         double sh = b[i], sl = 0.0;
+#pragma unroll 4
         for (int q = rp[i]; q < rp[i + 1]; ++q) {
             double a = av[q], xv = x[ci[q]];
             double ph = a * xv;
@@ -304,6 +311,7 @@ __global__ void k_residual(int n, const int* __restrict__ rp, const int* __restr
         r[i] = sh + sl;
     } else {
         double s = b[i];
+#pragma unroll 4
         for (int q = rp[i]; q < rp[i + 1]; ++q) s = __builtin_fma(-av[q], x[ci[q]], s);
         r[i] = s;
     }
